@@ -1,0 +1,229 @@
+"""Seeded synthetic problem instances for multi-patch isogeometric elasticity.
+
+This module only draws random numbers and lays out problem descriptions
+(patch corner coordinates, spline degree and continuity, element counts,
+Lame parameters, Dirichlet faces and load modes).  It contains none of the
+solver's arithmetic: both the CPU oracle and the GPU library read the plain
+dictionaries produced here, and each evaluates them with its own code.
+
+Problem dictionary layout
+-------------------------
+``dim``          2 or 3.
+``patches``      list of patch dicts, colexicographic over the patch grid:
+    ``corners``  (2**dim, dim) float64 corner coordinates; corner index
+                 a1 + 2*a2 + 4*a3 with a_l in {0, 1} (colexicographic, the
+                 first parametric direction runs fastest).  The patch map is
+                 the multilinear interpolant of its corners.
+    ``p``        spline degree (same in every direction).
+    ``reg``      continuity C^reg across interior knots (reg = p - 1 gives
+                 knots of multiplicity one).
+    ``n_el``     elements per parametric direction (uniform open knots).
+    ``lam``, ``mu``  Lame parameters of the patch.
+    ``bc``       2*dim face flags, order (dir1 min, dir1 max, dir2 min, ...):
+                 0 = natural (traction-free or interface), 1 = Dirichlet u=0.
+``load``         list of separable trigonometric body-force modes
+                 (component, amplitude, k[dim], phase[dim]) meaning
+                 f_component(x) += amplitude * prod_d sin(pi*k_d*x_d + phase_d).
+``tol``          MINRES tolerance on the preconditioned residual ratio.
+
+Material constants: E = 1, nu = 0.3 gives lambda = 0.3/0.52, mu = 1/2.6
+(the paper's "steel" values, Section 6).
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+STEEL_LAM = 0.3 / 0.52
+STEEL_MU = 1.0 / 2.6
+
+FACE_FREE = 0
+FACE_DIRICHLET = 1
+
+
+def _grid_vertices(grid, rng, delta):
+    """Vertex lattice of the unit square/cube split into ``grid`` patches.
+
+    Vertices strictly inside the domain are moved by U(-delta, delta)^dim;
+    boundary vertices stay, so the outer boundary is the unit box.
+    Returns an array of shape grid+1 (reversed, colex) + (dim,).
+    """
+    dim = len(grid)
+    axes = [np.linspace(0.0, 1.0, g + 1) for g in grid]
+    shape = tuple(g + 1 for g in grid)
+    verts = np.zeros(shape + (dim,))
+    for idx in np.ndindex(*shape):
+        interior = all(0 < idx[d] < grid[d] for d in range(dim))
+        pos = np.array([axes[d][idx[d]] for d in range(dim)])
+        if interior and delta > 0:
+            pos = pos + rng.uniform(-delta, delta, size=dim)
+        verts[idx] = pos
+    return verts
+
+
+def _patches_from_grid(grid, verts, p, reg, n_el, lam, mu, dirichlet_planes):
+    """Build patch dicts, colexicographic over the patch grid.
+
+    ``dirichlet_planes``: list of (direction, side) of the unit box that carry
+    u = 0 (side 0 = coordinate 0, side 1 = coordinate 1).
+    """
+    dim = len(grid)
+    patches = []
+    pid = 0
+    for pidx in np.ndindex(*tuple(reversed(grid))):
+        pidx = tuple(reversed(pidx))  # pidx[0] runs fastest
+        corners = np.zeros((2 ** dim, dim))
+        for c in range(2 ** dim):
+            a = [(c >> d) & 1 for d in range(dim)]
+            corners[c] = verts[tuple(pidx[d] + a[d] for d in range(dim))]
+        bc = [FACE_FREE] * (2 * dim)
+        for (d, side) in dirichlet_planes:
+            if side == 0 and pidx[d] == 0:
+                bc[2 * d] = FACE_DIRICHLET
+            if side == 1 and pidx[d] == grid[d] - 1:
+                bc[2 * d + 1] = FACE_DIRICHLET
+        patches.append(dict(corners=corners, p=int(p), reg=int(reg),
+                            n_el=[int(n) for n in n_el],
+                            lam=float(lam[pid]), mu=float(mu[pid]), bc=bc))
+        pid += 1
+    return patches
+
+
+def _random_modes(rng, n_modes, dim):
+    modes = []
+    for _ in range(n_modes):
+        comp = int(rng.integers(0, dim))
+        amp = float(rng.normal())
+        k = [int(v) for v in rng.integers(1, 4, size=dim)]
+        ph = [float(v) for v in rng.uniform(0.0, 2.0 * math.pi, size=dim)]
+        modes.append((comp, amp, k, ph))
+    return modes
+
+
+def _lognormal(rng, n):
+    return np.exp(rng.normal(0.0, 0.5, size=n))
+
+
+def make_c1(seed=0, n_el=16, p=2, grid=(2, 2), delta=0.1):
+    """2D: unit square in 2x2 bilinear patches, interior vertex moved by
+    U(-0.1, 0.1)^2, p=2 C^1, 16x16 elements per patch, lambda = mu = 1,
+    f = (sin(pi x) sin(pi y), cos(pi x) sin(pi y)), u = 0 on x = 0."""
+    rng = np.random.default_rng(seed)
+    verts = _grid_vertices(grid, rng, delta)
+    n_p = int(np.prod(grid))
+    patches = _patches_from_grid(grid, verts, p, p - 1, [n_el] * 2,
+                                 np.ones(n_p), np.ones(n_p), [(0, 0)])
+    half_pi = 0.5 * math.pi
+    load = [(0, 1.0, [1, 1], [0.0, 0.0]),
+            (1, 1.0, [1, 1], [half_pi, 0.0])]
+    return dict(name="c1", dim=2, patches=patches, load=load, tol=1e-8)
+
+
+def make_c2(seed=0, n_el=32, p=3, grid=(2, 2, 2), delta=0.05):
+    """3D: unit cube in 2x2x2 trilinear patches, the interior vertex moved by
+    U(-0.05, 0.05)^3, p=3 C^2, 32^3 elements per patch, E=1 nu=0.3,
+    f = (sin sin sin, cos sin sin, sin cos sin)(pi x, pi y, pi z),
+    u = 0 on z = 0."""
+    rng = np.random.default_rng(seed)
+    verts = _grid_vertices(grid, rng, delta)
+    n_p = int(np.prod(grid))
+    patches = _patches_from_grid(grid, verts, p, p - 1, [n_el] * 3,
+                                 np.full(n_p, STEEL_LAM), np.full(n_p, STEEL_MU),
+                                 [(2, 0)])
+    hp = 0.5 * math.pi
+    load = [(0, 1.0, [1, 1, 1], [0.0, 0.0, 0.0]),
+            (1, 1.0, [1, 1, 1], [hp, 0.0, 0.0]),
+            (2, 1.0, [1, 1, 1], [0.0, hp, 0.0])]
+    return dict(name="c2", dim=3, patches=patches, load=load, tol=1e-8)
+
+
+def make_c3(seed=0, p=3, n_el=24, grid=(4, 4, 4), rel_delta=0.1, n_modes=8):
+    """3D: unit cube in 4x4x4 patches, interior vertices moved by
+    U(-0.1 h_patch, 0.1 h_patch)^3, p in {2..5} at C^{p-1}, 24^3 elements,
+    per-patch lambda, mu ~ lognormal(0, 0.5), 8 seeded trig load modes,
+    u = 0 on z = 0."""
+    rng = np.random.default_rng(seed)
+    delta = rel_delta / max(grid)
+    verts = _grid_vertices(grid, rng, delta)
+    n_p = int(np.prod(grid))
+    lam = _lognormal(rng, n_p)
+    mu = _lognormal(rng, n_p)
+    patches = _patches_from_grid(grid, verts, p, p - 1, [n_el] * 3, lam, mu,
+                                 [(2, 0)])
+    return dict(name="c3", dim=3, patches=patches,
+                load=_random_modes(rng, n_modes, 3), tol=1e-8)
+
+
+def make_c4(seed=0, n_problems=32, el_range=(8, 40), p_choices=(2, 3, 4),
+            rel_delta=0.1, n_modes=8):
+    """Ragged batch: each problem has a patch grid uniform in {1,2,3}^3,
+    elements per direction uniform in [8, 40] (shared by the problem's
+    patches), p uniform in {2,3,4} at C^{p-1}, perturbed interior vertices,
+    lognormal Lame parameters, 8 seeded trig modes, u = 0 on z = 0."""
+    rng = np.random.default_rng(seed)
+    probs = []
+    for j in range(n_problems):
+        grid = tuple(int(g) for g in rng.integers(1, 4, size=3))
+        n_el = [int(v) for v in rng.integers(el_range[0], el_range[1] + 1, size=3)]
+        p = int(rng.choice(p_choices))
+        delta = rel_delta / max(grid)
+        verts = _grid_vertices(grid, rng, delta)
+        n_p = int(np.prod(grid))
+        lam = _lognormal(rng, n_p)
+        mu = _lognormal(rng, n_p)
+        patches = _patches_from_grid(grid, verts, p, p - 1, n_el, lam, mu, [(2, 0)])
+        probs.append(dict(name=f"c4_{j}", dim=3, patches=patches,
+                          load=_random_modes(rng, n_modes, 3), tol=1e-8))
+    return probs
+
+
+def make_c5(seed=0, n_el=32, p=3, grid=(3, 3, 3), rel_delta=0.1, n_modes=64):
+    """Adjoint workload: 3x3x3 patches, 32^3 elements, p=3 C^2, lognormal
+    per-patch Lame parameters, 64 seeded trig load modes whose amplitudes are
+    the load coefficients, u = 0 on z = 0."""
+    rng = np.random.default_rng(seed)
+    delta = rel_delta / max(grid)
+    verts = _grid_vertices(grid, rng, delta)
+    n_p = int(np.prod(grid))
+    lam = _lognormal(rng, n_p)
+    mu = _lognormal(rng, n_p)
+    patches = _patches_from_grid(grid, verts, p, p - 1, [n_el] * 3, lam, mu,
+                                 [(2, 0)])
+    return dict(name="c5", dim=3, patches=patches,
+                load=_random_modes(rng, n_modes, 3), tol=1e-8)
+
+
+def redraw_parameters(prob, seed):
+    """Second parameter draw (Lame per patch and load amplitudes) on the same
+    geometry and discretisation; used for the adjoint target field."""
+    rng = np.random.default_rng(seed)
+    out = copy.deepcopy(prob)
+    n_p = len(out["patches"])
+    lam = _lognormal(rng, n_p)
+    mu = _lognormal(rng, n_p)
+    for k, pa in enumerate(out["patches"]):
+        pa["lam"] = float(lam[k])
+        pa["mu"] = float(mu[k])
+    out["load"] = [(c, float(rng.normal()), k, ph) for (c, _a, k, ph) in out["load"]]
+    return out
+
+
+def with_overrides(prob, **kw):
+    out = copy.deepcopy(prob)
+    out.update(kw)
+    return out
+
+
+def random_vector(n, seed):
+    """Seeded N(0,1) vector, shared input for both implementations."""
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+CONFIGS = {
+    "c1": make_c1,
+    "c2": make_c2,
+    "c3": make_c3,
+    "c5": make_c5,
+}
