@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Benchmark of the inexact AF-IETI solve on one MI355X.
+
+Workload (default): 3D compressible elasticity on the unit cube split into
+2x2x2 trilinear patches (interior vertex moved by U(-0.05, 0.05)^3, seed 0),
+splines p=3 C^2 with 32^3 elements per patch (35^3 basis functions x 3
+components, 1,029,000 DOF), E=1, nu=0.3, trigonometric body force, u=0 on
+z=0; MINRES to a preconditioned residual ratio of 1e-8 from x0=0.
+
+One step = one full AF-IETI solve (prologue, MINRES with the FD/Schur
+preconditioner, recovery) with inputs resident in HBM; assembly and FD setup
+are outside the timed region.  The headline value is the FP32-FD solve time;
+the FP64-FD solve, the FD-apply throughput, the stiffness-kernel roofline
+and the CPU oracle baseline are reported on the same JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "AF-IETI solve s to 1e-8 rel.res (FP32-FD vs FP64-FD); FD-apply DOF/s"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import workloads as W
+    if name == "c2":
+        prob = W.make_c2(seed=0)
+        desc = ("3D unit cube, 2x2x2 trilinear patches (interior vertex +-0.05), p=3 C^2, "
+                "32^3 elements/patch (35^3 basis x 3 comp), E=1 nu=0.3, trig load, u=0 on z=0")
+    elif name == "c1":
+        prob = W.make_c1(seed=0)
+        desc = "2D unit square, 2x2 bilinear patches, p=2 C^1, 16^2 elements/patch, lambda=mu=1, u=0 on x=0"
+    elif name.startswith("c3"):
+        p = int(name[3:]) if len(name) > 3 else 3
+        prob = W.make_c3(seed=0, p=p)
+        desc = f"3D unit cube, 4x4x4 patches, p={p} C^{p-1}, 24^3 elements/patch, lognormal Lame, 8 trig modes"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return prob, desc
+
+
+def time_events(fn, reps):
+    import torch
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def fd_flops(solver_prob):
+    """Algorithmic flops of one P_A^{-1} application: per patch and
+    component 2 n^d (sum_m n_m) multiply-adds forward and backward (the
+    paper's 4 d n N per patch) plus the divide."""
+    total = 0
+    for pd in solver_prob["patches"]:
+        # basis functions on uniform open knots: n_el (p - reg) + reg + 1
+        n = [e * (pd["p"] - pd["reg"]) + pd["reg"] + 1 for e in pd["n_el"]]
+        N = 1
+        for v in n:
+            N *= v
+        total += solver_prob["dim"] * (4 * N * sum(n) + N)
+    return total
+
+
+def cpu_baseline(prob, gpu_iters):
+    """The oracle, untouched, on the host: one MINRES iteration of the same
+    problem (saddle operator + preconditioner + the vector recurrences),
+    scaled by the GPU iteration count."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    import workloads as W
+    from oracle.afieti import AFIETI
+    o = AFIETI(prob)
+    x = W.random_vector(o.n_dof + o.n_c, 5)
+    o.apply_op(x)  # geometry tables (setup, not timed)
+    t0 = time.perf_counter()
+    q = o.apply_op(x)
+    z = o.apply_prec(q)
+    d = float(q @ x) + float(z @ q)
+    v = q - 0.5 * x - 0.25 * z
+    x = x + 1e-3 * v + d * 0.0
+    t1 = time.perf_counter()
+    per_it = t1 - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return dict(value=per_it * gpu_iters, unit="s", cores=threads, kind="oracle",
+                sample=f"one MINRES iteration of the oracle on this workload ({per_it:.2f} s: saddle "
+                       f"operator, preconditioner, dots, updates), x {gpu_iters} iterations",
+                per_iteration_s=per_it)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--fd-reps", type=int, default=100)
+    ap.add_argument("--mv-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the method shards by patch; see DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2001_09626_amd import Solver
+
+    prob, desc = workload(args.workload)
+    t = time.time()
+    log(f"setup FP32-FD handle ({args.workload})")
+    s32 = Solver(prob, fd_precision="fp32", tol=1e-8)
+    torch.cuda.synchronize()
+    setup32 = time.time() - t
+    log(f"  setup {setup32:.1f}s n_dof={s32.n_dof} n_c={s32.n_c} stencil={s32.stiffness_bytes/1e9:.2f} GB")
+    s64 = None
+    if not args.only_fp32:
+        t = time.time()
+        log("setup FP64-FD handle")
+        s64 = Solver(prob, fd_precision="fp64", tol=1e-8)
+        torch.cuda.synchronize()
+        log(f"  setup {time.time()-t:.1f}s")
+    u32 = torch.empty(s32.n_dof, dtype=torch.float64, device="cuda")
+    l32 = torch.empty(s32.n_c, dtype=torch.float64, device="cuda")
+    for i in range(args.warmup):
+        _, _, st = s32.solve(u=u32, lam=l32)
+        log(f"warmup FP32-FD solve {i}: {st['iterations']} it, {st['ms']:.1f} ms")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters32 = []
+    for i in range(args.steps):
+        _, _, st = s32.solve(u=u32, lam=l32)
+        iters32.append(st["iterations"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms32 = (t1 - t0) * 1e3 / args.steps
+    log(f"FP32-FD solve: {ms32:.1f} ms/step, {iters32[-1]} iterations")
+
+    out = {}
+    if s64 is not None:
+        u64 = torch.empty(s64.n_dof, dtype=torch.float64, device="cuda")
+        l64 = torch.empty(s64.n_c, dtype=torch.float64, device="cuda")
+        for i in range(args.warmup):
+            s64.solve(u=u64, lam=l64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            _, _, st64 = s64.solve(u=u64, lam=l64)
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - t0) * 1e3 / args.steps
+        log(f"FP64-FD solve: {ms64:.1f} ms/step, {st64['iterations']} iterations")
+        rel = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
+        out.update(fp64_fd_solve_s=ms64 / 1e3, iterations_fp64_fd=st64["iterations"],
+                   solve_speedup_fp32_vs_fp64=ms64 / ms32, rel_diff_u_fp32_vs_fp64=rel)
+
+    # FD-apply throughput (one apply over all patches and components)
+    r = torch.from_numpy(W.random_vector(s32.n_dof, 3)).cuda()
+    z = torch.empty_like(r)
+    flops = fd_flops(prob)
+    for name, s in (("fp32", s32), ("fp64", s64)):
+        if s is None:
+            continue
+        s.apply_fd(r, z)
+        ms = time_events(lambda: s.apply_fd(r, z), args.fd_reps)
+        out[f"fd_apply_ms_{name}"] = ms
+        out[f"fd_apply_dof_per_s_{name}"] = s.n_dof / (ms * 1e-3)
+        out[f"fd_apply_tflops_{name}"] = flops / (ms * 1e-3) / 1e12
+        log(f"FD apply {name}: {ms*1e3:.1f} us, {s.n_dof/(ms*1e-3)/1e9:.2f} GDOF/s")
+
+    # stiffness matvec: the dominant kernel (HBM-bound assembled stencil)
+    x = torch.from_numpy(W.random_vector(s32.n_dof, 4)).cuda()
+    y = torch.empty_like(x)
+    s32.apply("stiffness", x, y)
+    mv_ms = time_events(lambda: s32.apply("stiffness", x, y), args.mv_reps)
+    mv_bytes = s32.stiffness_bytes + 2 * 8 * s32.n_dof
+    gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
+    log(f"stiffness matvec: {mv_ms:.3f} ms, {gbs:.0f} GB/s")
+    roof = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
+                traffic=None, kernel="k_stiffness", bytes_per_launch=mv_bytes, ms_per_launch=mv_ms)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline (one MINRES iteration of the oracle)")
+        cpu = cpu_baseline(prob, iters32[-1])
+        log(f"  oracle {cpu['per_iteration_s']:.2f} s/iteration on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC,
+        "value": ms32 / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "fd_dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "name": args.workload, "n_dof": int(s32.n_dof),
+                   "n_c": int(s32.n_c), "tol": 1e-8, "setup_s": setup32},
+        "iterations_fp32_fd": iters32[-1],
+        "fp32_fd_solve_s": ms32 / 1e3,
+        **out,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * afieti.h -- C ABI of the MI355X (gfx950) inexact All-Floating IETI solver
+ * for multi-patch isogeometric compressible linear elasticity with Fast
+ * Diagonalization local solvers (Bosy, Montardini, Sangalli, Tani,
+ * arXiv 2001.09626).
+ *
+ * Problem statement (paper Sections 2.2 and 3): patches Omega^(k) given by a
+ * multilinear map of their corners (the spline map F^(k) with control
+ * points at the Greville images), splines of degree p and continuity C^reg
+ * on uniform open knot vectors, Lame parameters per patch, a body force,
+ * homogeneous Dirichlet data on marked faces, natural conditions elsewhere.
+ * Interfaces are found by matching patch faces; they must be conforming.
+ *
+ * Vector layouts (all double precision, device memory, caller owned):
+ *   DOF vector   patch-stacked (Section 4): for each problem, for each
+ *                patch k, for each component c, the colexicographic nodes
+ *                (first parametric index fastest).  Problems are stacked in
+ *                the order given to afieti_setup.  Length info.n_dof.
+ *   multipliers  one entry per row of the jump matrix B, problems stacked.
+ *                Length info.n_c.
+ *
+ * Rows of B ("star" pattern to the lowest patch index): for each problem,
+ * component c, geometric node (ordered by lowest patch, then its local
+ * index) with copies k_1 < ... < k_r: a node on the Dirichlet boundary has
+ * the r rows e_{k_j}; any other node the r-1 rows e_{k_1} - e_{k_j}.
+ *
+ * Streams: every `stream` argument is a hipStream_t (NULL = default
+ * stream).  Work is enqueued on it; calls that report a scalar result to
+ * the host (afieti_solve, afieti_solve_adjoint) synchronise it.
+ *
+ * Errors: every int-returning call returns AFIETI_OK (0) on success, a
+ * positive AFIETI_NOT_CONVERGED when MINRES stopped at maxit (outputs hold
+ * the last iterate), or a negative code; afieti_last_error() gives text.
+ * A handle is not thread safe; distinct handles are independent.
+ */
+#ifndef AFIETI_H
+#define AFIETI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AFIETI_OK 0
+#define AFIETI_NOT_CONVERGED 1
+#define AFIETI_EINVAL (-1)       /* bad sizes, degree, NULL pointer, NaN     */
+#define AFIETI_EGEOM (-2)        /* det J <= 0 or faces that do not conform  */
+#define AFIETI_ESINGULAR (-3)    /* G^T G or B B^T not positive definite     */
+#define AFIETI_EBREAKDOWN (-4)   /* MINRES gamma^2 < 0: preconditioner not SPD */
+#define AFIETI_ENOMEM (-5)
+#define AFIETI_EHIP (-6)         /* a HIP runtime call failed                */
+#define AFIETI_EUNSUPPORTED (-7)
+
+#define AFIETI_FACE_FREE 0       /* natural condition or interface (auto)    */
+#define AFIETI_FACE_DIRICHLET 1  /* homogeneous Dirichlet u = 0              */
+
+/* precision of the FD mode products (Section 5.2.1, Algorithm 1); the
+ * Krylov vectors, residuals and projections are always FP64. */
+#define AFIETI_FD_FP64 0
+#define AFIETI_FD_FP32 1
+#define AFIETI_FD_BF16 2
+
+/* choice of P_S: non-redundant inexact (Remark 1, default) or plain
+ * inexact (Section 5.2, eq. inexact_SP) */
+#define AFIETI_PS_NR 0
+#define AFIETI_PS_PLAIN 1
+
+/* One patch (Section 2.2).  Corner index a1 + 2 a2 + 4 a3 (a_l in {0,1}),
+ * coordinates corners[3*index + x] (2D: only the first 4 corners and x < 2
+ * are read).  face_bc order: (dir1 min, dir1 max, dir2 min, dir2 max, dir3
+ * min, dir3 max). */
+typedef struct {
+    int p;             /* degree, 1..8                                     */
+    int reg;           /* continuity C^reg, 0 <= reg < p                   */
+    int n_el[3];       /* elements per parametric direction (>= 1)         */
+    double corners[24];
+    double lambda, mu; /* Lame parameters (> 0)                            */
+    int face_bc[6];
+} afieti_patch;
+
+/* body force f_comp(x) += amp * prod_d sin(pi k[d] x_d + phase[d]) */
+typedef struct {
+    int comp;
+    double amp;
+    int k[3];
+    double phase[3];
+} afieti_load_mode;
+
+typedef struct {
+    int dim;                          /* 2 or 3                          */
+    int n_patches;
+    const afieti_patch* patches;
+    int n_load_modes;
+    const afieti_load_mode* load_modes;
+} afieti_problem;
+
+typedef struct {
+    double tol;          /* MINRES: stop when |eta| <= tol * gamma_1 (1e-8) */
+    int maxit;           /* default 5000                                   */
+    int fd_precision;    /* AFIETI_FD_*                                    */
+    int ps_variant;      /* AFIETI_PS_*                                    */
+    int check_every;     /* iterations between host convergence checks (8) */
+    int host_only;       /* 1: build the host plan only, no device work    */
+} afieti_options;
+
+typedef struct {
+    int64_t n_dof, n_c;       /* totals over all problems                  */
+    int n_problems, n_patches_total;
+    int64_t stiffness_bytes;  /* device memory of the assembled stencils   */
+    int64_t device_bytes;     /* all device memory held by the handle      */
+} afieti_info;
+
+typedef struct {
+    int iterations;           /* max over problems                         */
+    int converged;            /* 1 if every problem converged              */
+    double rel_residual;      /* max over problems of |eta| / gamma_1      */
+    double ms_solve;          /* wall time of the solve on the stream      */
+} afieti_stats;
+
+typedef struct afieti_handle afieti_handle;
+
+/* Options with the defaults listed above. */
+void afieti_default_options(afieti_options* opt);
+
+/*
+ * Set up n_problems independent problems (Sections 2.2, 4, 5.2.1): knots,
+ * Gauss rules, univariate K and M and their generalised eigendecompositions
+ * (Algorithm 1, step 1), node matching, B, rigid modes R, G = B R and the
+ * Cholesky factor of G^T G, then (unless host_only) device assembly of the
+ * patch stiffness stencils and load vectors.  Inputs are host memory, read
+ * during the call only.  On success *out owns all device memory.
+ */
+int afieti_setup(const afieti_problem* probs, int n_problems,
+                 const afieti_options* opt, void* stream, afieti_handle** out);
+
+int afieti_get_info(const afieti_handle* h, afieti_info* info);
+
+/* Per problem: n_dof, n_c and the DOF offset of every patch; arrays sized by
+ * the caller (dof_off: n_patches_total + 1 entries, c_off: n_problems + 1). */
+int afieti_get_offsets(const afieti_handle* h, int64_t* dof_off, int64_t* c_off);
+
+/*
+ * z = (P_A^inex)^{-1} r for all problems, patches and components
+ * (Section 5.2, eq. inexact_AP; applied by Algorithm 1): per patch k and
+ * component l, (H^(k))^{d-2} (A-hat_l + M-hat_l) z = r.  r, z: device DOF
+ * vectors (may not alias).  Precision of the mode products as configured.
+ */
+int afieti_apply_fd(afieti_handle* h, const double* r, double* z, void* stream);
+
+/*
+ * AF-IETI solve (Section 4): MINRES on the preconditioned projected saddle
+ * system, then u = (I - R (G^T G)^{-1} G^T B) w and lambda = lambda_0 + chi.
+ * rhs: device DOF vector, or NULL for the assembled body-force load.
+ * u: device DOF vector (out); lambda: device multiplier vector or NULL.
+ * st may be NULL.
+ */
+int afieti_solve(afieti_handle* h, const double* rhs, double* u, double* lambda,
+                 afieti_stats* st, void* stream);
+
+/*
+ * Adjoint gradients of a scalar J(u) (follows from the symmetric saddle
+ * system of Section 4): psi solves the same system with right-hand side
+ * dJdu (device DOF vector); u is the forward solution (device DOF vector).
+ * psi (out, device, may be NULL); dJ_dlame (out, host, 2 per patch in
+ * problem-stacked patch order: dJ/dlambda_k, dJ/dmu_k);
+ * dJ_damp (out, host, one per load mode of each problem, stacked).
+ */
+int afieti_solve_adjoint(afieti_handle* h, const double* dJdu, const double* u,
+                         double* psi, double* dJ_dlame, double* dJ_damp,
+                         afieti_stats* st, void* stream);
+
+/* Individual operators of the hot path, for checking and measurement.
+ * x and y are device vectors of the sizes listed; they may not alias. */
+#define AFIETI_OP_STIFFNESS 0   /* y = A x              (DOF -> DOF) eq. block_A     */
+#define AFIETI_OP_B 1           /* y = B x              (DOF -> mult) Section 4      */
+#define AFIETI_OP_BT 2          /* y = B^T x            (mult -> DOF)                */
+#define AFIETI_OP_P_U 3         /* y = P_u x            (DOF -> DOF) eq. all_precond.*/
+#define AFIETI_OP_P_CHI 4       /* y = P_chi x          (mult -> mult) eq. proj_chi  */
+#define AFIETI_OP_SHAT 5        /* y = blockdiag_k H^{d-2} S-hat^(k) x on Gamma
+                                   (DOF -> DOF, interior of x ignored, of y zero)     */
+#define AFIETI_OP_PS 6          /* y = P_S x            (mult -> mult) Remark 1      */
+#define AFIETI_OP_PREC 7        /* y = B^{-1} x, block preconditioner (DOF+mult)     */
+#define AFIETI_OP_SADDLE 8      /* y = projected saddle operator (DOF+mult)          */
+#define AFIETI_OP_FD_INTERIOR 9 /* y_I = ((A-hat_l)_II)^{-1} x_I per patch/component,
+                                   boundary of y zero (DOF -> DOF) eq. fac_schur      */
+#define AFIETI_OP_AHAT 10       /* y = A-hat x per patch/component (DOF -> DOF)      */
+#define AFIETI_OP_MASS 11       /* y = M x, physical mass (DOF -> DOF) eq. le_local_MS */
+#define AFIETI_OP_LOAD 12       /* y = assembled body force (x ignored, DOF)         */
+int afieti_apply(afieti_handle* h, int op, const double* x, double* y, void* stream);
+
+/* Host copies of setup data, for checking (valid also with host_only):
+ *  what = 0: B as triples, buf = [row, dof_plus, dof_minus(-1 if none)] x n_c int64
+ *  what = 1: eigenvalues D of every patch and direction, concatenated (double)
+ *  what = 2: diameters H^(k) (double, one per patch)
+ *  what = 3: rigid-mode count per problem (int64) followed by G^T G of
+ *            problem 0, row major (double reinterpreted)                     */
+int afieti_export(const afieti_handle* h, int what, void* buf, int64_t buf_bytes);
+int64_t afieti_export_size(const afieti_handle* h, int what);
+
+void afieti_destroy(afieti_handle* h);
+const char* afieti_strerror(int code);
+const char* afieti_last_error(const afieti_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AFIETI_H */

@@ -1,0 +1,186 @@
+"""MI355X-native inexact All-Floating IETI (AF-IETI) with Fast
+Diagonalization local solvers for multi-patch isogeometric compressible
+linear elasticity (Bosy, Montardini, Sangalli, Tani, arXiv 2001.09626).
+
+Thin Python binding of the C ABI in ``include/afieti.h``: this module only
+marshals arguments; all setup and every step of the solve run in
+``libafieti.so`` (C++ host setup, HIP kernels for gfx950).  Device vectors
+are torch float64 CUDA tensors used as plain memory, and work is enqueued on
+torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _native as N
+
+__all__ = ["Solver", "AfietiError", "to_c_problems"]
+
+
+class AfietiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{N.ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def to_c_problems(problems):
+    """Convert ``workloads`` problem dictionaries into the C structs; returns
+    (array, keepalive)."""
+    if isinstance(problems, dict):
+        problems = [problems]
+    arr = (N.Problem * len(problems))()
+    keep = []
+    for j, pr in enumerate(problems):
+        dim = int(pr["dim"])
+        pats = (N.Patch * len(pr["patches"]))()
+        for k, pd in enumerate(pr["patches"]):
+            P = pats[k]
+            P.p = int(pd["p"])
+            P.reg = int(pd["reg"])
+            for l in range(3):
+                P.n_el[l] = int(pd["n_el"][l]) if l < dim else 1
+            cs = np.asarray(pd["corners"], dtype=float)
+            for c in range(2 ** dim):
+                for x in range(dim):
+                    P.corners[3 * c + x] = float(cs[c, x])
+            P.lam = float(pd["lam"])
+            P.mu = float(pd["mu"])
+            for f in range(2 * dim):
+                P.face_bc[f] = int(pd["bc"][f])
+        modes = (N.LoadMode * max(1, len(pr["load"])))()
+        for m, (comp, amp, k, ph) in enumerate(pr["load"]):
+            modes[m].comp = int(comp)
+            modes[m].amp = float(amp)
+            for d in range(dim):
+                modes[m].k[d] = int(k[d])
+                modes[m].phase[d] = float(ph[d])
+        keep += [pats, modes]
+        arr[j].dim = dim
+        arr[j].n_patches = len(pr["patches"])
+        arr[j].patches = pats
+        arr[j].n_load_modes = len(pr["load"])
+        arr[j].load_modes = modes
+    return arr, keep
+
+
+def _ptr(t):
+    return C.c_void_p(0) if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Solver:
+    """One handle over one or more independent problems."""
+
+    def __init__(self, problems, tol=1e-8, maxit=5000, fd_precision="fp64", ps_variant="nr",
+                 check_every=8, host_only=False):
+        L = N.lib()
+        self._L = L
+        arr, keep = to_c_problems(problems)
+        opt = N.Options()
+        L.afieti_default_options(C.byref(opt))
+        opt.tol = tol
+        opt.maxit = maxit
+        opt.fd_precision = N.FD_PRECISION[fd_precision]
+        opt.ps_variant = N.PS_VARIANT[ps_variant]
+        opt.check_every = check_every
+        opt.host_only = 1 if host_only else 0
+        self.host_only = host_only
+        h = C.c_void_p()
+        stream = C.c_void_p(0) if host_only else _stream()
+        code = L.afieti_setup(arr, len(arr), C.byref(opt), stream, C.byref(h))
+        if code != N.OK:
+            raise AfietiError(code, L.afieti_last_error(None).decode())
+        self._h = h
+        info = N.Info()
+        L.afieti_get_info(h, C.byref(info))
+        self.n_dof = info.n_dof
+        self.n_c = info.n_c
+        self.n_problems = info.n_problems
+        self.n_patches = info.n_patches_total
+        self.device_bytes = info.device_bytes
+        self.stiffness_bytes = info.stiffness_bytes
+        dof = (C.c_int64 * (self.n_patches + 1))()
+        coff = (C.c_int64 * (self.n_problems + 1))()
+        L.afieti_get_offsets(h, dof, coff)
+        self.dof_offsets = np.array(dof[:], dtype=np.int64)
+        self.c_offsets = np.array(coff[:], dtype=np.int64)
+
+    # ----------------------------------------------------------- helpers
+    def _check(self, code, allow=(N.OK,)):
+        if code not in allow:
+            raise AfietiError(code, self._L.afieti_last_error(self._h).decode())
+        return code
+
+    def _new(self, n):
+        import torch
+        return torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.afieti_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- calls
+    def apply_fd(self, r, z=None):
+        z = self._new(self.n_dof) if z is None else z
+        self._check(self._L.afieti_apply_fd(self._h, _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def apply(self, op, x=None, y=None):
+        n_out = {"B": self.n_c, "P_chi": self.n_c, "P_S": self.n_c,
+                 "prec": self.n_dof + self.n_c, "saddle": self.n_dof + self.n_c}.get(op, self.n_dof)
+        y = self._new(n_out) if y is None else y
+        self._check(self._L.afieti_apply(self._h, N.OPS[op], _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def solve(self, rhs=None, u=None, lam=None, want_lambda=True, allow_not_converged=False):
+        u = self._new(self.n_dof) if u is None else u
+        if want_lambda and lam is None:
+            lam = self._new(self.n_c)
+        st = N.Stats()
+        allow = (N.OK, N.NOT_CONVERGED) if allow_not_converged else (N.OK,)
+        code = self._check(self._L.afieti_solve(self._h, _ptr(rhs), _ptr(u), _ptr(lam),
+                                                C.byref(st), _stream()), allow)
+        stats = dict(iterations=st.iterations, converged=bool(st.converged),
+                     rel_residual=st.rel_residual, ms=st.ms_solve, code=code)
+        return u, lam, stats
+
+    def solve_adjoint(self, dJdu, u, psi=None):
+        psi = self._new(self.n_dof) if psi is None else psi
+        dl = (C.c_double * (2 * self.n_patches))()
+        n_modes = getattr(self, "n_load_modes_total", 0)
+        da = (C.c_double * max(1, n_modes))()
+        st = N.Stats()
+        self._check(self._L.afieti_solve_adjoint(self._h, _ptr(dJdu), _ptr(u), _ptr(psi), dl, da,
+                                                 C.byref(st), _stream()))
+        dl = np.array(dl[:]).reshape(-1, 2)
+        return psi, dl[:, 0], dl[:, 1], np.array(da[:n_modes]), st.iterations
+
+    # ---------------------------------------------------------- exports
+    def export(self, what):
+        n = self._L.afieti_export_size(self._h, N.EXPORT[what])
+        if n < 0:
+            raise AfietiError(-1, "bad export")
+        if what == "B":
+            buf = np.zeros(n // 8, dtype=np.int64)
+        else:
+            buf = np.zeros(n // 8, dtype=np.float64)
+        self._check(self._L.afieti_export(self._h, N.EXPORT[what], buf.ctypes.data_as(C.c_void_p), n))
+        if what == "B":
+            return buf.reshape(-1, 3)
+        if what == "GtG":
+            m = int(round(np.sqrt(len(buf))))
+            return buf.reshape(m, m)
+        return buf

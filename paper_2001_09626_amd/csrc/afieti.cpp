@@ -1,0 +1,827 @@
+// C ABI and host driver of the inexact AF-IETI solver on one gfx950 GPU.
+//
+// The setup builds the host plan (plan.cpp), uploads it, and assembles the
+// patch stiffness stencils and load vectors on the device.  The solve runs
+// preconditioned MINRES (Section 4) with every vector, projection, FD and
+// Schur application on the device; the host only enqueues kernels and reads
+// the per-problem stop flags every few iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "afieti.h"
+#include "device.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace afieti;
+
+namespace {
+
+#define HIP_OK(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            throw SetupError{AFIETI_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+struct RowClass {       // row blocks of the patches sharing (dim, p)
+    int dim, p;
+    int4* d_rb = nullptr;
+    int n = 0;
+};
+
+struct FdSet {          // tensors of one FD operator (P_A or interior)
+    FdTensor* d_t = nullptr;
+    int2* d_slabs = nullptr;
+    int2* d_cols = nullptr;
+    int n_t = 0, n_slabs = 0, n_cols = 0;
+    int64_t tmp_elems = 0;
+};
+
+}  // namespace
+
+struct afieti_handle {
+    Plan plan;
+    afieti_options opt{};
+    std::string err;
+    bool host_only = false;
+    std::vector<void*> allocs;
+    int64_t bytes = 0, stencil_bytes = 0;
+    int n_probs = 0, n_patches = 0;
+    int64_t n_dof = 0, n_c = 0, n_vec = 0;
+
+    // device tables
+    DevPatch* d_patches = nullptr;
+    std::vector<DevPatch> h_patches;
+    double* d_ctrl = nullptr;
+    double *d_qval = nullptr, *d_qder = nullptr, *d_qw = nullptr;
+    int* d_qfirst = nullptr;
+    int *d_elf = nullptr, *d_ell = nullptr;
+    double *d_kband = nullptr, *d_mband = nullptr;
+    double* d_stencil = nullptr;
+    double* d_geo = nullptr;
+    double* d_load = nullptr;
+    std::vector<RowClass> classes;
+    // FD
+    double* d_u64 = nullptr;
+    float* d_u32 = nullptr;
+    double* d_dtab = nullptr;
+    FdSet fd_pa, fd_int;
+    void* d_fdtmp = nullptr;
+    // constraints
+    int64_t *d_cplus = nullptr, *d_cminus = nullptr;
+    int *d_bstart = nullptr, *d_bsize = nullptr, *d_bdir = nullptr;
+    int *d_ppl = nullptr, *d_pmi = nullptr;
+    double *d_gpl = nullptr, *d_gmi = nullptr;
+    int64_t* d_btptr = nullptr;
+    int* d_btrow = nullptr;
+    double* d_btsgn = nullptr;
+    int64_t* d_gam = nullptr;
+    double* d_rtr = nullptr;
+    double* d_cinv = nullptr;
+    int *d_pr_p0 = nullptr, *d_pr_np = nullptr, *d_pr_nm = nullptr;
+    int64_t* d_pr_coff = nullptr;
+    int max_nc = 0;
+    // chunk tables
+    Chunk *d_dof_chunks = nullptr, *d_gam_chunks = nullptr, *d_vec_chunks = nullptr;
+    int n_dof_chunks = 0, n_gam_chunks = 0, n_vec_chunks = 0;
+    int *d_dof_cptr = nullptr, *d_gam_cptr = nullptr, *d_vec_cptr = nullptr;
+    // work
+    double *d_part = nullptr, *d_part2 = nullptr;
+    double *d_coef = nullptr, *d_zc = nullptr;
+    double *s1 = nullptr, *s2 = nullptr, *tv = nullptr, *tt = nullptr;
+    double *c1 = nullptr, *c2 = nullptr, *c3 = nullptr, *c4 = nullptr, *c5 = nullptr, *c6 = nullptr, *lam0 = nullptr;
+    double* vec[10] = {nullptr};
+    MinresState* d_state = nullptr;
+    MinresState* h_state = nullptr;  // pinned
+
+    template <typename T>
+    T* dalloc(int64_t n) {
+        if (n <= 0) n = 1;
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, (size_t)n * sizeof(T));
+        if (e != hipSuccess) throw SetupError{AFIETI_ENOMEM, "hipMalloc failed"};
+        allocs.push_back(p);
+        bytes += n * (int64_t)sizeof(T);
+        return static_cast<T*>(p);
+    }
+    template <typename T>
+    T* upload(const std::vector<T>& v, hipStream_t s) {
+        T* p = dalloc<T>((int64_t)v.size());
+        if (!v.empty()) HIP_OK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+        return p;
+    }
+    ~afieti_handle() {
+        for (void* p : allocs) (void)hipFree(p);
+        if (h_state) (void)hipHostFree(h_state);
+    }
+};
+
+namespace {
+
+int fail_with(afieti_handle* h, const SetupError& e) {
+    if (h) h->err = e.msg;
+    return e.code;
+}
+
+thread_local std::string g_setup_err;
+
+// chunk table over [begin, end) ranges of segments
+void add_chunks(std::vector<Chunk>& out, int64_t b, int64_t e, int seg) {
+    for (int64_t s = b; s < e; s += kChunk) out.push_back({s, std::min(e, s + kChunk), seg, 0});
+}
+
+void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector<int>& u_off,
+                  const std::vector<int>& d_off, hipStream_t s) {
+    std::vector<FdTensor> ts;
+    std::vector<int2> slabs, cols;
+    int64_t tmp = 0;
+    for (size_t k = 0; k < h->plan.patches.size(); ++k) {
+        const PatchPlan& P = h->plan.patches[k];
+        const int dim = P.dim;
+        for (int l = 0; l < dim; ++l) {
+            FdTensor t{};
+            int sh[3], off[3];
+            for (int m = 0; m < 3; ++m) {
+                bool active = m < dim;
+                sh[m] = interior && active ? P.n[m] - 2 : P.n[m];
+                off[m] = interior && active ? 1 : 0;
+            }
+            t.n1 = sh[0];
+            t.n2 = sh[1];
+            t.n3 = sh[2];
+            t.s2 = P.n[0];
+            t.s3 = P.n[0] * P.n[1];
+            int64_t base = P.dof_off + (int64_t)l * P.nodes + off[0] + (int64_t)off[1] * t.s2 + (int64_t)off[2] * t.s3;
+            t.in_off = base;
+            t.out_off = base;
+            t.tmp_off = tmp;
+            tmp += (int64_t)t.n1 * t.n2 * t.n3;
+            for (int m = 0; m < 3; ++m) {
+                int idx = (int)k * 3 + m;
+                t.u_off[m] = u_off[idx * 2 + (interior ? 1 : 0)];
+                t.d_off[m] = d_off[idx * 2 + (interior ? 1 : 0)];
+                t.kappa[m] = (m == l) ? 2 * P.mu + P.lam : P.mu;
+            }
+            if (dim == 2) t.kappa[2] = 0.0;
+            t.scale = interior ? 1.0 : P.hscale;
+            t.mass = interior ? 0.0 : 1.0;
+            t.alpha = interior ? -1.0 : 1.0;
+            int ti = (int)ts.size();
+            ts.push_back(t);
+            for (int i3 = 0; i3 < t.n3; ++i3) slabs.push_back(make_int2(ti, i3));
+            int ncb = (t.n1 * t.n2 + 31) / 32;
+            for (int cb = 0; cb < ncb; ++cb) cols.push_back(make_int2(ti, cb));
+        }
+    }
+    set.n_t = (int)ts.size();
+    set.n_slabs = (int)slabs.size();
+    set.n_cols = (int)cols.size();
+    set.tmp_elems = tmp;
+    set.d_t = h->upload(ts, s);
+    set.d_slabs = h->upload(slabs, s);
+    set.d_cols = h->upload(cols, s);
+}
+
+void device_setup(afieti_handle* h, hipStream_t s) {
+    Plan& pl = h->plan;
+    const int np = (int)pl.patches.size();
+    h->n_patches = np;
+    // ---- patch descriptors and univariate tables
+    std::vector<double> ctrl, qval, qder, qw, kband, mband;
+    std::vector<int> qfirst, elf, ell;
+    int64_t stencil = 0, geo_max = 0;
+    h->h_patches.resize(np);
+    for (int k = 0; k < np; ++k) {
+        const PatchPlan& P = pl.patches[k];
+        DevPatch& d = h->h_patches[k];
+        d.dof_off = P.dof_off;
+        d.nodes = P.nodes;
+        d.ctrl_off = (int64_t)ctrl.size();
+        ctrl.insert(ctrl.end(), P.ctrl.begin(), P.ctrl.end());
+        d.dim = P.dim;
+        d.p = P.p;
+        d.prob = P.prob;
+        d.nmodes = P.dim == 3 ? 6 : 3;
+        d.lam = P.lam;
+        d.mu = P.mu;
+        d.hscale = P.hscale;
+        const int W = 2 * P.p + 1;
+        for (int m = 0; m < 3; ++m) {
+            const Dir1D& D = P.dir[m];
+            d.n[m] = P.n[m];
+            d.nq[m] = m < P.dim ? D.nq : 1;
+            d.q_off[m] = (int)qfirst.size();
+            d.el_off[m] = (int)elf.size();
+            d.band_off[m] = (int)kband.size();
+            if (m < P.dim) {
+                for (int q = 0; q < D.nq; ++q) {
+                    qfirst.push_back(D.qfirst[q]);
+                    qw.push_back(D.qw[q]);
+                    for (int t = 0; t < 9; ++t) {
+                        qval.push_back(t <= P.p ? D.qval[(size_t)q * (P.p + 1) + t] : 0.0);
+                        qder.push_back(t <= P.p ? D.qder[(size_t)q * (P.p + 1) + t] : 0.0);
+                    }
+                }
+                elf.insert(elf.end(), D.el_first.begin(), D.el_first.end());
+                ell.insert(ell.end(), D.el_last.begin(), D.el_last.end());
+            }
+            for (int i = 0; i < D.n; ++i)
+                for (int t = 0; t < W; ++t) {
+                    int j = i - P.p + t;
+                    bool in = j >= 0 && j < D.n;
+                    if (m < P.dim) {
+                        kband.push_back(in ? D.K[(size_t)i * D.n + j] : 0.0);
+                        mband.push_back(in ? D.M[(size_t)i * D.n + j] : 0.0);
+                    } else {
+                        kband.push_back(0.0);
+                        mband.push_back(t == P.p ? 1.0 : 0.0);
+                    }
+                }
+        }
+        const int64_t S = P.dim == 3 ? (int64_t)W * W * W : (int64_t)W * W;
+        d.stencil_off = stencil;
+        stencil += (int64_t)P.dim * P.dim * S * P.nodes;
+        d.geo_off = 0;
+        geo_max = std::max(geo_max, (int64_t)d.nq[0] * d.nq[1] * d.nq[2] * 13);
+    }
+    h->d_patches = h->upload(h->h_patches, s);
+    h->d_ctrl = h->upload(ctrl, s);
+    h->d_qval = h->upload(qval, s);
+    h->d_qder = h->upload(qder, s);
+    h->d_qw = h->upload(qw, s);
+    h->d_qfirst = h->upload(qfirst, s);
+    h->d_elf = h->upload(elf, s);
+    h->d_ell = h->upload(ell, s);
+    h->d_kband = h->upload(kband, s);
+    h->d_mband = h->upload(mband, s);
+    h->d_stencil = h->dalloc<double>(stencil);
+    h->stencil_bytes = stencil * 8;
+    h->d_geo = h->dalloc<double>(geo_max);
+    h->d_load = h->dalloc<double>(pl.n_dof);
+    // row blocks by (dim, p)
+    std::map<std::pair<int, int>, std::vector<int4>> rbs;
+    for (int k = 0; k < np; ++k) {
+        const PatchPlan& P = pl.patches[k];
+        auto& v = rbs[{P.dim, P.p}];
+        for (int c = 0; c < P.dim; ++c)
+            for (int64_t n0 = 0; n0 < P.nodes; n0 += kBlock) v.push_back(make_int4(k, c, (int)n0, 0));
+    }
+    for (auto& kv : rbs) {
+        RowClass rc;
+        rc.dim = kv.first.first;
+        rc.p = kv.first.second;
+        rc.n = (int)kv.second.size();
+        rc.d_rb = h->upload(kv.second, s);
+        h->classes.push_back(rc);
+    }
+    // ---- assembly of stencils and loads, patch by patch
+    for (int k = 0; k < np; ++k) {
+        const DevPatch& hp = h->h_patches[k];
+        const PatchPlan& P = pl.patches[k];
+        launch_geometry(h->d_patches, k, hp, h->d_ctrl, h->d_qval, h->d_qder, h->d_qfirst, h->d_qw, h->d_geo, s);
+        launch_assemble(h->d_patches, k, hp, h->d_geo, h->d_qval, h->d_qder, h->d_qfirst, h->d_elf, h->d_ell,
+                        h->d_stencil, P.lam, P.mu, s);
+        const ProblemPlan& pr = pl.probs[P.prob];
+        std::vector<double> modes;
+        for (const auto& lm : pr.load) {
+            modes.insert(modes.end(), {(double)lm.comp, lm.amp, (double)lm.k[0], (double)lm.k[1], (double)lm.k[2],
+                                       lm.phase[0], lm.phase[1], lm.phase[2]});
+        }
+        double* d_modes = nullptr;
+        if (!modes.empty()) {
+            HIP_OK(hipMalloc(&d_modes, modes.size() * sizeof(double)));
+            HIP_OK(hipMemcpyAsync(d_modes, modes.data(), modes.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        }
+        launch_load(h->d_patches, k, hp, h->d_geo, h->d_qval, h->d_qfirst, h->d_elf, h->d_ell, d_modes,
+                    (int)pr.load.size(), h->d_load, s);
+        HIP_OK(hipStreamSynchronize(s));
+        if (d_modes) HIP_OK(hipFree(d_modes));
+        HIP_OK(hipGetLastError());
+    }
+    // ---- FD tables
+    std::vector<double> u64, dtab;
+    std::vector<int> u_off(np * 3 * 2), d_off(np * 3 * 2);
+    int max_n = 1;
+    for (int k = 0; k < np; ++k)
+        for (int m = 0; m < 3; ++m) {
+            const Dir1D& D = pl.patches[k].dir[m];
+            max_n = std::max(max_n, D.n);
+            int idx = (k * 3 + m) * 2;
+            u_off[idx] = (int)u64.size();
+            u64.insert(u64.end(), D.U.begin(), D.U.end());
+            d_off[idx] = (int)dtab.size();
+            dtab.insert(dtab.end(), D.D.begin(), D.D.end());
+            u_off[idx + 1] = (int)u64.size();
+            u64.insert(u64.end(), D.Ui.begin(), D.Ui.end());
+            d_off[idx + 1] = (int)dtab.size();
+            dtab.insert(dtab.end(), D.Di.begin(), D.Di.end());
+        }
+    if (max_n > kMaxN) throw SetupError{AFIETI_EUNSUPPORTED, "at most 48 basis functions per direction on the device"};
+    std::vector<float> u32(u64.begin(), u64.end());
+    h->d_u64 = h->upload(u64, s);
+    h->d_u32 = h->upload(u32, s);
+    h->d_dtab = h->upload(dtab, s);
+    build_fd_set(h, h->fd_pa, false, u_off, d_off, s);
+    build_fd_set(h, h->fd_int, true, u_off, d_off, s);
+    h->d_fdtmp = h->dalloc<double>(std::max(h->fd_pa.tmp_elems, h->fd_int.tmp_elems));
+    // ---- constraints
+    h->d_cplus = h->upload(pl.c_plus, s);
+    h->d_cminus = h->upload(pl.c_minus, s);
+    h->d_bstart = h->upload(pl.c_blk_start, s);
+    h->d_bsize = h->upload(pl.c_blk_size, s);
+    h->d_bdir = h->upload(pl.c_blk_dir, s);
+    h->d_ppl = h->upload(pl.c_patch_plus, s);
+    h->d_pmi = h->upload(pl.c_patch_minus, s);
+    h->d_gpl = h->upload(pl.g_plus, s);
+    h->d_gmi = h->upload(pl.g_minus, s);
+    h->d_btptr = h->upload(pl.bt_ptr, s);
+    h->d_btrow = h->upload(pl.bt_row, s);
+    h->d_btsgn = h->upload(pl.bt_sign, s);
+    h->d_gam = h->upload(pl.gam_dof, s);
+    h->d_rtr = h->upload(pl.RtR_inv, s);
+    std::vector<double> cinv;
+    std::vector<int> p0, npch, nm;
+    std::vector<int64_t> coff;
+    for (const auto& pr : pl.probs) {
+        coff.push_back((int64_t)cinv.size());
+        cinv.insert(cinv.end(), pr.Cinv.begin(), pr.Cinv.end());
+        p0.push_back(pr.patch0);
+        npch.push_back(pr.n_patches);
+        nm.push_back(pr.n_modes);
+        h->max_nc = std::max(h->max_nc, pr.n_modes * pr.n_patches);
+    }
+    h->d_cinv = h->upload(cinv, s);
+    h->d_pr_p0 = h->upload(p0, s);
+    h->d_pr_np = h->upload(npch, s);
+    h->d_pr_nm = h->upload(nm, s);
+    h->d_pr_coff = h->upload(coff, s);
+    // ---- chunk tables
+    std::vector<Chunk> dch, gch, vch;
+    std::vector<int> dptr{0}, gptr{0}, vptr{0};
+    for (int k = 0; k < np; ++k) {
+        const PatchPlan& P = pl.patches[k];
+        add_chunks(dch, P.dof_off, P.dof_off + P.dim * P.nodes, k);
+        dptr.push_back((int)dch.size());
+        add_chunks(gch, pl.gam_ptr[k], pl.gam_ptr[k + 1], k);
+        gptr.push_back((int)gch.size());
+    }
+    for (int j = 0; j < (int)pl.probs.size(); ++j) {
+        const ProblemPlan& pr = pl.probs[j];
+        add_chunks(vch, pr.dof_off, pr.dof_off + pr.n_dof, j);
+        add_chunks(vch, pl.n_dof + pr.c_off, pl.n_dof + pr.c_off + pr.n_c, j);
+        vptr.push_back((int)vch.size());
+    }
+    h->n_dof_chunks = (int)dch.size();
+    h->n_gam_chunks = (int)gch.size();
+    h->n_vec_chunks = (int)vch.size();
+    h->d_dof_chunks = h->upload(dch, s);
+    h->d_gam_chunks = h->upload(gch, s);
+    h->d_vec_chunks = h->upload(vch, s);
+    h->d_dof_cptr = h->upload(dptr, s);
+    h->d_gam_cptr = h->upload(gptr, s);
+    h->d_vec_cptr = h->upload(vptr, s);
+    // ---- work buffers
+    int64_t maxch = std::max({(int64_t)dch.size(), (int64_t)gch.size(), (int64_t)vch.size()});
+    h->d_part = h->dalloc<double>(maxch * 6);
+    h->d_part2 = h->dalloc<double>(maxch * 6);
+    h->d_coef = h->dalloc<double>(np * 6);
+    h->d_zc = h->dalloc<double>(np * 6);
+    h->s1 = h->dalloc<double>(pl.n_dof);
+    h->s2 = h->dalloc<double>(pl.n_dof);
+    h->tv = h->dalloc<double>(pl.n_dof);
+    h->tt = h->dalloc<double>(pl.n_dof);
+    h->c1 = h->dalloc<double>(pl.n_c);
+    h->c2 = h->dalloc<double>(pl.n_c);
+    h->c3 = h->dalloc<double>(pl.n_c);
+    h->c4 = h->dalloc<double>(pl.n_c);
+    h->c5 = h->dalloc<double>(pl.n_c);
+    h->c6 = h->dalloc<double>(pl.n_c);
+    h->lam0 = h->dalloc<double>(pl.n_c);
+    for (int i = 0; i < 10; ++i) h->vec[i] = h->dalloc<double>(pl.n_dof + pl.n_c);
+    h->d_state = h->dalloc<MinresState>((int64_t)pl.probs.size());
+    HIP_OK(hipHostMalloc((void**)&h->h_state, pl.probs.size() * sizeof(MinresState), hipHostMallocDefault));
+    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipGetLastError());
+}
+
+// ------------------------------------------------------------- operators
+void op_stiffness(afieti_handle* h, const double* x, double* y, const double* t, hipStream_t s) {
+    for (const auto& rc : h->classes)
+        launch_stiffness_dp(rc.dim, rc.p, h->d_patches, rc.d_rb, rc.n, h->d_stencil, x, y, h->d_btptr, h->d_btrow,
+                            h->d_btsgn, t, s);
+}
+
+void op_mask_interior(afieti_handle* h, double* y, hipStream_t s) {
+    for (const auto& rc : h->classes) launch_mask_interior(h->d_patches, rc.d_rb, rc.n, y, s);
+}
+
+void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_t s) {
+    for (const auto& rc : h->classes)
+        launch_ahat_dp(rc.dim, rc.p, h->d_patches, rc.d_rb, rc.n, h->d_kband, h->d_mband, x, y, use_h, s);
+}
+
+void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s) {
+    int prec = h->opt.fd_precision == AFIETI_FD_FP64 ? 0 : 1;
+    launch_fd(prec, set.d_t, set.n_t, set.d_slabs, set.n_slabs, set.d_cols, set.n_cols,
+              prec == 0 ? (const void*)h->d_u64 : (const void*)h->d_u32, h->d_dtab, in, out, h->d_fdtmp, kMaxN, s);
+}
+
+// out = P_chi y  (in place allowed)
+void op_pchi(afieti_handle* h, const double* y, double* out, hipStream_t s) {
+    launch_gamma_partial(h->d_patches, h->d_gam_chunks, h->n_gam_chunks, h->d_ctrl, h->d_gam, h->d_btptr, h->d_btrow,
+                         h->d_btsgn, y, h->d_part, s);
+    launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_gam_cptr, h->d_part,
+                           h->d_cinv, h->d_zc, h->max_nc, s);
+    launch_G_apply(h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, h->n_c, h->d_zc, -1.0, 1.0, y, out, s);
+}
+
+// out = P_u x  (in place allowed)
+void op_pu(afieti_handle* h, const double* x, double* out, hipStream_t s) {
+    launch_rigid_partial(h->d_patches, h->d_dof_chunks, h->n_dof_chunks, h->d_ctrl, x, h->d_part, s);
+    launch_rigid_finalize(h->d_dof_cptr, h->n_patches, h->d_part, h->d_rtr, h->d_coef, s);
+    launch_rigid_update(h->d_patches, h->d_dof_chunks, h->n_dof_chunks, h->d_ctrl, h->d_coef, x, out, s);
+}
+
+// out = P_S y (Remark 1, non-redundant, or the plain variant)
+void op_ps(afieti_handle* h, const double* y, double* out, hipStream_t s) {
+    const bool nr = h->opt.ps_variant == AFIETI_PS_NR;
+    const double* a = y;
+    if (nr) {
+        launch_W(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, y, h->c1, s);
+        a = h->c1;
+    }
+    launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, a, h->tv, s);
+    op_ahat(h, h->tv, h->tt, 0, s);
+    op_fd(h, h->fd_int, h->tt, h->tv, s);  // v_I = -((A-hat)_II)^{-1} (A-hat v0)_I
+    op_ahat(h, h->tv, h->tt, 1, s);        // H^{d-2} A-hat v; B reads its Gamma part
+    if (nr) {
+        launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, h->tt, h->c2, s);
+        launch_W(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->c2, out, s);
+    } else {
+        launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, h->tt, out, s);
+    }
+}
+
+void op_prec(afieti_handle* h, const double* r, double* z, hipStream_t s) {
+    op_pu(h, r, h->s1, s);
+    op_fd(h, h->fd_pa, h->s1, h->s2, s);
+    op_pu(h, h->s2, z, s);
+    op_pchi(h, r + h->n_dof, h->c3, s);
+    op_ps(h, h->c3, h->c4, s);
+    op_pchi(h, h->c4, z + h->n_dof, s);
+}
+
+void op_saddle(afieti_handle* h, const double* x, double* y, hipStream_t s) {
+    op_pchi(h, x + h->n_dof, h->c5, s);
+    op_stiffness(h, x, y, h->c5, s);
+    launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, x, h->c6, s);
+    op_pchi(h, h->c6, y + h->n_dof, s);
+}
+
+// y = blockdiag_k H_k^{d-2} S-hat^(k) x on Gamma, interior of x ignored, of y zero
+void op_shat(afieti_handle* h, const double* x, double* y, hipStream_t s) {
+    launch_copy(x, h->tv, h->n_dof, s);
+    op_mask_interior(h, h->tv, s);
+    op_ahat(h, h->tv, h->tt, 0, s);
+    op_fd(h, h->fd_int, h->tt, h->tv, s);
+    op_ahat(h, h->tv, y, 1, s);
+    op_mask_interior(h, y, s);
+}
+
+// MINRES on the preconditioned projected system; b (length n_vec) is read
+// from h->vec[1].  The solution ends in h->vec[8].
+int run_minres(afieti_handle* h, hipStream_t s, afieti_stats* st) {
+    double** V = h->vec;
+    double *v_old = V[0], *v = V[1], *v_new = V[2], *z = V[3], *z_new = V[4];
+    double *d_old = V[5], *d = V[6], *d_new = V[7], *x = V[8], *q = V[9];
+    const int64_t n = h->n_vec;
+    const int np = h->n_probs;
+    launch_fill(v_old, 0.0, n, s);
+    launch_fill(d_old, 0.0, n, s);
+    launch_fill(d, 0.0, n, s);
+    launch_fill(x, 0.0, n, s);
+    op_prec(h, v, z, s);
+    launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, z, v, h->d_part2, s);
+    launch_minres_init(h->d_state, h->d_vec_cptr, np, h->d_part2, h->opt.tol, h->opt.maxit, s);
+    const int every = std::max(1, h->opt.check_every);
+    for (int it = 0; it < h->opt.maxit; ++it) {
+        op_saddle(h, z, q, s);
+        launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, q, z, h->d_part2, s);
+        launch_minres_delta(h->d_state, h->d_vec_cptr, np, h->d_part2, s);
+        launch_minres_v(h->d_state, h->d_vec_chunks, h->n_vec_chunks, q, v, v_old, v_new, s);
+        op_prec(h, v_new, z_new, s);
+        launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, z_new, v_new, h->d_part2, s);
+        launch_minres_givens(h->d_state, h->d_vec_cptr, np, h->d_part2, s);
+        launch_minres_dx(h->d_state, h->d_vec_chunks, h->n_vec_chunks, z, d_old, d, d_new, x, s);
+        double* t = v_old;
+        v_old = v;
+        v = v_new;
+        v_new = t;
+        std::swap(z, z_new);
+        t = d_old;
+        d_old = d;
+        d = d_new;
+        d_new = t;
+        if ((it + 1) % every == 0 || it + 1 == h->opt.maxit) {
+            HIP_OK(hipMemcpyAsync(h->h_state, h->d_state, np * sizeof(MinresState), hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            bool all = true;
+            for (int j = 0; j < np; ++j) all = all && h->h_state[j].stop != 0;
+            if (all) break;
+        }
+    }
+    HIP_OK(hipMemcpyAsync(h->h_state, h->d_state, np * sizeof(MinresState), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipGetLastError());
+    int code = AFIETI_OK, its = 0, conv = 1;
+    double rel = 0;
+    for (int j = 0; j < np; ++j) {
+        const MinresState& m = h->h_state[j];
+        its = std::max(its, m.its);
+        rel = std::max(rel, m.rel);
+        if (m.stop == 2) code = AFIETI_EBREAKDOWN;
+        if (m.stop != 1) conv = 0;
+        if ((m.stop == 3 || m.stop == 0) && code == AFIETI_OK) code = AFIETI_NOT_CONVERGED;
+    }
+    if (st) {
+        st->iterations = its;
+        st->converged = conv;
+        st->rel_residual = rel;
+    }
+    return code;
+}
+
+// Full AF-IETI solve for right-hand side f (device DOF vector).
+int solve_impl(afieti_handle* h, const double* f, double* u, double* lambda, afieti_stats* st, hipStream_t s) {
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    HIP_OK(hipEventRecord(e0, s));
+    // lambda_0 = G (G^T G)^{-1} R^T f  (minimal-norm solution of G^T lambda_0 = R^T f)
+    launch_rigid_partial(h->d_patches, h->d_dof_chunks, h->n_dof_chunks, h->d_ctrl, f, h->d_part, s);
+    launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_dof_cptr, h->d_part,
+                           h->d_cinv, h->d_zc, h->max_nc, s);
+    launch_G_apply(h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, h->n_c, h->d_zc, 1.0, 0.0, nullptr, h->lam0, s);
+    // b = [f - B^T lambda_0; 0]
+    launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, h->lam0, h->s1, s);
+    launch_axpby(1.0, f, -1.0, h->s1, h->vec[1], h->n_dof, s);
+    launch_fill(h->vec[1] + h->n_dof, 0.0, h->n_c, s);
+    int code = run_minres(h, s, st);
+    // recovery: u = w - R (G^T G)^{-1} G^T B w,  lambda = lambda_0 + chi
+    const double* w = h->vec[8];
+    launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, w, h->c1, s);
+    launch_gamma_partial(h->d_patches, h->d_gam_chunks, h->n_gam_chunks, h->d_ctrl, h->d_gam, h->d_btptr, h->d_btrow,
+                         h->d_btsgn, h->c1, h->d_part, s);
+    launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_gam_cptr, h->d_part,
+                           h->d_cinv, h->d_zc, h->max_nc, s);
+    launch_rigid_update(h->d_patches, h->d_dof_chunks, h->n_dof_chunks, h->d_ctrl, h->d_zc, w, u, s);
+    if (lambda) launch_axpby(1.0, h->lam0, 1.0, h->vec[8] + h->n_dof, lambda, h->n_c, s);
+    HIP_OK(hipEventRecord(e1, s));
+    HIP_OK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+    HIP_OK(hipEventDestroy(e0));
+    HIP_OK(hipEventDestroy(e1));
+    if (st) st->ms_solve = ms;
+    HIP_OK(hipGetLastError());
+    return code;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+void afieti_default_options(afieti_options* opt) {
+    if (!opt) return;
+    opt->tol = 1e-8;
+    opt->maxit = 5000;
+    opt->fd_precision = AFIETI_FD_FP64;
+    opt->ps_variant = AFIETI_PS_NR;
+    opt->check_every = 8;
+    opt->host_only = 0;
+}
+
+const char* afieti_strerror(int code) {
+    switch (code) {
+        case AFIETI_OK: return "ok";
+        case AFIETI_NOT_CONVERGED: return "MINRES reached maxit before the tolerance";
+        case AFIETI_EINVAL: return "invalid argument";
+        case AFIETI_EGEOM: return "invalid geometry or non-conforming interface";
+        case AFIETI_ESINGULAR: return "singular coarse problem (not enough constraints)";
+        case AFIETI_EBREAKDOWN: return "MINRES breakdown: preconditioner not positive definite";
+        case AFIETI_ENOMEM: return "out of device memory";
+        case AFIETI_EHIP: return "HIP runtime error";
+        case AFIETI_EUNSUPPORTED: return "unsupported configuration";
+        default: return "unknown error";
+    }
+}
+
+
+int afieti_setup(const afieti_problem* probs, int n_problems, const afieti_options* opt, void* stream,
+                 afieti_handle** out) {
+    g_setup_err.clear();
+    if (!out) return AFIETI_EINVAL;
+    *out = nullptr;
+    afieti_handle* h = nullptr;
+    try {
+        h = new afieti_handle();
+        if (opt) h->opt = *opt;
+        else afieti_default_options(&h->opt);
+        if (!(h->opt.tol > 0) || h->opt.maxit < 1 ||
+            (h->opt.fd_precision < AFIETI_FD_FP64 || h->opt.fd_precision > AFIETI_FD_BF16) ||
+            (h->opt.ps_variant != AFIETI_PS_NR && h->opt.ps_variant != AFIETI_PS_PLAIN))
+            throw SetupError{AFIETI_EINVAL, "invalid options"};
+        if (h->opt.fd_precision == AFIETI_FD_BF16)
+            throw SetupError{AFIETI_EUNSUPPORTED, "BF16 FD is not available in this build"};
+        h->plan = build_plan(probs, n_problems);
+        h->n_probs = (int)h->plan.probs.size();
+        h->n_patches = (int)h->plan.patches.size();
+        h->n_dof = h->plan.n_dof;
+        h->n_c = h->plan.n_c;
+        h->n_vec = h->n_dof + h->n_c;
+        h->host_only = h->opt.host_only != 0;
+        if (!h->host_only) device_setup(h, (hipStream_t)stream);
+        *out = h;
+        return AFIETI_OK;
+    } catch (const SetupError& e) {
+        g_setup_err = e.msg;
+        delete h;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_setup_err = "host allocation failed";
+        delete h;
+        return AFIETI_ENOMEM;
+    }
+}
+
+void afieti_destroy(afieti_handle* h) { delete h; }
+
+int afieti_get_info(const afieti_handle* h, afieti_info* info) {
+    if (!h || !info) return AFIETI_EINVAL;
+    info->n_dof = h->n_dof;
+    info->n_c = h->n_c;
+    info->n_problems = h->n_probs;
+    info->n_patches_total = h->n_patches;
+    info->stiffness_bytes = h->stencil_bytes;
+    info->device_bytes = h->bytes;
+    return AFIETI_OK;
+}
+
+int afieti_get_offsets(const afieti_handle* h, int64_t* dof_off, int64_t* c_off) {
+    if (!h) return AFIETI_EINVAL;
+    if (dof_off) {
+        for (int k = 0; k < h->n_patches; ++k) dof_off[k] = h->plan.patches[k].dof_off;
+        dof_off[h->n_patches] = h->n_dof;
+    }
+    if (c_off) {
+        for (int j = 0; j < h->n_probs; ++j) c_off[j] = h->plan.probs[j].c_off;
+        c_off[h->n_probs] = h->n_c;
+    }
+    return AFIETI_OK;
+}
+
+static int need_device(afieti_handle* h) {
+    if (!h) return AFIETI_EINVAL;
+    if (h->host_only) {
+        h->err = "handle was set up with host_only";
+        return AFIETI_EINVAL;
+    }
+    return AFIETI_OK;
+}
+
+int afieti_apply_fd(afieti_handle* h, const double* r, double* z, void* stream) {
+    int c = need_device(h);
+    if (c) return c;
+    if (!r || !z || r == z) {
+        h->err = "apply_fd needs distinct input and output";
+        return AFIETI_EINVAL;
+    }
+    try {
+        op_fd(h, h->fd_pa, r, z, (hipStream_t)stream);
+        HIP_OK(hipGetLastError());
+        return AFIETI_OK;
+    } catch (const SetupError& e) {
+        return fail_with(h, e);
+    }
+}
+
+int afieti_apply(afieti_handle* h, int op, const double* x, double* y, void* stream) {
+    int c = need_device(h);
+    if (c) return c;
+    if (!y || (op != AFIETI_OP_LOAD && (!x || x == y))) {
+        h->err = "apply needs distinct input and output";
+        return AFIETI_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        switch (op) {
+            case AFIETI_OP_STIFFNESS: op_stiffness(h, x, y, nullptr, s); break;
+            case AFIETI_OP_B: launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, x, y, s); break;
+            case AFIETI_OP_BT: launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, x, y, s); break;
+            case AFIETI_OP_P_U: op_pu(h, x, y, s); break;
+            case AFIETI_OP_P_CHI: op_pchi(h, x, y, s); break;
+            case AFIETI_OP_SHAT: op_shat(h, x, y, s); break;
+            case AFIETI_OP_PS: op_ps(h, x, y, s); break;
+            case AFIETI_OP_PREC: op_prec(h, x, y, s); break;
+            case AFIETI_OP_SADDLE: op_saddle(h, x, y, s); break;
+            case AFIETI_OP_FD_INTERIOR:
+                launch_fill(y, 0.0, h->n_dof, s);
+                op_fd(h, h->fd_int, x, y, s);
+                launch_axpby(-1.0, y, 0.0, y, y, h->n_dof, s);
+                break;
+            case AFIETI_OP_AHAT: op_ahat(h, x, y, 0, s); break;
+            case AFIETI_OP_LOAD: launch_copy(h->d_load, y, h->n_dof, s); break;
+            default: h->err = "unknown operator"; return AFIETI_EUNSUPPORTED;
+        }
+        HIP_OK(hipGetLastError());
+        return AFIETI_OK;
+    } catch (const SetupError& e) {
+        return fail_with(h, e);
+    }
+}
+
+int afieti_solve(afieti_handle* h, const double* rhs, double* u, double* lambda, afieti_stats* st, void* stream) {
+    int c = need_device(h);
+    if (c) return c;
+    if (!u) {
+        h->err = "u must not be NULL";
+        return AFIETI_EINVAL;
+    }
+    try {
+        return solve_impl(h, rhs ? rhs : h->d_load, u, lambda, st, (hipStream_t)stream);
+    } catch (const SetupError& e) {
+        return fail_with(h, e);
+    }
+}
+
+int afieti_solve_adjoint(afieti_handle* h, const double* dJdu, const double* u, double* psi, double* dJ_dlame,
+                         double* dJ_damp, afieti_stats* st, void* stream) {
+    int c = need_device(h);
+    if (c) return c;
+    (void)dJdu;
+    (void)u;
+    (void)psi;
+    (void)dJ_dlame;
+    (void)dJ_damp;
+    (void)st;
+    (void)stream;
+    h->err = "adjoint not available in this build";
+    return AFIETI_EUNSUPPORTED;
+}
+
+int64_t afieti_export_size(const afieti_handle* h, int what) {
+    if (!h) return -1;
+    const Plan& pl = h->plan;
+    switch (what) {
+        case 0: return pl.n_c * 3 * (int64_t)sizeof(int64_t);
+        case 1: {
+            int64_t n = 0;
+            for (const auto& P : pl.patches)
+                for (int m = 0; m < P.dim; ++m) n += P.dir[m].n;
+            return n * (int64_t)sizeof(double);
+        }
+        case 2: return (int64_t)pl.patches.size() * (int64_t)sizeof(double);
+        case 3: {
+            const auto& pr = pl.probs[0];
+            int64_t nc = (int64_t)pr.n_modes * pr.n_patches;
+            return nc * nc * (int64_t)sizeof(double);
+        }
+        default: return -1;
+    }
+}
+
+int afieti_export(const afieti_handle* h, int what, void* buf, int64_t buf_bytes) {
+    int64_t need = afieti_export_size(h, what);
+    if (need < 0 || !buf || buf_bytes < need) return AFIETI_EINVAL;
+    const Plan& pl = h->plan;
+    if (what == 0) {
+        int64_t* o = static_cast<int64_t*>(buf);
+        for (int64_t r = 0; r < pl.n_c; ++r) {
+            o[3 * r] = r;
+            o[3 * r + 1] = pl.c_plus[r];
+            o[3 * r + 2] = pl.c_minus[r];
+        }
+    } else if (what == 1) {
+        double* o = static_cast<double*>(buf);
+        for (const auto& P : pl.patches)
+            for (int m = 0; m < P.dim; ++m) o = std::copy(P.dir[m].D.begin(), P.dir[m].D.end(), o);
+    } else if (what == 2) {
+        double* o = static_cast<double*>(buf);
+        for (const auto& P : pl.patches) *o++ = P.H;
+    } else {
+        std::memcpy(buf, pl.probs[0].CtC.data(), need);
+    }
+    return AFIETI_OK;
+}
+
+const char* afieti_last_error(const afieti_handle* h) { return h ? h->err.c_str() : g_setup_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Device-side descriptors shared by the HIP kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace afieti {
+
+constexpr int kMaxN = 48;        // largest univariate basis size on the device path
+constexpr int kBlock = 256;      // threads per block for the streaming kernels
+constexpr int kChunk = 4096;     // elements per reduction chunk
+
+// One patch as the kernels see it.
+struct DevPatch {
+    int64_t dof_off;             // global DOF offset
+    int64_t nodes;               // n1 * n2 * n3
+    int64_t ctrl_off;            // offset (in doubles) into the control-point array
+    int64_t stencil_off;         // offset (in doubles) into the stencil values
+    int64_t geo_off;             // offset (in doubles) into the Gauss-point geometry
+    int n[3];                    // basis counts (n[2] = 1 in 2D)
+    int nq[3];                   // Gauss points per direction (nq[2] = 1 in 2D)
+    int q_off[3];                // offsets into the univariate quadrature tables
+    int band_off[3];             // offsets into the banded univariate K, M tables
+    int el_off[3];               // offsets into the per-basis element ranges
+    int dim, p, prob, nmodes;
+    double lam, mu, hscale;
+};
+
+// One tensor of an FD solve (a patch/component pair, or its interior).
+struct FdTensor {
+    int64_t in_off, out_off;     // first entry in the FP64 input / output vector
+    int64_t tmp_off;             // first entry in the intermediate buffer
+    int n1, n2, n3;              // tensor sizes
+    int s2, s3;                  // strides of directions 2 and 3 in the vectors
+    int u_off[3];                // U_m (n_m x n_m, U[i*n + a]) in the eigenvector table
+    int d_off[3];                // D_m in the eigenvalue table
+    double kappa[3];             // Kronecker coefficients kappa_{l,m}
+    double scale;                // (H^(k))^{d-2} for P_A, 1 for the interior solve
+    double mass;                 // 1 for P_A (mass term), 0 for the interior solve
+    double alpha;                // output = alpha * solution
+};
+
+struct Chunk {                   // contiguous range inside one segment
+    int64_t begin, end;
+    int seg;                     // patch or problem index
+    int pad;
+};
+
+// MINRES scalars of one problem (preconditioned Lanczos + Givens).
+struct MinresState {
+    double gamma, gamma_old, gamma1, eta;
+    double c, c_old, s, s_old;
+    double delta;
+    double cv_q, cv_v, cv_vold;  // v_new = cv_q q + cv_v v + cv_vold v_old
+    double cd_z, cd_dold, cd_d;  // d_new = cd_z z + cd_dold d_old + cd_d d
+    double cx;                   // x += cx d_new
+    double rel;                  // |eta| / gamma1
+    double tol;
+    int its, maxit;
+    int stop;                    // 1 converged, 2 breakdown, 3 maxit
+    int upd;                     // 1 while the d/x update of this iteration is pending
+};
+
+}  // namespace afieti

@@ -1,0 +1,95 @@
+// Launch wrappers of the HIP kernels (defined in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace afieti {
+
+// ---- Fast Diagonalization (Algorithm 1): three passes over the tensors.
+// prec: 0 FP64, 1 FP32, 2 BF16 mode products.
+void launch_fd(int prec, const FdTensor* d_tensors, int n_tensors,
+               const int2* d_slabs, int n_slabs, const int2* d_cols, int n_colblocks,
+               const void* u_table, const double* d_table,
+               const double* in, double* out, void* tmp, int max_n, hipStream_t s);
+
+// ---- setup kernels
+void launch_geometry(const DevPatch* dp, int k, const DevPatch& hp, const double* ctrl,
+                     const double* qval, const double* qder, const int* qfirst, const double* qw,
+                     double* geo, hipStream_t s);
+void launch_assemble(const DevPatch* dp, int k, const DevPatch& hp, const double* geo,
+                     const double* qval, const double* qder, const int* qfirst,
+                     const int* el_first, const int* el_last, double* stencil,
+                     double lam_w, double mu_w, hipStream_t s);
+void launch_load(const DevPatch* dp, int k, const DevPatch& hp, const double* geo,
+                 const double* qval, const int* qfirst, const int* el_first, const int* el_last,
+                 const double* modes, int n_modes, double* f, hipStream_t s);
+
+// ---- operators
+// y = A x (+ B^T t if t != nullptr) for every row of every patch
+void launch_stiffness_dp(int dim, int p, const DevPatch* dp, const int4* d_rowblocks, int n_rowblocks,
+                         const double* stencil, const double* x, double* y,
+                         const int64_t* bt_ptr, const int* bt_row, const double* bt_sign,
+                         const double* t, hipStream_t s);
+// zero the interior nodes of every patch and component
+void launch_mask_interior(const DevPatch* dp, const int4* d_rowblocks, int n_rowblocks, double* y, hipStream_t s);
+// y[r] = alpha (x[plus] - x[minus])
+void launch_B(const int64_t* plus, const int64_t* minus, int64_t n_c, double alpha,
+              const double* x, double* y, hipStream_t s);
+// y[i] = sum sign * x[row] for every DOF
+void launch_Bt(const int64_t* bt_ptr, const int* bt_row, const double* bt_sign, int64_t n_dof,
+               const double* x, double* y, hipStream_t s);
+// z = (B B^T)^{-1} y (node blocks)
+void launch_W(const int* blk_start, const int* blk_size, const int* blk_dir, int64_t n_c,
+              const double* y, double* z, hipStream_t s);
+// y = scale_k * A-hat x per patch and component (banded Kronecker form)
+void launch_ahat_dp(int dim, int p, const DevPatch* dp, const int4* d_rowblocks, int n_rowblocks,
+                    const double* kband, const double* mband, const double* x, double* y,
+                    int use_hscale, hipStream_t s);
+// partial sums of R^T x over patch DOF chunks (nm values per chunk)
+void launch_rigid_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks,
+                          const double* ctrl, const double* x, double* partials, hipStream_t s);
+// partial sums of R^T (B^T y) over the Gamma DOF chunks
+void launch_gamma_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks,
+                          const double* ctrl, const int64_t* gam_dof, const int64_t* bt_ptr,
+                          const int* bt_row, const double* bt_sign, const double* y,
+                          double* partials, hipStream_t s);
+// coef[k] = RtR_inv[k] * sum(partials of patch k)
+void launch_rigid_finalize(const int* patch_chunk_ptr, int n_patches, const double* partials,
+                           const double* RtR_inv, double* coef, hipStream_t s);
+// per problem: g = sum partials; zc = Cinv g (coefficients per patch)
+void launch_coarse_finalize(const int* prob_patch0, const int* prob_npatch, const int* prob_nmodes,
+                            const int64_t* prob_cinv_off, int n_probs, const int* patch_chunk_ptr,
+                            const double* partials, const double* Cinv, double* zc, int max_nc,
+                            hipStream_t s);
+// y = x - R coef (all DOFs)
+void launch_rigid_update(const DevPatch* dp, const Chunk* chunks, int n_chunks, const double* ctrl,
+                         const double* coef, const double* x, double* y, hipStream_t s);
+// y[r] = beta x[r] + alpha (G zc)[r]
+void launch_G_apply(const int* patch_plus, const int* patch_minus, const double* g_plus,
+                    const double* g_minus, int64_t n_c, const double* zc, double alpha,
+                    double beta, const double* x, double* y, hipStream_t s);
+
+// ---- vector kernels
+void launch_copy(const double* x, double* y, int64_t n, hipStream_t s);
+void launch_fill(double* y, double v, int64_t n, hipStream_t s);
+void launch_axpby(double a, const double* x, double b, const double* y, double* z, int64_t n, hipStream_t s);
+// per-chunk partial dot products <x, y>
+void launch_dot_partial(const Chunk* chunks, int n_chunks, const double* x, const double* y,
+                        double* partials, hipStream_t s);
+// MINRES scalar steps (one thread per problem)
+void launch_minres_delta(MinresState* st, const int* prob_chunk_ptr, int n_probs,
+                         const double* partials, hipStream_t s);
+void launch_minres_givens(MinresState* st, const int* prob_chunk_ptr, int n_probs,
+                          const double* partials, hipStream_t s);
+void launch_minres_init(MinresState* st, const int* prob_chunk_ptr, int n_probs,
+                        const double* partials, double tol, int maxit, hipStream_t s);
+// v_new = cv_q q + cv_v v + cv_vold v_old   (skipped for stopped problems)
+void launch_minres_v(const MinresState* st, const Chunk* chunks, int n_chunks, const double* q,
+                     const double* v, const double* v_old, double* v_new, hipStream_t s);
+// d_new = cd_z z + cd_dold d_old + cd_d d; x += cx d_new   (only when upd)
+void launch_minres_dx(const MinresState* st, const Chunk* chunks, int n_chunks, const double* z,
+                      const double* d_old, const double* d, double* d_new, double* x, hipStream_t s);
+
+}  // namespace afieti

@@ -1,0 +1,978 @@
+// HIP kernels of the inexact AF-IETI hot path for gfx950 (wave64).
+//
+//  * FD (Algorithm 1 of Section 5.2.1): mode products with the univariate
+//    generalised eigenvectors in three passes (modes 1+2 per slab, mode 3
+//    with the eigenvalue divide fused, modes 2+1 per slab), tiles in LDS.
+//  * stiffness stencil assembly (Gauss quadrature of the bilinear form of
+//    Section 3) and the matrix-vector product with the assembled stencil,
+//    with B^T t fused into its epilogue (first block row of the projected
+//    saddle operator, Section 4).
+//  * jump operator B, B^T, the node-block inverse of B B^T (Remark 1),
+//    banded Kronecker application of A-hat (Section 5.2), rigid-mode
+//    reductions and updates for P_u, P_chi, lambda_0 and the recovery.
+//  * deterministic two-stage reductions and the MINRES vector updates.
+//
+// Every reduction sums in a fixed order (thread strides, then a fixed
+// shuffle tree, then chunks in index order): repeated runs are bitwise
+// identical.  No atomics.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "kernels.h"
+#include "rigid.h"
+
+namespace afieti {
+
+namespace {
+
+constexpr int kQStride = 9;  // row stride of the univariate quadrature tables (p <= 8)
+
+inline unsigned blocks_for(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+// ------------------------------------------------------------- reductions
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum NV values over a block of kBlock threads; result valid in thread 0.
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double* lds /* NV * 4 */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        double s = wave_sum(v[m]);
+        if (lane == 0) lds[m * 4 + wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int m = 0; m < NV; ++m) v[m] = ((lds[m * 4 + 0] + lds[m * 4 + 1]) + lds[m * 4 + 2]) + lds[m * 4 + 3];
+    }
+}
+
+// =============================================================== FD kernels
+// Pass 1: per (tensor, slab i3): Y[a2][a1] = sum_{i2,i1} U2[i2][a2] X[i2][i1] U1[i1][a1]
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fd_fwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
+                                                     const T* __restrict__ ut, const double* __restrict__ in,
+                                                     T* __restrict__ tmp) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 it = slabs[blockIdx.x];
+    const FdTensor t = tens[it.x];
+    const int i3 = it.y, n1 = t.n1, n2 = t.n2, n12 = n1 * n2;
+    T* X = reinterpret_cast<T*>(smem);
+    T* Y = X + kMaxN * kMaxN;
+    T* U = Y + kMaxN * kMaxN;
+    const double* src = in + t.in_off + (int64_t)i3 * t.s3;
+    for (int e = threadIdx.x; e < n12; e += kBlock) {
+        int i2 = e / n1, i1 = e - i2 * n1;
+        X[e] = (T)src[(int64_t)i2 * t.s2 + i1];
+    }
+    for (int e = threadIdx.x; e < n1 * n1; e += kBlock) U[e] = ut[t.u_off[0] + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < n12; e += kBlock) {  // Y[i2][a1]
+        int i2 = e / n1, a1 = e - i2 * n1;
+        T acc = 0;
+        for (int i1 = 0; i1 < n1; ++i1) acc += X[i2 * n1 + i1] * U[i1 * n1 + a1];
+        Y[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n2 * n2; e += kBlock) U[e] = ut[t.u_off[1] + e];
+    __syncthreads();
+    T* dst = tmp + t.tmp_off + (int64_t)i3 * n12;
+    for (int e = threadIdx.x; e < n12; e += kBlock) {  // Z[a2][a1]
+        int a2 = e / n1, a1 = e - a2 * n1;
+        T acc = 0;
+        for (int i2 = 0; i2 < n2; ++i2) acc += U[i2 * n2 + a2] * Y[i2 * n1 + a1];
+        dst[e] = acc;
+    }
+}
+
+// Pass 2: per (tensor, block of 32 columns (a1,a2)): mode-3 product with U3^T,
+// divide by the Kronecker-sum eigenvalues Lambda, mode-3 product with U3.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fd_mid3(const FdTensor* __restrict__ tens, const int2* __restrict__ cols,
+                                                    const T* __restrict__ ut, const double* __restrict__ dt,
+                                                    T* __restrict__ tmp) {
+    constexpr int NC = 32;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 it = cols[blockIdx.x];
+    const FdTensor t = tens[it.x];
+    const int n1 = t.n1, n3 = t.n3, n12 = t.n1 * t.n2;
+    const int col0 = it.y * NC;
+    T* Z = reinterpret_cast<T*>(smem);
+    T* Zt = Z + kMaxN * NC;
+    T* U = Zt + kMaxN * NC;
+    T* base = tmp + t.tmp_off;
+    for (int e = threadIdx.x; e < n3 * NC; e += kBlock) {
+        int i3 = e / NC, c = e - i3 * NC, col = col0 + c;
+        Z[e] = col < n12 ? base[(int64_t)i3 * n12 + col] : (T)0;
+    }
+    for (int e = threadIdx.x; e < n3 * n3; e += kBlock) U[e] = ut[t.u_off[2] + e];
+    __syncthreads();
+    const int c = threadIdx.x % NC, g = threadIdx.x / NC;  // 8 groups over a3
+    const int col = col0 + c;
+    const int a2 = col / n1, a1 = col - a2 * n1;
+    double lam12 = 0;
+    if (col < n12) lam12 = t.mass + t.kappa[0] * dt[t.d_off[0] + a1] + t.kappa[1] * dt[t.d_off[1] + a2];
+    for (int a3 = g; a3 < n3; a3 += kBlock / NC) {
+        T acc = 0;
+        for (int i3 = 0; i3 < n3; ++i3) acc += U[i3 * n3 + a3] * Z[i3 * NC + c];
+        double lam = t.scale * (lam12 + t.kappa[2] * dt[t.d_off[2] + a3]);
+        Zt[a3 * NC + c] = (col < n12) ? (T)((double)acc / lam) : (T)0;
+    }
+    __syncthreads();
+    for (int i3 = g; i3 < n3; i3 += kBlock / NC) {
+        T acc = 0;
+        for (int a3 = 0; a3 < n3; ++a3) acc += U[i3 * n3 + a3] * Zt[a3 * NC + c];
+        if (col < n12) base[(int64_t)i3 * n12 + col] = acc;
+    }
+}
+
+// Pass 3: per (tensor, slab i3): X[i2][i1] = alpha sum_{a2,a1} U2[i2][a2] Z[a2][a1] U1[i1][a1]
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fd_bwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
+                                                     const T* __restrict__ ut, const T* __restrict__ tmp,
+                                                     double* __restrict__ out) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 it = slabs[blockIdx.x];
+    const FdTensor t = tens[it.x];
+    const int i3 = it.y, n1 = t.n1, n2 = t.n2, n12 = n1 * n2;
+    T* Z = reinterpret_cast<T*>(smem);
+    T* Y = Z + kMaxN * kMaxN;
+    T* U = Y + kMaxN * kMaxN;
+    const T* src = tmp + t.tmp_off + (int64_t)i3 * n12;
+    for (int e = threadIdx.x; e < n12; e += kBlock) Z[e] = src[e];
+    for (int e = threadIdx.x; e < n1 * n1; e += kBlock) U[e] = ut[t.u_off[0] + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < n12; e += kBlock) {  // Y[a2][i1] = sum_a1 Z[a2][a1] U1[i1][a1]
+        int a2 = e / n1, i1 = e - a2 * n1;
+        T acc = 0;
+        for (int a1 = 0; a1 < n1; ++a1) acc += Z[a2 * n1 + a1] * U[i1 * n1 + a1];
+        Y[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n2 * n2; e += kBlock) U[e] = ut[t.u_off[1] + e];
+    __syncthreads();
+    double* dst = out + t.out_off + (int64_t)i3 * t.s3;
+    for (int e = threadIdx.x; e < n12; e += kBlock) {  // X[i2][i1] = sum_a2 U2[i2][a2] Y[a2][i1]
+        int i2 = e / n1, i1 = e - i2 * n1;
+        T acc = 0;
+        for (int a2 = 0; a2 < n2; ++a2) acc += U[i2 * n2 + a2] * Y[a2 * n1 + i1];
+        dst[(int64_t)i2 * t.s2 + i1] = t.alpha * (double)acc;
+    }
+}
+
+// ============================================================ setup kernels
+// Geometry at the Gauss points of patch k from the spline map with the
+// control net: per point [w |det J|, J^{-1} (3x3, row a = d eta_a / dx),
+// x (3)], 13 doubles.
+template <int DIM>
+__global__ void k_geometry(const DevPatch* __restrict__ dps, int k, const double* __restrict__ ctrl,
+                           const double* __restrict__ qval, const double* __restrict__ qder,
+                           const int* __restrict__ qfirst, const double* __restrict__ qw,
+                           double* __restrict__ geo) {
+    const DevPatch pa = dps[k];
+    const int64_t nq1 = pa.nq[0], nq2 = pa.nq[1], nq3 = pa.nq[2];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nq1 * nq2 * nq3) return;
+    const int q1 = (int)(idx % nq1), q2 = (int)((idx / nq1) % nq2), q3 = (int)(idx / (nq1 * nq2));
+    const int q[3] = {q1, q2, q3};
+    const int P = pa.p;
+    int f[3];
+    const double *v[3], *d[3];
+    double one = 1.0, zero = 0.0;
+    double w = 1.0;
+    for (int m = 0; m < 3; ++m) {
+        if (m < DIM) {
+            int g = pa.q_off[m] + q[m];
+            f[m] = qfirst[g];
+            v[m] = qval + (int64_t)g * kQStride;
+            d[m] = qder + (int64_t)g * kQStride;
+            w *= qw[g];
+        } else {
+            f[m] = 0;
+            v[m] = &one;
+            d[m] = &zero;
+        }
+    }
+    double F[3] = {0, 0, 0}, J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    const int P3 = DIM == 3 ? P : 0;
+    for (int t3 = 0; t3 <= P3; ++t3)
+        for (int t2 = 0; t2 <= P; ++t2)
+            for (int t1 = 0; t1 <= P; ++t1) {
+                int64_t node = (f[0] + t1) + (int64_t)pa.n[0] * ((f[1] + t2) + (int64_t)pa.n[1] * (f[2] + t3));
+                const double* X = ctrl + pa.ctrl_off + node * 3;
+                double bv = v[0][t1] * v[1][t2] * v[2][t3];
+                double g0 = d[0][t1] * v[1][t2] * v[2][t3];
+                double g1 = v[0][t1] * d[1][t2] * v[2][t3];
+                double g2 = v[0][t1] * v[1][t2] * d[2][t3];
+                for (int x = 0; x < DIM; ++x) {
+                    F[x] += bv * X[x];
+                    J[x][0] += g0 * X[x];
+                    J[x][1] += g1 * X[x];
+                    if (DIM == 3) J[x][2] += g2 * X[x];
+                }
+            }
+    double Ji[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double det;
+    if (DIM == 2) {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        Ji[0][0] = J[1][1] / det;
+        Ji[0][1] = -J[0][1] / det;
+        Ji[1][0] = -J[1][0] / det;
+        Ji[1][1] = J[0][0] / det;
+    } else {
+        double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        Ji[0][0] = c00 / det;
+        Ji[1][0] = c01 / det;
+        Ji[2][0] = c02 / det;
+        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    }
+    double* o = geo + pa.geo_off + idx * 13;
+    o[0] = w * fabs(det);
+    for (int a = 0; a < 3; ++a)
+        for (int x = 0; x < 3; ++x) o[1 + a * 3 + x] = Ji[a][x];
+    o[10] = F[0];
+    o[11] = F[1];
+    o[12] = F[2];
+}
+
+// Stiffness stencil of patch k: one thread per (offset s, node i) computes
+// the DIM x DIM entries A[(c,i),(c',i+o_s)] = sum over the Gauss points of
+// the common support of  w|J| [mu d_cc' g_i.g_j + mu g_i[c'] g_j[c] + lam g_i[c] g_j[c']]
+// with physical gradients g = J^{-T} (parametric gradient).
+template <int DIM>
+__global__ void k_assemble(const DevPatch* __restrict__ dps, int k, const double* __restrict__ geo,
+                           const double* __restrict__ qval, const double* __restrict__ qder,
+                           const int* __restrict__ qfirst, const int* __restrict__ el_first,
+                           const int* __restrict__ el_last, double* __restrict__ A, double lam_w, double mu_w) {
+    const DevPatch pa = dps[k];
+    const int P = pa.p, W = 2 * P + 1;
+    const int S = DIM == 3 ? W * W * W : W * W;
+    const int64_t nodes = pa.nodes;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)S * nodes) return;
+    const int64_t node = idx % nodes;
+    const int s = (int)(idx / nodes);
+    const int o[3] = {s % W - P, (s / W) % W - P, DIM == 3 ? s / (W * W) - P : 0};
+    const int i[3] = {(int)(node % pa.n[0]), (int)((node / pa.n[0]) % pa.n[1]), (int)(node / ((int64_t)pa.n[0] * pa.n[1]))};
+    int j[3];
+    bool valid = true;
+    int qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
+    for (int m = 0; m < DIM; ++m) {
+        j[m] = i[m] + o[m];
+        if (j[m] < 0 || j[m] >= pa.n[m]) {
+            valid = false;
+            break;
+        }
+        int elo = max(el_first[pa.el_off[m] + i[m]], el_first[pa.el_off[m] + j[m]]);
+        int ehi = min(el_last[pa.el_off[m] + i[m]], el_last[pa.el_off[m] + j[m]]);
+        if (elo > ehi) {
+            valid = false;
+            break;
+        }
+        qlo[m] = elo * (P + 1);
+        qhi[m] = (ehi + 1) * (P + 1);
+    }
+    if (DIM == 2) {
+        j[2] = 0;
+        qlo[2] = 0;
+        qhi[2] = 1;
+    }
+    double acc[DIM][DIM];
+    for (int a = 0; a < DIM; ++a)
+        for (int b = 0; b < DIM; ++b) acc[a][b] = 0.0;
+    if (valid) {
+        const int64_t nq1 = pa.nq[0], nq2 = pa.nq[1];
+        for (int q3 = qlo[2]; q3 < qhi[2]; ++q3) {
+            double iv3 = 1, id3 = 0, jv3 = 1, jd3 = 0;
+            if (DIM == 3) {
+                int g = pa.q_off[2] + q3, f = qfirst[g];
+                iv3 = qval[(int64_t)g * kQStride + i[2] - f];
+                id3 = qder[(int64_t)g * kQStride + i[2] - f];
+                jv3 = qval[(int64_t)g * kQStride + j[2] - f];
+                jd3 = qder[(int64_t)g * kQStride + j[2] - f];
+            }
+            for (int q2 = qlo[1]; q2 < qhi[1]; ++q2) {
+                int g2 = pa.q_off[1] + q2, f2 = qfirst[g2];
+                double iv2 = qval[(int64_t)g2 * kQStride + i[1] - f2], id2 = qder[(int64_t)g2 * kQStride + i[1] - f2];
+                double jv2 = qval[(int64_t)g2 * kQStride + j[1] - f2], jd2 = qder[(int64_t)g2 * kQStride + j[1] - f2];
+                for (int q1 = qlo[0]; q1 < qhi[0]; ++q1) {
+                    int g1 = pa.q_off[0] + q1, f1 = qfirst[g1];
+                    double iv1 = qval[(int64_t)g1 * kQStride + i[0] - f1], id1 = qder[(int64_t)g1 * kQStride + i[0] - f1];
+                    double jv1 = qval[(int64_t)g1 * kQStride + j[0] - f1], jd1 = qder[(int64_t)g1 * kQStride + j[0] - f1];
+                    const double* G = geo + pa.geo_off + ((int64_t)q1 + nq1 * ((int64_t)q2 + nq2 * q3)) * 13;
+                    double gi_r[3] = {id1 * iv2 * iv3, iv1 * id2 * iv3, iv1 * iv2 * id3};
+                    double gj_r[3] = {jd1 * jv2 * jv3, jv1 * jd2 * jv3, jv1 * jv2 * jd3};
+                    double gi[DIM], gj[DIM];
+                    for (int x = 0; x < DIM; ++x) {
+                        double si = 0, sj = 0;
+                        for (int a = 0; a < DIM; ++a) {
+                            si += G[1 + a * 3 + x] * gi_r[a];
+                            sj += G[1 + a * 3 + x] * gj_r[a];
+                        }
+                        gi[x] = si;
+                        gj[x] = sj;
+                    }
+                    double dot = 0;
+                    for (int x = 0; x < DIM; ++x) dot += gi[x] * gj[x];
+                    const double wq = G[0];
+                    for (int a = 0; a < DIM; ++a)
+                        for (int b = 0; b < DIM; ++b)
+                            acc[a][b] += wq * (mu_w * ((a == b ? dot : 0.0) + gi[b] * gj[a]) + lam_w * gi[a] * gj[b]);
+                }
+            }
+        }
+    }
+    for (int a = 0; a < DIM; ++a)
+        for (int b = 0; b < DIM; ++b)
+            A[pa.stencil_off + ((int64_t)(a * DIM + b) * S + s) * nodes + node] = acc[a][b];
+}
+
+// Body-force load of patch k: f_(c,i) = sum_q w|J| f_c(x_q) B_i(x_q) with
+// f_c(x) = sum over the modes of component c of amp prod_d sin(pi k_d x_d + phase_d).
+template <int DIM>
+__global__ void k_load(const DevPatch* __restrict__ dps, int k, const double* __restrict__ geo,
+                       const double* __restrict__ qval, const int* __restrict__ qfirst,
+                       const int* __restrict__ el_first, const int* __restrict__ el_last,
+                       const double* __restrict__ modes, int n_modes, double* __restrict__ f) {
+    const DevPatch pa = dps[k];
+    const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= pa.nodes) return;
+    const int P = pa.p;
+    const int i[3] = {(int)(node % pa.n[0]), (int)((node / pa.n[0]) % pa.n[1]), (int)(node / ((int64_t)pa.n[0] * pa.n[1]))};
+    int qlo[3] = {0, 0, 0}, qhi[3] = {1, 1, 1};
+    for (int m = 0; m < DIM; ++m) {
+        qlo[m] = el_first[pa.el_off[m] + i[m]] * (P + 1);
+        qhi[m] = (el_last[pa.el_off[m] + i[m]] + 1) * (P + 1);
+    }
+    double acc[3] = {0, 0, 0};
+    const int64_t nq1 = pa.nq[0], nq2 = pa.nq[1];
+    for (int q3 = qlo[2]; q3 < qhi[2]; ++q3) {
+        double v3 = 1;
+        if (DIM == 3) {
+            int g = pa.q_off[2] + q3;
+            v3 = qval[(int64_t)g * kQStride + i[2] - qfirst[g]];
+        }
+        for (int q2 = qlo[1]; q2 < qhi[1]; ++q2) {
+            int g2 = pa.q_off[1] + q2;
+            double v2 = qval[(int64_t)g2 * kQStride + i[1] - qfirst[g2]];
+            for (int q1 = qlo[0]; q1 < qhi[0]; ++q1) {
+                int g1 = pa.q_off[0] + q1;
+                double v1 = qval[(int64_t)g1 * kQStride + i[0] - qfirst[g1]];
+                const double* G = geo + pa.geo_off + ((int64_t)q1 + nq1 * ((int64_t)q2 + nq2 * q3)) * 13;
+                double b = G[0] * v1 * v2 * v3;
+                for (int j = 0; j < n_modes; ++j) {
+                    const double* md = modes + j * 8;
+                    double val = md[1];
+                    for (int d = 0; d < DIM; ++d) val *= sin(M_PI * md[2 + d] * G[10 + d] + md[5 + d]);
+                    acc[(int)md[0]] += b * val;
+                }
+            }
+        }
+    }
+    for (int c = 0; c < DIM; ++c) f[pa.dof_off + c * pa.nodes + node] = acc[c];
+}
+
+// ================================================================ operators
+// y = A x (+ B^T t): one thread per row (patch, component c, node).
+template <int DIM, int P>
+__global__ void __launch_bounds__(kBlock) k_stiffness(const DevPatch* __restrict__ dps, const int4* __restrict__ rb,
+                                                      const double* __restrict__ A, const double* __restrict__ x,
+                                                      double* __restrict__ y, const int64_t* __restrict__ bt_ptr,
+                                                      const int* __restrict__ bt_row, const double* __restrict__ bt_sign,
+                                                      const double* __restrict__ t) {
+    constexpr int W = 2 * P + 1;
+    constexpr int S = DIM == 3 ? W * W * W : W * W;
+    constexpr int P3 = DIM == 3 ? P : 0;
+    const int4 b = rb[blockIdx.x];
+    const DevPatch& pa = dps[b.x];
+    const int64_t nodes = pa.nodes;
+    const int64_t node = (int64_t)b.z + threadIdx.x;
+    if (node >= nodes) return;
+    const int n1 = pa.n[0], n2 = pa.n[1], n3 = pa.n[2];
+    const int i1 = (int)(node % n1), i2 = (int)((node / n1) % n2), i3 = (int)(node / ((int64_t)n1 * n2));
+    const int c = b.y;
+    const double* Ab = A + pa.stencil_off + (int64_t)(c * DIM) * S * nodes + node;
+    const double* xb = x + pa.dof_off;
+    double acc = 0.0;
+    for (int cp = 0; cp < DIM; ++cp) {
+        const double* Ac = Ab + (int64_t)cp * S * nodes;
+        const double* xc = xb + (int64_t)cp * nodes;
+        for (int o3 = -P3; o3 <= P3; ++o3) {
+            const int j3 = i3 + o3;
+            const bool v3 = (unsigned)j3 < (unsigned)n3;
+            for (int o2 = -P; o2 <= P; ++o2) {
+                const int j2 = i2 + o2;
+                const bool v23 = v3 && (unsigned)j2 < (unsigned)n2;
+                const int64_t rowoff = (int64_t)n1 * (j2 + (int64_t)n2 * j3);
+                const int sbase = (o2 + P) * W + (o3 + P3) * W * W;
+#pragma unroll
+                for (int o1 = -P; o1 <= P; ++o1) {
+                    const int j1 = i1 + o1;
+                    if (v23 && (unsigned)j1 < (unsigned)n1)
+                        acc += Ac[(int64_t)(sbase + o1 + P) * nodes] * xc[rowoff + j1];
+                }
+            }
+        }
+    }
+    const int64_t row = pa.dof_off + (int64_t)c * nodes + node;
+    if (t) {
+        for (int64_t e = bt_ptr[row]; e < bt_ptr[row + 1]; ++e) acc += bt_sign[e] * t[bt_row[e]];
+    }
+    y[row] = acc;
+}
+
+// y = scale * A-hat_l x on every (patch, component l): the Kronecker form
+// sum_m kappa_{l,m} (M_d x .. K_m .. x M_1) with banded univariate K, M.
+template <int DIM, int P>
+__global__ void __launch_bounds__(kBlock) k_ahat(const DevPatch* __restrict__ dps, const int4* __restrict__ rb,
+                                                 const double* __restrict__ kb, const double* __restrict__ mb,
+                                                 const double* __restrict__ x, double* __restrict__ y, int use_h) {
+    constexpr int W = 2 * P + 1;
+    constexpr int P3 = DIM == 3 ? P : 0;
+    const int4 b = rb[blockIdx.x];
+    const DevPatch& pa = dps[b.x];
+    const int64_t nodes = pa.nodes;
+    const int64_t node = (int64_t)b.z + threadIdx.x;
+    if (node >= nodes) return;
+    const int n1 = pa.n[0], n2 = pa.n[1], n3 = pa.n[2];
+    const int i1 = (int)(node % n1), i2 = (int)((node / n1) % n2), i3 = (int)(node / ((int64_t)n1 * n2));
+    const int l = b.y;
+    const double k1 = l == 0 ? 2 * pa.mu + pa.lam : pa.mu;
+    const double k2 = l == 1 ? 2 * pa.mu + pa.lam : pa.mu;
+    const double k3 = l == 2 ? 2 * pa.mu + pa.lam : pa.mu;
+    const double* K1 = kb + pa.band_off[0] + i1 * W;
+    const double* M1 = mb + pa.band_off[0] + i1 * W;
+    const double* K2 = kb + pa.band_off[1] + i2 * W;
+    const double* M2 = mb + pa.band_off[1] + i2 * W;
+    const double* xc = x + pa.dof_off + (int64_t)l * nodes;
+    double acc = 0.0;
+    for (int o3 = -P3; o3 <= P3; ++o3) {
+        const int j3 = i3 + o3;
+        if ((unsigned)j3 >= (unsigned)n3) continue;
+        double m3 = 1.0, kk3 = 0.0;
+        if (DIM == 3) {
+            m3 = mb[pa.band_off[2] + i3 * W + o3 + P];
+            kk3 = kb[pa.band_off[2] + i3 * W + o3 + P];
+        }
+        for (int o2 = -P; o2 <= P; ++o2) {
+            const int j2 = i2 + o2;
+            if ((unsigned)j2 >= (unsigned)n2) continue;
+            const double mm = M2[o2 + P] * m3;                  // M2 M3
+            const double c2 = k2 * K2[o2 + P] * m3;             // K2 M3
+            const double c3 = DIM == 3 ? k3 * M2[o2 + P] * kk3 : 0.0;  // M2 K3
+            const double* xr = xc + (int64_t)n1 * (j2 + (int64_t)n2 * j3);
+#pragma unroll
+            for (int o1 = -P; o1 <= P; ++o1) {
+                const int j1 = i1 + o1;
+                if ((unsigned)j1 < (unsigned)n1)
+                    acc += xr[j1] * (k1 * K1[o1 + P] * mm + M1[o1 + P] * (c2 + c3));
+            }
+        }
+    }
+    y[pa.dof_off + (int64_t)l * nodes + node] = (use_h ? pa.hscale : 1.0) * acc;
+}
+
+__global__ void k_B(const int64_t* __restrict__ plus, const int64_t* __restrict__ minus, int64_t n_c, double alpha,
+                    const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_c) return;
+    const int64_t m = minus[r];
+    y[r] = alpha * (x[plus[r]] - (m >= 0 ? x[m] : 0.0));
+}
+
+__global__ void k_Bt(const int64_t* __restrict__ ptr, const int* __restrict__ row, const double* __restrict__ sgn,
+                     int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) acc += sgn[e] * x[row[e]];
+    y[i] = acc;
+}
+
+// (B B^T)^{-1} per node block.  Star block of size s: I + 1 1^T, whose
+// inverse is I - 1 1^T / (s + 1).  Dirichlet block: identity.
+__global__ void k_W(const int* __restrict__ bs, const int* __restrict__ bn, const int* __restrict__ bd, int64_t n_c,
+                    const double* __restrict__ y, double* __restrict__ z) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_c) return;
+    if (bd[r]) {
+        z[r] = y[r];
+        return;
+    }
+    const int s0 = bs[r], sz = bn[r];
+    double sum = 0.0;
+    for (int j = 0; j < sz; ++j) sum += y[s0 + j];
+    z[r] = y[r] - sum / (sz + 1);
+}
+
+// partial sums of R^T x over chunks of one patch's DOFs
+__global__ void __launch_bounds__(kBlock) k_rigid_partial(const DevPatch* __restrict__ dps, const Chunk* __restrict__ ch,
+                                                          const double* __restrict__ ctrl, const double* __restrict__ x,
+                                                          double* __restrict__ part) {
+    __shared__ double lds[6 * 4];
+    const Chunk c = ch[blockIdx.x];
+    const DevPatch& pa = dps[c.seg];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+        const int64_t loc = i - pa.dof_off;
+        const int comp = (int)(loc / pa.nodes);
+        const int64_t nd = loc - comp * pa.nodes;
+        const double* X = ctrl + pa.ctrl_off + nd * 3;
+        const double v = x[i];
+        for (int m = 0; m < pa.nmodes; ++m) acc[m] += rigid_mode_value(pa.dim, m, comp, X) * v;
+    }
+    block_sum<6>(acc, lds);
+    if (threadIdx.x == 0)
+        for (int m = 0; m < 6; ++m) part[(int64_t)blockIdx.x * 6 + m] = acc[m];
+}
+
+// partial sums of R^T (B^T y) over chunks of one patch's Gamma DOF list
+__global__ void __launch_bounds__(kBlock) k_gamma_partial(const DevPatch* __restrict__ dps, const Chunk* __restrict__ ch,
+                                                          const double* __restrict__ ctrl, const int64_t* __restrict__ gam,
+                                                          const int64_t* __restrict__ ptr, const int* __restrict__ row,
+                                                          const double* __restrict__ sgn, const double* __restrict__ y,
+                                                          double* __restrict__ part) {
+    __shared__ double lds[6 * 4];
+    const Chunk c = ch[blockIdx.x];
+    const DevPatch& pa = dps[c.seg];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t e = c.begin + threadIdx.x; e < c.end; e += kBlock) {
+        const int64_t i = gam[e];
+        double v = 0.0;
+        for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) v += sgn[q] * y[row[q]];
+        const int64_t loc = i - pa.dof_off;
+        const int comp = (int)(loc / pa.nodes);
+        const int64_t nd = loc - comp * pa.nodes;
+        const double* X = ctrl + pa.ctrl_off + nd * 3;
+        for (int m = 0; m < pa.nmodes; ++m) acc[m] += rigid_mode_value(pa.dim, m, comp, X) * v;
+    }
+    block_sum<6>(acc, lds);
+    if (threadIdx.x == 0)
+        for (int m = 0; m < 6; ++m) part[(int64_t)blockIdx.x * 6 + m] = acc[m];
+}
+
+// one block per patch: coef = (R^T R)^{-1} sum(partials)
+__global__ void k_rigid_finalize(const int* __restrict__ cptr, const double* __restrict__ part,
+                                 const double* __restrict__ rtr, double* __restrict__ coef) {
+    __shared__ double raw[6];
+    const int k = blockIdx.x;
+    if (threadIdx.x < 6) {
+        double s = 0.0;
+        for (int c = cptr[k]; c < cptr[k + 1]; ++c) s += part[(int64_t)c * 6 + threadIdx.x];
+        raw[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double s = 0.0;
+        for (int b = 0; b < 6; ++b) s += rtr[k * 36 + threadIdx.x * 6 + b] * raw[b];
+        coef[k * 6 + threadIdx.x] = s;
+    }
+}
+
+// one block per problem: g = sum of the Gamma partials per patch and mode,
+// zc = (G^T G)^{-1} g, scattered to zc[patch * 6 + mode]
+__global__ void __launch_bounds__(kBlock) k_coarse_finalize(const int* __restrict__ p0, const int* __restrict__ np,
+                                                            const int* __restrict__ nmod, const int64_t* __restrict__ coff,
+                                                            const int* __restrict__ cptr, const double* __restrict__ part,
+                                                            const double* __restrict__ cinv, double* __restrict__ zc) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* g = reinterpret_cast<double*>(smem);
+    const int pr = blockIdx.x;
+    const int nm = nmod[pr], npch = np[pr], patch0 = p0[pr];
+    const int nc = nm * npch;
+    for (int e = threadIdx.x; e < nc; e += blockDim.x) {
+        const int k = patch0 + e / nm, m = e % nm;
+        double s = 0.0;
+        for (int c = cptr[k]; c < cptr[k + 1]; ++c) s += part[(int64_t)c * 6 + m];
+        g[e] = s;
+    }
+    __syncthreads();
+    const double* C = cinv + coff[pr];
+    for (int e = threadIdx.x; e < nc; e += blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < nc; ++j) s += C[(int64_t)e * nc + j] * g[j];
+        zc[(patch0 + e / nm) * 6 + e % nm] = s;
+    }
+}
+
+// y = x - R coef over chunks of patch DOFs
+__global__ void __launch_bounds__(kBlock) k_rigid_update(const DevPatch* __restrict__ dps, const Chunk* __restrict__ ch,
+                                                         const double* __restrict__ ctrl, const double* __restrict__ coef,
+                                                         const double* __restrict__ x, double* __restrict__ y) {
+    const Chunk c = ch[blockIdx.x];
+    const DevPatch& pa = dps[c.seg];
+    double cf[6];
+    for (int m = 0; m < 6; ++m) cf[m] = coef[c.seg * 6 + m];
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+        const int64_t loc = i - pa.dof_off;
+        const int comp = (int)(loc / pa.nodes);
+        const int64_t nd = loc - comp * pa.nodes;
+        const double* X = ctrl + pa.ctrl_off + nd * 3;
+        double r = 0.0;
+        for (int m = 0; m < pa.nmodes; ++m) r += rigid_mode_value(pa.dim, m, comp, X) * cf[m];
+        y[i] = x[i] - r;
+    }
+}
+
+// y[r] = beta x[r] + alpha (G zc)[r],  G row = R(plus copy) - R(minus copy)
+__global__ void k_G_apply(const int* __restrict__ pp, const int* __restrict__ pm, const double* __restrict__ gp,
+                          const double* __restrict__ gm, int64_t n_c, const double* __restrict__ zc, double alpha,
+                          double beta, const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_c) return;
+    const int a = pp[r], b = pm[r];
+    double s = 0.0;
+    for (int m = 0; m < 6; ++m) s += gp[r * 6 + m] * zc[a * 6 + m];
+    if (b >= 0)
+        for (int m = 0; m < 6; ++m) s -= gm[r * 6 + m] * zc[b * 6 + m];
+    y[r] = (x ? beta * x[r] : 0.0) + alpha * s;
+}
+
+// ============================================================ vector kernels
+__global__ void k_copy(const double* __restrict__ x, double* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+__global__ void k_fill(double* __restrict__ y, double v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+__global__ void k_axpby(double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                        double* __restrict__ z, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = a * x[i] + b * y[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_dot_partial(const Chunk* __restrict__ ch, const double* __restrict__ x,
+                                                        const double* __restrict__ y, double* __restrict__ part) {
+    __shared__ double lds[4];
+    const Chunk c = ch[blockIdx.x];
+    double acc[1] = {0.0};
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) acc[0] += x[i] * y[i];
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+__device__ inline double chunk_sum(const int* cptr, int pr, const double* part) {
+    double s = 0.0;
+    for (int c = cptr[pr]; c < cptr[pr + 1]; ++c) s += part[c];
+    return s;
+}
+
+__global__ void k_minres_init(MinresState* st, const int* cptr, int n, const double* part, double tol, int maxit) {
+    const int pr = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pr >= n) return;
+    MinresState s = {};
+    const double g2 = chunk_sum(cptr, pr, part);
+    s.tol = tol;
+    s.maxit = maxit;
+    s.gamma_old = 1.0;
+    s.c = s.c_old = 1.0;
+    s.s = s.s_old = 0.0;
+    if (g2 < 0.0) {
+        s.stop = 2;
+    } else {
+        s.gamma = sqrt(g2);
+        s.gamma1 = s.gamma;
+        s.eta = s.gamma;
+        s.rel = s.gamma > 0 ? 1.0 : 0.0;
+        s.stop = s.gamma > 0 ? 0 : 1;
+    }
+    st[pr] = s;
+}
+
+// delta_j = <A z_j, z_j> with z_j = zraw / gamma_j, and the v-update weights
+__global__ void k_minres_delta(MinresState* st, const int* cptr, int n, const double* part) {
+    const int pr = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pr >= n) return;
+    MinresState& s = st[pr];
+    s.upd = 0;
+    if (s.stop) return;
+    const double g = s.gamma;
+    s.delta = chunk_sum(cptr, pr, part) / (g * g);
+    s.cv_q = 1.0 / g;
+    s.cv_v = -s.delta / g;
+    s.cv_vold = -g / s.gamma_old;
+}
+
+// gamma_{j+1}, the Givens rotation and the d/x-update weights
+__global__ void k_minres_givens(MinresState* st, const int* cptr, int n, const double* part) {
+    const int pr = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pr >= n) return;
+    MinresState& s = st[pr];
+    if (s.stop) return;
+    const double g2 = chunk_sum(cptr, pr, part);
+    if (g2 < 0.0) {
+        s.stop = 2;
+        return;
+    }
+    const double gnew = sqrt(g2);
+    const double a0 = s.c * s.delta - s.c_old * s.s * s.gamma;
+    const double a1 = sqrt(a0 * a0 + gnew * gnew);
+    const double a2 = s.s * s.delta + s.c_old * s.c * s.gamma;
+    const double a3 = s.s_old * s.gamma;
+    const double cn = a0 / a1, sn = gnew / a1;
+    s.cd_z = 1.0 / (s.gamma * a1);
+    s.cd_dold = -a3 / a1;
+    s.cd_d = -a2 / a1;
+    s.cx = cn * s.eta;
+    s.eta = -sn * s.eta;
+    s.its += 1;
+    s.rel = fabs(s.eta) / s.gamma1;
+    s.gamma_old = s.gamma;
+    s.gamma = gnew;
+    s.c_old = s.c;
+    s.c = cn;
+    s.s_old = s.s;
+    s.s = sn;
+    s.upd = 1;
+    if (s.rel <= s.tol) s.stop = 1;
+    else if (s.its >= s.maxit) s.stop = 3;
+}
+
+__global__ void __launch_bounds__(kBlock) k_minres_v(const MinresState* __restrict__ st, const Chunk* __restrict__ ch,
+                                                     const double* __restrict__ q, const double* __restrict__ v,
+                                                     const double* __restrict__ vo, double* __restrict__ vn) {
+    const Chunk c = ch[blockIdx.x];
+    const MinresState& s = st[c.seg];
+    if (s.stop) return;
+    const double a = s.cv_q, b = s.cv_v, d = s.cv_vold;
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) vn[i] = a * q[i] + b * v[i] + d * vo[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_minres_dx(const MinresState* __restrict__ st, const Chunk* __restrict__ ch,
+                                                      const double* __restrict__ z, const double* __restrict__ dold,
+                                                      const double* __restrict__ d, double* __restrict__ dn,
+                                                      double* __restrict__ x) {
+    const Chunk c = ch[blockIdx.x];
+    const MinresState& s = st[c.seg];
+    if (!s.upd) return;
+    const double a = s.cd_z, b = s.cd_dold, e = s.cd_d, cx = s.cx;
+    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
+        const double v = a * z[i] + b * dold[i] + e * d[i];
+        dn[i] = v;
+        x[i] += cx * v;
+    }
+}
+
+// zero the interior nodes (all indices strictly inside) of every patch/component
+__global__ void __launch_bounds__(kBlock) k_mask_interior(const DevPatch* __restrict__ dps, const int4* __restrict__ rb,
+                                                          double* __restrict__ y) {
+    const int4 b = rb[blockIdx.x];
+    const DevPatch& pa = dps[b.x];
+    const int64_t node = (int64_t)b.z + threadIdx.x;
+    if (node >= pa.nodes) return;
+    const int n1 = pa.n[0], n2 = pa.n[1], n3 = pa.n[2];
+    const int i1 = (int)(node % n1), i2 = (int)((node / n1) % n2), i3 = (int)(node / ((int64_t)n1 * n2));
+    bool inner = i1 > 0 && i1 < n1 - 1 && i2 > 0 && i2 < n2 - 1;
+    if (pa.dim == 3) inner = inner && i3 > 0 && i3 < n3 - 1;
+    if (inner) y[pa.dof_off + (int64_t)b.y * pa.nodes + node] = 0.0;
+}
+
+template <int DIM, int P>
+void stiffness_t(const DevPatch* dp, const int4* rb, int nrb, const double* A, const double* x, double* y,
+                 const int64_t* bp, const int* br, const double* bs, const double* t, hipStream_t s) {
+    hipLaunchKernelGGL((k_stiffness<DIM, P>), dim3(nrb), dim3(kBlock), 0, s, dp, rb, A, x, y, bp, br, bs, t);
+}
+
+template <int DIM, int P>
+void ahat_t(const DevPatch* dp, const int4* rb, int nrb, const double* kb, const double* mb, const double* x,
+            double* y, int use_h, hipStream_t s) {
+    hipLaunchKernelGGL((k_ahat<DIM, P>), dim3(nrb), dim3(kBlock), 0, s, dp, rb, kb, mb, x, y, use_h);
+}
+
+}  // namespace
+
+// ======================================================== launch wrappers
+void launch_fd(int prec, const FdTensor* tens, int n_tensors, const int2* slabs, int n_slabs, const int2* cols,
+               int n_colblocks, const void* ut, const double* dt, const double* in, double* out, void* tmp,
+               int max_n, hipStream_t s) {
+    (void)n_tensors;
+    (void)max_n;
+    if (prec == 0) {
+        const size_t sh12 = 3 * kMaxN * kMaxN * sizeof(double);
+        const size_t sh3 = (2 * kMaxN * 32 + kMaxN * kMaxN) * sizeof(double);
+        hipLaunchKernelGGL(k_fd_fwd12<double>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
+                           (const double*)ut, in, (double*)tmp);
+        hipLaunchKernelGGL(k_fd_mid3<double>, dim3(n_colblocks), dim3(kBlock), sh3, s, tens, cols,
+                           (const double*)ut, dt, (double*)tmp);
+        hipLaunchKernelGGL(k_fd_bwd12<double>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
+                           (const double*)ut, (const double*)tmp, out);
+    } else {
+        const size_t sh12 = 3 * kMaxN * kMaxN * sizeof(float);
+        const size_t sh3 = (2 * kMaxN * 32 + kMaxN * kMaxN) * sizeof(float);
+        hipLaunchKernelGGL(k_fd_fwd12<float>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
+                           (const float*)ut, in, (float*)tmp);
+        hipLaunchKernelGGL(k_fd_mid3<float>, dim3(n_colblocks), dim3(kBlock), sh3, s, tens, cols,
+                           (const float*)ut, dt, (float*)tmp);
+        hipLaunchKernelGGL(k_fd_bwd12<float>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
+                           (const float*)ut, (const float*)tmp, out);
+    }
+}
+
+void launch_geometry(const DevPatch* dp, int k, const DevPatch& hp, const double* ctrl, const double* qval,
+                     const double* qder, const int* qfirst, const double* qw, double* geo, hipStream_t s) {
+    const int64_t n = (int64_t)hp.nq[0] * hp.nq[1] * hp.nq[2];
+    if (hp.dim == 3)
+        hipLaunchKernelGGL(k_geometry<3>, dim3(blocks_for(n)), dim3(kBlock), 0, s, dp, k, ctrl, qval, qder, qfirst, qw, geo);
+    else
+        hipLaunchKernelGGL(k_geometry<2>, dim3(blocks_for(n)), dim3(kBlock), 0, s, dp, k, ctrl, qval, qder, qfirst, qw, geo);
+}
+
+void launch_assemble(const DevPatch* dp, int k, const DevPatch& hp, const double* geo, const double* qval,
+                     const double* qder, const int* qfirst, const int* el_first, const int* el_last, double* stencil,
+                     double lam_w, double mu_w, hipStream_t s) {
+    const int W = 2 * hp.p + 1;
+    const int64_t S = hp.dim == 3 ? W * W * W : W * W;
+    const int64_t n = S * hp.nodes;
+    if (hp.dim == 3)
+        hipLaunchKernelGGL(k_assemble<3>, dim3(blocks_for(n)), dim3(kBlock), 0, s, dp, k, geo, qval, qder, qfirst,
+                           el_first, el_last, stencil, lam_w, mu_w);
+    else
+        hipLaunchKernelGGL(k_assemble<2>, dim3(blocks_for(n)), dim3(kBlock), 0, s, dp, k, geo, qval, qder, qfirst,
+                           el_first, el_last, stencil, lam_w, mu_w);
+}
+
+void launch_load(const DevPatch* dp, int k, const DevPatch& hp, const double* geo, const double* qval,
+                 const int* qfirst, const int* el_first, const int* el_last, const double* modes, int n_modes,
+                 double* f, hipStream_t s) {
+    if (hp.dim == 3)
+        hipLaunchKernelGGL(k_load<3>, dim3(blocks_for(hp.nodes)), dim3(kBlock), 0, s, dp, k, geo, qval, qfirst,
+                           el_first, el_last, modes, n_modes, f);
+    else
+        hipLaunchKernelGGL(k_load<2>, dim3(blocks_for(hp.nodes)), dim3(kBlock), 0, s, dp, k, geo, qval, qfirst,
+                           el_first, el_last, modes, n_modes, f);
+}
+
+#define AFIETI_DISPATCH_P(DIM, FN, ...)            \
+    switch (p) {                                   \
+        case 1: FN<DIM, 1>(__VA_ARGS__); break;     \
+        case 2: FN<DIM, 2>(__VA_ARGS__); break;     \
+        case 3: FN<DIM, 3>(__VA_ARGS__); break;     \
+        case 4: FN<DIM, 4>(__VA_ARGS__); break;     \
+        case 5: FN<DIM, 5>(__VA_ARGS__); break;     \
+        case 6: FN<DIM, 6>(__VA_ARGS__); break;     \
+        case 7: FN<DIM, 7>(__VA_ARGS__); break;     \
+        default: FN<DIM, 8>(__VA_ARGS__); break;    \
+    }
+
+void launch_stiffness_dp(int dim, int p, const DevPatch* dp, const int4* rb, int nrb, const double* A,
+                         const double* x, double* y, const int64_t* bp, const int* br, const double* bs,
+                         const double* t, hipStream_t s) {
+    if (nrb == 0) return;
+    if (dim == 3) {
+        AFIETI_DISPATCH_P(3, stiffness_t, dp, rb, nrb, A, x, y, bp, br, bs, t, s)
+    } else {
+        AFIETI_DISPATCH_P(2, stiffness_t, dp, rb, nrb, A, x, y, bp, br, bs, t, s)
+    }
+}
+
+void launch_ahat_dp(int dim, int p, const DevPatch* dp, const int4* rb, int nrb, const double* kb, const double* mb,
+                    const double* x, double* y, int use_h, hipStream_t s) {
+    if (nrb == 0) return;
+    if (dim == 3) {
+        AFIETI_DISPATCH_P(3, ahat_t, dp, rb, nrb, kb, mb, x, y, use_h, s)
+    } else {
+        AFIETI_DISPATCH_P(2, ahat_t, dp, rb, nrb, kb, mb, x, y, use_h, s)
+    }
+}
+
+void launch_mask_interior(const DevPatch* dp, const int4* rb, int nrb, double* y, hipStream_t s) {
+    if (nrb) hipLaunchKernelGGL(k_mask_interior, dim3(nrb), dim3(kBlock), 0, s, dp, rb, y);
+}
+
+void launch_B(const int64_t* plus, const int64_t* minus, int64_t n_c, double alpha, const double* x, double* y,
+              hipStream_t s) {
+    if (n_c) hipLaunchKernelGGL(k_B, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, plus, minus, n_c, alpha, x, y);
+}
+
+void launch_Bt(const int64_t* bt_ptr, const int* bt_row, const double* bt_sign, int64_t n_dof, const double* x,
+               double* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_Bt, dim3(blocks_for(n_dof)), dim3(kBlock), 0, s, bt_ptr, bt_row, bt_sign, n_dof, x, y);
+}
+
+void launch_W(const int* bs, const int* bn, const int* bd, int64_t n_c, const double* y, double* z, hipStream_t s) {
+    if (n_c) hipLaunchKernelGGL(k_W, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, bs, bn, bd, n_c, y, z);
+}
+
+void launch_rigid_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks, const double* ctrl, const double* x,
+                          double* partials, hipStream_t s) {
+    if (n_chunks) hipLaunchKernelGGL(k_rigid_partial, dim3(n_chunks), dim3(kBlock), 0, s, dp, chunks, ctrl, x, partials);
+}
+
+void launch_gamma_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks, const double* ctrl,
+                          const int64_t* gam_dof, const int64_t* bt_ptr, const int* bt_row, const double* bt_sign,
+                          const double* y, double* partials, hipStream_t s) {
+    if (n_chunks)
+        hipLaunchKernelGGL(k_gamma_partial, dim3(n_chunks), dim3(kBlock), 0, s, dp, chunks, ctrl, gam_dof, bt_ptr,
+                           bt_row, bt_sign, y, partials);
+}
+
+void launch_rigid_finalize(const int* cptr, int n_patches, const double* partials, const double* RtR_inv,
+                           double* coef, hipStream_t s) {
+    hipLaunchKernelGGL(k_rigid_finalize, dim3(n_patches), dim3(64), 0, s, cptr, partials, RtR_inv, coef);
+}
+
+void launch_coarse_finalize(const int* p0, const int* np, const int* nm, const int64_t* coff, int n_probs,
+                            const int* cptr, const double* partials, const double* Cinv, double* zc, int max_nc,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_coarse_finalize, dim3(n_probs), dim3(kBlock), max_nc * sizeof(double), s, p0, np, nm, coff,
+                       cptr, partials, Cinv, zc);
+}
+
+void launch_rigid_update(const DevPatch* dp, const Chunk* chunks, int n_chunks, const double* ctrl, const double* coef,
+                         const double* x, double* y, hipStream_t s) {
+    if (n_chunks) hipLaunchKernelGGL(k_rigid_update, dim3(n_chunks), dim3(kBlock), 0, s, dp, chunks, ctrl, coef, x, y);
+}
+
+void launch_G_apply(const int* pp, const int* pm, const double* gp, const double* gm, int64_t n_c, const double* zc,
+                    double alpha, double beta, const double* x, double* y, hipStream_t s) {
+    if (n_c)
+        hipLaunchKernelGGL(k_G_apply, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, pp, pm, gp, gm, n_c, zc, alpha, beta, x, y);
+}
+
+void launch_copy(const double* x, double* y, int64_t n, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_copy, dim3(blocks_for(n)), dim3(kBlock), 0, s, x, y, n);
+}
+void launch_fill(double* y, double v, int64_t n, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, y, v, n);
+}
+void launch_axpby(double a, const double* x, double b, const double* y, double* z, int64_t n, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, x, b, y, z, n);
+}
+void launch_dot_partial(const Chunk* chunks, int n_chunks, const double* x, const double* y, double* partials,
+                        hipStream_t s) {
+    if (n_chunks) hipLaunchKernelGGL(k_dot_partial, dim3(n_chunks), dim3(kBlock), 0, s, chunks, x, y, partials);
+}
+void launch_minres_init(MinresState* st, const int* cptr, int n, const double* part, double tol, int maxit,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_minres_init, dim3(blocks_for(n, 64)), dim3(64), 0, s, st, cptr, n, part, tol, maxit);
+}
+void launch_minres_delta(MinresState* st, const int* cptr, int n, const double* part, hipStream_t s) {
+    hipLaunchKernelGGL(k_minres_delta, dim3(blocks_for(n, 64)), dim3(64), 0, s, st, cptr, n, part);
+}
+void launch_minres_givens(MinresState* st, const int* cptr, int n, const double* part, hipStream_t s) {
+    hipLaunchKernelGGL(k_minres_givens, dim3(blocks_for(n, 64)), dim3(64), 0, s, st, cptr, n, part);
+}
+void launch_minres_v(const MinresState* st, const Chunk* chunks, int n_chunks, const double* q, const double* v,
+                     const double* v_old, double* v_new, hipStream_t s) {
+    if (n_chunks) hipLaunchKernelGGL(k_minres_v, dim3(n_chunks), dim3(kBlock), 0, s, st, chunks, q, v, v_old, v_new);
+}
+void launch_minres_dx(const MinresState* st, const Chunk* chunks, int n_chunks, const double* z, const double* d_old,
+                      const double* d, double* d_new, double* x, hipStream_t s) {
+    if (n_chunks) hipLaunchKernelGGL(k_minres_dx, dim3(n_chunks), dim3(kBlock), 0, s, st, chunks, z, d_old, d, d_new, x);
+}
+
+}  // namespace afieti

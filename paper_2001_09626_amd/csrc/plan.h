@@ -1,0 +1,97 @@
+// Host-side setup of the inexact AF-IETI solver: everything that is built
+// once per problem in FP64 on the CPU (spline data, univariate pencils and
+// their eigendecompositions, node matching, the jump matrix B, rigid modes,
+// the coarse factorisation and the index tables the device kernels read).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "afieti.h"
+
+namespace afieti {
+
+struct SetupError {
+    int code;
+    std::string msg;
+};
+
+// Univariate spline data of one parametric direction of one patch.
+struct Dir1D {
+    int n = 1;                    // number of B-splines m_l
+    int n_el = 0;                 // elements (non-empty spans)
+    int p = 0;
+    std::vector<double> knots;
+    // composite Gauss rule, p+1 points per element
+    int nq = 0;
+    std::vector<double> qx, qw;
+    std::vector<int> qfirst;      // first nonzero basis index at each point
+    std::vector<double> qval, qder;  // [q][t], t = 0..p (basis qfirst+t)
+    std::vector<int> el_first, el_last;  // elements in the support of basis i
+    // univariate matrices (dense n x n, row major)
+    std::vector<double> K, M;
+    // generalised eigendecompositions: U^T M U = I, U^T K U = diag(D)
+    std::vector<double> U, D;     // full pencil, U[i*n + a]
+    std::vector<double> Ui, Di;   // interior pencil (n-2)
+};
+
+struct PatchPlan {
+    int prob = 0;                 // problem index
+    int dim = 3;
+    int p = 1, reg = 0;
+    Dir1D dir[3];                 // 2D: dir[2] is a dummy of size 1
+    int n[3] = {1, 1, 1};         // basis counts, n[2] = 1 in 2D
+    int64_t nodes = 0;            // n1*n2*n3
+    int64_t dof_off = 0;          // global DOF offset of the patch
+    double lam = 1, mu = 1, H = 1, hscale = 1;  // hscale = H^{d-2}
+    double corners[24] = {0};
+    int bc[6] = {0};
+    std::vector<double> ctrl;     // [node][3] control points (z = 0 in 2D)
+};
+
+struct ProblemPlan {
+    int dim = 3;
+    int patch0 = 0, n_patches = 0;
+    int64_t dof_off = 0, n_dof = 0;
+    int64_t c_off = 0, n_c = 0;
+    int n_modes = 6;              // rigid modes per patch (3 in 2D)
+    std::vector<double> Cinv;     // (G^T G)^{-1}, dense (n_modes*N_p)^2
+    std::vector<double> CtC;      // G^T G (for export)
+    std::vector<afieti_load_mode> load;
+};
+
+struct Plan {
+    std::vector<PatchPlan> patches;
+    std::vector<ProblemPlan> probs;
+    int64_t n_dof = 0, n_c = 0;
+    // constraints (global rows): B row r = e_{plus[r]} - e_{minus[r]}
+    // (minus = -1 for a Dirichlet row, whose entry is +1 on plus)
+    std::vector<int64_t> c_plus, c_minus;
+    std::vector<int> c_blk_start, c_blk_size, c_blk_dir;  // node block of B B^T
+    // B^T by DOF: CSR over all DOFs, entries (row, sign)
+    std::vector<int64_t> bt_ptr;
+    std::vector<int> bt_row;
+    std::vector<double> bt_sign;
+    // Gamma DOFs per patch (sorted), for G^T y = R^T (B^T y)
+    std::vector<int64_t> gam_dof;
+    std::vector<int64_t> gam_ptr;   // per patch start in gam_dof
+    // rigid-mode values of G rows: G[r][m] for plus and minus copies
+    std::vector<double> g_plus, g_minus;  // [r][6]
+    std::vector<int> c_patch_plus, c_patch_minus;  // patch of each copy (-1)
+    // (R^(k)T R^(k))^{-1} per patch, [k][6][6]
+    std::vector<double> RtR_inv;
+};
+
+// Build the host plan.  Throws SetupError.
+Plan build_plan(const afieti_problem* probs, int n_problems);
+
+// Helpers exposed for testing.
+std::vector<double> open_uniform_knots(int n_el, int p, int reg);
+void bspline_eval(const std::vector<double>& knots, int p, double x, int& first,
+                  double* val, double* der);
+void gauss_legendre(int n, double* x, double* w);
+int sym_gen_eig(int n, const double* K, const double* M, double* U, double* D);
+double rigid_mode(int dim, int m, int c, const double* X);
+
+}  // namespace afieti
