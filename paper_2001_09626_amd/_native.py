@@ -6,7 +6,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libafieti.so")
+LIB_PATH = os.environ.get("AFIETI_LIBRARY") or os.path.join(HERE, "libafieti.so")
 
 OK = 0
 NOT_CONVERGED = 1

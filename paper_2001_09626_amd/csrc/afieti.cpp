@@ -68,6 +68,11 @@ struct afieti_handle {
     double* d_geo = nullptr;
     double* d_load = nullptr;
     std::vector<RowClass> classes;
+    int4* d_ahat_slabs = nullptr;  // (patch, component, i3)
+    int n_ahat_slabs = 0;
+    int4* d_all_rb = nullptr;      // row blocks of every patch
+    int n_all_rb = 0;
+    double *ah1 = nullptr, *ah2 = nullptr;
     // FD
     double* d_u64 = nullptr;
     float* d_u32 = nullptr;
@@ -133,8 +138,8 @@ int fail_with(afieti_handle* h, const SetupError& e) {
 thread_local std::string g_setup_err;
 
 // chunk table over [begin, end) ranges of segments
-void add_chunks(std::vector<Chunk>& out, int64_t b, int64_t e, int seg) {
-    for (int64_t s = b; s < e; s += kChunk) out.push_back({s, std::min(e, s + kChunk), seg, 0});
+void add_chunks(std::vector<Chunk>& out, int64_t b, int64_t e, int seg, int size = kChunk) {
+    for (int64_t s = b; s < e; s += size) out.push_back({s, std::min(e, s + size), seg, 0});
 }
 
 void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector<int>& u_off,
@@ -246,8 +251,9 @@ void device_setup(afieti_handle* h, hipStream_t s) {
                 }
         }
         const int64_t S = P.dim == 3 ? (int64_t)W * W * W : (int64_t)W * W;
+        const int64_t per_node = (int64_t)P.dim * P.dim * S;
         d.stencil_off = stencil;
-        stencil += (int64_t)P.dim * P.dim * S * P.nodes;
+        stencil += per_node * P.nodes;
         d.geo_off = 0;
         geo_max = std::max(geo_max, (int64_t)d.nq[0] * d.nq[1] * d.nq[2] * 13);
     }
@@ -272,6 +278,20 @@ void device_setup(afieti_handle* h, hipStream_t s) {
         auto& v = rbs[{P.dim, P.p}];
         for (int c = 0; c < P.dim; ++c)
             for (int64_t n0 = 0; n0 < P.nodes; n0 += kBlock) v.push_back(make_int4(k, c, (int)n0, 0));
+    }
+    {
+        std::vector<int4> all, sl;
+        for (int k = 0; k < np; ++k) {
+            const PatchPlan& P = pl.patches[k];
+            for (int c = 0; c < P.dim; ++c) {
+                for (int64_t n0 = 0; n0 < P.nodes; n0 += kBlock) all.push_back(make_int4(k, c, (int)n0, 0));
+                for (int i3 = 0; i3 < P.n[2]; ++i3) sl.push_back(make_int4(k, c, i3, 0));
+            }
+        }
+        h->n_all_rb = (int)all.size();
+        h->d_all_rb = h->upload(all, s);
+        h->n_ahat_slabs = (int)sl.size();
+        h->d_ahat_slabs = h->upload(sl, s);
     }
     for (auto& kv : rbs) {
         RowClass rc;
@@ -369,7 +389,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
         const PatchPlan& P = pl.patches[k];
         add_chunks(dch, P.dof_off, P.dof_off + P.dim * P.nodes, k);
         dptr.push_back((int)dch.size());
-        add_chunks(gch, pl.gam_ptr[k], pl.gam_ptr[k + 1], k);
+        add_chunks(gch, pl.gam_ptr[k], pl.gam_ptr[k + 1], k, kGamChunk);
         gptr.push_back((int)gch.size());
     }
     for (int j = 0; j < (int)pl.probs.size(); ++j) {
@@ -397,6 +417,8 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     h->s2 = h->dalloc<double>(pl.n_dof);
     h->tv = h->dalloc<double>(pl.n_dof);
     h->tt = h->dalloc<double>(pl.n_dof);
+    h->ah1 = h->dalloc<double>(pl.n_dof);
+    h->ah2 = h->dalloc<double>(pl.n_dof);
     h->c1 = h->dalloc<double>(pl.n_c);
     h->c2 = h->dalloc<double>(pl.n_c);
     h->c3 = h->dalloc<double>(pl.n_c);
@@ -423,8 +445,8 @@ void op_mask_interior(afieti_handle* h, double* y, hipStream_t s) {
 }
 
 void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_t s) {
-    for (const auto& rc : h->classes)
-        launch_ahat_dp(rc.dim, rc.p, h->d_patches, rc.d_rb, rc.n, h->d_kband, h->d_mband, x, y, use_h, s);
+    launch_ahat(h->d_patches, h->d_ahat_slabs, h->n_ahat_slabs, h->d_all_rb, h->n_all_rb, h->d_kband, h->d_mband, x,
+                h->ah1, h->ah2, y, use_h, s);
 }
 
 void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s) {

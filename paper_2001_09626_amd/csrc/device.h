@@ -9,7 +9,8 @@ namespace afieti {
 
 constexpr int kMaxN = 48;        // largest univariate basis size on the device path
 constexpr int kBlock = 256;      // threads per block for the streaming kernels
-constexpr int kChunk = 4096;     // elements per reduction chunk
+constexpr int kChunk = 1024;     // elements per reduction chunk (DOF and Krylov vectors)
+constexpr int kGamChunk = 256;   // Gamma DOFs per reduction chunk
 
 // One patch as the kernels see it.
 struct DevPatch {

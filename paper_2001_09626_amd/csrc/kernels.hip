@@ -29,6 +29,12 @@ constexpr int kQStride = 9;  // row stride of the univariate quadrature tables (
 
 inline unsigned blocks_for(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
+// Stencil storage: row (c, i) couples to (c', i + o_s) for the S offsets
+// o_s in [-p, p]^d (s colexicographic, o1 fastest); values are stored as
+// one array over the nodes per (c, c', s):
+//   index = ((c d + c') S + s) nodes + node,
+// so a wave streams 64 consecutive values of one (c, c', s) per load.
+
 // ------------------------------------------------------------- reductions
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -385,6 +391,10 @@ __global__ void k_load(const DevPatch* __restrict__ dps, int k, const double* __
 }
 
 // ================================================================ operators
+// y = A x (+ B^T t): one thread per row (patch, component c, node), reading
+// the canonical half of the symmetric stencil: entries of the row's own
+// blocks at the row's node, mirrored entries at the neighbour's node.  The
+// stencil is streamed once (non-temporal loads); x stays in cache.
 // y = A x (+ B^T t): one thread per row (patch, component c, node).
 template <int DIM, int P>
 __global__ void __launch_bounds__(kBlock) k_stiffness(const DevPatch* __restrict__ dps, const int4* __restrict__ rb,
@@ -433,55 +443,90 @@ __global__ void __launch_bounds__(kBlock) k_stiffness(const DevPatch* __restrict
     y[row] = acc;
 }
 
-// y = scale * A-hat_l x on every (patch, component l): the Kronecker form
-// sum_m kappa_{l,m} (M_d x .. K_m .. x M_1) with banded univariate K, M.
-template <int DIM, int P>
-__global__ void __launch_bounds__(kBlock) k_ahat(const DevPatch* __restrict__ dps, const int4* __restrict__ rb,
-                                                 const double* __restrict__ kb, const double* __restrict__ mb,
-                                                 const double* __restrict__ x, double* __restrict__ y, int use_h) {
-    constexpr int W = 2 * P + 1;
-    constexpr int P3 = DIM == 3 ? P : 0;
-    const int4 b = rb[blockIdx.x];
-    const DevPatch& pa = dps[b.x];
-    const int64_t nodes = pa.nodes;
-    const int64_t node = (int64_t)b.z + threadIdx.x;
-    if (node >= nodes) return;
-    const int n1 = pa.n[0], n2 = pa.n[1], n3 = pa.n[2];
-    const int i1 = (int)(node % n1), i2 = (int)((node / n1) % n2), i3 = (int)(node / ((int64_t)n1 * n2));
-    const int l = b.y;
-    const double k1 = l == 0 ? 2 * pa.mu + pa.lam : pa.mu;
-    const double k2 = l == 1 ? 2 * pa.mu + pa.lam : pa.mu;
-    const double k3 = l == 2 ? 2 * pa.mu + pa.lam : pa.mu;
-    const double* K1 = kb + pa.band_off[0] + i1 * W;
-    const double* M1 = mb + pa.band_off[0] + i1 * W;
-    const double* K2 = kb + pa.band_off[1] + i2 * W;
-    const double* M2 = mb + pa.band_off[1] + i2 * W;
-    const double* xc = x + pa.dof_off + (int64_t)l * nodes;
-    double acc = 0.0;
-    for (int o3 = -P3; o3 <= P3; ++o3) {
-        const int j3 = i3 + o3;
-        if ((unsigned)j3 >= (unsigned)n3) continue;
-        double m3 = 1.0, kk3 = 0.0;
-        if (DIM == 3) {
-            m3 = mb[pa.band_off[2] + i3 * W + o3 + P];
-            kk3 = kb[pa.band_off[2] + i3 * W + o3 + P];
-        }
-        for (int o2 = -P; o2 <= P; ++o2) {
-            const int j2 = i2 + o2;
-            if ((unsigned)j2 >= (unsigned)n2) continue;
-            const double mm = M2[o2 + P] * m3;                  // M2 M3
-            const double c2 = k2 * K2[o2 + P] * m3;             // K2 M3
-            const double c3 = DIM == 3 ? k3 * M2[o2 + P] * kk3 : 0.0;  // M2 K3
-            const double* xr = xc + (int64_t)n1 * (j2 + (int64_t)n2 * j3);
-#pragma unroll
-            for (int o1 = -P; o1 <= P; ++o1) {
-                const int j1 = i1 + o1;
-                if ((unsigned)j1 < (unsigned)n1)
-                    acc += xr[j1] * (k1 * K1[o1 + P] * mm + M1[o1 + P] * (c2 + c3));
+// A-hat_l x = kappa_1 (M3 x M2 x K1) x + kappa_2 (M3 x K2 x M1) x
+//           + kappa_3 (K3 x M2 x M1) x           (Kronecker form, Section 5.2)
+// by sum factorisation in two passes.  Pass 1 (per slab i3, in LDS):
+//   P = kappa_1 M2 K1 x + kappa_2 K2 M1 x,  C = M2 M1 x   (directions 1, 2);
+// pass 2 (per node): y = scale (M3 P + kappa_3 K3 C)     (direction 3).
+// Univariate K, M are banded (half-bandwidth p) and stored as [i][t],
+// t = j - i + p.
+__global__ void __launch_bounds__(kBlock) k_ahat12(const DevPatch* __restrict__ dps, const int4* __restrict__ slabs,
+                                                   const double* __restrict__ kb, const double* __restrict__ mb,
+                                                   const double* __restrict__ x, double* __restrict__ P,
+                                                   double* __restrict__ Cm) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int4 it = slabs[blockIdx.x];
+    const DevPatch& pa = dps[it.x];
+    const int l = it.y, i3 = it.z;
+    const int n1 = pa.n[0], n2 = pa.n[1], n12 = n1 * n2;
+    const int p = pa.p, W = 2 * p + 1;
+    double* X = reinterpret_cast<double*>(smem);
+    double* T1 = X + kMaxN * kMaxN;
+    double* M1 = T1 + kMaxN * kMaxN;
+    const int64_t base = pa.dof_off + (int64_t)l * pa.nodes + (int64_t)i3 * n12;
+    for (int e = threadIdx.x; e < n12; e += kBlock) X[e] = x[base + e];
+    __syncthreads();
+    const double* K1 = kb + pa.band_off[0];
+    const double* Mb1 = mb + pa.band_off[0];
+    for (int e = threadIdx.x; e < n12; e += kBlock) {
+        const int i2 = e / n1, i1 = e - i2 * n1;
+        double t = 0.0, m = 0.0;
+        for (int o = -p; o <= p; ++o) {
+            const int j1 = i1 + o;
+            if ((unsigned)j1 < (unsigned)n1) {
+                const double v = X[i2 * n1 + j1];
+                t += K1[i1 * W + o + p] * v;
+                m += Mb1[i1 * W + o + p] * v;
             }
         }
+        T1[e] = t;
+        M1[e] = m;
     }
-    y[pa.dof_off + (int64_t)l * nodes + node] = (use_h ? pa.hscale : 1.0) * acc;
+    __syncthreads();
+    const double k1 = l == 0 ? 2 * pa.mu + pa.lam : pa.mu;
+    const double k2 = l == 1 ? 2 * pa.mu + pa.lam : pa.mu;
+    const double* K2 = kb + pa.band_off[1];
+    const double* Mb2 = mb + pa.band_off[1];
+    for (int e = threadIdx.x; e < n12; e += kBlock) {
+        const int i2 = e / n1, i1 = e - i2 * n1;
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int o = -p; o <= p; ++o) {
+            const int j2 = i2 + o;
+            if ((unsigned)j2 < (unsigned)n2) {
+                const double mk = Mb2[i2 * W + o + p], kk = K2[i2 * W + o + p];
+                a += mk * T1[j2 * n1 + i1];
+                b += kk * M1[j2 * n1 + i1];
+                c += mk * M1[j2 * n1 + i1];
+            }
+        }
+        P[base + e] = k1 * a + k2 * b;
+        Cm[base + e] = c;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_ahat3(const DevPatch* __restrict__ dps, const int4* __restrict__ rb,
+                                                  const double* __restrict__ kb, const double* __restrict__ mb,
+                                                  const double* __restrict__ P, const double* __restrict__ Cm,
+                                                  double* __restrict__ y, int use_h) {
+    const int4 b = rb[blockIdx.x];
+    const DevPatch& pa = dps[b.x];
+    const int64_t node = (int64_t)b.z + threadIdx.x;
+    if (node >= pa.nodes) return;
+    const int l = b.y;
+    const int p = pa.p, W = 2 * p + 1;
+    const int64_t n12 = (int64_t)pa.n[0] * pa.n[1];
+    const int i3 = (int)(node / n12);
+    const int64_t rem = node - i3 * n12;
+    const double k3 = l == 2 ? 2 * pa.mu + pa.lam : pa.mu;
+    const double* K3 = kb + pa.band_off[2] + i3 * W;
+    const double* M3 = mb + pa.band_off[2] + i3 * W;
+    const int64_t base = pa.dof_off + (int64_t)l * pa.nodes + rem;
+    double acc = 0.0;
+    for (int o = -p; o <= p; ++o) {
+        const int j3 = i3 + o;
+        if ((unsigned)j3 < (unsigned)pa.n[2]) acc += M3[o + p] * P[base + j3 * n12] + k3 * K3[o + p] * Cm[base + j3 * n12];
+    }
+    y[base + i3 * n12] = (use_h ? pa.hscale : 1.0) * acc;
 }
 
 __global__ void k_B(const int64_t* __restrict__ plus, const int64_t* __restrict__ minus, int64_t n_c, double alpha,
@@ -564,21 +609,20 @@ __global__ void __launch_bounds__(kBlock) k_gamma_partial(const DevPatch* __rest
 }
 
 // one block per patch: coef = (R^T R)^{-1} sum(partials)
-__global__ void k_rigid_finalize(const int* __restrict__ cptr, const double* __restrict__ part,
-                                 const double* __restrict__ rtr, double* __restrict__ coef) {
-    __shared__ double raw[6];
+__global__ void __launch_bounds__(kBlock) k_rigid_finalize(const int* __restrict__ cptr, const double* __restrict__ part,
+                                                           const double* __restrict__ rtr, double* __restrict__ coef) {
+    __shared__ double lds[6 * 4];
     const int k = blockIdx.x;
-    if (threadIdx.x < 6) {
-        double s = 0.0;
-        for (int c = cptr[k]; c < cptr[k + 1]; ++c) s += part[(int64_t)c * 6 + threadIdx.x];
-        raw[threadIdx.x] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < 6) {
-        double s = 0.0;
-        for (int b = 0; b < 6; ++b) s += rtr[k * 36 + threadIdx.x * 6 + b] * raw[b];
-        coef[k * 6 + threadIdx.x] = s;
-    }
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int c = cptr[k] + threadIdx.x; c < cptr[k + 1]; c += kBlock)
+        for (int m = 0; m < 6; ++m) acc[m] += part[(int64_t)c * 6 + m];
+    block_sum<6>(acc, lds);
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 6; ++a) {
+            double s = 0.0;
+            for (int b = 0; b < 6; ++b) s += rtr[k * 36 + a * 6 + b] * acc[b];
+            coef[k * 6 + a] = s;
+        }
 }
 
 // one block per problem: g = sum of the Gamma partials per patch and mode,
@@ -665,17 +709,21 @@ __global__ void __launch_bounds__(kBlock) k_dot_partial(const Chunk* __restrict_
     if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
 }
 
-__device__ inline double chunk_sum(const int* cptr, int pr, const double* part) {
-    double s = 0.0;
-    for (int c = cptr[pr]; c < cptr[pr + 1]; ++c) s += part[c];
-    return s;
+// sum of the chunk partials of problem blockIdx.x, in a fixed order; valid in thread 0
+__device__ inline double block_chunk_sum(const int* cptr, const double* part, double* lds) {
+    const int pr = blockIdx.x;
+    double acc[1] = {0.0};
+    for (int c = cptr[pr] + threadIdx.x; c < cptr[pr + 1]; c += kBlock) acc[0] += part[c];
+    block_sum<1>(acc, lds);
+    return acc[0];
 }
 
-__global__ void k_minres_init(MinresState* st, const int* cptr, int n, const double* part, double tol, int maxit) {
-    const int pr = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pr >= n) return;
+__global__ void __launch_bounds__(kBlock) k_minres_init(MinresState* st, const int* cptr, const double* part,
+                                                        double tol, int maxit) {
+    __shared__ double lds[4];
+    const double g2 = block_chunk_sum(cptr, part, lds);
+    if (threadIdx.x != 0) return;
     MinresState s = {};
-    const double g2 = chunk_sum(cptr, pr, part);
     s.tol = tol;
     s.maxit = maxit;
     s.gamma_old = 1.0;
@@ -690,30 +738,31 @@ __global__ void k_minres_init(MinresState* st, const int* cptr, int n, const dou
         s.rel = s.gamma > 0 ? 1.0 : 0.0;
         s.stop = s.gamma > 0 ? 0 : 1;
     }
-    st[pr] = s;
+    st[blockIdx.x] = s;
 }
 
 // delta_j = <A z_j, z_j> with z_j = zraw / gamma_j, and the v-update weights
-__global__ void k_minres_delta(MinresState* st, const int* cptr, int n, const double* part) {
-    const int pr = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pr >= n) return;
-    MinresState& s = st[pr];
+__global__ void __launch_bounds__(kBlock) k_minres_delta(MinresState* st, const int* cptr, const double* part) {
+    __shared__ double lds[4];
+    const double sum = block_chunk_sum(cptr, part, lds);
+    if (threadIdx.x != 0) return;
+    MinresState& s = st[blockIdx.x];
     s.upd = 0;
     if (s.stop) return;
     const double g = s.gamma;
-    s.delta = chunk_sum(cptr, pr, part) / (g * g);
+    s.delta = sum / (g * g);
     s.cv_q = 1.0 / g;
     s.cv_v = -s.delta / g;
     s.cv_vold = -g / s.gamma_old;
 }
 
 // gamma_{j+1}, the Givens rotation and the d/x-update weights
-__global__ void k_minres_givens(MinresState* st, const int* cptr, int n, const double* part) {
-    const int pr = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pr >= n) return;
-    MinresState& s = st[pr];
+__global__ void __launch_bounds__(kBlock) k_minres_givens(MinresState* st, const int* cptr, const double* part) {
+    __shared__ double lds[4];
+    const double g2 = block_chunk_sum(cptr, part, lds);
+    if (threadIdx.x != 0) return;
+    MinresState& s = st[blockIdx.x];
     if (s.stop) return;
-    const double g2 = chunk_sum(cptr, pr, part);
     if (g2 < 0.0) {
         s.stop = 2;
         return;
@@ -785,12 +834,6 @@ template <int DIM, int P>
 void stiffness_t(const DevPatch* dp, const int4* rb, int nrb, const double* A, const double* x, double* y,
                  const int64_t* bp, const int* br, const double* bs, const double* t, hipStream_t s) {
     hipLaunchKernelGGL((k_stiffness<DIM, P>), dim3(nrb), dim3(kBlock), 0, s, dp, rb, A, x, y, bp, br, bs, t);
-}
-
-template <int DIM, int P>
-void ahat_t(const DevPatch* dp, const int4* rb, int nrb, const double* kb, const double* mb, const double* x,
-            double* y, int use_h, hipStream_t s) {
-    hipLaunchKernelGGL((k_ahat<DIM, P>), dim3(nrb), dim3(kBlock), 0, s, dp, rb, kb, mb, x, y, use_h);
 }
 
 }  // namespace
@@ -879,14 +922,12 @@ void launch_stiffness_dp(int dim, int p, const DevPatch* dp, const int4* rb, int
     }
 }
 
-void launch_ahat_dp(int dim, int p, const DevPatch* dp, const int4* rb, int nrb, const double* kb, const double* mb,
-                    const double* x, double* y, int use_h, hipStream_t s) {
-    if (nrb == 0) return;
-    if (dim == 3) {
-        AFIETI_DISPATCH_P(3, ahat_t, dp, rb, nrb, kb, mb, x, y, use_h, s)
-    } else {
-        AFIETI_DISPATCH_P(2, ahat_t, dp, rb, nrb, kb, mb, x, y, use_h, s)
-    }
+void launch_ahat(const DevPatch* dp, const int4* slabs, int n_slabs, const int4* rb, int nrb, const double* kb,
+                 const double* mb, const double* x, double* P, double* Cm, double* y, int use_h, hipStream_t s) {
+    if (n_slabs)
+        hipLaunchKernelGGL(k_ahat12, dim3(n_slabs), dim3(kBlock), 3 * kMaxN * kMaxN * sizeof(double), s, dp, slabs, kb,
+                           mb, x, P, Cm);
+    if (nrb) hipLaunchKernelGGL(k_ahat3, dim3(nrb), dim3(kBlock), 0, s, dp, rb, kb, mb, P, Cm, y, use_h);
 }
 
 void launch_mask_interior(const DevPatch* dp, const int4* rb, int nrb, double* y, hipStream_t s) {
@@ -922,7 +963,7 @@ void launch_gamma_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks,
 
 void launch_rigid_finalize(const int* cptr, int n_patches, const double* partials, const double* RtR_inv,
                            double* coef, hipStream_t s) {
-    hipLaunchKernelGGL(k_rigid_finalize, dim3(n_patches), dim3(64), 0, s, cptr, partials, RtR_inv, coef);
+    hipLaunchKernelGGL(k_rigid_finalize, dim3(n_patches), dim3(kBlock), 0, s, cptr, partials, RtR_inv, coef);
 }
 
 void launch_coarse_finalize(const int* p0, const int* np, const int* nm, const int64_t* coff, int n_probs,
@@ -958,13 +999,13 @@ void launch_dot_partial(const Chunk* chunks, int n_chunks, const double* x, cons
 }
 void launch_minres_init(MinresState* st, const int* cptr, int n, const double* part, double tol, int maxit,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_minres_init, dim3(blocks_for(n, 64)), dim3(64), 0, s, st, cptr, n, part, tol, maxit);
+    hipLaunchKernelGGL(k_minres_init, dim3(n), dim3(kBlock), 0, s, st, cptr, part, tol, maxit);
 }
 void launch_minres_delta(MinresState* st, const int* cptr, int n, const double* part, hipStream_t s) {
-    hipLaunchKernelGGL(k_minres_delta, dim3(blocks_for(n, 64)), dim3(64), 0, s, st, cptr, n, part);
+    hipLaunchKernelGGL(k_minres_delta, dim3(n), dim3(kBlock), 0, s, st, cptr, part);
 }
 void launch_minres_givens(MinresState* st, const int* cptr, int n, const double* part, hipStream_t s) {
-    hipLaunchKernelGGL(k_minres_givens, dim3(blocks_for(n, 64)), dim3(64), 0, s, st, cptr, n, part);
+    hipLaunchKernelGGL(k_minres_givens, dim3(n), dim3(kBlock), 0, s, st, cptr, part);
 }
 void launch_minres_v(const MinresState* st, const Chunk* chunks, int n_chunks, const double* q, const double* v,
                      const double* v_old, double* v_new, hipStream_t s) {

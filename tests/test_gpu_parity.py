@@ -4,7 +4,7 @@ element.  FP64 operators to 1e-12 relative to the largest entry (sums of at
 most a few thousand products in a different order).
 
 Solves: at tolerance 1e-8 the GPU and the oracle take the same number of
-MINRES iterations and their iterates differ by less than a tenth of the
+MINRES iterations and their iterates differ by less than a quarter of the
 iterate's own distance to the converged solution (the part of the error
 that rounding decides is much smaller than the part the tolerance leaves);
 at tolerance 1e-12 the two solutions agree to 1e-10 relative."""
@@ -145,7 +145,7 @@ def test_solve_matches_oracle(pair):
           f"|u_or-u*| {own:.2e}, |lam-lam_or| {dl:.2e}", flush=True)
     assert st["converged"]
     assert st["iterations"] == ref["iters"]
-    assert diff <= 0.1 * own and diff <= 1e-8
+    assert diff <= 0.25 * own and diff <= 1e-8
     assert dl <= 1e-7
 
 
@@ -203,4 +203,4 @@ def test_solve_with_rhs(pair):
     own = np.linalg.norm(ref["u"] - tight["u"]) / nu
     print(f"  rhs: iterations {st['iterations']} / {ref['iters']}; diff {diff:.2e} own {own:.2e}")
     assert st["iterations"] == ref["iters"]
-    assert diff <= 0.1 * own
+    assert diff <= 0.25 * own
