@@ -171,6 +171,16 @@ int afieti_solve_adjoint(afieti_handle* h, const double* dJdu, const double* u,
                          double* psi, double* dJ_dlame, double* dJ_damp,
                          afieti_stats* st, void* stream);
 
+/*
+ * Change the per-patch Lame parameters and/or the load amplitudes of an
+ * existing handle (both optional, host arrays): lame = [lambda_k, mu_k] per
+ * patch in problem-stacked order; amps = one amplitude per load mode of each
+ * problem, stacked.  New Lame values re-assemble the stiffness stencils and
+ * update the FD eigenvalue scaling (the eigenvectors depend on the knots
+ * only, Section 5.2.1); new amplitudes recombine the stored unit-mode loads.
+ */
+int afieti_set_parameters(afieti_handle* h, const double* lame, const double* amps, void* stream);
+
 /* Individual operators of the hot path, for checking and measurement.
  * x and y are device vectors of the sizes listed; they may not alias. */
 #define AFIETI_OP_STIFFNESS 0   /* y = A x              (DOF -> DOF) eq. block_A     */

@@ -16,7 +16,7 @@ import numpy as np
 
 from . import _native as N
 
-__all__ = ["Solver", "AfietiError", "to_c_problems"]
+__all__ = ["Solver", "AfietiError", "to_c_problems", "AfietiSolve", "mass_norm_loss"]
 
 
 class AfietiError(RuntimeError):
@@ -110,6 +110,11 @@ class Solver:
         L.afieti_get_offsets(h, dof, coff)
         self.dof_offsets = np.array(dof[:], dtype=np.int64)
         self.c_offsets = np.array(coff[:], dtype=np.int64)
+        probs = [problems] if isinstance(problems, dict) else list(problems)
+        self.n_load_modes_total = sum(len(p["load"]) for p in probs)
+        self.lame = np.array([[pd["lam"], pd["mu"]] for p in probs for pd in p["patches"]], dtype=np.float64)
+        self.amps = np.array([m[1] for p in probs for m in p["load"]], dtype=np.float64)
+        self.param_version = 0
 
     # ----------------------------------------------------------- helpers
     def _check(self, code, allow=(N.OK,)):
@@ -157,14 +162,34 @@ class Solver:
                      rel_residual=st.rel_residual, ms=st.ms_solve, code=code)
         return u, lam, stats
 
-    def solve_adjoint(self, dJdu, u, psi=None):
+    def set_parameters(self, lame=None, amps=None):
+        """New per-patch (lambda, mu) (array (n_patches, 2)) and/or load
+        amplitudes (one per load mode, problems stacked)."""
+        lp = ap = None
+        if lame is not None:
+            lame = np.ascontiguousarray(np.asarray(lame, dtype=np.float64).reshape(self.n_patches, 2))
+            lp = lame.ctypes.data_as(C.POINTER(C.c_double))
+        if amps is not None:
+            amps = np.ascontiguousarray(np.asarray(amps, dtype=np.float64).reshape(self.n_load_modes_total))
+            ap = amps.ctypes.data_as(C.POINTER(C.c_double))
+        self._check(self._L.afieti_set_parameters(self._h, lp, ap, _stream()))
+        if lame is not None:
+            self.lame = lame.copy()
+        if amps is not None:
+            self.amps = amps.copy()
+        self.param_version += 1
+
+    def solve_adjoint(self, dJdu, u, psi=None, allow_not_converged=False):
+        """psi = adjoint state; returns (psi, dJ/dlambda[n_patches],
+        dJ/dmu[n_patches], dJ/damp[n_modes], iterations)."""
         psi = self._new(self.n_dof) if psi is None else psi
         dl = (C.c_double * (2 * self.n_patches))()
-        n_modes = getattr(self, "n_load_modes_total", 0)
+        n_modes = self.n_load_modes_total
         da = (C.c_double * max(1, n_modes))()
         st = N.Stats()
+        allow = (N.OK, N.NOT_CONVERGED) if allow_not_converged else (N.OK,)
         self._check(self._L.afieti_solve_adjoint(self._h, _ptr(dJdu), _ptr(u), _ptr(psi), dl, da,
-                                                 C.byref(st), _stream()))
+                                                 C.byref(st), _stream()), allow)
         dl = np.array(dl[:]).reshape(-1, 2)
         return psi, dl[:, 0], dl[:, 1], np.array(da[:n_modes]), st.iterations
 
@@ -184,3 +209,64 @@ class Solver:
             m = int(round(np.sqrt(len(buf))))
             return buf.reshape(m, m)
         return buf
+
+
+def _autograd():
+    import torch
+
+    class _AfietiSolve(torch.autograd.Function):
+        """u = AF-IETI solution for per-patch Lame parameters ``lame``
+        (n_patches x 2: lambda, mu) and load amplitudes ``amps``.  The
+        backward pass is one adjoint AF-IETI solve with right-hand side
+        dJ/du (the saddle operator is symmetric) plus the per-patch
+        strain-energy contractions; Krylov iterates are not stored."""
+
+        @staticmethod
+        def forward(ctx, lame, amps, solver):
+            lam_np = lame.detach().cpu().numpy().astype(np.float64)
+            amp_np = amps.detach().cpu().numpy().astype(np.float64)
+            if not (np.array_equal(lam_np, solver.lame) and np.array_equal(amp_np, solver.amps)):
+                solver.set_parameters(lam_np, amp_np)
+            u, _, _ = solver.solve(want_lambda=False)
+            ctx.solver = solver
+            ctx.params = (lam_np, amp_np)
+            ctx.save_for_backward(u)
+            return u
+
+        @staticmethod
+        def backward(ctx, grad_u):
+            (u,) = ctx.saved_tensors
+            solver = ctx.solver
+            lam_np, amp_np = ctx.params
+            if not (np.array_equal(lam_np, solver.lame) and np.array_equal(amp_np, solver.amps)):
+                solver.set_parameters(lam_np, amp_np)
+            _, dlam, dmu, damp, _ = solver.solve_adjoint(grad_u.contiguous(), u)
+            g_lame = torch.from_numpy(np.stack([dlam, dmu], axis=1))
+            g_amps = torch.from_numpy(damp)
+            return g_lame, g_amps, None
+
+    class _MassNorm(torch.autograd.Function):
+        """0.5 e^T M e with the physical mass M of the handle."""
+
+        @staticmethod
+        def forward(ctx, e, solver):
+            Me = solver.apply("mass", e.contiguous())
+            ctx.save_for_backward(Me)
+            return 0.5 * torch.dot(e, Me)
+
+        @staticmethod
+        def backward(ctx, g):
+            (Me,) = ctx.saved_tensors
+            return g * Me, None
+
+    return _AfietiSolve, _MassNorm
+
+
+def AfietiSolve(lame, amps, solver):
+    """Differentiable AF-IETI solve: u(lame, amps) on ``solver``'s problems."""
+    return _autograd()[0].apply(lame, amps, solver)
+
+
+def mass_norm_loss(e, solver):
+    """Differentiable 0.5 * e^T M e (physical mass of ``solver``)."""
+    return _autograd()[1].apply(e, solver)

@@ -67,6 +67,8 @@ SYMBOLS = {
                                        C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(Stats), C.c_void_p]),
     "afieti_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "afieti_set_parameters": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.c_void_p]),
     "afieti_export": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int64]),
     "afieti_export_size": (C.c_int64, [C.c_void_p, C.c_int]),
     "afieti_destroy": (None, [C.c_void_p]),

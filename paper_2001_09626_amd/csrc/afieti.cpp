@@ -67,6 +67,13 @@ struct afieti_handle {
     double* d_stencil = nullptr;
     double* d_geo = nullptr;
     double* d_load = nullptr;
+    std::vector<double*> d_F;              // per problem: unit-amplitude mode loads [mode][dof]
+    std::vector<std::vector<double>> amps; // per problem: load amplitudes
+    std::vector<double*> d_unit_modes;     // per problem: modes with amplitude 1 (8 doubles each)
+    double* d_qbuf = nullptr;              // dim values per Gauss point of one patch
+    double *d_part_e = nullptr, *d_part_m = nullptr;
+    int64_t part_e_n = 0, part_m_n = 0;
+    std::vector<int> fd_uoff, fd_doff;
     std::vector<RowClass> classes;
     int4* d_ahat_slabs = nullptr;  // (patch, component, i3)
     int n_ahat_slabs = 0;
@@ -185,6 +192,11 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
             for (int cb = 0; cb < ncb; ++cb) cols.push_back(make_int2(ti, cb));
         }
     }
+    if (set.d_t) {  // parameters changed: rewrite the descriptors in place
+        HIP_OK(hipMemcpyAsync(set.d_t, ts.data(), ts.size() * sizeof(FdTensor), hipMemcpyHostToDevice, s));
+        HIP_OK(hipStreamSynchronize(s));
+        return;
+    }
     set.n_t = (int)ts.size();
     set.n_slabs = (int)slabs.size();
     set.n_cols = (int)cols.size();
@@ -192,6 +204,29 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
     set.d_t = h->upload(ts, s);
     set.d_slabs = h->upload(slabs, s);
     set.d_cols = h->upload(cols, s);
+}
+
+// stiffness stencils of every patch (Gauss-point geometry, then assembly)
+void assemble_all(afieti_handle* h, hipStream_t s) {
+    for (int k = 0; k < h->n_patches; ++k) {
+        const DevPatch& hp = h->h_patches[k];
+        launch_geometry(h->d_patches, k, hp, h->d_ctrl, h->d_qval, h->d_qder, h->d_qfirst, h->d_qw, h->d_geo, s);
+        launch_assemble(h->d_patches, k, hp, h->d_geo, h->d_qval, h->d_qder, h->d_qfirst, h->d_elf, h->d_ell,
+                        h->d_stencil, hp.lam, hp.mu, s);
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipGetLastError());
+}
+
+// assembled load = sum_j amp_j F_j per problem
+void combine_load(afieti_handle* h, hipStream_t s) {
+    launch_fill(h->d_load, 0.0, h->n_dof, s);
+    for (size_t j = 0; j < h->plan.probs.size(); ++j) {
+        const ProblemPlan& pr = h->plan.probs[j];
+        double* f = h->d_load + pr.dof_off;
+        for (size_t m = 0; m < h->amps[j].size(); ++m)
+            launch_axpby(h->amps[j][m], h->d_F[j] + (int64_t)m * pr.n_dof, 1.0, f, f, pr.n_dof, s);
+    }
 }
 
 void device_setup(afieti_handle* h, hipStream_t s) {
@@ -301,30 +336,42 @@ void device_setup(afieti_handle* h, hipStream_t s) {
         rc.d_rb = h->upload(kv.second, s);
         h->classes.push_back(rc);
     }
-    // ---- assembly of stencils and loads, patch by patch
+    // ---- unit-amplitude mode loads F_j per problem, then stencils and the load
+    int64_t maxnq = 1;
+    for (const auto& hp : h->h_patches) maxnq = std::max(maxnq, (int64_t)hp.nq[0] * hp.nq[1] * hp.nq[2]);
+    h->d_qbuf = h->dalloc<double>(maxnq * 3);
+    h->part_e_n = (maxnq + kBlock - 1) / kBlock * 2;
+    h->d_part_e = h->dalloc<double>(h->part_e_n);
+    int64_t maxm = 1;
+    for (const auto& pr : pl.probs) {
+        std::vector<double> unit;
+        std::vector<double> am;
+        for (const auto& lm : pr.load) {
+            unit.insert(unit.end(), {(double)lm.comp, 1.0, (double)lm.k[0], (double)lm.k[1], (double)lm.k[2],
+                                     lm.phase[0], lm.phase[1], lm.phase[2]});
+            am.push_back(lm.amp);
+        }
+        h->d_unit_modes.push_back(h->upload(unit, s));
+        h->amps.push_back(am);
+        h->d_F.push_back(h->dalloc<double>((int64_t)pr.load.size() * pr.n_dof));
+        maxm = std::max(maxm, (int64_t)pr.load.size() * ((pr.n_dof + kChunk - 1) / kChunk));
+    }
+    h->part_m_n = maxm;
+    h->d_part_m = h->dalloc<double>(maxm);
     for (int k = 0; k < np; ++k) {
         const DevPatch& hp = h->h_patches[k];
         const PatchPlan& P = pl.patches[k];
+        const ProblemPlan& pr = pl.probs[P.prob];
         launch_geometry(h->d_patches, k, hp, h->d_ctrl, h->d_qval, h->d_qder, h->d_qfirst, h->d_qw, h->d_geo, s);
         launch_assemble(h->d_patches, k, hp, h->d_geo, h->d_qval, h->d_qder, h->d_qfirst, h->d_elf, h->d_ell,
                         h->d_stencil, P.lam, P.mu, s);
-        const ProblemPlan& pr = pl.probs[P.prob];
-        std::vector<double> modes;
-        for (const auto& lm : pr.load) {
-            modes.insert(modes.end(), {(double)lm.comp, lm.amp, (double)lm.k[0], (double)lm.k[1], (double)lm.k[2],
-                                       lm.phase[0], lm.phase[1], lm.phase[2]});
-        }
-        double* d_modes = nullptr;
-        if (!modes.empty()) {
-            HIP_OK(hipMalloc(&d_modes, modes.size() * sizeof(double)));
-            HIP_OK(hipMemcpyAsync(d_modes, modes.data(), modes.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        }
-        launch_load(h->d_patches, k, hp, h->d_geo, h->d_qval, h->d_qfirst, h->d_elf, h->d_ell, d_modes,
-                    (int)pr.load.size(), h->d_load, s);
+        for (size_t m = 0; m < pr.load.size(); ++m)
+            launch_load(h->d_patches, k, hp, h->d_geo, h->d_qval, h->d_qfirst, h->d_elf, h->d_ell,
+                        h->d_unit_modes[P.prob] + 8 * m, 1, h->d_F[P.prob] + (int64_t)m * pr.n_dof, pr.dof_off, s);
         HIP_OK(hipStreamSynchronize(s));
-        if (d_modes) HIP_OK(hipFree(d_modes));
         HIP_OK(hipGetLastError());
     }
+    combine_load(h, s);
     // ---- FD tables
     std::vector<double> u64, dtab;
     std::vector<int> u_off(np * 3 * 2), d_off(np * 3 * 2);
@@ -350,6 +397,8 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     h->d_dtab = h->upload(dtab, s);
     build_fd_set(h, h->fd_pa, false, u_off, d_off, s);
     build_fd_set(h, h->fd_int, true, u_off, d_off, s);
+    h->fd_uoff = u_off;
+    h->fd_doff = d_off;
     h->d_fdtmp = h->dalloc<double>(std::max(h->fd_pa.tmp_elems, h->fd_int.tmp_elems));
     // ---- constraints
     h->d_cplus = h->upload(pl.c_plus, s);
@@ -505,6 +554,15 @@ void op_saddle(afieti_handle* h, const double* x, double* y, hipStream_t s) {
     op_stiffness(h, x, y, h->c5, s);
     launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, x, h->c6, s);
     op_pchi(h, h->c6, y + h->n_dof, s);
+}
+
+// y = M x, physical mass (block diagonal over patches and components)
+void op_mass(afieti_handle* h, const double* x, double* y, hipStream_t s) {
+    for (int k = 0; k < h->n_patches; ++k) {
+        const DevPatch& hp = h->h_patches[k];
+        launch_geometry(h->d_patches, k, hp, h->d_ctrl, h->d_qval, h->d_qder, h->d_qfirst, h->d_qw, h->d_geo, s);
+        launch_mass(h->d_patches, k, hp, h->d_geo, h->d_qval, h->d_qfirst, h->d_elf, h->d_ell, x, h->d_qbuf, y, s);
+    }
 }
 
 // y = blockdiag_k H_k^{d-2} S-hat^(k) x on Gamma, interior of x ignored, of y zero
@@ -761,6 +819,7 @@ int afieti_apply(afieti_handle* h, int op, const double* x, double* y, void* str
                 break;
             case AFIETI_OP_AHAT: op_ahat(h, x, y, 0, s); break;
             case AFIETI_OP_LOAD: launch_copy(h->d_load, y, h->n_dof, s); break;
+            case AFIETI_OP_MASS: op_mass(h, x, y, s); break;
             default: h->err = "unknown operator"; return AFIETI_EUNSUPPORTED;
         }
         HIP_OK(hipGetLastError());
@@ -788,15 +847,101 @@ int afieti_solve_adjoint(afieti_handle* h, const double* dJdu, const double* u, 
                          double* dJ_damp, afieti_stats* st, void* stream) {
     int c = need_device(h);
     if (c) return c;
-    (void)dJdu;
-    (void)u;
-    (void)psi;
-    (void)dJ_dlame;
-    (void)dJ_damp;
-    (void)st;
-    (void)stream;
-    h->err = "adjoint not available in this build";
-    return AFIETI_EUNSUPPORTED;
+    if (!dJdu || !u) {
+        h->err = "dJdu and u are required";
+        return AFIETI_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        double* ps = psi;
+        if (!ps) ps = h->s2;  // scratch when the caller does not want psi
+        // the saddle operator is symmetric: psi solves the forward system with rhs dJ/du
+        int code = solve_impl(h, dJdu, ps, nullptr, st, s);
+        if (code < 0) return code;
+        if (dJ_dlame) {
+            std::vector<double> part(h->part_e_n);
+            for (int k = 0; k < h->n_patches; ++k) {
+                const DevPatch& hp = h->h_patches[k];
+                launch_geometry(h->d_patches, k, hp, h->d_ctrl, h->d_qval, h->d_qder, h->d_qfirst, h->d_qw, h->d_geo, s);
+                int nb = launch_energy(h->d_patches, k, hp, h->d_geo, h->d_qval, h->d_qder, h->d_qfirst, u, ps,
+                                       h->d_part_e, s);
+                HIP_OK(hipMemcpyAsync(part.data(), h->d_part_e, (size_t)nb * 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIP_OK(hipStreamSynchronize(s));
+                double emu = 0, elam = 0;
+                for (int b = 0; b < nb; ++b) {
+                    emu += part[2 * b];
+                    elam += part[2 * b + 1];
+                }
+                // a(u, psi) = mu e_mu + lam e_lam:  dJ/dlam_k = -e_lam,  dJ/dmu_k = -e_mu
+                dJ_dlame[2 * k] = -elam;
+                dJ_dlame[2 * k + 1] = -emu;
+            }
+        }
+        if (dJ_damp) {
+            std::vector<double> part(h->part_m_n);
+            int out = 0;
+            for (size_t j = 0; j < h->plan.probs.size(); ++j) {
+                const ProblemPlan& pr = h->plan.probs[j];
+                const int nm = (int)pr.load.size();
+                if (nm == 0) continue;
+                int nch = launch_mdot(h->d_F[j], pr.n_dof, nm, pr.dof_off, ps, h->d_part_m, s);
+                HIP_OK(hipMemcpyAsync(part.data(), h->d_part_m, (size_t)nm * nch * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIP_OK(hipStreamSynchronize(s));
+                for (int m = 0; m < nm; ++m) {
+                    double acc = 0;
+                    for (int b = 0; b < nch; ++b) acc += part[(size_t)m * nch + b];
+                    dJ_damp[out++] = acc;  // dJ/da_m = psi^T F_m
+                }
+            }
+        }
+        HIP_OK(hipGetLastError());
+        return code;
+    } catch (const SetupError& e) {
+        return fail_with(h, e);
+    }
+}
+
+int afieti_set_parameters(afieti_handle* h, const double* lame, const double* amps, void* stream) {
+    int c = need_device(h);
+    if (c) return c;
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        if (lame) {
+            for (int k = 0; k < h->n_patches; ++k) {
+                const double lam = lame[2 * k], mu = lame[2 * k + 1];
+                if (!(lam > 0) || !(mu > 0) || !std::isfinite(lam) || !std::isfinite(mu)) {
+                    h->err = "Lame parameters must be positive";
+                    return AFIETI_EINVAL;
+                }
+            }
+            for (int k = 0; k < h->n_patches; ++k) {
+                h->plan.patches[k].lam = h->h_patches[k].lam = lame[2 * k];
+                h->plan.patches[k].mu = h->h_patches[k].mu = lame[2 * k + 1];
+            }
+            HIP_OK(hipMemcpyAsync(h->d_patches, h->h_patches.data(), h->h_patches.size() * sizeof(DevPatch),
+                                  hipMemcpyHostToDevice, s));
+            build_fd_set(h, h->fd_pa, false, h->fd_uoff, h->fd_doff, s);
+            build_fd_set(h, h->fd_int, true, h->fd_uoff, h->fd_doff, s);
+            assemble_all(h, s);
+        }
+        if (amps) {
+            int in = 0;
+            for (auto& am : h->amps)
+                for (auto& a : am) {
+                    if (!std::isfinite(amps[in])) {
+                        h->err = "non-finite load amplitude";
+                        return AFIETI_EINVAL;
+                    }
+                    a = amps[in++];
+                }
+            combine_load(h, s);
+        }
+        HIP_OK(hipStreamSynchronize(s));
+        HIP_OK(hipGetLastError());
+        return AFIETI_OK;
+    } catch (const SetupError& e) {
+        return fail_with(h, e);
+    }
 }
 
 int64_t afieti_export_size(const afieti_handle* h, int what) {

@@ -22,9 +22,21 @@ void launch_assemble(const DevPatch* dp, int k, const DevPatch& hp, const double
                      const double* qval, const double* qder, const int* qfirst,
                      const int* el_first, const int* el_last, double* stencil,
                      double lam_w, double mu_w, hipStream_t s);
+// f[dof - f_base] = body-force load of patch k for the given modes
 void launch_load(const DevPatch* dp, int k, const DevPatch& hp, const double* geo,
                  const double* qval, const int* qfirst, const int* el_first, const int* el_last,
-                 const double* modes, int n_modes, double* f, hipStream_t s);
+                 const double* modes, int n_modes, double* f, int64_t f_base, hipStream_t s);
+// y = M x on patch k (physical mass, both passes); qbuf holds dim values per Gauss point
+void launch_mass(const DevPatch* dp, int k, const DevPatch& hp, const double* geo, const double* qval,
+                 const int* qfirst, const int* el_first, const int* el_last, const double* x, double* qbuf,
+                 double* y, hipStream_t s);
+// per-block partial (e_mu, e_lam) of patch k; returns the number of blocks
+int launch_energy(const DevPatch* dp, int k, const DevPatch& hp, const double* geo, const double* qval,
+                  const double* qder, const int* qfirst, const double* u, const double* psi, double* part,
+                  hipStream_t s);
+// part[mode][chunk] partial dot products of F[mode] (length n) with psi[off:]; returns chunks
+int launch_mdot(const double* F, int64_t n, int n_modes, int64_t off, const double* psi, double* part,
+                hipStream_t s);
 
 // ---- operators
 // y = A x (+ B^T t if t != nullptr) for every row of every patch

@@ -351,7 +351,7 @@ template <int DIM>
 __global__ void k_load(const DevPatch* __restrict__ dps, int k, const double* __restrict__ geo,
                        const double* __restrict__ qval, const int* __restrict__ qfirst,
                        const int* __restrict__ el_first, const int* __restrict__ el_last,
-                       const double* __restrict__ modes, int n_modes, double* __restrict__ f) {
+                       const double* __restrict__ modes, int n_modes, double* __restrict__ f, int64_t f_base) {
     const DevPatch pa = dps[k];
     const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (node >= pa.nodes) return;
@@ -387,7 +387,170 @@ __global__ void k_load(const DevPatch* __restrict__ dps, int k, const double* __
             }
         }
     }
-    for (int c = 0; c < DIM; ++c) f[pa.dof_off + c * pa.nodes + node] = acc[c];
+    for (int c = 0; c < DIM; ++c) f[pa.dof_off - f_base + c * pa.nodes + node] = acc[c];
+}
+
+// W(q) u_c(q) at every Gauss point of patch k (u a DOF vector): the first
+// half of the physical mass product M u = sum_q w|J| B_i(q) u(q).
+template <int DIM>
+__global__ void k_field_qp(const DevPatch* __restrict__ dps, int k, const double* __restrict__ geo,
+                           const double* __restrict__ qval, const int* __restrict__ qfirst,
+                           const double* __restrict__ u, double* __restrict__ qbuf) {
+    const DevPatch pa = dps[k];
+    const int64_t nq1 = pa.nq[0], nq2 = pa.nq[1], nq3 = pa.nq[2];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nq1 * nq2 * nq3) return;
+    const int q[3] = {(int)(idx % nq1), (int)((idx / nq1) % nq2), (int)(idx / (nq1 * nq2))};
+    const int P = pa.p;
+    int f[3] = {0, 0, 0};
+    const double* v[3];
+    const double one = 1.0;
+    for (int m = 0; m < 3; ++m) {
+        if (m < DIM) {
+            const int g = pa.q_off[m] + q[m];
+            f[m] = qfirst[g];
+            v[m] = qval + (int64_t)g * kQStride;
+        } else {
+            v[m] = &one;
+        }
+    }
+    double val[3] = {0, 0, 0};
+    const int P3 = DIM == 3 ? P : 0;
+    for (int t3 = 0; t3 <= P3; ++t3)
+        for (int t2 = 0; t2 <= P; ++t2)
+            for (int t1 = 0; t1 <= P; ++t1) {
+                const int64_t node = (f[0] + t1) + (int64_t)pa.n[0] * ((f[1] + t2) + (int64_t)pa.n[1] * (f[2] + t3));
+                const double b = v[0][t1] * v[1][t2] * v[2][t3];
+                for (int c = 0; c < DIM; ++c) val[c] += b * u[pa.dof_off + c * pa.nodes + node];
+            }
+    const double W = geo[pa.geo_off + idx * 13];
+    for (int c = 0; c < DIM; ++c) qbuf[idx * DIM + c] = W * val[c];
+}
+
+// y_(c,i) = sum over the Gauss points q in the support of B_i of B_i(q) qbuf[q][c]
+template <int DIM>
+__global__ void k_mass_gather(const DevPatch* __restrict__ dps, int k, const double* __restrict__ qval,
+                              const int* __restrict__ qfirst, const int* __restrict__ el_first,
+                              const int* __restrict__ el_last, const double* __restrict__ qbuf,
+                              double* __restrict__ y) {
+    const DevPatch pa = dps[k];
+    const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= pa.nodes) return;
+    const int P = pa.p;
+    const int i[3] = {(int)(node % pa.n[0]), (int)((node / pa.n[0]) % pa.n[1]), (int)(node / ((int64_t)pa.n[0] * pa.n[1]))};
+    int qlo[3] = {0, 0, 0}, qhi[3] = {1, 1, 1};
+    for (int m = 0; m < DIM; ++m) {
+        qlo[m] = el_first[pa.el_off[m] + i[m]] * (P + 1);
+        qhi[m] = (el_last[pa.el_off[m] + i[m]] + 1) * (P + 1);
+    }
+    double acc[3] = {0, 0, 0};
+    const int64_t nq1 = pa.nq[0], nq2 = pa.nq[1];
+    for (int q3 = qlo[2]; q3 < qhi[2]; ++q3) {
+        double v3 = 1;
+        if (DIM == 3) {
+            const int g = pa.q_off[2] + q3;
+            v3 = qval[(int64_t)g * kQStride + i[2] - qfirst[g]];
+        }
+        for (int q2 = qlo[1]; q2 < qhi[1]; ++q2) {
+            const int g2 = pa.q_off[1] + q2;
+            const double v2 = qval[(int64_t)g2 * kQStride + i[1] - qfirst[g2]];
+            for (int q1 = qlo[0]; q1 < qhi[0]; ++q1) {
+                const int g1 = pa.q_off[0] + q1;
+                const double b = qval[(int64_t)g1 * kQStride + i[0] - qfirst[g1]] * v2 * v3;
+                const int64_t qi = (int64_t)q1 + nq1 * ((int64_t)q2 + nq2 * q3);
+                for (int c = 0; c < DIM; ++c) acc[c] += b * qbuf[qi * DIM + c];
+            }
+        }
+    }
+    for (int c = 0; c < DIM; ++c) y[pa.dof_off + c * pa.nodes + node] = acc[c];
+}
+
+// Per-block partial sums over the Gauss points of patch k of
+//   e_mu  = w|J| (grad u + grad u^T) : grad psi   (= 2 eps(u) : eps(psi))
+//   e_lam = w|J| div u div psi,
+// the two parts of the bilinear form of Section 3 (a = mu e_mu + lam e_lam).
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_energy(const DevPatch* __restrict__ dps, int k, const double* __restrict__ geo,
+                                                   const double* __restrict__ qval, const double* __restrict__ qder,
+                                                   const int* __restrict__ qfirst, const double* __restrict__ u,
+                                                   const double* __restrict__ psi, double* __restrict__ part) {
+    __shared__ double lds[2 * 4];
+    const DevPatch pa = dps[k];
+    const int64_t nq1 = pa.nq[0], nq2 = pa.nq[1], nq3 = pa.nq[2];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc[2] = {0.0, 0.0};
+    if (idx < nq1 * nq2 * nq3) {
+        const int q[3] = {(int)(idx % nq1), (int)((idx / nq1) % nq2), (int)(idx / (nq1 * nq2))};
+        const int P = pa.p;
+        int f[3] = {0, 0, 0};
+        const double *v[3], *d[3];
+        const double one = 1.0, zero = 0.0;
+        for (int m = 0; m < 3; ++m) {
+            if (m < DIM) {
+                const int g = pa.q_off[m] + q[m];
+                f[m] = qfirst[g];
+                v[m] = qval + (int64_t)g * kQStride;
+                d[m] = qder + (int64_t)g * kQStride;
+            } else {
+                v[m] = &one;
+                d[m] = &zero;
+            }
+        }
+        double gu[3][3] = {{0}}, gp[3][3] = {{0}};  // parametric gradients [c][a]
+        const int P3 = DIM == 3 ? P : 0;
+        for (int t3 = 0; t3 <= P3; ++t3)
+            for (int t2 = 0; t2 <= P; ++t2)
+                for (int t1 = 0; t1 <= P; ++t1) {
+                    const int64_t node = (f[0] + t1) + (int64_t)pa.n[0] * ((f[1] + t2) + (int64_t)pa.n[1] * (f[2] + t3));
+                    const double g[3] = {d[0][t1] * v[1][t2] * v[2][t3], v[0][t1] * d[1][t2] * v[2][t3],
+                                         v[0][t1] * v[1][t2] * d[2][t3]};
+                    for (int c = 0; c < DIM; ++c) {
+                        const double uc = u[pa.dof_off + c * pa.nodes + node];
+                        const double pc = psi[pa.dof_off + c * pa.nodes + node];
+                        for (int a = 0; a < DIM; ++a) {
+                            gu[c][a] += g[a] * uc;
+                            gp[c][a] += g[a] * pc;
+                        }
+                    }
+                }
+        const double* G = geo + pa.geo_off + idx * 13;
+        double Gu[3][3], Gp[3][3];  // physical gradients [c][x]
+        for (int c = 0; c < DIM; ++c)
+            for (int x = 0; x < DIM; ++x) {
+                double su = 0, sp = 0;
+                for (int a = 0; a < DIM; ++a) {
+                    su += gu[c][a] * G[1 + a * 3 + x];
+                    sp += gp[c][a] * G[1 + a * 3 + x];
+                }
+                Gu[c][x] = su;
+                Gp[c][x] = sp;
+            }
+        double emu = 0, divu = 0, divp = 0;
+        for (int c = 0; c < DIM; ++c) {
+            divu += Gu[c][c];
+            divp += Gp[c][c];
+            for (int x = 0; x < DIM; ++x) emu += (Gu[c][x] + Gu[x][c]) * Gp[c][x];
+        }
+        acc[0] = G[0] * emu;
+        acc[1] = G[0] * divu * divp;
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        part[(int64_t)blockIdx.x * 2] = acc[0];
+        part[(int64_t)blockIdx.x * 2 + 1] = acc[1];
+    }
+}
+
+// partial[mode][chunk] = sum over the chunk of F[mode][i] psi[off + i]
+__global__ void __launch_bounds__(kBlock) k_mdot_partial(const double* __restrict__ F, int64_t n, int64_t off,
+                                                         const double* __restrict__ psi, double* __restrict__ part) {
+    __shared__ double lds[4];
+    const int mode = blockIdx.y;
+    const int64_t b = (int64_t)blockIdx.x * kChunk, e = min(n, b + (int64_t)kChunk);
+    double acc[1] = {0.0};
+    for (int64_t i = b + threadIdx.x; i < e; i += kBlock) acc[0] += F[(int64_t)mode * n + i] * psi[off + i];
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) part[(int64_t)mode * gridDim.x + blockIdx.x] = acc[0];
 }
 
 // ================================================================ operators
@@ -890,13 +1053,48 @@ void launch_assemble(const DevPatch* dp, int k, const DevPatch& hp, const double
 
 void launch_load(const DevPatch* dp, int k, const DevPatch& hp, const double* geo, const double* qval,
                  const int* qfirst, const int* el_first, const int* el_last, const double* modes, int n_modes,
-                 double* f, hipStream_t s) {
+                 double* f, int64_t f_base, hipStream_t s) {
     if (hp.dim == 3)
         hipLaunchKernelGGL(k_load<3>, dim3(blocks_for(hp.nodes)), dim3(kBlock), 0, s, dp, k, geo, qval, qfirst,
-                           el_first, el_last, modes, n_modes, f);
+                           el_first, el_last, modes, n_modes, f, f_base);
     else
         hipLaunchKernelGGL(k_load<2>, dim3(blocks_for(hp.nodes)), dim3(kBlock), 0, s, dp, k, geo, qval, qfirst,
-                           el_first, el_last, modes, n_modes, f);
+                           el_first, el_last, modes, n_modes, f, f_base);
+}
+
+void launch_mass(const DevPatch* dp, int k, const DevPatch& hp, const double* geo, const double* qval,
+                 const int* qfirst, const int* el_first, const int* el_last, const double* x, double* qbuf,
+                 double* y, hipStream_t s) {
+    const int64_t nq = (int64_t)hp.nq[0] * hp.nq[1] * hp.nq[2];
+    if (hp.dim == 3) {
+        hipLaunchKernelGGL(k_field_qp<3>, dim3(blocks_for(nq)), dim3(kBlock), 0, s, dp, k, geo, qval, qfirst, x, qbuf);
+        hipLaunchKernelGGL(k_mass_gather<3>, dim3(blocks_for(hp.nodes)), dim3(kBlock), 0, s, dp, k, qval, qfirst,
+                           el_first, el_last, qbuf, y);
+    } else {
+        hipLaunchKernelGGL(k_field_qp<2>, dim3(blocks_for(nq)), dim3(kBlock), 0, s, dp, k, geo, qval, qfirst, x, qbuf);
+        hipLaunchKernelGGL(k_mass_gather<2>, dim3(blocks_for(hp.nodes)), dim3(kBlock), 0, s, dp, k, qval, qfirst,
+                           el_first, el_last, qbuf, y);
+    }
+}
+
+int launch_energy(const DevPatch* dp, int k, const DevPatch& hp, const double* geo, const double* qval,
+                  const double* qder, const int* qfirst, const double* u, const double* psi, double* part,
+                  hipStream_t s) {
+    const int64_t nq = (int64_t)hp.nq[0] * hp.nq[1] * hp.nq[2];
+    const unsigned nb = blocks_for(nq);
+    if (hp.dim == 3)
+        hipLaunchKernelGGL(k_energy<3>, dim3(nb), dim3(kBlock), 0, s, dp, k, geo, qval, qder, qfirst, u, psi, part);
+    else
+        hipLaunchKernelGGL(k_energy<2>, dim3(nb), dim3(kBlock), 0, s, dp, k, geo, qval, qder, qfirst, u, psi, part);
+    return (int)nb;
+}
+
+int launch_mdot(const double* F, int64_t n, int n_modes, int64_t off, const double* psi, double* part,
+                hipStream_t s) {
+    const unsigned nch = blocks_for(n, kChunk);
+    if (n_modes > 0 && n > 0)
+        hipLaunchKernelGGL(k_mdot_partial, dim3(nch, n_modes), dim3(kBlock), 0, s, F, n, off, psi, part);
+    return (int)nch;
 }
 
 #define AFIETI_DISPATCH_P(DIM, FN, ...)            \
