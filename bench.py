@@ -40,6 +40,10 @@ def workload(name):
     elif name == "c1":
         prob = W.make_c1(seed=0)
         desc = "2D unit square, 2x2 bilinear patches, p=2 C^1, 16^2 elements/patch, lambda=mu=1, u=0 on x=0"
+    elif name == "c4":
+        prob = W.make_c4(seed=0)
+        desc = ("ragged batch of 32 3D problems: patch grids in {1,2,3}^3, 8..40 elements per direction, "
+                "p in {2,3,4}, lognormal Lame, 8 trig modes, u=0 on z=0")
     elif name.startswith("c3"):
         p = int(name[3:]) if len(name) > 3 else 3
         prob = W.make_c3(seed=0, p=p)
@@ -66,6 +70,8 @@ def fd_flops(solver_prob):
     """Algorithmic flops of one P_A^{-1} application: per patch and
     component 2 n^d (sum_m n_m) multiply-adds forward and backward (the
     paper's 4 d n N per patch) plus the divide."""
+    if isinstance(solver_prob, list):
+        return sum(fd_flops(p) for p in solver_prob)
     total = 0
     for pd in solver_prob["patches"]:
         # basis functions on uniform open knots: n_el (p - reg) + reg + 1
@@ -196,7 +202,7 @@ def main():
                 traffic=None, kernel="k_stiffness", bytes_per_launch=mv_bytes, ms_per_launch=mv_ms)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload != "c4":
         log("CPU oracle baseline (one MINRES iteration of the oracle)")
         cpu = cpu_baseline(prob, iters32[-1])
         log(f"  oracle {cpu['per_iteration_s']:.2f} s/iteration on {cpu['cores']} threads")

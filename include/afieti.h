@@ -103,6 +103,9 @@ typedef struct {
     int ps_variant;      /* AFIETI_PS_*                                    */
     int check_every;     /* iterations between host convergence checks (8) */
     int host_only;       /* 1: build the host plan only, no device work    */
+    int use_graph;       /* 1: replay MINRES iterations as a captured HIP
+                            graph (6 iterations per launch) on a stream the
+                            handle owns; 0: enqueue kernels one by one     */
 } afieti_options;
 
 typedef struct {
@@ -136,6 +139,11 @@ int afieti_setup(const afieti_problem* probs, int n_problems,
                  const afieti_options* opt, void* stream, afieti_handle** out);
 
 int afieti_get_info(const afieti_handle* h, afieti_info* info);
+
+/* Per-problem results of the last solve (host arrays of n_problems entries,
+ * each may be NULL): MINRES iterations, |eta| / gamma_1, and status
+ * (1 converged, 2 breakdown, 3 maxit reached). */
+int afieti_get_problem_stats(const afieti_handle* h, int* iterations, double* rel_residual, int* status);
 
 /* Per problem: n_dof, n_c and the DOF offset of every patch; arrays sized by
  * the caller (dof_off: n_patches_total + 1 entries, c_off: n_problems + 1). */

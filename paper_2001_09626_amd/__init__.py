@@ -78,7 +78,7 @@ class Solver:
     """One handle over one or more independent problems."""
 
     def __init__(self, problems, tol=1e-8, maxit=5000, fd_precision="fp64", ps_variant="nr",
-                 check_every=8, host_only=False):
+                 check_every=12, host_only=False, use_graph=True):
         L = N.lib()
         self._L = L
         arr, keep = to_c_problems(problems)
@@ -90,6 +90,7 @@ class Solver:
         opt.ps_variant = N.PS_VARIANT[ps_variant]
         opt.check_every = check_every
         opt.host_only = 1 if host_only else 0
+        opt.use_graph = 1 if use_graph else 0
         self.host_only = host_only
         h = C.c_void_p()
         stream = C.c_void_p(0) if host_only else _stream()
@@ -161,6 +162,15 @@ class Solver:
         stats = dict(iterations=st.iterations, converged=bool(st.converged),
                      rel_residual=st.rel_residual, ms=st.ms_solve, code=code)
         return u, lam, stats
+
+    def problem_stats(self):
+        """Per-problem (iterations, |eta|/gamma_1, status) of the last solve;
+        status 1 converged, 2 breakdown, 3 maxit."""
+        its = (C.c_int * self.n_problems)()
+        rel = (C.c_double * self.n_problems)()
+        sta = (C.c_int * self.n_problems)()
+        self._check(self._L.afieti_get_problem_stats(self._h, its, rel, sta))
+        return np.array(its[:]), np.array(rel[:]), np.array(sta[:])
 
     def set_parameters(self, lame=None, amps=None):
         """New per-patch (lambda, mu) (array (n_patches, 2)) and/or load

@@ -40,7 +40,8 @@ class Problem(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("fd_precision", C.c_int),
-                ("ps_variant", C.c_int), ("check_every", C.c_int), ("host_only", C.c_int)]
+                ("ps_variant", C.c_int), ("check_every", C.c_int), ("host_only", C.c_int),
+                ("use_graph", C.c_int)]
 
 
 class Info(C.Structure):
@@ -59,6 +60,8 @@ SYMBOLS = {
     "afieti_setup": (C.c_int, [C.POINTER(Problem), C.c_int, C.POINTER(Options), C.c_void_p,
                                C.POINTER(C.c_void_p)]),
     "afieti_get_info": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
+    "afieti_get_problem_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double),
+                                           C.POINTER(C.c_int)]),
     "afieti_get_offsets": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "afieti_apply_fd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "afieti_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

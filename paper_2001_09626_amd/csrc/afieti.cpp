@@ -112,6 +112,10 @@ struct afieti_handle {
     double* vec[10] = {nullptr};
     MinresState* d_state = nullptr;
     MinresState* h_state = nullptr;  // pinned
+    const MinresState* mask = nullptr;  // set while MINRES runs: skip stopped problems
+    hipStream_t gstream = nullptr;      // non-blocking stream for the captured iteration graph
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 
     template <typename T>
     T* dalloc(int64_t n) {
@@ -130,8 +134,13 @@ struct afieti_handle {
         return p;
     }
     ~afieti_handle() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (gstream) (void)hipStreamSynchronize(gstream);
         for (void* p : allocs) (void)hipFree(p);
         if (h_state) (void)hipHostFree(h_state);
+        if (ev_a) (void)hipEventDestroy(ev_a);
+        if (ev_b) (void)hipEventDestroy(ev_b);
+        if (gstream) (void)hipStreamDestroy(gstream);
     }
 };
 
@@ -185,6 +194,7 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
             t.scale = interior ? 1.0 : P.hscale;
             t.mass = interior ? 0.0 : 1.0;
             t.alpha = interior ? -1.0 : 1.0;
+            t.prob = P.prob;
             int ti = (int)ts.size();
             ts.push_back(t);
             for (int i3 = 0; i3 < t.n3; ++i3) slabs.push_back(make_int2(ti, i3));
@@ -478,6 +488,9 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     for (int i = 0; i < 10; ++i) h->vec[i] = h->dalloc<double>(pl.n_dof + pl.n_c);
     h->d_state = h->dalloc<MinresState>((int64_t)pl.probs.size());
     HIP_OK(hipHostMalloc((void**)&h->h_state, pl.probs.size() * sizeof(MinresState), hipHostMallocDefault));
+    HIP_OK(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&h->ev_a, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&h->ev_b, hipEventDisableTiming));
     HIP_OK(hipStreamSynchronize(s));
     HIP_OK(hipGetLastError());
 }
@@ -486,7 +499,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
 void op_stiffness(afieti_handle* h, const double* x, double* y, const double* t, hipStream_t s) {
     for (const auto& rc : h->classes)
         launch_stiffness_dp(rc.dim, rc.p, h->d_patches, rc.d_rb, rc.n, h->d_stencil, x, y, h->d_btptr, h->d_btrow,
-                            h->d_btsgn, t, s);
+                            h->d_btsgn, t, h->mask, s);
 }
 
 void op_mask_interior(afieti_handle* h, double* y, hipStream_t s) {
@@ -495,13 +508,13 @@ void op_mask_interior(afieti_handle* h, double* y, hipStream_t s) {
 
 void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_t s) {
     launch_ahat(h->d_patches, h->d_ahat_slabs, h->n_ahat_slabs, h->d_all_rb, h->n_all_rb, h->d_kband, h->d_mband, x,
-                h->ah1, h->ah2, y, use_h, s);
+                h->ah1, h->ah2, y, use_h, h->mask, s);
 }
 
 void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s) {
     int prec = h->opt.fd_precision == AFIETI_FD_FP64 ? 0 : 1;
     launch_fd(prec, set.d_t, set.n_t, set.d_slabs, set.n_slabs, set.d_cols, set.n_cols,
-              prec == 0 ? (const void*)h->d_u64 : (const void*)h->d_u32, h->d_dtab, in, out, h->d_fdtmp, kMaxN, s);
+              prec == 0 ? (const void*)h->d_u64 : (const void*)h->d_u32, h->d_dtab, in, out, h->d_fdtmp, h->mask, s);
 }
 
 // out = P_chi y  (in place allowed)
@@ -575,50 +588,95 @@ void op_shat(afieti_handle* h, const double* x, double* y, hipStream_t s) {
     op_mask_interior(h, y, s);
 }
 
-// MINRES on the preconditioned projected system; b (length n_vec) is read
-// from h->vec[1].  The solution ends in h->vec[8].
-int run_minres(afieti_handle* h, hipStream_t s, afieti_stats* st) {
+// Rotating MINRES buffers: the rotation (3, 2 and 3 buffers) has period 6.
+struct MinresBufs {
+    double *v_old, *v, *v_new, *z, *z_new, *d_old, *d, *d_new;
+};
+
+MinresBufs initial_bufs(afieti_handle* h) {
     double** V = h->vec;
-    double *v_old = V[0], *v = V[1], *v_new = V[2], *z = V[3], *z_new = V[4];
-    double *d_old = V[5], *d = V[6], *d_new = V[7], *x = V[8], *q = V[9];
+    return {V[0], V[1], V[2], V[3], V[4], V[5], V[6], V[7]};
+}
+
+// One MINRES iteration (Lanczos step with the saddle operator and the block
+// preconditioner, Givens update, d and x updates), then buffer rotation.
+void minres_iteration(afieti_handle* h, hipStream_t s, MinresBufs& b) {
+    double* x = h->vec[8];
+    double* q = h->vec[9];
+    const int np = h->n_probs;
+    op_saddle(h, b.z, q, s);
+    launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, q, b.z, h->d_part2, s);
+    launch_minres_delta(h->d_state, h->d_vec_cptr, np, h->d_part2, s);
+    launch_minres_v(h->d_state, h->d_vec_chunks, h->n_vec_chunks, q, b.v, b.v_old, b.v_new, s);
+    op_prec(h, b.v_new, b.z_new, s);
+    launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, b.z_new, b.v_new, h->d_part2, s);
+    launch_minres_givens(h->d_state, h->d_vec_cptr, np, h->d_part2, s);
+    launch_minres_dx(h->d_state, h->d_vec_chunks, h->n_vec_chunks, b.z, b.d_old, b.d, b.d_new, x, s);
+    double* t = b.v_old;
+    b.v_old = b.v;
+    b.v = b.v_new;
+    b.v_new = t;
+    std::swap(b.z, b.z_new);
+    t = b.d_old;
+    b.d_old = b.d;
+    b.d = b.d_new;
+    b.d_new = t;
+}
+
+constexpr int kGraphIters = 6;
+
+bool all_stopped(afieti_handle* h, hipStream_t s) {
+    HIP_OK(hipMemcpyAsync(h->h_state, h->d_state, h->n_probs * sizeof(MinresState), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int j = 0; j < h->n_probs; ++j)
+        if (h->h_state[j].stop == 0) return false;
+    return true;
+}
+
+// MINRES on the preconditioned projected system; b (length n_vec) is read
+// from h->vec[1].  The solution ends in h->vec[8].  Problems that have
+// stopped are masked out of the large kernels.
+int run_minres(afieti_handle* h, hipStream_t s, afieti_stats* st) {
+    MinresBufs b = initial_bufs(h);
     const int64_t n = h->n_vec;
     const int np = h->n_probs;
-    launch_fill(v_old, 0.0, n, s);
-    launch_fill(d_old, 0.0, n, s);
-    launch_fill(d, 0.0, n, s);
-    launch_fill(x, 0.0, n, s);
-    op_prec(h, v, z, s);
-    launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, z, v, h->d_part2, s);
+    launch_fill(b.v_old, 0.0, n, s);
+    launch_fill(b.d_old, 0.0, n, s);
+    launch_fill(b.d, 0.0, n, s);
+    launch_fill(h->vec[8], 0.0, n, s);
+    op_prec(h, b.v, b.z, s);
+    launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, b.z, b.v, h->d_part2, s);
     launch_minres_init(h->d_state, h->d_vec_cptr, np, h->d_part2, h->opt.tol, h->opt.maxit, s);
-    const int every = std::max(1, h->opt.check_every);
-    for (int it = 0; it < h->opt.maxit; ++it) {
-        op_saddle(h, z, q, s);
-        launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, q, z, h->d_part2, s);
-        launch_minres_delta(h->d_state, h->d_vec_cptr, np, h->d_part2, s);
-        launch_minres_v(h->d_state, h->d_vec_chunks, h->n_vec_chunks, q, v, v_old, v_new, s);
-        op_prec(h, v_new, z_new, s);
-        launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, z_new, v_new, h->d_part2, s);
-        launch_minres_givens(h->d_state, h->d_vec_cptr, np, h->d_part2, s);
-        launch_minres_dx(h->d_state, h->d_vec_chunks, h->n_vec_chunks, z, d_old, d, d_new, x, s);
-        double* t = v_old;
-        v_old = v;
-        v = v_new;
-        v_new = t;
-        std::swap(z, z_new);
-        t = d_old;
-        d_old = d;
-        d = d_new;
-        d_new = t;
-        if ((it + 1) % every == 0 || it + 1 == h->opt.maxit) {
-            HIP_OK(hipMemcpyAsync(h->h_state, h->d_state, np * sizeof(MinresState), hipMemcpyDeviceToHost, s));
-            HIP_OK(hipStreamSynchronize(s));
-            bool all = true;
-            for (int j = 0; j < np; ++j) all = all && h->h_state[j].stop != 0;
-            if (all) break;
+    h->mask = h->d_state;
+    if (h->opt.use_graph) {
+        hipStream_t g = h->gstream;
+        if (!h->graph_exec) {
+            hipGraph_t graph;
+            HIP_OK(hipStreamBeginCapture(g, hipStreamCaptureModeThreadLocal));
+            MinresBufs bc = initial_bufs(h);
+            for (int r = 0; r < kGraphIters; ++r) minres_iteration(h, g, bc);
+            HIP_OK(hipStreamEndCapture(g, &graph));
+            HIP_OK(hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0));
+            HIP_OK(hipGraphDestroy(graph));
+        }
+        HIP_OK(hipEventRecord(h->ev_a, s));
+        HIP_OK(hipStreamWaitEvent(g, h->ev_a, 0));
+        const int every = std::max(1, h->opt.check_every / kGraphIters);
+        for (int it = 0, launches = 0; it < h->opt.maxit; it += kGraphIters) {
+            HIP_OK(hipGraphLaunch(h->graph_exec, g));
+            if (++launches % every == 0 && all_stopped(h, g)) break;
+        }
+        HIP_OK(hipEventRecord(h->ev_b, g));
+        HIP_OK(hipStreamWaitEvent(s, h->ev_b, 0));
+    } else {
+        const int every = std::max(1, h->opt.check_every);
+        for (int it = 0; it < h->opt.maxit; ++it) {
+            minres_iteration(h, s, b);
+            if (((it + 1) % every == 0 || it + 1 == h->opt.maxit) && all_stopped(h, s)) break;
         }
     }
-    HIP_OK(hipMemcpyAsync(h->h_state, h->d_state, np * sizeof(MinresState), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+    h->mask = nullptr;
+    all_stopped(h, s);
     HIP_OK(hipGetLastError());
     int code = AFIETI_OK, its = 0, conv = 1;
     double rel = 0;
@@ -687,6 +745,7 @@ void afieti_default_options(afieti_options* opt) {
     opt->ps_variant = AFIETI_PS_NR;
     opt->check_every = 8;
     opt->host_only = 0;
+    opt->use_graph = 1;
 }
 
 const char* afieti_strerror(int code) {
@@ -942,6 +1001,16 @@ int afieti_set_parameters(afieti_handle* h, const double* lame, const double* am
     } catch (const SetupError& e) {
         return fail_with(h, e);
     }
+}
+
+int afieti_get_problem_stats(const afieti_handle* h, int* iterations, double* rel_residual, int* status) {
+    if (!h || h->host_only || !h->h_state) return AFIETI_EINVAL;
+    for (int j = 0; j < h->n_probs; ++j) {
+        if (iterations) iterations[j] = h->h_state[j].its;
+        if (rel_residual) rel_residual[j] = h->h_state[j].rel;
+        if (status) status[j] = h->h_state[j].stop;
+    }
+    return AFIETI_OK;
 }
 
 int64_t afieti_export_size(const afieti_handle* h, int what) {

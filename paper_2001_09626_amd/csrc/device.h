@@ -40,6 +40,8 @@ struct FdTensor {
     double scale;                // (H^(k))^{d-2} for P_A, 1 for the interior solve
     double mass;                 // 1 for P_A (mass term), 0 for the interior solve
     double alpha;                // output = alpha * solution
+    int prob;                    // problem index (for the stop mask)
+    int pad;
 };
 
 struct Chunk {                   // contiguous range inside one segment

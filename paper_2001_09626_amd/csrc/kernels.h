@@ -8,11 +8,12 @@
 namespace afieti {
 
 // ---- Fast Diagonalization (Algorithm 1): three passes over the tensors.
-// prec: 0 FP64, 1 FP32, 2 BF16 mode products.
+// prec: 0 FP64, 1 FP32 mode products.  Kernels of problems whose MINRES has
+// stopped (mask[prob].stop != 0) return at once; mask may be NULL.
 void launch_fd(int prec, const FdTensor* d_tensors, int n_tensors,
                const int2* d_slabs, int n_slabs, const int2* d_cols, int n_colblocks,
                const void* u_table, const double* d_table,
-               const double* in, double* out, void* tmp, int max_n, hipStream_t s);
+               const double* in, double* out, void* tmp, const MinresState* mask, hipStream_t s);
 
 // ---- setup kernels
 void launch_geometry(const DevPatch* dp, int k, const DevPatch& hp, const double* ctrl,
@@ -43,7 +44,7 @@ int launch_mdot(const double* F, int64_t n, int n_modes, int64_t off, const doub
 void launch_stiffness_dp(int dim, int p, const DevPatch* dp, const int4* d_rowblocks, int n_rowblocks,
                          const double* stencil, const double* x, double* y,
                          const int64_t* bt_ptr, const int* bt_row, const double* bt_sign,
-                         const double* t, hipStream_t s);
+                         const double* t, const MinresState* mask, hipStream_t s);
 // zero the interior nodes of every patch and component
 void launch_mask_interior(const DevPatch* dp, const int4* d_rowblocks, int n_rowblocks, double* y, hipStream_t s);
 // y[r] = alpha (x[plus] - x[minus])
@@ -60,7 +61,7 @@ void launch_W(const int* blk_start, const int* blk_size, const int* blk_dir, int
 // slabs: (patch, component, i3); rb: row blocks (patch, component, node0).
 void launch_ahat(const DevPatch* dp, const int4* slabs, int n_slabs, const int4* rb, int nrb,
                  const double* kband, const double* mband, const double* x, double* P, double* Cm,
-                 double* y, int use_hscale, hipStream_t s);
+                 double* y, int use_hscale, const MinresState* mask, hipStream_t s);
 // partial sums of R^T x over patch DOF chunks (nm values per chunk)
 void launch_rigid_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks,
                           const double* ctrl, const double* x, double* partials, hipStream_t s);

@@ -62,10 +62,11 @@ __device__ inline void block_sum(double (&v)[NV], double* lds /* NV * 4 */) {
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fd_fwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
                                                      const T* __restrict__ ut, const double* __restrict__ in,
-                                                     T* __restrict__ tmp) {
+                                                     T* __restrict__ tmp, const MinresState* __restrict__ mask) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 it = slabs[blockIdx.x];
     const FdTensor t = tens[it.x];
+    if (mask && mask[t.prob].stop) return;
     const int i3 = it.y, n1 = t.n1, n2 = t.n2, n12 = n1 * n2;
     T* X = reinterpret_cast<T*>(smem);
     T* Y = X + kMaxN * kMaxN;
@@ -100,11 +101,12 @@ __global__ void __launch_bounds__(kBlock) k_fd_fwd12(const FdTensor* __restrict_
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fd_mid3(const FdTensor* __restrict__ tens, const int2* __restrict__ cols,
                                                     const T* __restrict__ ut, const double* __restrict__ dt,
-                                                    T* __restrict__ tmp) {
+                                                    T* __restrict__ tmp, const MinresState* __restrict__ mask) {
     constexpr int NC = 32;
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 it = cols[blockIdx.x];
     const FdTensor t = tens[it.x];
+    if (mask && mask[t.prob].stop) return;
     const int n1 = t.n1, n3 = t.n3, n12 = t.n1 * t.n2;
     const int col0 = it.y * NC;
     T* Z = reinterpret_cast<T*>(smem);
@@ -140,10 +142,11 @@ __global__ void __launch_bounds__(kBlock) k_fd_mid3(const FdTensor* __restrict__
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fd_bwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
                                                      const T* __restrict__ ut, const T* __restrict__ tmp,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out, const MinresState* __restrict__ mask) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 it = slabs[blockIdx.x];
     const FdTensor t = tens[it.x];
+    if (mask && mask[t.prob].stop) return;
     const int i3 = it.y, n1 = t.n1, n2 = t.n2, n12 = n1 * n2;
     T* Z = reinterpret_cast<T*>(smem);
     T* Y = Z + kMaxN * kMaxN;
@@ -564,12 +567,13 @@ __global__ void __launch_bounds__(kBlock) k_stiffness(const DevPatch* __restrict
                                                       const double* __restrict__ A, const double* __restrict__ x,
                                                       double* __restrict__ y, const int64_t* __restrict__ bt_ptr,
                                                       const int* __restrict__ bt_row, const double* __restrict__ bt_sign,
-                                                      const double* __restrict__ t) {
+                                                      const double* __restrict__ t, const MinresState* __restrict__ mask) {
     constexpr int W = 2 * P + 1;
     constexpr int S = DIM == 3 ? W * W * W : W * W;
     constexpr int P3 = DIM == 3 ? P : 0;
     const int4 b = rb[blockIdx.x];
     const DevPatch& pa = dps[b.x];
+    if (mask && mask[pa.prob].stop) return;
     const int64_t nodes = pa.nodes;
     const int64_t node = (int64_t)b.z + threadIdx.x;
     if (node >= nodes) return;
@@ -616,10 +620,11 @@ __global__ void __launch_bounds__(kBlock) k_stiffness(const DevPatch* __restrict
 __global__ void __launch_bounds__(kBlock) k_ahat12(const DevPatch* __restrict__ dps, const int4* __restrict__ slabs,
                                                    const double* __restrict__ kb, const double* __restrict__ mb,
                                                    const double* __restrict__ x, double* __restrict__ P,
-                                                   double* __restrict__ Cm) {
+                                                   double* __restrict__ Cm, const MinresState* __restrict__ mask) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int4 it = slabs[blockIdx.x];
     const DevPatch& pa = dps[it.x];
+    if (mask && mask[pa.prob].stop) return;
     const int l = it.y, i3 = it.z;
     const int n1 = pa.n[0], n2 = pa.n[1], n12 = n1 * n2;
     const int p = pa.p, W = 2 * p + 1;
@@ -670,9 +675,10 @@ __global__ void __launch_bounds__(kBlock) k_ahat12(const DevPatch* __restrict__ 
 __global__ void __launch_bounds__(kBlock) k_ahat3(const DevPatch* __restrict__ dps, const int4* __restrict__ rb,
                                                   const double* __restrict__ kb, const double* __restrict__ mb,
                                                   const double* __restrict__ P, const double* __restrict__ Cm,
-                                                  double* __restrict__ y, int use_h) {
+                                                  double* __restrict__ y, int use_h, const MinresState* __restrict__ mask) {
     const int4 b = rb[blockIdx.x];
     const DevPatch& pa = dps[b.x];
+    if (mask && mask[pa.prob].stop) return;
     const int64_t node = (int64_t)b.z + threadIdx.x;
     if (node >= pa.nodes) return;
     const int l = b.y;
@@ -995,8 +1001,9 @@ __global__ void __launch_bounds__(kBlock) k_mask_interior(const DevPatch* __rest
 
 template <int DIM, int P>
 void stiffness_t(const DevPatch* dp, const int4* rb, int nrb, const double* A, const double* x, double* y,
-                 const int64_t* bp, const int* br, const double* bs, const double* t, hipStream_t s) {
-    hipLaunchKernelGGL((k_stiffness<DIM, P>), dim3(nrb), dim3(kBlock), 0, s, dp, rb, A, x, y, bp, br, bs, t);
+                 const int64_t* bp, const int* br, const double* bs, const double* t, const MinresState* mask,
+                 hipStream_t s) {
+    hipLaunchKernelGGL((k_stiffness<DIM, P>), dim3(nrb), dim3(kBlock), 0, s, dp, rb, A, x, y, bp, br, bs, t, mask);
 }
 
 }  // namespace
@@ -1004,27 +1011,26 @@ void stiffness_t(const DevPatch* dp, const int4* rb, int nrb, const double* A, c
 // ======================================================== launch wrappers
 void launch_fd(int prec, const FdTensor* tens, int n_tensors, const int2* slabs, int n_slabs, const int2* cols,
                int n_colblocks, const void* ut, const double* dt, const double* in, double* out, void* tmp,
-               int max_n, hipStream_t s) {
+               const MinresState* mask, hipStream_t s) {
     (void)n_tensors;
-    (void)max_n;
     if (prec == 0) {
         const size_t sh12 = 3 * kMaxN * kMaxN * sizeof(double);
         const size_t sh3 = (2 * kMaxN * 32 + kMaxN * kMaxN) * sizeof(double);
         hipLaunchKernelGGL(k_fd_fwd12<double>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
-                           (const double*)ut, in, (double*)tmp);
+                           (const double*)ut, in, (double*)tmp, mask);
         hipLaunchKernelGGL(k_fd_mid3<double>, dim3(n_colblocks), dim3(kBlock), sh3, s, tens, cols,
-                           (const double*)ut, dt, (double*)tmp);
+                           (const double*)ut, dt, (double*)tmp, mask);
         hipLaunchKernelGGL(k_fd_bwd12<double>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
-                           (const double*)ut, (const double*)tmp, out);
+                           (const double*)ut, (const double*)tmp, out, mask);
     } else {
         const size_t sh12 = 3 * kMaxN * kMaxN * sizeof(float);
         const size_t sh3 = (2 * kMaxN * 32 + kMaxN * kMaxN) * sizeof(float);
         hipLaunchKernelGGL(k_fd_fwd12<float>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
-                           (const float*)ut, in, (float*)tmp);
+                           (const float*)ut, in, (float*)tmp, mask);
         hipLaunchKernelGGL(k_fd_mid3<float>, dim3(n_colblocks), dim3(kBlock), sh3, s, tens, cols,
-                           (const float*)ut, dt, (float*)tmp);
+                           (const float*)ut, dt, (float*)tmp, mask);
         hipLaunchKernelGGL(k_fd_bwd12<float>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
-                           (const float*)ut, (const float*)tmp, out);
+                           (const float*)ut, (const float*)tmp, out, mask);
     }
 }
 
@@ -1111,21 +1117,22 @@ int launch_mdot(const double* F, int64_t n, int n_modes, int64_t off, const doub
 
 void launch_stiffness_dp(int dim, int p, const DevPatch* dp, const int4* rb, int nrb, const double* A,
                          const double* x, double* y, const int64_t* bp, const int* br, const double* bs,
-                         const double* t, hipStream_t s) {
+                         const double* t, const MinresState* mask, hipStream_t s) {
     if (nrb == 0) return;
     if (dim == 3) {
-        AFIETI_DISPATCH_P(3, stiffness_t, dp, rb, nrb, A, x, y, bp, br, bs, t, s)
+        AFIETI_DISPATCH_P(3, stiffness_t, dp, rb, nrb, A, x, y, bp, br, bs, t, mask, s)
     } else {
-        AFIETI_DISPATCH_P(2, stiffness_t, dp, rb, nrb, A, x, y, bp, br, bs, t, s)
+        AFIETI_DISPATCH_P(2, stiffness_t, dp, rb, nrb, A, x, y, bp, br, bs, t, mask, s)
     }
 }
 
 void launch_ahat(const DevPatch* dp, const int4* slabs, int n_slabs, const int4* rb, int nrb, const double* kb,
-                 const double* mb, const double* x, double* P, double* Cm, double* y, int use_h, hipStream_t s) {
+                 const double* mb, const double* x, double* P, double* Cm, double* y, int use_h,
+                 const MinresState* mask, hipStream_t s) {
     if (n_slabs)
         hipLaunchKernelGGL(k_ahat12, dim3(n_slabs), dim3(kBlock), 3 * kMaxN * kMaxN * sizeof(double), s, dp, slabs, kb,
-                           mb, x, P, Cm);
-    if (nrb) hipLaunchKernelGGL(k_ahat3, dim3(nrb), dim3(kBlock), 0, s, dp, rb, kb, mb, P, Cm, y, use_h);
+                           mb, x, P, Cm, mask);
+    if (nrb) hipLaunchKernelGGL(k_ahat3, dim3(nrb), dim3(kBlock), 0, s, dp, rb, kb, mb, P, Cm, y, use_h, mask);
 }
 
 void launch_mask_interior(const DevPatch* dp, const int4* rb, int nrb, double* y, hipStream_t s) {
