@@ -67,6 +67,15 @@ extern "C" {
 #define AFIETI_PS_NR 0
 #define AFIETI_PS_PLAIN 1
 
+/* how the patch stiffness A^(k) is applied: AUTO = matrix-free where
+ * possible (3D, C^{p-1}, p <= 6; sum-factorised Gauss quadrature of the
+ * bilinear form of Section 3), assembled stencil elsewhere; ASSEMBLED =
+ * always the assembled FP64 stencil; MATRIX_FREE = always matrix-free
+ * (EUNSUPPORTED where not possible).  Both apply the same quadrature. */
+#define AFIETI_STIFFNESS_AUTO 0
+#define AFIETI_STIFFNESS_ASSEMBLED 1
+#define AFIETI_STIFFNESS_MATRIX_FREE 2
+
 /* One patch (Section 2.2).  Corner index a1 + 2 a2 + 4 a3 (a_l in {0,1}),
  * coordinates corners[3*index + x] (2D: only the first 4 corners and x < 2
  * are read).  face_bc order: (dir1 min, dir1 max, dir2 min, dir2 max, dir3
@@ -106,6 +115,7 @@ typedef struct {
     int use_graph;       /* 1: replay MINRES iterations as a captured HIP
                             graph (6 iterations per launch) on a stream the
                             handle owns; 0: enqueue kernels one by one     */
+    int stiffness;       /* AFIETI_STIFFNESS_*                             */
 } afieti_options;
 
 typedef struct {

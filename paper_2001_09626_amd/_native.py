@@ -15,6 +15,7 @@ ERRORS = {-1: "EINVAL", -2: "EGEOM", -3: "ESINGULAR", -4: "EBREAKDOWN",
 
 FD_PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 PS_VARIANT = {"nr": 0, "plain": 1}
+STIFFNESS = {"auto": 0, "assembled": 1, "matrix_free": 2}
 
 OPS = {"stiffness": 0, "B": 1, "Bt": 2, "P_u": 3, "P_chi": 4, "Shat": 5, "P_S": 6,
        "prec": 7, "saddle": 8, "fd_interior": 9, "Ahat": 10, "mass": 11, "load": 12}
@@ -41,7 +42,7 @@ class Problem(C.Structure):
 class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("fd_precision", C.c_int),
                 ("ps_variant", C.c_int), ("check_every", C.c_int), ("host_only", C.c_int),
-                ("use_graph", C.c_int)]
+                ("use_graph", C.c_int), ("stiffness", C.c_int)]
 
 
 class Info(C.Structure):

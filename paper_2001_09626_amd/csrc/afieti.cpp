@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -30,10 +31,12 @@ namespace {
             throw SetupError{AFIETI_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
     } while (0)
 
-struct RowClass {       // row blocks of the patches sharing (dim, p)
-    int dim, p;
+struct RowClass {       // row blocks of the patches sharing (dim, p, stiffness mode)
+    int dim, p, mf;
     int4* d_rb = nullptr;
     int n = 0;
+    int4* d_bricks = nullptr;  // matrix-free bricks (patch, b1, b2, b3)
+    int n_bricks = 0;
 };
 
 struct FdSet {          // tensors of one FD operator (P_A or interior)
@@ -65,6 +68,8 @@ struct afieti_handle {
     int *d_elf = nullptr, *d_ell = nullptr;
     double *d_kband = nullptr, *d_mband = nullptr;
     double* d_stencil = nullptr;
+    double* d_qx = nullptr;
+    double* d_ybuf = nullptr;  // matrix-free per-brick partial results
     double* d_geo = nullptr;
     double* d_load = nullptr;
     std::vector<double*> d_F;              // per problem: unit-amplitude mode loads [mode][dof]
@@ -220,6 +225,7 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
 void assemble_all(afieti_handle* h, hipStream_t s) {
     for (int k = 0; k < h->n_patches; ++k) {
         const DevPatch& hp = h->h_patches[k];
+        if (hp.mf) continue;  // the matrix-free operator reads lambda, mu at run time
         launch_geometry(h->d_patches, k, hp, h->d_ctrl, h->d_qval, h->d_qder, h->d_qfirst, h->d_qw, h->d_geo, s);
         launch_assemble(h->d_patches, k, hp, h->d_geo, h->d_qval, h->d_qder, h->d_qfirst, h->d_elf, h->d_ell,
                         h->d_stencil, hp.lam, hp.mu, s);
@@ -244,7 +250,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     const int np = (int)pl.patches.size();
     h->n_patches = np;
     // ---- patch descriptors and univariate tables
-    std::vector<double> ctrl, qval, qder, qw, kband, mband;
+    std::vector<double> ctrl, qval, qder, qw, qx, kband, mband;
     std::vector<int> qfirst, elf, ell;
     int64_t stencil = 0, geo_max = 0;
     h->h_patches.resize(np);
@@ -262,6 +268,35 @@ void device_setup(afieti_handle* h, hipStream_t s) {
         d.lam = P.lam;
         d.mu = P.mu;
         d.hscale = P.hscale;
+        for (int c = 0; c < 24; ++c) d.corners[c] = P.corners[c];
+        // Jacobian of the trilinear map: for direction a with the other two
+        // directions b < c, dF/deta_a = sum over the 4 edges along a of
+        // (X(end) - X(start)) times the bilinear weights in (eta_b, eta_c)
+        for (int aa = 0; aa < 3; ++aa) {
+            const int bb = aa == 0 ? 1 : 0, cc = aa == 2 ? 1 : 2;
+            for (int x = 0; x < 3; ++x) {
+                double e[2][2];
+                for (int sb = 0; sb < 2; ++sb)
+                    for (int sc = 0; sc < 2; ++sc) {
+                        const int c0 = (sb << bb) | (sc << cc), c1 = c0 | (1 << aa);
+                        e[sb][sc] = P.dim == 3 ? P.corners[3 * c1 + x] - P.corners[3 * c0 + x] : 0.0;
+                    }
+                double* o = &d.jcoef[(aa * 3 + x) * 4];
+                o[0] = e[0][0];
+                o[1] = e[1][0] - e[0][0];
+                o[2] = e[0][1] - e[0][0];
+                o[3] = e[1][1] - e[1][0] - e[0][1] + e[0][0];
+            }
+        }
+        // matrix-free stiffness: 3D, maximal continuity, p <= 6
+        const bool mf_ok = P.dim == 3 && P.reg == P.p - 1 && P.p <= 6;
+        d.mf = (h->opt.stiffness == AFIETI_STIFFNESS_MATRIX_FREE || h->opt.stiffness == AFIETI_STIFFNESS_AUTO) && mf_ok;
+        if (h->opt.stiffness == AFIETI_STIFFNESS_MATRIX_FREE && !mf_ok)
+            throw SetupError{AFIETI_EUNSUPPORTED, "matrix-free stiffness needs 3D C^{p-1} patches with p <= 6"};
+        for (int m = 0; m < 3; ++m) {
+            const int be = mf_brick_elems(P.p);
+            d.nb[m] = m < P.dim ? (P.dir[m].n_el + be - 1) / be : 1;
+        }
         const int W = 2 * P.p + 1;
         for (int m = 0; m < 3; ++m) {
             const Dir1D& D = P.dir[m];
@@ -274,6 +309,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
                 for (int q = 0; q < D.nq; ++q) {
                     qfirst.push_back(D.qfirst[q]);
                     qw.push_back(D.qw[q]);
+                    qx.push_back(D.qx[q]);
                     for (int t = 0; t < 9; ++t) {
                         qval.push_back(t <= P.p ? D.qval[(size_t)q * (P.p + 1) + t] : 0.0);
                         qder.push_back(t <= P.p ? D.qder[(size_t)q * (P.p + 1) + t] : 0.0);
@@ -298,7 +334,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
         const int64_t S = P.dim == 3 ? (int64_t)W * W * W : (int64_t)W * W;
         const int64_t per_node = (int64_t)P.dim * P.dim * S;
         d.stencil_off = stencil;
-        stencil += per_node * P.nodes;
+        if (!d.mf) stencil += per_node * P.nodes;
         d.geo_off = 0;
         geo_max = std::max(geo_max, (int64_t)d.nq[0] * d.nq[1] * d.nq[2] * 13);
     }
@@ -307,6 +343,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     h->d_qval = h->upload(qval, s);
     h->d_qder = h->upload(qder, s);
     h->d_qw = h->upload(qw, s);
+    h->d_qx = h->upload(qx, s);
     h->d_qfirst = h->upload(qfirst, s);
     h->d_elf = h->upload(elf, s);
     h->d_ell = h->upload(ell, s);
@@ -316,11 +353,11 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     h->stencil_bytes = stencil * 8;
     h->d_geo = h->dalloc<double>(geo_max);
     h->d_load = h->dalloc<double>(pl.n_dof);
-    // row blocks by (dim, p)
-    std::map<std::pair<int, int>, std::vector<int4>> rbs;
+    // row blocks by (dim, p, matrix-free)
+    std::map<std::tuple<int, int, int>, std::vector<int4>> rbs;
     for (int k = 0; k < np; ++k) {
         const PatchPlan& P = pl.patches[k];
-        auto& v = rbs[{P.dim, P.p}];
+        auto& v = rbs[{P.dim, P.p, h->h_patches[k].mf}];
         for (int c = 0; c < P.dim; ++c)
             for (int64_t n0 = 0; n0 < P.nodes; n0 += kBlock) v.push_back(make_int4(k, c, (int)n0, 0));
     }
@@ -338,14 +375,35 @@ void device_setup(afieti_handle* h, hipStream_t s) {
         h->n_ahat_slabs = (int)sl.size();
         h->d_ahat_slabs = h->upload(sl, s);
     }
+    int64_t ybuf = 0;
     for (auto& kv : rbs) {
         RowClass rc;
-        rc.dim = kv.first.first;
-        rc.p = kv.first.second;
+        rc.dim = std::get<0>(kv.first);
+        rc.p = std::get<1>(kv.first);
+        rc.mf = std::get<2>(kv.first);
         rc.n = (int)kv.second.size();
         rc.d_rb = h->upload(kv.second, s);
+        if (rc.mf) {
+            std::vector<int4> bricks;
+            const int be = mf_brick_elems(rc.p), nbd = be + rc.p;
+            for (int k = 0; k < np; ++k) {
+                DevPatch& d = h->h_patches[k];
+                if (!d.mf || d.p != rc.p) continue;
+                d.brick_off = (int64_t)bricks.size();
+                d.ybuf_off = ybuf;
+                for (int b3 = 0; b3 < d.nb[2]; ++b3)
+                    for (int b2 = 0; b2 < d.nb[1]; ++b2)
+                        for (int b1 = 0; b1 < d.nb[0]; ++b1) bricks.push_back(make_int4(k, b1, b2, b3));
+                ybuf += (int64_t)d.nb[0] * d.nb[1] * d.nb[2] * 3 * nbd * nbd * nbd;
+            }
+            rc.n_bricks = (int)bricks.size();
+            rc.d_bricks = h->upload(bricks, s);
+        }
         h->classes.push_back(rc);
     }
+    h->d_ybuf = h->dalloc<double>(ybuf);
+    HIP_OK(hipMemcpyAsync(h->d_patches, h->h_patches.data(), h->h_patches.size() * sizeof(DevPatch),
+                          hipMemcpyHostToDevice, s));
     // ---- unit-amplitude mode loads F_j per problem, then stencils and the load
     int64_t maxnq = 1;
     for (const auto& hp : h->h_patches) maxnq = std::max(maxnq, (int64_t)hp.nq[0] * hp.nq[1] * hp.nq[2]);
@@ -373,8 +431,9 @@ void device_setup(afieti_handle* h, hipStream_t s) {
         const PatchPlan& P = pl.patches[k];
         const ProblemPlan& pr = pl.probs[P.prob];
         launch_geometry(h->d_patches, k, hp, h->d_ctrl, h->d_qval, h->d_qder, h->d_qfirst, h->d_qw, h->d_geo, s);
-        launch_assemble(h->d_patches, k, hp, h->d_geo, h->d_qval, h->d_qder, h->d_qfirst, h->d_elf, h->d_ell,
-                        h->d_stencil, P.lam, P.mu, s);
+        if (!hp.mf)
+            launch_assemble(h->d_patches, k, hp, h->d_geo, h->d_qval, h->d_qder, h->d_qfirst, h->d_elf, h->d_ell,
+                            h->d_stencil, P.lam, P.mu, s);
         for (size_t m = 0; m < pr.load.size(); ++m)
             launch_load(h->d_patches, k, hp, h->d_geo, h->d_qval, h->d_qfirst, h->d_elf, h->d_ell,
                         h->d_unit_modes[P.prob] + 8 * m, 1, h->d_F[P.prob] + (int64_t)m * pr.n_dof, pr.dof_off, s);
@@ -497,9 +556,15 @@ void device_setup(afieti_handle* h, hipStream_t s) {
 
 // ------------------------------------------------------------- operators
 void op_stiffness(afieti_handle* h, const double* x, double* y, const double* t, hipStream_t s) {
-    for (const auto& rc : h->classes)
-        launch_stiffness_dp(rc.dim, rc.p, h->d_patches, rc.d_rb, rc.n, h->d_stencil, x, y, h->d_btptr, h->d_btrow,
-                            h->d_btsgn, t, h->mask, s);
+    for (const auto& rc : h->classes) {
+        if (rc.mf)
+            launch_stiffness_mf(rc.p, h->d_patches, rc.d_bricks, rc.n_bricks, rc.d_rb, rc.n, h->d_qval, h->d_qder,
+                                h->d_qfirst, h->d_qx, h->d_qw, x, h->d_ybuf, y, h->d_btptr, h->d_btrow, h->d_btsgn, t,
+                                h->mask, s);
+        else
+            launch_stiffness_dp(rc.dim, rc.p, h->d_patches, rc.d_rb, rc.n, h->d_stencil, x, y, h->d_btptr, h->d_btrow,
+                                h->d_btsgn, t, h->mask, s);
+    }
 }
 
 void op_mask_interior(afieti_handle* h, double* y, hipStream_t s) {
@@ -746,6 +811,7 @@ void afieti_default_options(afieti_options* opt) {
     opt->check_every = 8;
     opt->host_only = 0;
     opt->use_graph = 1;
+    opt->stiffness = AFIETI_STIFFNESS_AUTO;
 }
 
 const char* afieti_strerror(int code) {

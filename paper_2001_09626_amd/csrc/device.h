@@ -26,6 +26,12 @@ struct DevPatch {
     int el_off[3];               // offsets into the per-basis element ranges
     int dim, p, prob, nmodes;
     double lam, mu, hscale;
+    double corners[24];          // multilinear patch map (corner a1 + 2 a2 + 4 a3)
+    double jcoef[36];            // dF_x/deta_a = c0 + c1 eta_b + c2 eta_c + c3 eta_b eta_c, [a][x][4]
+    int nb[3];                   // matrix-free bricks per direction
+    int mf;                      // 1: stiffness applied matrix-free
+    int64_t brick_off;           // first brick of the patch in the brick list
+    int64_t ybuf_off;            // offset (in doubles) of its bricks' partial results
 };
 
 // One tensor of an FD solve (a patch/component pair, or its interior).
