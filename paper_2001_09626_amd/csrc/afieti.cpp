@@ -42,8 +42,9 @@ struct RowClass {       // row blocks of the patches sharing (dim, p, stiffness 
 struct FdSet {          // tensors of one FD operator (P_A or interior)
     FdTensor* d_t = nullptr;
     int2* d_slabs = nullptr;
-    int2* d_cols = nullptr;
-    int n_t = 0, n_slabs = 0, n_cols = 0;
+    int2* d_cols = nullptr;    // 32-column blocks (VALU pass 2)
+    int2* d_cols64 = nullptr;  // 64-column blocks (MFMA pass 2)
+    int n_t = 0, n_slabs = 0, n_cols = 0, n_cols64 = 0;
     int64_t tmp_elems = 0;
 };
 
@@ -166,7 +167,7 @@ void add_chunks(std::vector<Chunk>& out, int64_t b, int64_t e, int seg, int size
 void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector<int>& u_off,
                   const std::vector<int>& d_off, hipStream_t s) {
     std::vector<FdTensor> ts;
-    std::vector<int2> slabs, cols;
+    std::vector<int2> slabs, cols, cols64;
     int64_t tmp = 0;
     for (size_t k = 0; k < h->plan.patches.size(); ++k) {
         const PatchPlan& P = h->plan.patches[k];
@@ -205,6 +206,8 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
             for (int i3 = 0; i3 < t.n3; ++i3) slabs.push_back(make_int2(ti, i3));
             int ncb = (t.n1 * t.n2 + 31) / 32;
             for (int cb = 0; cb < ncb; ++cb) cols.push_back(make_int2(ti, cb));
+            int ncb64 = (t.n1 * t.n2 + 63) / 64;
+            for (int cb = 0; cb < ncb64; ++cb) cols64.push_back(make_int2(ti, cb));
         }
     }
     if (set.d_t) {  // parameters changed: rewrite the descriptors in place
@@ -219,6 +222,8 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
     set.d_t = h->upload(ts, s);
     set.d_slabs = h->upload(slabs, s);
     set.d_cols = h->upload(cols, s);
+    set.n_cols64 = (int)cols64.size();
+    set.d_cols64 = h->upload(cols64, s);
 }
 
 // stiffness stencils of every patch (Gauss-point geometry, then assembly)
@@ -577,8 +582,14 @@ void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_
 }
 
 void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s) {
-    int prec = h->opt.fd_precision == AFIETI_FD_FP64 ? 0 : 1;
-    launch_fd(prec, set.d_t, set.n_t, set.d_slabs, set.n_slabs, set.d_cols, set.n_cols,
+    int prec = 0;
+    switch (h->opt.fd_precision) {
+        case AFIETI_FD_FP32: prec = 2; break;       // MFMA, FP32 operands
+        case AFIETI_FD_BF16: prec = 3; break;       // MFMA, BF16 operands
+        case AFIETI_FD_FP32_VALU: prec = 1; break;  // vector ALU, FP32
+        default: prec = 0;                          // vector ALU, FP64
+    }
+    launch_fd(prec, set.d_t, set.n_t, set.d_slabs, set.n_slabs, set.d_cols, set.n_cols, set.d_cols64, set.n_cols64,
               prec == 0 ? (const void*)h->d_u64 : (const void*)h->d_u32, h->d_dtab, in, out, h->d_fdtmp, h->mask, s);
 }
 
@@ -841,11 +852,9 @@ int afieti_setup(const afieti_problem* probs, int n_problems, const afieti_optio
         if (opt) h->opt = *opt;
         else afieti_default_options(&h->opt);
         if (!(h->opt.tol > 0) || h->opt.maxit < 1 ||
-            (h->opt.fd_precision < AFIETI_FD_FP64 || h->opt.fd_precision > AFIETI_FD_BF16) ||
+            (h->opt.fd_precision < AFIETI_FD_FP64 || h->opt.fd_precision > AFIETI_FD_FP32_VALU) ||
             (h->opt.ps_variant != AFIETI_PS_NR && h->opt.ps_variant != AFIETI_PS_PLAIN))
             throw SetupError{AFIETI_EINVAL, "invalid options"};
-        if (h->opt.fd_precision == AFIETI_FD_BF16)
-            throw SetupError{AFIETI_EUNSUPPORTED, "BF16 FD is not available in this build"};
         h->plan = build_plan(probs, n_problems);
         h->n_probs = (int)h->plan.probs.size();
         h->n_patches = (int)h->plan.patches.size();

@@ -8,11 +8,13 @@
 namespace afieti {
 
 // ---- Fast Diagonalization (Algorithm 1): three passes over the tensors.
-// prec: 0 FP64, 1 FP32 mode products.  Kernels of problems whose MINRES has
+// Kernels of problems whose MINRES has
 // stopped (mask[prob].stop != 0) return at once; mask may be NULL.
+// prec 0: FP64 (VALU); 1: FP32 (VALU); 2: FP32 on MFMA; 3: BF16 on MFMA (FP32
+// accumulation).  d_cols: 32-column blocks (VALU), d_cols64: 64-column blocks (MFMA).
 void launch_fd(int prec, const FdTensor* d_tensors, int n_tensors,
                const int2* d_slabs, int n_slabs, const int2* d_cols, int n_colblocks,
-               const void* u_table, const double* d_table,
+               const int2* d_cols64, int n_colblocks64, const void* u_table, const double* d_table,
                const double* in, double* out, void* tmp, const MinresState* mask, hipStream_t s);
 
 // ---- setup kernels

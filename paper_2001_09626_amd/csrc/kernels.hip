@@ -17,6 +17,8 @@
 // identical.  No atomics.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.h"
 #include "kernels.h"
 #include "rigid.h"
@@ -170,6 +172,219 @@ __global__ void __launch_bounds__(kBlock) k_fd_bwd12(const FdTensor* __restrict_
         T acc = 0;
         for (int a2 = 0; a2 < n2; ++a2) acc += U[i2 * n2 + a2] * Y[a2 * n1 + i1];
         dst[(int64_t)i2 * t.s2 + i1] = t.alpha * (double)acc;
+    }
+}
+
+// ================================================== FD on MFMA (FP32, BF16)
+// The same three passes with the slab and column GEMMs on the matrix cores:
+// v_mfma_f32_16x16x4_f32 (FP32 operands) or v_mfma_f32_16x16x32_bf16 (BF16
+// operands), FP32 accumulation.  Operand tiles are staged in LDS, zero
+// padded to multiples of 16 (rows/columns) and of the MFMA depth K, so the
+// inner loops carry no bounds checks.  Lane layout (wave64): A element
+// (row l%16, k-group l/16), B element (k-group l/16, column l%16), result
+// rows 4(l/16)+r, column l%16 in accumulator register r.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kNP = 48;       // padded tile rows/columns (n <= 48)
+constexpr int kLD = kNP + 4;  // LDS leading dimension (bank spread)
+
+template <bool BF16>
+struct MfmaK {
+    static constexpr int K = BF16 ? 32 : 4;                   // depth of one instruction
+    static constexpr int KP = BF16 ? 64 : kNP;                // padded depth of a 48-wide contraction
+    using T = typename std::conditional<BF16, __bf16, float>::type;
+};
+
+// C tile (16x16 at rows m0, cols n0) += sum_k A(m, k) B(k, n) with
+// A(m, k) = At ? a[k * lda + m] : a[m * lda + k], B(k, n) = Bt ? b[n * ldb + k] : b[k * ldb + n]
+template <bool BF16, bool At, bool Bt>
+__device__ inline floatx4 mfma_tile(const typename MfmaK<BF16>::T* __restrict__ a, int lda,
+                                    const typename MfmaK<BF16>::T* __restrict__ b, int ldb, int m0, int n0, int kdim) {
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (!BF16) {
+        for (int k0 = 0; k0 < kdim; k0 += 4) {
+            const int k = k0 + g;
+            const float av = At ? a[k * lda + m0 + r] : a[(m0 + r) * lda + k];
+            const float bv = Bt ? b[(n0 + r) * ldb + k] : b[k * ldb + n0 + r];
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        }
+    } else {
+        for (int k0 = 0; k0 < kdim; k0 += 32) {
+            bf16x8 av, bv;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const int k = k0 + 8 * g + v;
+                av[v] = At ? a[k * lda + m0 + r] : a[(m0 + r) * lda + k];
+                bv[v] = Bt ? b[(n0 + r) * ldb + k] : b[k * ldb + n0 + r];
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        }
+    }
+    return acc;
+}
+
+// stage a rows x cols block (row stride src_ld in global) into LDS as T,
+// zero padded to prow x pcol with leading dimension ld
+template <typename T, typename S>
+__device__ inline void stage(T* dst, int ld, int prow, int pcol, const S* src, int64_t src_ld, int rows, int cols) {
+    for (int e = threadIdx.x; e < prow * pcol; e += kBlock) {
+        const int i = e / pcol, j = e - i * pcol;
+        dst[i * ld + j] = (i < rows && j < cols) ? (T)(float)src[(int64_t)i * src_ld + j] : (T)0.f;
+    }
+}
+
+__device__ inline int pad16(int n) { return (n + 15) & ~15; }
+
+// Pass 1: Y = X U1 (rows i2, cols a1), Z = U2^T Y, per slab i3 -> tmp (FP32)
+template <bool BF16>
+__global__ void __launch_bounds__(kBlock) k_fdm_fwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
+                                                      const float* __restrict__ ut, const double* __restrict__ in,
+                                                      float* __restrict__ tmp, const MinresState* __restrict__ mask) {
+    using T = typename MfmaK<BF16>::T;
+    constexpr int KP = MfmaK<BF16>::KP;
+    constexpr int LDK = KP + 4;
+    __shared__ T X[kNP * LDK];      // [i2][i1]
+    __shared__ T Y[KP * kLD];       // [i2][a1]  (rows padded to the depth of the next GEMM)
+    __shared__ T U1[KP * kLD];      // [i1][a1]
+    __shared__ T U2[KP * kLD];      // [i2][a2]
+    const int2 it = slabs[blockIdx.x];
+    const FdTensor t = tens[it.x];
+    if (mask && mask[t.prob].stop) return;
+    const int i3 = it.y, n1 = t.n1, n2 = t.n2;
+    const int p1 = pad16(n1), p2 = pad16(n2);
+    const int k1 = BF16 ? ((n1 + 31) & ~31) : p1, k2 = BF16 ? ((n2 + 31) & ~31) : p2;
+    stage(X, LDK, p2, k1, in + t.in_off + (int64_t)i3 * t.s3, t.s2, n2, n1);
+    stage(U1, kLD, k1, p1, ut + t.u_off[0], n1, n1, n1);
+    stage(U2, kLD, k2, p2, ut + t.u_off[1], n2, n2, n2);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int t1 = p1 / 16, tiles1 = (p2 / 16) * t1;
+    for (int tl = wave; tl < tiles1; tl += kBlock / 64) {
+        const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
+        floatx4 acc = mfma_tile<BF16, false, false>(X, LDK, U1, kLD, m0, n0, k1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Y[(m0 + 4 * g + q) * kLD + n0 + r] = (T)acc[q];
+    }
+    for (int e = threadIdx.x; e < (k2 - p2) * kLD; e += kBlock) Y[p2 * kLD + e] = (T)0.f;  // depth padding
+    __syncthreads();
+    float* dst = tmp + t.tmp_off + (int64_t)i3 * n1 * n2;
+    const int tiles2 = (p2 / 16) * t1;
+    for (int tl = wave; tl < tiles2; tl += kBlock / 64) {
+        const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
+        floatx4 acc = mfma_tile<BF16, true, false>(U2, kLD, Y, kLD, m0, n0, k2);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int a2 = m0 + 4 * g + q, a1 = n0 + r;
+            if (a2 < n2 && a1 < n1) dst[a2 * n1 + a1] = acc[q];
+        }
+    }
+}
+
+// Pass 2: per block of 64 columns c = (a2, a1): Zt = U3^T Zc, divide by Lambda,
+// W = U3 Zt, written back in place
+template <bool BF16>
+__global__ void __launch_bounds__(kBlock) k_fdm_mid3(const FdTensor* __restrict__ tens, const int2* __restrict__ cols,
+                                                     const float* __restrict__ ut, const double* __restrict__ dt,
+                                                     float* __restrict__ tmp, const MinresState* __restrict__ mask) {
+    using T = typename MfmaK<BF16>::T;
+    constexpr int NC = 64;
+    constexpr int KP = MfmaK<BF16>::KP;
+    constexpr int LDC = NC + 4;
+    constexpr int LDU = KP + 4;  // U3 is read along both indices up to the depth KP
+    __shared__ T Zc[KP * LDC];   // [i3][c]
+    __shared__ T Zt[KP * LDC];   // [a3][c]
+    __shared__ T U3[KP * LDU];   // [i3][a3]
+    const int2 it = cols[blockIdx.x];
+    const FdTensor t = tens[it.x];
+    if (mask && mask[t.prob].stop) return;
+    const int n1 = t.n1, n3 = t.n3, n12 = t.n1 * t.n2;
+    const int p3 = pad16(n3), k3 = BF16 ? ((n3 + 31) & ~31) : p3;
+    const int col0 = it.y * NC;
+    float* base = tmp + t.tmp_off;
+    for (int e = threadIdx.x; e < k3 * NC; e += kBlock) {
+        const int i3 = e / NC, c = e - i3 * NC, col = col0 + c;
+        Zc[i3 * LDC + c] = (i3 < n3 && col < n12) ? (T)base[(int64_t)i3 * n12 + col] : (T)0.f;
+    }
+    stage(U3, LDU, k3, k3, ut + t.u_off[2], n3, n3, n3);
+    for (int e = threadIdx.x; e < (k3 - p3) * LDC; e += kBlock) Zt[p3 * LDC + e] = (T)0.f;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int tiles = (p3 / 16) * (NC / 16);
+    for (int tl = wave; tl < tiles; tl += kBlock / 64) {
+        const int m0 = (tl / (NC / 16)) * 16, n0 = (tl % (NC / 16)) * 16;
+        floatx4 acc = mfma_tile<BF16, true, false>(U3, LDU, Zc, LDC, m0, n0, k3);
+        const int col = col0 + n0 + r;
+        const int a2 = col / n1, a1 = col - a2 * n1;
+        double lam12 = 0.0;
+        if (col < n12) lam12 = t.mass + t.kappa[0] * dt[t.d_off[0] + a1] + t.kappa[1] * dt[t.d_off[1] + a2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int a3 = m0 + 4 * g + q;
+            float v = 0.f;
+            if (a3 < n3 && col < n12) v = (float)((double)acc[q] / (t.scale * (lam12 + t.kappa[2] * dt[t.d_off[2] + a3])));
+            Zt[a3 * LDC + n0 + r] = (T)v;
+        }
+    }
+    __syncthreads();
+    for (int tl = wave; tl < tiles; tl += kBlock / 64) {
+        const int m0 = (tl / (NC / 16)) * 16, n0 = (tl % (NC / 16)) * 16;
+        floatx4 acc = mfma_tile<BF16, false, false>(U3, LDU, Zt, LDC, m0, n0, k3);
+        const int col = col0 + n0 + r;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i3 = m0 + 4 * g + q;
+            if (i3 < n3 && col < n12) base[(int64_t)i3 * n12 + col] = acc[q];
+        }
+    }
+}
+
+// Pass 3: Y = Z U1^T (rows a2, cols i1), X = U2 Y, alpha X -> FP64 output
+template <bool BF16>
+__global__ void __launch_bounds__(kBlock) k_fdm_bwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
+                                                      const float* __restrict__ ut, const float* __restrict__ tmp,
+                                                      double* __restrict__ out, const MinresState* __restrict__ mask) {
+    using T = typename MfmaK<BF16>::T;
+    constexpr int KP = MfmaK<BF16>::KP;
+    constexpr int LDK = KP + 4;
+    __shared__ T Z[kNP * LDK];     // [a2][a1]
+    __shared__ T Y[KP * kLD];      // [a2][i1]
+    __shared__ T U1[kNP * LDK];    // [i1][a1]
+    __shared__ T U2[kNP * LDK];    // [i2][a2]
+    const int2 it = slabs[blockIdx.x];
+    const FdTensor t = tens[it.x];
+    if (mask && mask[t.prob].stop) return;
+    const int i3 = it.y, n1 = t.n1, n2 = t.n2;
+    const int p1 = pad16(n1), p2 = pad16(n2);
+    const int k1 = BF16 ? ((n1 + 31) & ~31) : p1, k2 = BF16 ? ((n2 + 31) & ~31) : p2;
+    stage(Z, LDK, p2, k1, tmp + t.tmp_off + (int64_t)i3 * n1 * n2, n1, n2, n1);
+    stage(U1, LDK, p1, k1, ut + t.u_off[0], n1, n1, n1);
+    stage(U2, LDK, p2, k2, ut + t.u_off[1], n2, n2, n2);
+    for (int e = threadIdx.x; e < (k2 - p2) * kLD; e += kBlock) Y[p2 * kLD + e] = (T)0.f;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int t1 = p1 / 16, tiles = (p2 / 16) * t1;
+    for (int tl = wave; tl < tiles; tl += kBlock / 64) {
+        const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
+        floatx4 acc = mfma_tile<BF16, false, true>(Z, LDK, U1, LDK, m0, n0, k1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Y[(m0 + 4 * g + q) * kLD + n0 + r] = (T)acc[q];
+    }
+    __syncthreads();
+    double* dst = out + t.out_off + (int64_t)i3 * t.s3;
+    for (int tl = wave; tl < tiles; tl += kBlock / 64) {
+        const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
+        floatx4 acc = mfma_tile<BF16, false, false>(U2, LDK, Y, kLD, m0, n0, k2);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i2 = m0 + 4 * g + q, i1 = n0 + r;
+            if (i2 < n2 && i1 < n1) dst[(int64_t)i2 * t.s2 + i1] = t.alpha * (double)acc[q];
+        }
     }
 }
 
@@ -1331,9 +1546,13 @@ void stiffness_t(const DevPatch* dp, const int4* rb, int nrb, const double* A, c
 
 // ======================================================== launch wrappers
 void launch_fd(int prec, const FdTensor* tens, int n_tensors, const int2* slabs, int n_slabs, const int2* cols,
-               int n_colblocks, const void* ut, const double* dt, const double* in, double* out, void* tmp,
-               const MinresState* mask, hipStream_t s) {
+               int n_colblocks, const int2* cols64, int n_colblocks64, const void* ut, const double* dt,
+               const double* in, double* out, void* tmp, const MinresState* mask, hipStream_t s) {
     (void)n_tensors;
+    if (prec == 2 || prec == 3) {
+        cols = cols64;
+        n_colblocks = n_colblocks64;
+    }
     if (prec == 0) {
         const size_t sh12 = 3 * kMaxN * kMaxN * sizeof(double);
         const size_t sh3 = (2 * kMaxN * 32 + kMaxN * kMaxN) * sizeof(double);
@@ -1343,6 +1562,23 @@ void launch_fd(int prec, const FdTensor* tens, int n_tensors, const int2* slabs,
                            (const double*)ut, dt, (double*)tmp, mask);
         hipLaunchKernelGGL(k_fd_bwd12<double>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
                            (const double*)ut, (const double*)tmp, out, mask);
+    } else if (prec == 2 || prec == 3) {
+        // MFMA: 2 = FP32 operands, 3 = BF16 operands; 64-column blocks in pass 2
+        if (prec == 2) {
+            hipLaunchKernelGGL(k_fdm_fwd12<false>, dim3(n_slabs), dim3(kBlock), 0, s, tens, slabs, (const float*)ut, in,
+                               (float*)tmp, mask);
+            hipLaunchKernelGGL(k_fdm_mid3<false>, dim3(n_colblocks), dim3(kBlock), 0, s, tens, cols, (const float*)ut,
+                               dt, (float*)tmp, mask);
+            hipLaunchKernelGGL(k_fdm_bwd12<false>, dim3(n_slabs), dim3(kBlock), 0, s, tens, slabs, (const float*)ut,
+                               (const float*)tmp, out, mask);
+        } else {
+            hipLaunchKernelGGL(k_fdm_fwd12<true>, dim3(n_slabs), dim3(kBlock), 0, s, tens, slabs, (const float*)ut, in,
+                               (float*)tmp, mask);
+            hipLaunchKernelGGL(k_fdm_mid3<true>, dim3(n_colblocks), dim3(kBlock), 0, s, tens, cols, (const float*)ut, dt,
+                               (float*)tmp, mask);
+            hipLaunchKernelGGL(k_fdm_bwd12<true>, dim3(n_slabs), dim3(kBlock), 0, s, tens, slabs, (const float*)ut,
+                               (const float*)tmp, out, mask);
+        }
     } else {
         const size_t sh12 = 3 * kMaxN * kMaxN * sizeof(float);
         const size_t sh3 = (2 * kMaxN * 32 + kMaxN * kMaxN) * sizeof(float);
