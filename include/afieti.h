@@ -58,12 +58,14 @@ extern "C" {
 
 /* precision of the FD mode products (Section 5.2.1, Algorithm 1); the
  * Krylov vectors, residuals and projections are always FP64.  FP32 and BF16
- * run on the matrix cores with FP32 accumulation; FP32_VALU is the FP32
- * vector-ALU path (for comparison). */
+ * run on the matrix cores with FP32 accumulation; FP64 runs on the vector
+ * ALU (measured faster than FP64 on the matrix cores at these sizes, which
+ * FP64_MFMA selects); FP32_VALU is the FP32 vector-ALU path. */
 #define AFIETI_FD_FP64 0
 #define AFIETI_FD_FP32 1
 #define AFIETI_FD_BF16 2
 #define AFIETI_FD_FP32_VALU 3
+#define AFIETI_FD_FP64_MFMA 4
 
 /* choice of P_S: non-redundant inexact (Remark 1, default) or plain
  * inexact (Section 5.2, eq. inexact_SP) */

@@ -587,10 +587,12 @@ void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hi
         case AFIETI_FD_FP32: prec = 2; break;       // MFMA, FP32 operands
         case AFIETI_FD_BF16: prec = 3; break;       // MFMA, BF16 operands
         case AFIETI_FD_FP32_VALU: prec = 1; break;  // vector ALU, FP32
-        default: prec = 0;                          // vector ALU, FP64
+        case AFIETI_FD_FP64_MFMA: prec = 4; break;  // MFMA, FP64
+        default: prec = 0;                          // vector ALU, FP64 (measured faster)
     }
+    const bool f64 = prec == 0 || prec == 4;
     launch_fd(prec, set.d_t, set.n_t, set.d_slabs, set.n_slabs, set.d_cols, set.n_cols, set.d_cols64, set.n_cols64,
-              prec == 0 ? (const void*)h->d_u64 : (const void*)h->d_u32, h->d_dtab, in, out, h->d_fdtmp, h->mask, s);
+              f64 ? (const void*)h->d_u64 : (const void*)h->d_u32, h->d_dtab, in, out, h->d_fdtmp, h->mask, s);
 }
 
 // out = P_chi y  (in place allowed)
@@ -852,7 +854,7 @@ int afieti_setup(const afieti_problem* probs, int n_problems, const afieti_optio
         if (opt) h->opt = *opt;
         else afieti_default_options(&h->opt);
         if (!(h->opt.tol > 0) || h->opt.maxit < 1 ||
-            (h->opt.fd_precision < AFIETI_FD_FP64 || h->opt.fd_precision > AFIETI_FD_FP32_VALU) ||
+            (h->opt.fd_precision < AFIETI_FD_FP64 || h->opt.fd_precision > AFIETI_FD_FP64_MFMA) ||
             (h->opt.ps_variant != AFIETI_PS_NR && h->opt.ps_variant != AFIETI_PS_PLAIN))
             throw SetupError{AFIETI_EINVAL, "invalid options"};
         h->plan = build_plan(probs, n_problems);

@@ -11,7 +11,7 @@ namespace afieti {
 // Kernels of problems whose MINRES has
 // stopped (mask[prob].stop != 0) return at once; mask may be NULL.
 // prec 0: FP64 (VALU); 1: FP32 (VALU); 2: FP32 on MFMA; 3: BF16 on MFMA (FP32
-// accumulation).  d_cols: 32-column blocks (VALU), d_cols64: 64-column blocks (MFMA).
+// accumulation); 4: FP64 on MFMA.  d_cols: 32-column blocks (VALU), d_cols64: 64-column blocks (MFMA).
 void launch_fd(int prec, const FdTensor* d_tensors, int n_tensors,
                const int2* d_slabs, int n_slabs, const int2* d_cols, int n_colblocks,
                const int2* d_cols64, int n_colblocks64, const void* u_table, const double* d_table,

@@ -184,32 +184,44 @@ __global__ void __launch_bounds__(kBlock) k_fd_bwd12(const FdTensor* __restrict_
 // (row l%16, k-group l/16), B element (k-group l/16, column l%16), result
 // rows 4(l/16)+r, column l%16 in accumulator register r.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kNP = 48;       // padded tile rows/columns (n <= 48)
 constexpr int kLD = kNP + 4;  // LDS leading dimension (bank spread)
 
-template <bool BF16>
+// MODE 0: FP32 operands (v_mfma_f32_16x16x4_f32), 1: BF16 operands
+// (v_mfma_f32_16x16x32_bf16), 2: FP64 (v_mfma_f64_16x16x4_f64).  Result row
+// of accumulator register q in lane group g: 4g + q (FP32 accumulators) or
+// g + 4q (FP64 accumulators).
+template <int MODE>
 struct MfmaK {
-    static constexpr int K = BF16 ? 32 : 4;                   // depth of one instruction
-    static constexpr int KP = BF16 ? 64 : kNP;                // padded depth of a 48-wide contraction
-    using T = typename std::conditional<BF16, __bf16, float>::type;
+    static constexpr int K = MODE == 1 ? 32 : 4;    // depth of one instruction
+    static constexpr int KP = MODE == 1 ? 64 : kNP; // padded depth of a 48-wide contraction
+    using T = typename std::conditional<MODE == 0, float, typename std::conditional<MODE == 1, __bf16, double>::type>::type;
+    using Acc = typename std::conditional<MODE == 2, doublex4, floatx4>::type;
+    using Tmp = typename std::conditional<MODE == 2, double, float>::type;  // between passes
+    using U = typename std::conditional<MODE == 2, double, float>::type;    // eigenvector table
+    __device__ static inline int row(int g, int q) { return MODE == 2 ? g + 4 * q : 4 * g + q; }
+    __device__ static inline int kpad(int n) { return MODE == 1 ? (n + 31) & ~31 : (n + 15) & ~15; }
 };
 
 // C tile (16x16 at rows m0, cols n0) += sum_k A(m, k) B(k, n) with
 // A(m, k) = At ? a[k * lda + m] : a[m * lda + k], B(k, n) = Bt ? b[n * ldb + k] : b[k * ldb + n]
-template <bool BF16, bool At, bool Bt>
-__device__ inline floatx4 mfma_tile(const typename MfmaK<BF16>::T* __restrict__ a, int lda,
-                                    const typename MfmaK<BF16>::T* __restrict__ b, int ldb, int m0, int n0, int kdim) {
+template <int MODE, bool At, bool Bt>
+__device__ inline typename MfmaK<MODE>::Acc mfma_tile(const typename MfmaK<MODE>::T* __restrict__ a, int lda,
+                                                      const typename MfmaK<MODE>::T* __restrict__ b, int ldb, int m0,
+                                                      int n0, int kdim) {
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    if constexpr (!BF16) {
+    typename MfmaK<MODE>::Acc acc = {0, 0, 0, 0};
+    if constexpr (MODE != 1) {
         for (int k0 = 0; k0 < kdim; k0 += 4) {
             const int k = k0 + g;
-            const float av = At ? a[k * lda + m0 + r] : a[(m0 + r) * lda + k];
-            const float bv = Bt ? b[(n0 + r) * ldb + k] : b[k * ldb + n0 + r];
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+            const auto av = At ? a[k * lda + m0 + r] : a[(m0 + r) * lda + k];
+            const auto bv = Bt ? b[(n0 + r) * ldb + k] : b[k * ldb + n0 + r];
+            if constexpr (MODE == 0) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+            else acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
     } else {
         for (int k0 = 0; k0 < kdim; k0 += 32) {
@@ -232,19 +244,25 @@ template <typename T, typename S>
 __device__ inline void stage(T* dst, int ld, int prow, int pcol, const S* src, int64_t src_ld, int rows, int cols) {
     for (int e = threadIdx.x; e < prow * pcol; e += kBlock) {
         const int i = e / pcol, j = e - i * pcol;
-        dst[i * ld + j] = (i < rows && j < cols) ? (T)(float)src[(int64_t)i * src_ld + j] : (T)0.f;
+        if constexpr (std::is_same<T, __bf16>::value)
+            dst[i * ld + j] = (i < rows && j < cols) ? (T)(float)src[(int64_t)i * src_ld + j] : (T)0.f;
+        else
+            dst[i * ld + j] = (i < rows && j < cols) ? (T)src[(int64_t)i * src_ld + j] : (T)0;
     }
 }
 
 __device__ inline int pad16(int n) { return (n + 15) & ~15; }
 
-// Pass 1: Y = X U1 (rows i2, cols a1), Z = U2^T Y, per slab i3 -> tmp (FP32)
-template <bool BF16>
+// Pass 1: Y = X U1 (rows i2, cols a1), Z = U2^T Y, per slab i3 -> tmp
+template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_fdm_fwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
-                                                      const float* __restrict__ ut, const double* __restrict__ in,
-                                                      float* __restrict__ tmp, const MinresState* __restrict__ mask) {
-    using T = typename MfmaK<BF16>::T;
-    constexpr int KP = MfmaK<BF16>::KP;
+                                                      const typename MfmaK<MODE>::U* __restrict__ ut,
+                                                      const double* __restrict__ in,
+                                                      typename MfmaK<MODE>::Tmp* __restrict__ tmp,
+                                                      const MinresState* __restrict__ mask) {
+    using M = MfmaK<MODE>;
+    using T = typename M::T;
+    constexpr int KP = M::KP;
     constexpr int LDK = KP + 4;
     __shared__ T X[kNP * LDK];      // [i2][i1]
     __shared__ T Y[KP * kLD];       // [i2][a1]  (rows padded to the depth of the next GEMM)
@@ -255,7 +273,7 @@ __global__ void __launch_bounds__(kBlock) k_fdm_fwd12(const FdTensor* __restrict
     if (mask && mask[t.prob].stop) return;
     const int i3 = it.y, n1 = t.n1, n2 = t.n2;
     const int p1 = pad16(n1), p2 = pad16(n2);
-    const int k1 = BF16 ? ((n1 + 31) & ~31) : p1, k2 = BF16 ? ((n2 + 31) & ~31) : p2;
+    const int k1 = M::kpad(n1), k2 = M::kpad(n2);
     stage(X, LDK, p2, k1, in + t.in_off + (int64_t)i3 * t.s3, t.s2, n2, n1);
     stage(U1, kLD, k1, p1, ut + t.u_off[0], n1, n1, n1);
     stage(U2, kLD, k2, p2, ut + t.u_off[1], n2, n2, n2);
@@ -265,20 +283,20 @@ __global__ void __launch_bounds__(kBlock) k_fdm_fwd12(const FdTensor* __restrict
     const int t1 = p1 / 16, tiles1 = (p2 / 16) * t1;
     for (int tl = wave; tl < tiles1; tl += kBlock / 64) {
         const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
-        floatx4 acc = mfma_tile<BF16, false, false>(X, LDK, U1, kLD, m0, n0, k1);
+        auto acc = mfma_tile<MODE, false, false>(X, LDK, U1, kLD, m0, n0, k1);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Y[(m0 + 4 * g + q) * kLD + n0 + r] = (T)acc[q];
+        for (int q = 0; q < 4; ++q) Y[(m0 + M::row(g, q)) * kLD + n0 + r] = (T)acc[q];
     }
     for (int e = threadIdx.x; e < (k2 - p2) * kLD; e += kBlock) Y[p2 * kLD + e] = (T)0.f;  // depth padding
     __syncthreads();
-    float* dst = tmp + t.tmp_off + (int64_t)i3 * n1 * n2;
+    typename M::Tmp* dst = tmp + t.tmp_off + (int64_t)i3 * n1 * n2;
     const int tiles2 = (p2 / 16) * t1;
     for (int tl = wave; tl < tiles2; tl += kBlock / 64) {
         const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
-        floatx4 acc = mfma_tile<BF16, true, false>(U2, kLD, Y, kLD, m0, n0, k2);
+        auto acc = mfma_tile<MODE, true, false>(U2, kLD, Y, kLD, m0, n0, k2);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int a2 = m0 + 4 * g + q, a1 = n0 + r;
+            const int a2 = m0 + M::row(g, q), a1 = n0 + r;
             if (a2 < n2 && a1 < n1) dst[a2 * n1 + a1] = acc[q];
         }
     }
@@ -286,13 +304,16 @@ __global__ void __launch_bounds__(kBlock) k_fdm_fwd12(const FdTensor* __restrict
 
 // Pass 2: per block of 64 columns c = (a2, a1): Zt = U3^T Zc, divide by Lambda,
 // W = U3 Zt, written back in place
-template <bool BF16>
+template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_fdm_mid3(const FdTensor* __restrict__ tens, const int2* __restrict__ cols,
-                                                     const float* __restrict__ ut, const double* __restrict__ dt,
-                                                     float* __restrict__ tmp, const MinresState* __restrict__ mask) {
-    using T = typename MfmaK<BF16>::T;
+                                                     const typename MfmaK<MODE>::U* __restrict__ ut,
+                                                     const double* __restrict__ dt,
+                                                     typename MfmaK<MODE>::Tmp* __restrict__ tmp,
+                                                     const MinresState* __restrict__ mask) {
+    using M = MfmaK<MODE>;
+    using T = typename M::T;
     constexpr int NC = 64;
-    constexpr int KP = MfmaK<BF16>::KP;
+    constexpr int KP = M::KP;
     constexpr int LDC = NC + 4;
     constexpr int LDU = KP + 4;  // U3 is read along both indices up to the depth KP
     __shared__ T Zc[KP * LDC];   // [i3][c]
@@ -302,9 +323,9 @@ __global__ void __launch_bounds__(kBlock) k_fdm_mid3(const FdTensor* __restrict_
     const FdTensor t = tens[it.x];
     if (mask && mask[t.prob].stop) return;
     const int n1 = t.n1, n3 = t.n3, n12 = t.n1 * t.n2;
-    const int p3 = pad16(n3), k3 = BF16 ? ((n3 + 31) & ~31) : p3;
+    const int p3 = pad16(n3), k3 = M::kpad(n3);
     const int col0 = it.y * NC;
-    float* base = tmp + t.tmp_off;
+    typename M::Tmp* base = tmp + t.tmp_off;
     for (int e = threadIdx.x; e < k3 * NC; e += kBlock) {
         const int i3 = e / NC, c = e - i3 * NC, col = col0 + c;
         Zc[i3 * LDC + c] = (i3 < n3 && col < n12) ? (T)base[(int64_t)i3 * n12 + col] : (T)0.f;
@@ -317,39 +338,41 @@ __global__ void __launch_bounds__(kBlock) k_fdm_mid3(const FdTensor* __restrict_
     const int tiles = (p3 / 16) * (NC / 16);
     for (int tl = wave; tl < tiles; tl += kBlock / 64) {
         const int m0 = (tl / (NC / 16)) * 16, n0 = (tl % (NC / 16)) * 16;
-        floatx4 acc = mfma_tile<BF16, true, false>(U3, LDU, Zc, LDC, m0, n0, k3);
+        auto acc = mfma_tile<MODE, true, false>(U3, LDU, Zc, LDC, m0, n0, k3);
         const int col = col0 + n0 + r;
         const int a2 = col / n1, a1 = col - a2 * n1;
         double lam12 = 0.0;
         if (col < n12) lam12 = t.mass + t.kappa[0] * dt[t.d_off[0] + a1] + t.kappa[1] * dt[t.d_off[1] + a2];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int a3 = m0 + 4 * g + q;
-            float v = 0.f;
-            if (a3 < n3 && col < n12) v = (float)((double)acc[q] / (t.scale * (lam12 + t.kappa[2] * dt[t.d_off[2] + a3])));
+            const int a3 = m0 + M::row(g, q);
+            double v = 0.0;
+            if (a3 < n3 && col < n12) v = (double)acc[q] / (t.scale * (lam12 + t.kappa[2] * dt[t.d_off[2] + a3]));
             Zt[a3 * LDC + n0 + r] = (T)v;
         }
     }
     __syncthreads();
     for (int tl = wave; tl < tiles; tl += kBlock / 64) {
         const int m0 = (tl / (NC / 16)) * 16, n0 = (tl % (NC / 16)) * 16;
-        floatx4 acc = mfma_tile<BF16, false, false>(U3, LDU, Zt, LDC, m0, n0, k3);
+        auto acc = mfma_tile<MODE, false, false>(U3, LDU, Zt, LDC, m0, n0, k3);
         const int col = col0 + n0 + r;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int i3 = m0 + 4 * g + q;
+            const int i3 = m0 + M::row(g, q);
             if (i3 < n3 && col < n12) base[(int64_t)i3 * n12 + col] = acc[q];
         }
     }
 }
 
 // Pass 3: Y = Z U1^T (rows a2, cols i1), X = U2 Y, alpha X -> FP64 output
-template <bool BF16>
+template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_fdm_bwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
-                                                      const float* __restrict__ ut, const float* __restrict__ tmp,
+                                                      const typename MfmaK<MODE>::U* __restrict__ ut,
+                                                      const typename MfmaK<MODE>::Tmp* __restrict__ tmp,
                                                       double* __restrict__ out, const MinresState* __restrict__ mask) {
-    using T = typename MfmaK<BF16>::T;
-    constexpr int KP = MfmaK<BF16>::KP;
+    using M = MfmaK<MODE>;
+    using T = typename M::T;
+    constexpr int KP = M::KP;
     constexpr int LDK = KP + 4;
     __shared__ T Z[kNP * LDK];     // [a2][a1]
     __shared__ T Y[KP * kLD];      // [a2][i1]
@@ -360,7 +383,7 @@ __global__ void __launch_bounds__(kBlock) k_fdm_bwd12(const FdTensor* __restrict
     if (mask && mask[t.prob].stop) return;
     const int i3 = it.y, n1 = t.n1, n2 = t.n2;
     const int p1 = pad16(n1), p2 = pad16(n2);
-    const int k1 = BF16 ? ((n1 + 31) & ~31) : p1, k2 = BF16 ? ((n2 + 31) & ~31) : p2;
+    const int k1 = M::kpad(n1), k2 = M::kpad(n2);
     stage(Z, LDK, p2, k1, tmp + t.tmp_off + (int64_t)i3 * n1 * n2, n1, n2, n1);
     stage(U1, LDK, p1, k1, ut + t.u_off[0], n1, n1, n1);
     stage(U2, LDK, p2, k2, ut + t.u_off[1], n2, n2, n2);
@@ -371,21 +394,32 @@ __global__ void __launch_bounds__(kBlock) k_fdm_bwd12(const FdTensor* __restrict
     const int t1 = p1 / 16, tiles = (p2 / 16) * t1;
     for (int tl = wave; tl < tiles; tl += kBlock / 64) {
         const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
-        floatx4 acc = mfma_tile<BF16, false, true>(Z, LDK, U1, LDK, m0, n0, k1);
+        auto acc = mfma_tile<MODE, false, true>(Z, LDK, U1, LDK, m0, n0, k1);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Y[(m0 + 4 * g + q) * kLD + n0 + r] = (T)acc[q];
+        for (int q = 0; q < 4; ++q) Y[(m0 + M::row(g, q)) * kLD + n0 + r] = (T)acc[q];
     }
     __syncthreads();
     double* dst = out + t.out_off + (int64_t)i3 * t.s3;
     for (int tl = wave; tl < tiles; tl += kBlock / 64) {
         const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
-        floatx4 acc = mfma_tile<BF16, false, false>(U2, LDK, Y, kLD, m0, n0, k2);
+        auto acc = mfma_tile<MODE, false, false>(U2, LDK, Y, kLD, m0, n0, k2);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int i2 = m0 + 4 * g + q, i1 = n0 + r;
+            const int i2 = m0 + M::row(g, q), i1 = n0 + r;
             if (i2 < n2 && i1 < n1) dst[(int64_t)i2 * t.s2 + i1] = t.alpha * (double)acc[q];
         }
     }
+}
+
+template <int MODE>
+void fdm_launch(const FdTensor* tens, const int2* slabs, int n_slabs, const int2* cols, int n_cols, const void* ut,
+                const double* dt, const double* in, double* out, void* tmp, const MinresState* mask, hipStream_t s) {
+    using M = MfmaK<MODE>;
+    const auto* u = static_cast<const typename M::U*>(ut);
+    auto* tp = static_cast<typename M::Tmp*>(tmp);
+    hipLaunchKernelGGL(k_fdm_fwd12<MODE>, dim3(n_slabs), dim3(kBlock), 0, s, tens, slabs, u, in, tp, mask);
+    hipLaunchKernelGGL(k_fdm_mid3<MODE>, dim3(n_cols), dim3(kBlock), 0, s, tens, cols, u, dt, tp, mask);
+    hipLaunchKernelGGL(k_fdm_bwd12<MODE>, dim3(n_slabs), dim3(kBlock), 0, s, tens, slabs, u, tp, out, mask);
 }
 
 // ============================================================ setup kernels
@@ -1549,7 +1583,7 @@ void launch_fd(int prec, const FdTensor* tens, int n_tensors, const int2* slabs,
                int n_colblocks, const int2* cols64, int n_colblocks64, const void* ut, const double* dt,
                const double* in, double* out, void* tmp, const MinresState* mask, hipStream_t s) {
     (void)n_tensors;
-    if (prec == 2 || prec == 3) {
+    if (prec >= 2) {
         cols = cols64;
         n_colblocks = n_colblocks64;
     }
@@ -1562,23 +1596,11 @@ void launch_fd(int prec, const FdTensor* tens, int n_tensors, const int2* slabs,
                            (const double*)ut, dt, (double*)tmp, mask);
         hipLaunchKernelGGL(k_fd_bwd12<double>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
                            (const double*)ut, (const double*)tmp, out, mask);
-    } else if (prec == 2 || prec == 3) {
-        // MFMA: 2 = FP32 operands, 3 = BF16 operands; 64-column blocks in pass 2
-        if (prec == 2) {
-            hipLaunchKernelGGL(k_fdm_fwd12<false>, dim3(n_slabs), dim3(kBlock), 0, s, tens, slabs, (const float*)ut, in,
-                               (float*)tmp, mask);
-            hipLaunchKernelGGL(k_fdm_mid3<false>, dim3(n_colblocks), dim3(kBlock), 0, s, tens, cols, (const float*)ut,
-                               dt, (float*)tmp, mask);
-            hipLaunchKernelGGL(k_fdm_bwd12<false>, dim3(n_slabs), dim3(kBlock), 0, s, tens, slabs, (const float*)ut,
-                               (const float*)tmp, out, mask);
-        } else {
-            hipLaunchKernelGGL(k_fdm_fwd12<true>, dim3(n_slabs), dim3(kBlock), 0, s, tens, slabs, (const float*)ut, in,
-                               (float*)tmp, mask);
-            hipLaunchKernelGGL(k_fdm_mid3<true>, dim3(n_colblocks), dim3(kBlock), 0, s, tens, cols, (const float*)ut, dt,
-                               (float*)tmp, mask);
-            hipLaunchKernelGGL(k_fdm_bwd12<true>, dim3(n_slabs), dim3(kBlock), 0, s, tens, slabs, (const float*)ut,
-                               (const float*)tmp, out, mask);
-        }
+    } else if (prec == 2 || prec == 3 || prec == 4) {
+        // MFMA: 2 = FP32 operands, 3 = BF16 operands, 4 = FP64; 64-column blocks in pass 2
+        if (prec == 2) fdm_launch<0>(tens, slabs, n_slabs, cols, n_colblocks, ut, dt, in, out, tmp, mask, s);
+        else if (prec == 3) fdm_launch<1>(tens, slabs, n_slabs, cols, n_colblocks, ut, dt, in, out, tmp, mask, s);
+        else fdm_launch<2>(tens, slabs, n_slabs, cols, n_colblocks, ut, dt, in, out, tmp, mask, s);
     } else {
         const size_t sh12 = 3 * kMaxN * kMaxN * sizeof(float);
         const size_t sh3 = (2 * kMaxN * 32 + kMaxN * kMaxN) * sizeof(float);
