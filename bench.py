@@ -83,6 +83,27 @@ def fd_flops(solver_prob):
     return total
 
 
+def mf_flops(prob):
+    """Algorithmic FP64 flops of one matrix-free stiffness application
+    (sum-factorised quadrature, Section 3 bilinear form): per element brick
+    of BE^3 elements with NB = BE + p basis functions and QB = BE (p + 1)
+    Gauss points per direction, the forward gradient contractions
+    (2, 3, 3 products of length NB per output in directions 1, 2, 3), the
+    same number of transposed ones, and 238 flops per Gauss point for the
+    Jacobian of the trilinear map, its inverse, the stress and the flux."""
+    total = 0
+    for pd in prob["patches"]:
+        p = pd["p"]
+        BE = 2 if p <= 3 else 1
+        NB, QB = BE + p, BE * (p + 1)
+        nb = 1
+        for e in pd["n_el"]:
+            nb *= -(-e // BE)
+        fma = 3 * (2 * NB * NB * QB * NB + 3 * NB * QB * QB * NB + 3 * QB * QB * QB * NB)
+        total += nb * (2 * 2 * fma + 238 * QB ** 3)
+    return total
+
+
 def cpu_baseline(prob, gpu_iters):
     """The oracle, untouched, on the host: one MINRES iteration of the same
     problem (saddle operator + preconditioner + the vector recurrences),
@@ -190,16 +211,25 @@ def main():
         out[f"fd_apply_tflops_{name}"] = flops / (ms * 1e-3) / 1e12
         log(f"FD apply {name}: {ms*1e3:.1f} us, {s.n_dof/(ms*1e-3)/1e9:.2f} GDOF/s")
 
-    # stiffness matvec: the dominant kernel (HBM-bound assembled stencil)
+    # stiffness matvec: the dominant kernel of every MINRES iteration
     x = torch.from_numpy(W.random_vector(s32.n_dof, 4)).cuda()
     y = torch.empty_like(x)
     s32.apply("stiffness", x, y)
     mv_ms = time_events(lambda: s32.apply("stiffness", x, y), args.mv_reps)
-    mv_bytes = s32.stiffness_bytes + 2 * 8 * s32.n_dof
-    gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
-    log(f"stiffness matvec: {mv_ms:.3f} ms, {gbs:.0f} GB/s")
-    roof = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
-                traffic=None, kernel="k_stiffness", bytes_per_launch=mv_bytes, ms_per_launch=mv_ms)
+    if s32.stiffness_bytes == 0:
+        # matrix-free: bound by FP64 vector arithmetic
+        mv_flops = mf_flops(prob)
+        tfs = mv_flops / (mv_ms * 1e-3) / 1e12
+        log(f"stiffness matvec (matrix-free): {mv_ms:.3f} ms, {tfs:.2f} TFLOP/s FP64")
+        roof = dict(bound="alu", achieved=tfs, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=tfs / FP64_PEAK_TFLOPS,
+                    traffic=None, kernel="stiffness operator: k_mf_brick + k_mf_gather",
+                    flops_per_launch=mv_flops, ms_per_launch=mv_ms)
+    else:
+        mv_bytes = s32.stiffness_bytes + 2 * 8 * s32.n_dof
+        gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
+        log(f"stiffness matvec (assembled): {mv_ms:.3f} ms, {gbs:.0f} GB/s")
+        roof = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
+                    traffic=None, kernel="k_stiffness", bytes_per_launch=mv_bytes, ms_per_launch=mv_ms)
 
     cpu = None
     if not args.no_cpu_baseline and args.workload != "c4":

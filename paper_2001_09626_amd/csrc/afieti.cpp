@@ -71,6 +71,7 @@ struct afieti_handle {
     double* d_stencil = nullptr;
     double* d_qx = nullptr;
     double* d_ybuf = nullptr;  // matrix-free per-brick partial results
+    double* d_mftab = nullptr; // matrix-free per-brick univariate tables
     double* d_geo = nullptr;
     double* d_load = nullptr;
     std::vector<double*> d_F;              // per problem: unit-amplitude mode loads [mode][dof]
@@ -381,6 +382,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
         h->d_ahat_slabs = h->upload(sl, s);
     }
     int64_t ybuf = 0;
+    std::vector<double> mftab;
     for (auto& kv : rbs) {
         RowClass rc;
         rc.dim = std::get<0>(kv.first);
@@ -396,6 +398,32 @@ void device_setup(afieti_handle* h, hipStream_t s) {
                 if (!d.mf || d.p != rc.p) continue;
                 d.brick_off = (int64_t)bricks.size();
                 d.ybuf_off = ybuf;
+                // per-brick tables: V[q][t], D[q][t] of basis b be + t at the
+                // brick's Gauss point q (zero off the support and past the
+                // patch), weights W[q] (zero past the patch), points E[q]
+                const int qb = be * (rc.p + 1), pp = rc.p + 1;
+                const PatchPlan& PP = pl.patches[k];
+                for (int m = 0; m < 3; ++m) {
+                    const Dir1D& D = PP.dir[m];
+                    d.tab_off[m] = (int64_t)mftab.size();
+                    for (int b = 0; b < d.nb[m]; ++b) {
+                        const int nel = std::min(be, D.n_el - b * be);
+                        std::vector<double> T((size_t)mf_table_doubles(rc.p), 0.0);
+                        for (int q = 0; q < qb; ++q) {
+                            const bool in = q < nel * pp;
+                            const int g = b * be * pp + (in ? q : 0);
+                            for (int t = 0; t < nbd && in; ++t) {
+                                const int loc = b * be + t - D.qfirst[g];
+                                if (loc < 0 || loc > rc.p) continue;
+                                T[(size_t)q * nbd + t] = D.qval[(size_t)g * pp + loc];
+                                T[(size_t)qb * nbd + (size_t)q * nbd + t] = D.qder[(size_t)g * pp + loc];
+                            }
+                            T[(size_t)2 * qb * nbd + q] = in ? D.qw[g] : 0.0;
+                            T[(size_t)2 * qb * nbd + qb + q] = D.qx[g];
+                        }
+                        mftab.insert(mftab.end(), T.begin(), T.end());
+                    }
+                }
                 for (int b3 = 0; b3 < d.nb[2]; ++b3)
                     for (int b2 = 0; b2 < d.nb[1]; ++b2)
                         for (int b1 = 0; b1 < d.nb[0]; ++b1) bricks.push_back(make_int4(k, b1, b2, b3));
@@ -407,6 +435,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
         h->classes.push_back(rc);
     }
     h->d_ybuf = h->dalloc<double>(ybuf);
+    h->d_mftab = mftab.empty() ? nullptr : h->upload(mftab, s);
     HIP_OK(hipMemcpyAsync(h->d_patches, h->h_patches.data(), h->h_patches.size() * sizeof(DevPatch),
                           hipMemcpyHostToDevice, s));
     // ---- unit-amplitude mode loads F_j per problem, then stencils and the load
@@ -563,9 +592,8 @@ void device_setup(afieti_handle* h, hipStream_t s) {
 void op_stiffness(afieti_handle* h, const double* x, double* y, const double* t, hipStream_t s) {
     for (const auto& rc : h->classes) {
         if (rc.mf)
-            launch_stiffness_mf(rc.p, h->d_patches, rc.d_bricks, rc.n_bricks, rc.d_rb, rc.n, h->d_qval, h->d_qder,
-                                h->d_qfirst, h->d_qx, h->d_qw, x, h->d_ybuf, y, h->d_btptr, h->d_btrow, h->d_btsgn, t,
-                                h->mask, s);
+            launch_stiffness_mf(rc.p, h->d_patches, rc.d_bricks, rc.n_bricks, rc.d_rb, rc.n, h->d_mftab, x,
+                                h->d_ybuf, y, h->d_btptr, h->d_btrow, h->d_btsgn, t, h->mask, s);
         else
             launch_stiffness_dp(rc.dim, rc.p, h->d_patches, rc.d_rb, rc.n, h->d_stencil, x, y, h->d_btptr, h->d_btrow,
                                 h->d_btsgn, t, h->mask, s);

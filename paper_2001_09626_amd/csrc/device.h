@@ -32,6 +32,7 @@ struct DevPatch {
     int mf;                      // 1: stiffness applied matrix-free
     int64_t brick_off;           // first brick of the patch in the brick list
     int64_t ybuf_off;            // offset (in doubles) of its bricks' partial results
+    int64_t tab_off[3];          // offsets (in doubles) of its per-brick univariate tables
 };
 
 // One tensor of an FD solve (a patch/component pair, or its interior).

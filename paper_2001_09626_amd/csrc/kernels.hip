@@ -861,269 +861,271 @@ __global__ void __launch_bounds__(kBlock) k_stiffness(const DevPatch* __restrict
 
 // ===================================================== matrix-free stiffness
 // y = A x by quadrature of the bilinear form of Section 3 with sum
-// factorisation, brick by brick (BE^3 elements, C^{p-1} splines).  Per
-// brick: the (BE+p)^3 x 3 coefficients go to LDS; three forward 1D
-// contractions give the parametric gradients at the (BE(p+1))^3 Gauss
-// points; at each point the physical gradient, the stress
-// sigma = mu (grad u + grad u^T) + lam div u I and the flux
-// w|J| sigma J^{-T} are formed, with J of the multilinear patch map computed
-// analytically; three transposed contractions give the brick's
-// contribution to its nodes, written to a per-brick buffer.  A second kernel
-// sums, for every node, the contributions of the bricks that contain it in
-// a fixed order (deterministic, no atomics).
+// factorisation, brick by brick (BE^3 elements of a C^{p-1} patch, NB = BE + p
+// basis functions and QB = BE (p + 1) Gauss points per direction).  One
+// workgroup of NW wavefronts per brick:
+//   F1 (row per thread)    A0 = V1 x, A1 = D1 x along direction 1;
+//   F2 (row per thread)    B00 = V2 A0, B10 = D2 A0, B01 = V2 A1;
+//   Q  (Gauss column (q1, q2) per lane, wave w owns a range of q3)
+//      parametric gradients G = (V3 B01, V3 B10, D3 B00) in registers, the
+//      stress sigma = mu (grad u + grad u^T) + lam div u I and the flux
+//      w |J| sigma J^{-T} at each point (J of the trilinear patch map,
+//      analytic), then the partial transposed contractions
+//      P = (V3^T F1, V3^T F2, D3^T F3) over the wave's q3 range, summed over
+//      the waves in a fixed order;
+//   B2 (row per thread)    SD = V2^T P1, SV = D2^T P2 + V2^T P3;
+//   B1 (row per thread)    y = D1^T SD + V1^T SV, to the per-brick buffer.
+// The univariate tables of a brick are uniform across the workgroup and are
+// read from a per-brick table in global memory (scalar loads); only the
+// transposes between the row and column phases go through LDS.  A second
+// kernel sums, for every node, the contributions of the bricks that contain
+// it in a fixed order (deterministic, no atomics).
 template <int P>
 struct MfShape {
-    static constexpr int BE = P <= 3 ? 2 : 1;  // elements per brick direction
-    static constexpr int NB = BE + P;          // nodes per brick direction
-    static constexpr int QB = BE * (P + 1);    // Gauss points per brick direction
+    static constexpr int BE = P <= 3 ? 2 : 1;               // elements per brick direction
+    static constexpr int NB = BE + P;                       // basis functions per brick direction
+    static constexpr int QB = BE * (P + 1);                 // Gauss points per brick direction
+    static constexpr int NCOL = QB * QB;                    // Gauss columns (q1, q2)
+    static constexpr int TS = 2 * QB * NB + 2 * QB;         // table doubles per (direction, brick)
+    static constexpr int QA = QB | 1;                       // row stride of A / S in LDS (odd: no bank conflicts)
+    static constexpr int NCB = (NCOL + 15) / 16 * 16 + 8;   // t3 stride of B / P in LDS
+#ifndef AFIETI_MF_WAVES
+#define AFIETI_MF_WAVES 2
+#endif
+    static constexpr int NW = AFIETI_MF_WAVES;              // wavefronts per brick
+    static constexpr int QPG = (QB + NW - 1) / NW;          // q3 values per wavefront
+    static constexpr int NT = 64 * NW;                      // threads per brick
 };
 
 template <int P>
-__global__ void __launch_bounds__(kBlock) k_mf_brick(const DevPatch* __restrict__ dps, const int4* __restrict__ bricks,
-                                                     const double* __restrict__ qval, const double* __restrict__ qder,
-                                                     const int* __restrict__ qfirst, const double* __restrict__ qx,
-                                                     const double* __restrict__ qw, const double* __restrict__ x,
-                                                     double* __restrict__ ybuf, const MinresState* __restrict__ mask) {
-    constexpr int BE = MfShape<P>::BE, NB = MfShape<P>::NB, QB = MfShape<P>::QB;
-    constexpr int NB3 = NB * NB * NB, QB3 = QB * QB * QB;
-    __shared__ double sV[3][QB][NB], sD[3][QB][NB];
-    __shared__ double sW[3][QB], sE[3][QB];          // Gauss weights and points
-    __shared__ double sX[3][NB3];                    // coefficients [c][t3][t2][t1]
-    __shared__ double sA[2][3][NB * NB * QB];        // [V|D][c][t3][t2][q1]; later SD/SV
-    __shared__ double sB[3][3][NB * QB * QB];        // [c][B00|B10|B01][t3][q2][q1]; later P1..P3
-    __shared__ double sG[3][3][QB3];                 // [c][a][q3][q2][q1]: gradients, then fluxes
-    __shared__ double sC[36];
+__global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __restrict__ dps,
+                                                             const int4* __restrict__ bricks,
+                                                             const double* __restrict__ tab,
+                                                             const double* __restrict__ x, double* __restrict__ ybuf,
+                                                             const MinresState* __restrict__ mask) {
+    using S = MfShape<P>;
+    constexpr int BE = S::BE, NB = S::NB, QB = S::QB, NCOL = S::NCOL, TS = S::TS, QA = S::QA, NCB = S::NCB;
+    constexpr int QPG = S::QPG, NT = S::NT, NW = S::NW;
+    constexpr int NB3 = NB * NB * NB;
+    constexpr int AK = 3 * NB * NB * QA;  // offset of A1 / SV in sA
+    constexpr int BK = NB * NCB;          // stride of the k index in sB
+    constexpr int OD = QB * NB, OW = 2 * QB * NB, OE = 2 * QB * NB + QB;  // D, W, E within a table
+    __shared__ double sA[2 * AK];         // [A0|A1] (later [SD|SV]) [c][t3][t2][q1]
+    __shared__ double sB[9 * BK];         // [c][k][t3][q2 QB + q1]: B00, B10, B01, later P1, P2, P3
     const int4 br = bricks[blockIdx.x];
     const DevPatch& pa = dps[br.x];
     if (mask && mask[pa.prob].stop) return;
-    const int b[3] = {br.y, br.z, br.w};
     const int tid = threadIdx.x;
-    int nel[3];
-    for (int d = 0; d < 3; ++d) nel[d] = min(BE, pa.n[d] - P - b[d] * BE);  // elements of this brick (C^{p-1})
-    // univariate tables of the brick: basis n0 + t at Gauss point q0 + q
-    for (int e = tid; e < 3 * QB * NB; e += kBlock) {
-        const int d = e / (QB * NB), r = e % (QB * NB), q = r / NB, t = r % NB;
-        double v = 0.0, dv = 0.0;
-        if (q < nel[d] * (P + 1)) {
-            const int g = pa.q_off[d] + b[d] * BE * (P + 1) + q;
-            const int loc = b[d] * BE + t - qfirst[g];
-            if (loc >= 0 && loc <= P) {
-                v = qval[(int64_t)g * kQStride + loc];
-                dv = qder[(int64_t)g * kQStride + loc];
-            }
-        }
-        sV[d][q][t] = v;
-        sD[d][q][t] = dv;
-    }
-    for (int e = tid; e < 3 * QB; e += kBlock) {
-        const int d = e / QB, q = e % QB;
-        const bool in = q < nel[d] * (P + 1);
-        const int g = pa.q_off[d] + b[d] * BE * (P + 1) + (in ? q : 0);
-        sW[d][q] = in ? qw[g] : 0.0;
-        sE[d][q] = qx[g];
-    }
-    if (tid < 36) sC[tid] = pa.jcoef[tid];
-    const double* xb = x + pa.dof_off;
-    for (int e = tid; e < 3 * NB3; e += kBlock) {
-        const int c = e / NB3, r = e % NB3;
-        const int t3 = r / (NB * NB), t2 = (r / NB) % NB, t1 = r % NB;
-        const int i1 = b[0] * BE + t1, i2 = b[1] * BE + t2, i3 = b[2] * BE + t3;
-        double v = 0.0;
-        if (i1 < pa.n[0] && i2 < pa.n[1] && i3 < pa.n[2])
-            v = xb[(int64_t)c * pa.nodes + i1 + (int64_t)pa.n[0] * (i2 + (int64_t)pa.n[1] * i3)];
-        sX[c][r] = v;
-    }
-    __syncthreads();
-    // forward, direction 1: A0 = V1 x, A1 = D1 x along t1
-    for (int e = tid; e < 3 * NB * NB; e += kBlock) {
-        const int c = e / (NB * NB), r = e % (NB * NB);  // r = t3 NB + t2
+    const double* __restrict__ T1 = tab + pa.tab_off[0] + (int64_t)br.y * TS;
+    const double* __restrict__ T2 = tab + pa.tab_off[1] + (int64_t)br.z * TS;
+    const double* __restrict__ T3 = tab + pa.tab_off[2] + (int64_t)br.w * TS;
+    const int i1 = br.y * BE, i2 = br.z * BE, i3 = br.w * BE;  // first basis function of the brick
+    // ---- F1: rows (c, t3, t2)
+    for (int row = tid; row < 3 * NB * NB; row += NT) {
+        const int c = row / (NB * NB), t3 = (row / NB) % NB, t2 = row % NB;
+        const bool rin = i2 + t2 < pa.n[1] && i3 + t3 < pa.n[2];
+        const double* xr = x + pa.dof_off + (int64_t)c * pa.nodes +
+                           (int64_t)pa.n[0] * ((i2 + t2) + (int64_t)pa.n[1] * (i3 + t3)) + i1;
         double xl[NB];
 #pragma unroll
-        for (int t = 0; t < NB; ++t) xl[t] = sX[c][r * NB + t];
+        for (int t = 0; t < NB; ++t) xl[t] = (rin && i1 + t < pa.n[0]) ? xr[t] : 0.0;
+        double* a = sA + row * QA;
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
             double a0 = 0.0, a1 = 0.0;
 #pragma unroll
             for (int t = 0; t < NB; ++t) {
-                a0 += sV[0][q][t] * xl[t];
-                a1 += sD[0][q][t] * xl[t];
+                a0 += T1[q * NB + t] * xl[t];
+                a1 += T1[OD + q * NB + t] * xl[t];
             }
-            sA[0][c][r * QB + q] = a0;
-            sA[1][c][r * QB + q] = a1;
+            a[q] = a0;
+            a[AK + q] = a1;
         }
     }
     __syncthreads();
-    // forward, direction 2: B00 = V2 A0, B10 = D2 A0, B01 = V2 A1 along t2
-    for (int e = tid; e < 3 * NB * QB; e += kBlock) {
-        const int c = e / (NB * QB), r = e % (NB * QB);
-        const int t3 = r / QB, q1 = r % QB;
+    // ---- F2: rows (c, t3, q1)
+    for (int row = tid; row < 3 * NB * QB; row += NT) {
+        const int c = row / (NB * QB), t3 = (row / QB) % NB, q1 = row % QB;
+        const double* a = sA + (c * NB + t3) * NB * QA + q1;
         double a0[NB], a1[NB];
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
-            a0[t] = sA[0][c][(t3 * NB + t) * QB + q1];
-            a1[t] = sA[1][c][(t3 * NB + t) * QB + q1];
+            a0[t] = a[t * QA];
+            a1[t] = a[AK + t * QA];
         }
+        double* b = sB + (c * 3 * NB + t3) * NCB + q1;
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
             double b00 = 0.0, b10 = 0.0, b01 = 0.0;
 #pragma unroll
             for (int t = 0; t < NB; ++t) {
-                b00 += sV[1][q][t] * a0[t];
-                b10 += sD[1][q][t] * a0[t];
-                b01 += sV[1][q][t] * a1[t];
+                b00 += T2[q * NB + t] * a0[t];
+                b10 += T2[OD + q * NB + t] * a0[t];
+                b01 += T2[q * NB + t] * a1[t];
             }
-            const int o = (t3 * QB + q) * QB + q1;
-            sB[c][0][o] = b00;
-            sB[c][1][o] = b10;
-            sB[c][2][o] = b01;
+            b[q * QB] = b00;
+            b[BK + q * QB] = b10;
+            b[2 * BK + q * QB] = b01;
         }
     }
     __syncthreads();
-    // forward, direction 3: d/deta_1 = V3 B01, d/deta_2 = V3 B10, d/deta_3 = D3 B00
-    for (int e = tid; e < 3 * QB * QB; e += kBlock) {
-        const int c = e / (QB * QB), r = e % (QB * QB);  // r = q2 QB + q1
-        double b00[NB], b10[NB], b01[NB];
-#pragma unroll
-        for (int t = 0; t < NB; ++t) {
-            b00[t] = sB[c][0][t * QB * QB + r];
-            b10[t] = sB[c][1][t * QB * QB + r];
-            b01[t] = sB[c][2][t * QB * QB + r];
-        }
-#pragma unroll
-        for (int q = 0; q < QB; ++q) {
-            double g1 = 0.0, g2 = 0.0, g3 = 0.0;
-#pragma unroll
-            for (int t = 0; t < NB; ++t) {
-                g1 += sV[2][q][t] * b01[t];
-                g2 += sV[2][q][t] * b10[t];
-                g3 += sD[2][q][t] * b00[t];
-            }
-            sG[c][0][q * QB * QB + r] = g1;
-            sG[c][1][q * QB * QB + r] = g2;
-            sG[c][2][q * QB * QB + r] = g3;
-        }
-    }
-    __syncthreads();
-    // stress and flux at every Gauss point of the brick
+    // ---- Q: Gauss columns, wavefront w owns q3 in [w QPG, w QPG + QPG)
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int q3a = w * QPG;
+    // Gauss point q3a + j exists (always, when the wavefronts split QB evenly)
+    auto has = [&](int j) { return QPG * NW == QB || q3a + j < QB; };
     const double lam = pa.lam, mu = pa.mu;
-    for (int qi = tid; qi < QB3; qi += kBlock) {
-        const int q3 = qi / (QB * QB), q2 = (qi / QB) % QB, q1 = qi % QB;
-        const double w = sW[0][q1] * sW[1][q2] * sW[2][q3];
-        const double eta[3] = {sE[0][q1], sE[1][q2], sE[2][q3]};
-        // d F / d eta_a of the trilinear map is bilinear in the other two
-        // coordinates (b < c): c0 + c1 eta_b + c2 eta_c + c3 eta_b eta_c
-        double J[3][3];
+    for (int cb = 0; cb < NCOL; cb += 64) {
+        const int col = cb + (tid & 63);
+        const bool act = col < NCOL;
+        double F[3][3][QPG];  // [c][a][j]: gradient d u_c / d eta_a, then flux
+        if (act) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double eb = eta[a == 0 ? 1 : 0], ec = eta[a == 2 ? 1 : 2];
+            for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int xx = 0; xx < 3; ++xx) {
-                const double* c4 = &sC[(a * 3 + xx) * 4];
-                J[xx][a] = (c4[0] + c4[1] * eb) + (c4[2] + c4[3] * eb) * ec;
+                for (int k = 0; k < 3; ++k) {
+                    double bv[NB];
+#pragma unroll
+                    for (int t = 0; t < NB; ++t) bv[t] = sB[(c * 3 + k) * BK + t * NCB + col];
+                    // B00 -> d/deta_3 (D3), B10 -> d/deta_2 (V3), B01 -> d/deta_1 (V3)
+                    const int a = 2 - k;
+                    const int o = k == 0 ? OD : 0;
+#pragma unroll
+                    for (int j = 0; j < QPG; ++j) {
+                        double g = 0.0;
+                        if (has(j)) {
+#pragma unroll
+                            for (int t = 0; t < NB; ++t) g += T3[o + (q3a + j) * NB + t] * bv[t];
+                        }
+                        F[c][a][j] = g;
+                    }
+                }
+            const int q1 = col % QB, q2 = col / QB;
+            const double w12 = T1[OW + q1] * T2[OW + q2];
+            const double e1 = T1[OE + q1], e2 = T2[OE + q2];
+#pragma unroll
+            for (int j = 0; j < QPG; ++j) {
+                if (!has(j)) continue;
+                const double e3 = T3[OE + q3a + j];
+                const double eta[3] = {e1, e2, e3};
+                // d F / d eta_a of the trilinear map is bilinear in the other
+                // two coordinates (b < c): c0 + c1 eta_b + c2 eta_c + c3 eta_b eta_c
+                double J[3][3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double eb = eta[a == 0 ? 1 : 0], ec = eta[a == 2 ? 1 : 2];
+#pragma unroll
+                    for (int xx = 0; xx < 3; ++xx) {
+                        const double* c4 = &pa.jcoef[(a * 3 + xx) * 4];
+                        J[xx][a] = (c4[0] + c4[1] * eb) + (c4[2] + c4[3] * eb) * ec;
+                    }
+                }
+                const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+                const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+                const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+                const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+                const double id = 1.0 / det;
+                double Ji[3][3];  // Ji[a][x] = d eta_a / d x_x
+                Ji[0][0] = c00 * id;
+                Ji[1][0] = c01 * id;
+                Ji[2][0] = c02 * id;
+                Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+                Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+                Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+                Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+                Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+                Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+                const double W = w12 * T3[OW + q3a + j] * fabs(det);
+                double gr[3][3];  // physical gradient [c][x]
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int xx = 0; xx < 3; ++xx)
+                        gr[c][xx] = F[c][0][j] * Ji[0][xx] + F[c][1][j] * Ji[1][xx] + F[c][2][j] * Ji[2][xx];
+                const double dv = gr[0][0] + gr[1][1] + gr[2][2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double sg[3];
+#pragma unroll
+                    for (int xx = 0; xx < 3; ++xx) sg[xx] = mu * (gr[c][xx] + gr[xx][c]) + (c == xx ? lam * dv : 0.0);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) F[c][a][j] = W * (sg[0] * Ji[a][0] + sg[1] * Ji[a][1] + sg[2] * Ji[a][2]);
+                }
             }
         }
-        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-        const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-        double Ji[3][3];  // Ji[a][x] = d eta_a / d x_x
-        Ji[0][0] = c00 / det;
-        Ji[1][0] = c01 / det;
-        Ji[2][0] = c02 / det;
-        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
-        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
-        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
-        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
-        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
-        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
-        const double W = w * fabs(det);
-        double gr[3][3];  // physical gradient [c][x]
+        // P = sum over wavefronts (in order) of the partial contractions
+        auto partial = [&](int c, int a, int t) {
+            const int o = a == 2 ? OD : 0;
+            double v = 0.0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+            for (int j = 0; j < QPG; ++j)
+                if (has(j)) v += T3[o + (q3a + j) * NB + t] * F[c][a][j];
+            return v;
+        };
+        __syncthreads();  // every wavefront has read B
+        if (w == 0 && act) {
 #pragma unroll
-            for (int xx = 0; xx < 3; ++xx) {
-                double v = 0.0;
+            for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int a = 0; a < 3; ++a) v += sG[c][a][qi] * Ji[a][xx];
-                gr[c][xx] = v;
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int t = 0; t < NB; ++t) sB[(c * 3 + a) * BK + t * NCB + col] = partial(c, a, t);
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int r = 1; r < NW; ++r) {
+            if (w == r && act) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int t = 0; t < NB; ++t) sB[(c * 3 + a) * BK + t * NCB + col] += partial(c, a, t);
             }
-        const double dv = gr[0][0] + gr[1][1] + gr[2][2];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double sg[3];
-#pragma unroll
-            for (int xx = 0; xx < 3; ++xx) sg[xx] = mu * (gr[c][xx] + gr[xx][c]) + (c == xx ? lam * dv : 0.0);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) sG[c][a][qi] = W * (sg[0] * Ji[a][0] + sg[1] * Ji[a][1] + sg[2] * Ji[a][2]);
+            __syncthreads();
         }
     }
-    __syncthreads();
-    // backward, direction 3: P1 = V3^T F1, P2 = V3^T F2, P3 = D3^T F3 (into sB)
-    for (int e = tid; e < 3 * QB * QB; e += kBlock) {
-        const int c = e / (QB * QB), r = e % (QB * QB);
-        double f1[QB], f2[QB], f3[QB];
-#pragma unroll
-        for (int q = 0; q < QB; ++q) {
-            f1[q] = sG[c][0][q * QB * QB + r];
-            f2[q] = sG[c][1][q * QB * QB + r];
-            f3[q] = sG[c][2][q * QB * QB + r];
-        }
-#pragma unroll
-        for (int t = 0; t < NB; ++t) {
-            double p1 = 0.0, p2 = 0.0, p3 = 0.0;
-#pragma unroll
-            for (int q = 0; q < QB; ++q) {
-                p1 += sV[2][q][t] * f1[q];
-                p2 += sV[2][q][t] * f2[q];
-                p3 += sD[2][q][t] * f3[q];
-            }
-            sB[c][0][t * QB * QB + r] = p1;
-            sB[c][1][t * QB * QB + r] = p2;
-            sB[c][2][t * QB * QB + r] = p3;
-        }
-    }
-    __syncthreads();
-    // backward, direction 2: SD = V2^T P1, SV = D2^T P2 + V2^T P3 (into sA)
-    for (int e = tid; e < 3 * NB * QB; e += kBlock) {
-        const int c = e / (NB * QB), r = e % (NB * QB);
-        const int t3 = r / QB, q1 = r % QB;
+    // ---- B2: rows (c, t3, q1)
+    for (int row = tid; row < 3 * NB * QB; row += NT) {
+        const int c = row / (NB * QB), t3 = (row / QB) % NB, q1 = row % QB;
+        const double* pp = sB + (c * 3 * NB + t3) * NCB + q1;
         double p1[QB], p2[QB], p3[QB];
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
-            const int o = (t3 * QB + q) * QB + q1;
-            p1[q] = sB[c][0][o];
-            p2[q] = sB[c][1][o];
-            p3[q] = sB[c][2][o];
+            p1[q] = pp[q * QB];
+            p2[q] = pp[BK + q * QB];
+            p3[q] = pp[2 * BK + q * QB];
         }
+        double* s = sA + (c * NB + t3) * NB * QA + q1;
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
             double sd = 0.0, sv = 0.0;
 #pragma unroll
             for (int q = 0; q < QB; ++q) {
-                sd += sV[1][q][t] * p1[q];
-                sv += sD[1][q][t] * p2[q] + sV[1][q][t] * p3[q];
+                sd += T2[q * NB + t] * p1[q];
+                sv += T2[OD + q * NB + t] * p2[q] + T2[q * NB + t] * p3[q];
             }
-            sA[0][c][(t3 * NB + t) * QB + q1] = sd;
-            sA[1][c][(t3 * NB + t) * QB + q1] = sv;
+            s[t * QA] = sd;
+            s[AK + t * QA] = sv;
         }
     }
     __syncthreads();
-    // backward, direction 1: y = D1^T SD + V1^T SV, written to the brick buffer
+    // ---- B1: rows (c, t3, t2), written to the brick buffer
     double* yb = ybuf + pa.ybuf_off + (int64_t)(blockIdx.x - pa.brick_off) * 3 * NB3;
-    for (int e = tid; e < 3 * NB * NB; e += kBlock) {
-        const int c = e / (NB * NB), r = e % (NB * NB);
+    for (int row = tid; row < 3 * NB * NB; row += NT) {
+        const double* s = sA + row * QA;
         double sd[QB], sv[QB];
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
-            sd[q] = sA[0][c][r * QB + q];
-            sv[q] = sA[1][c][r * QB + q];
+            sd[q] = s[q];
+            sv[q] = s[AK + q];
         }
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
             double v = 0.0;
 #pragma unroll
-            for (int q = 0; q < QB; ++q) v += sD[0][q][t] * sd[q] + sV[0][q][t] * sv[q];
-            yb[c * NB3 + r * NB + t] = v;
+            for (int q = 0; q < QB; ++q) v += T1[OD + q * NB + t] * sd[q] + T1[q * NB + t] * sv[q];
+            yb[row * NB + t] = v;
         }
     }
 }
@@ -1168,12 +1170,10 @@ __global__ void __launch_bounds__(kBlock) k_mf_gather(const DevPatch* __restrict
 }
 
 template <int P>
-void mf_t(const DevPatch* dp, const int4* bricks, int n_bricks, const int4* rb, int nrb, const double* qval,
-          const double* qder, const int* qfirst, const double* qx, const double* qw, const double* x, double* ybuf,
-          double* y, const int64_t* bp, const int* br, const double* bs, const double* t, const MinresState* mask,
-          hipStream_t s) {
-    hipLaunchKernelGGL(k_mf_brick<P>, dim3(n_bricks), dim3(kBlock), 0, s, dp, bricks, qval, qder, qfirst, qx, qw, x,
-                       ybuf, mask);
+void mf_t(const DevPatch* dp, const int4* bricks, int n_bricks, const int4* rb, int nrb, const double* tab,
+          const double* x, double* ybuf, double* y, const int64_t* bp, const int* br, const double* bs,
+          const double* t, const MinresState* mask, hipStream_t s) {
+    hipLaunchKernelGGL(k_mf_brick<P>, dim3(n_bricks), dim3(MfShape<P>::NT), 0, s, dp, bricks, tab, x, ybuf, mask);
     hipLaunchKernelGGL(k_mf_gather<P>, dim3(nrb), dim3(kBlock), 0, s, dp, rb, ybuf, y, bp, br, bs, t, mask);
 }
 
@@ -1719,21 +1719,25 @@ void launch_mask_interior(const DevPatch* dp, const int4* rb, int nrb, double* y
 }
 
 void launch_stiffness_mf(int p, const DevPatch* dp, const int4* bricks, int n_bricks, const int4* rb, int nrb,
-                         const double* qval, const double* qder, const int* qfirst, const double* qx, const double* qw,
-                         const double* x, double* ybuf, double* y, const int64_t* bp, const int* br,
-                         const double* bs, const double* t, const MinresState* mask, hipStream_t s) {
+                         const double* tab, const double* x, double* ybuf, double* y, const int64_t* bp,
+                         const int* br, const double* bs, const double* t, const MinresState* mask, hipStream_t s) {
     if (n_bricks == 0) return;
     switch (p) {
-        case 1: mf_t<1>(dp, bricks, n_bricks, rb, nrb, qval, qder, qfirst, qx, qw, x, ybuf, y, bp, br, bs, t, mask, s); break;
-        case 2: mf_t<2>(dp, bricks, n_bricks, rb, nrb, qval, qder, qfirst, qx, qw, x, ybuf, y, bp, br, bs, t, mask, s); break;
-        case 3: mf_t<3>(dp, bricks, n_bricks, rb, nrb, qval, qder, qfirst, qx, qw, x, ybuf, y, bp, br, bs, t, mask, s); break;
-        case 4: mf_t<4>(dp, bricks, n_bricks, rb, nrb, qval, qder, qfirst, qx, qw, x, ybuf, y, bp, br, bs, t, mask, s); break;
-        case 5: mf_t<5>(dp, bricks, n_bricks, rb, nrb, qval, qder, qfirst, qx, qw, x, ybuf, y, bp, br, bs, t, mask, s); break;
-        default: mf_t<6>(dp, bricks, n_bricks, rb, nrb, qval, qder, qfirst, qx, qw, x, ybuf, y, bp, br, bs, t, mask, s); break;
+        case 1: mf_t<1>(dp, bricks, n_bricks, rb, nrb, tab, x, ybuf, y, bp, br, bs, t, mask, s); break;
+        case 2: mf_t<2>(dp, bricks, n_bricks, rb, nrb, tab, x, ybuf, y, bp, br, bs, t, mask, s); break;
+        case 3: mf_t<3>(dp, bricks, n_bricks, rb, nrb, tab, x, ybuf, y, bp, br, bs, t, mask, s); break;
+        case 4: mf_t<4>(dp, bricks, n_bricks, rb, nrb, tab, x, ybuf, y, bp, br, bs, t, mask, s); break;
+        case 5: mf_t<5>(dp, bricks, n_bricks, rb, nrb, tab, x, ybuf, y, bp, br, bs, t, mask, s); break;
+        default: mf_t<6>(dp, bricks, n_bricks, rb, nrb, tab, x, ybuf, y, bp, br, bs, t, mask, s); break;
     }
 }
 
 int mf_brick_elems(int p) { return p <= 3 ? 2 : 1; }
+
+int mf_table_doubles(int p) {
+    const int be = mf_brick_elems(p), nb = be + p, qb = be * (p + 1);
+    return 2 * qb * nb + 2 * qb;
+}
 
 void launch_B(const int64_t* plus, const int64_t* minus, int64_t n_c, double alpha, const double* x, double* y,
               hipStream_t s) {
