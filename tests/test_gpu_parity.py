@@ -13,6 +13,7 @@ import pytest
 
 import workloads as W
 from oracle.afieti import AFIETI
+from minres_band import same_iterations
 
 pytestmark = pytest.mark.gpu
 
@@ -144,7 +145,7 @@ def test_solve_matches_oracle(pair):
     print(f"  iterations gpu {st['iterations']} oracle {ref['iters']}; |u-u_or| {diff:.2e}, "
           f"|u_or-u*| {own:.2e}, |lam-lam_or| {dl:.2e}", flush=True)
     assert st["converged"]
-    assert st["iterations"] == ref["iters"]
+    assert same_iterations(st["iterations"], ref, 1e-8)
     assert diff <= 0.25 * own and diff <= 1e-8
     assert dl <= 1e-7
 
@@ -202,5 +203,5 @@ def test_solve_with_rhs(pair):
     diff = np.linalg.norm(_host(u) - ref["u"]) / nu
     own = np.linalg.norm(ref["u"] - tight["u"]) / nu
     print(f"  rhs: iterations {st['iterations']} / {ref['iters']}; diff {diff:.2e} own {own:.2e}")
-    assert st["iterations"] == ref["iters"]
+    assert same_iterations(st["iterations"], ref, 1e-8)
     assert diff <= 0.25 * own
