@@ -39,6 +39,13 @@ struct RowClass {       // row blocks of the patches sharing (dim, p, stiffness 
     int n_bricks = 0;
 };
 
+struct Lane {           // scratch of one concurrent branch
+    double* part = nullptr;   // per-chunk partial sums
+    double* coef = nullptr;   // rigid-mode coefficients (P_u)
+    double* zc = nullptr;     // coarse coefficients (P_chi)
+    void* fdtmp = nullptr;    // FD intermediate tensor
+};
+
 struct FdSet {          // tensors of one FD operator (P_A or interior)
     FdTensor* d_t = nullptr;
     int2* d_slabs = nullptr;
@@ -122,6 +129,14 @@ struct afieti_handle {
     const MinresState* mask = nullptr;  // set while MINRES runs: skip stopped problems
     hipStream_t gstream = nullptr;      // non-blocking stream for the captured iteration graph
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    // The independent blocks of the saddle operator and of the
+    // preconditioner run as two concurrent branches: the caller's stream and
+    // `side` (forked and joined with events).  Each branch owns its reduction
+    // partials, coarse coefficients and FD intermediate buffer.
+    Lane lane[2];
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool capturing = false;  // the branches fork only while the iteration graph is captured
     hipGraphExec_t graph_exec = nullptr;
 
     template <typename T>
@@ -143,10 +158,14 @@ struct afieti_handle {
     ~afieti_handle() {
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (gstream) (void)hipStreamSynchronize(gstream);
+        if (side) (void)hipStreamSynchronize(side);
         for (void* p : allocs) (void)hipFree(p);
         if (h_state) (void)hipHostFree(h_state);
         if (ev_a) (void)hipEventDestroy(ev_a);
         if (ev_b) (void)hipEventDestroy(ev_b);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
         if (gstream) (void)hipStreamDestroy(gstream);
     }
 };
@@ -503,6 +522,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     h->fd_uoff = u_off;
     h->fd_doff = d_off;
     h->d_fdtmp = h->dalloc<double>(std::max(h->fd_pa.tmp_elems, h->fd_int.tmp_elems));
+    h->lane[1].fdtmp = h->dalloc<double>(std::max(h->fd_pa.tmp_elems, h->fd_int.tmp_elems));
     // ---- constraints
     h->d_cplus = h->upload(pl.c_plus, s);
     h->d_cminus = h->upload(pl.c_minus, s);
@@ -584,20 +604,65 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     HIP_OK(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&h->ev_a, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&h->ev_b, hipEventDisableTiming));
+    h->lane[0] = Lane{h->d_part, h->d_coef, h->d_zc, h->d_fdtmp};
+    h->lane[1].part = h->dalloc<double>(maxch * 6);
+    h->lane[1].coef = h->dalloc<double>(np * 6);
+    h->lane[1].zc = h->dalloc<double>(np * 6);
+    HIP_OK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     HIP_OK(hipStreamSynchronize(s));
     HIP_OK(hipGetLastError());
 }
 
 // ------------------------------------------------------------- operators
-void op_stiffness(afieti_handle* h, const double* x, double* y, const double* t, hipStream_t s) {
+// Stiffness in two stages: the per-brick quadrature of the matrix-free
+// classes (reads x only), then the per-node gathers and the assembled
+// classes, which add B^T t when t != NULL.
+void op_stiffness_bricks(afieti_handle* h, const double* x, hipStream_t s) {
+    for (const auto& rc : h->classes)
+        if (rc.mf) launch_mf_bricks(rc.p, h->d_patches, rc.d_bricks, rc.n_bricks, h->d_mftab, x, h->d_ybuf, h->mask, s);
+}
+
+void op_stiffness_rows(afieti_handle* h, const double* x, double* y, const double* t, hipStream_t s) {
     for (const auto& rc : h->classes) {
         if (rc.mf)
-            launch_stiffness_mf(rc.p, h->d_patches, rc.d_bricks, rc.n_bricks, rc.d_rb, rc.n, h->d_mftab, x,
-                                h->d_ybuf, y, h->d_btptr, h->d_btrow, h->d_btsgn, t, h->mask, s);
+            launch_mf_gather(rc.p, h->d_patches, rc.d_rb, rc.n, h->d_ybuf, y, h->d_btptr, h->d_btrow, h->d_btsgn, t,
+                             h->mask, s);
         else
             launch_stiffness_dp(rc.dim, rc.p, h->d_patches, rc.d_rb, rc.n, h->d_stencil, x, y, h->d_btptr, h->d_btrow,
                                 h->d_btsgn, t, h->mask, s);
     }
+}
+
+void op_stiffness(afieti_handle* h, const double* x, double* y, const double* t, hipStream_t s) {
+    op_stiffness_bricks(h, x, s);
+    op_stiffness_rows(h, x, y, t, s);
+}
+
+// Concurrent branches exist only inside the captured MINRES iteration
+// graph, where the fork and the join become graph edges.  Everywhere else
+// (the first preconditioner application of a solve, the eager iteration
+// path, single operator calls) the side branch is the caller's stream
+// itself and the operators run in order.
+struct Branch {
+    hipStream_t s;  // stream of the side branch
+    int ln;         // its scratch
+};
+
+// the side branch starts after the work enqueued so far on s ...
+Branch fork(afieti_handle* h, hipStream_t s) {
+    if (!h->capturing) return {s, 0};
+    HIP_OK(hipEventRecord(h->ev_fork, s));
+    HIP_OK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    return {h->side, 1};
+}
+
+// ... and s continues after the side branch
+void join(afieti_handle* h, hipStream_t s) {
+    if (!h->capturing) return;
+    HIP_OK(hipEventRecord(h->ev_join, h->side));
+    HIP_OK(hipStreamWaitEvent(s, h->ev_join, 0));
 }
 
 void op_mask_interior(afieti_handle* h, double* y, hipStream_t s) {
@@ -609,7 +674,7 @@ void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_
                 h->ah1, h->ah2, y, use_h, h->mask, s);
 }
 
-void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s) {
+void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s, int ln = 0) {
     int prec = 0;
     switch (h->opt.fd_precision) {
         case AFIETI_FD_FP32: prec = 2; break;       // MFMA, FP32 operands
@@ -620,27 +685,29 @@ void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hi
     }
     const bool f64 = prec == 0 || prec == 4;
     launch_fd(prec, set.d_t, set.n_t, set.d_slabs, set.n_slabs, set.d_cols, set.n_cols, set.d_cols64, set.n_cols64,
-              f64 ? (const void*)h->d_u64 : (const void*)h->d_u32, h->d_dtab, in, out, h->d_fdtmp, h->mask, s);
+              f64 ? (const void*)h->d_u64 : (const void*)h->d_u32, h->d_dtab, in, out, h->lane[ln].fdtmp, h->mask, s);
 }
 
 // out = P_chi y  (in place allowed)
-void op_pchi(afieti_handle* h, const double* y, double* out, hipStream_t s) {
+void op_pchi(afieti_handle* h, const double* y, double* out, hipStream_t s, int ln = 0) {
+    const Lane& L = h->lane[ln];
     launch_gamma_partial(h->d_patches, h->d_gam_chunks, h->n_gam_chunks, h->d_ctrl, h->d_gam, h->d_btptr, h->d_btrow,
-                         h->d_btsgn, y, h->d_part, s);
-    launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_gam_cptr, h->d_part,
-                           h->d_cinv, h->d_zc, h->max_nc, s);
-    launch_G_apply(h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, h->n_c, h->d_zc, -1.0, 1.0, y, out, s);
+                         h->d_btsgn, y, L.part, s);
+    launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_gam_cptr, L.part,
+                           h->d_cinv, L.zc, h->max_nc, s);
+    launch_G_apply(h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, h->n_c, L.zc, -1.0, 1.0, y, out, s);
 }
 
 // out = P_u x  (in place allowed)
-void op_pu(afieti_handle* h, const double* x, double* out, hipStream_t s) {
-    launch_rigid_partial(h->d_patches, h->d_dof_chunks, h->n_dof_chunks, h->d_ctrl, x, h->d_part, s);
-    launch_rigid_finalize(h->d_dof_cptr, h->n_patches, h->d_part, h->d_rtr, h->d_coef, s);
-    launch_rigid_update(h->d_patches, h->d_dof_chunks, h->n_dof_chunks, h->d_ctrl, h->d_coef, x, out, s);
+void op_pu(afieti_handle* h, const double* x, double* out, hipStream_t s, int ln = 0) {
+    const Lane& L = h->lane[ln];
+    launch_rigid_partial(h->d_patches, h->d_dof_chunks, h->n_dof_chunks, h->d_ctrl, x, L.part, s);
+    launch_rigid_finalize(h->d_dof_cptr, h->n_patches, L.part, h->d_rtr, L.coef, s);
+    launch_rigid_update(h->d_patches, h->d_dof_chunks, h->n_dof_chunks, h->d_ctrl, L.coef, x, out, s);
 }
 
 // out = P_S y (Remark 1, non-redundant, or the plain variant)
-void op_ps(afieti_handle* h, const double* y, double* out, hipStream_t s) {
+void op_ps(afieti_handle* h, const double* y, double* out, hipStream_t s, int ln = 0) {
     const bool nr = h->opt.ps_variant == AFIETI_PS_NR;
     const double* a = y;
     if (nr) {
@@ -649,7 +716,7 @@ void op_ps(afieti_handle* h, const double* y, double* out, hipStream_t s) {
     }
     launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, a, h->tv, s);
     op_ahat(h, h->tv, h->tt, 0, s);
-    op_fd(h, h->fd_int, h->tt, h->tv, s);  // v_I = -((A-hat)_II)^{-1} (A-hat v0)_I
+    op_fd(h, h->fd_int, h->tt, h->tv, s, ln);  // v_I = -((A-hat)_II)^{-1} (A-hat v0)_I
     op_ahat(h, h->tv, h->tt, 1, s);        // H^{d-2} A-hat v; B reads its Gamma part
     if (nr) {
         launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, h->tt, h->c2, s);
@@ -659,20 +726,30 @@ void op_ps(afieti_handle* h, const double* y, double* out, hipStream_t s) {
     }
 }
 
+// z = [P_u P_A^{-1} P_u r_u ; P_chi P_S P_chi r_chi]: the two blocks are
+// independent and run concurrently (multiplier block on the side branch)
 void op_prec(afieti_handle* h, const double* r, double* z, hipStream_t s) {
+    const Branch b = fork(h, s);
+    op_pchi(h, r + h->n_dof, h->c3, b.s, b.ln);
+    op_ps(h, h->c3, h->c4, b.s, b.ln);
+    op_pchi(h, h->c4, z + h->n_dof, b.s, b.ln);
     op_pu(h, r, h->s1, s);
     op_fd(h, h->fd_pa, h->s1, h->s2, s);
     op_pu(h, h->s2, z, s);
-    op_pchi(h, r + h->n_dof, h->c3, s);
-    op_ps(h, h->c3, h->c4, s);
-    op_pchi(h, h->c4, z + h->n_dof, s);
+    join(h, s);
 }
 
+// y = [A w + B^T P_chi chi ; P_chi B w]: the multiplier work runs on the
+// side branch while the brick quadrature of A w runs; the gathers then add
+// B^T P_chi chi
 void op_saddle(afieti_handle* h, const double* x, double* y, hipStream_t s) {
-    op_pchi(h, x + h->n_dof, h->c5, s);
-    op_stiffness(h, x, y, h->c5, s);
-    launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, x, h->c6, s);
-    op_pchi(h, h->c6, y + h->n_dof, s);
+    const Branch b = fork(h, s);
+    op_pchi(h, x + h->n_dof, h->c5, b.s, b.ln);
+    launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, x, h->c6, b.s);
+    op_pchi(h, h->c6, y + h->n_dof, b.s, b.ln);
+    op_stiffness_bricks(h, x, s);
+    join(h, s);
+    op_stiffness_rows(h, x, y, h->c5, s);
 }
 
 // y = M x, physical mass (block diagonal over patches and components)
@@ -760,7 +837,13 @@ int run_minres(afieti_handle* h, hipStream_t s, afieti_stats* st) {
             hipGraph_t graph;
             HIP_OK(hipStreamBeginCapture(g, hipStreamCaptureModeThreadLocal));
             MinresBufs bc = initial_bufs(h);
+            struct Capturing {  // cleared on every exit, errors included
+                afieti_handle* h;
+                ~Capturing() { h->capturing = false; }
+            } guard{h};
+            h->capturing = true;
             for (int r = 0; r < kGraphIters; ++r) minres_iteration(h, g, bc);
+            h->capturing = false;
             HIP_OK(hipStreamEndCapture(g, &graph));
             HIP_OK(hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0));
             HIP_OK(hipGraphDestroy(graph));

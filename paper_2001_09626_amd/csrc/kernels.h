@@ -49,15 +49,18 @@ void launch_stiffness_dp(int dim, int p, const DevPatch* dp, const int4* d_rowbl
                          const double* t, const MinresState* mask, hipStream_t s);
 // zero the interior nodes of every patch and component
 void launch_mask_interior(const DevPatch* dp, const int4* d_rowblocks, int n_rowblocks, double* y, hipStream_t s);
-// Matrix-free y = A x (+ B^T t) for the 3D C^{p-1} patches of degree p:
-// per-brick sum-factorised quadrature into ybuf, then a per-node gather over
-// the row blocks rb.  bricks: (patch, b1, b2, b3) in patch order; tab: the
-// per-brick univariate tables (mf_table_doubles(p) doubles per direction and
-// brick, from DevPatch::tab_off[d]): V[q][t], D[q][t], W[q], E[q].
-void launch_stiffness_mf(int p, const DevPatch* dp, const int4* bricks, int n_bricks, const int4* rb, int nrb,
-                         const double* tab, const double* x, double* ybuf, double* y, const int64_t* bt_ptr,
-                         const int* bt_row, const double* bt_sign, const double* t, const MinresState* mask,
-                         hipStream_t s);
+// Matrix-free y = A x (+ B^T t) for the 3D C^{p-1} patches of degree p, in
+// two launches: launch_mf_bricks does the sum-factorised quadrature of every
+// brick (bricks: (patch, b1, b2, b3) in patch order) into ybuf,
+// launch_mf_gather sums the brick contributions per node over the row
+// blocks rb and adds B^T t.  tab: the per-brick univariate tables
+// (mf_table_doubles(p) doubles per direction and brick, from
+// DevPatch::tab_off[d]): V[q][t], D[q][t], W[q], E[q].
+void launch_mf_bricks(int p, const DevPatch* dp, const int4* bricks, int n_bricks, const double* tab,
+                      const double* x, double* ybuf, const MinresState* mask, hipStream_t s);
+void launch_mf_gather(int p, const DevPatch* dp, const int4* rb, int nrb, const double* ybuf, double* y,
+                      const int64_t* bt_ptr, const int* bt_row, const double* bt_sign, const double* t,
+                      const MinresState* mask, hipStream_t s);
 // elements per brick direction of the matrix-free kernel for degree p
 int mf_brick_elems(int p);
 // doubles per (direction, brick) table of the matrix-free kernel for degree p

@@ -1170,10 +1170,14 @@ __global__ void __launch_bounds__(kBlock) k_mf_gather(const DevPatch* __restrict
 }
 
 template <int P>
-void mf_t(const DevPatch* dp, const int4* bricks, int n_bricks, const int4* rb, int nrb, const double* tab,
-          const double* x, double* ybuf, double* y, const int64_t* bp, const int* br, const double* bs,
-          const double* t, const MinresState* mask, hipStream_t s) {
+void mf_bricks_t(const DevPatch* dp, const int4* bricks, int n_bricks, const double* tab, const double* x,
+                 double* ybuf, const MinresState* mask, hipStream_t s) {
     hipLaunchKernelGGL(k_mf_brick<P>, dim3(n_bricks), dim3(MfShape<P>::NT), 0, s, dp, bricks, tab, x, ybuf, mask);
+}
+
+template <int P>
+void mf_gather_t(const DevPatch* dp, const int4* rb, int nrb, const double* ybuf, double* y, const int64_t* bp,
+                 const int* br, const double* bs, const double* t, const MinresState* mask, hipStream_t s) {
     hipLaunchKernelGGL(k_mf_gather<P>, dim3(nrb), dim3(kBlock), 0, s, dp, rb, ybuf, y, bp, br, bs, t, mask);
 }
 
@@ -1363,7 +1367,8 @@ __global__ void __launch_bounds__(kBlock) k_rigid_finalize(const int* __restrict
 
 // one block per problem: g = sum of the partials per patch and mode (one
 // wave per entry, lanes strided over the chunks, fixed shuffle tree),
-// zc = (G^T G)^{-1} g, scattered to zc[patch * 6 + mode]
+// zc = (G^T G)^{-1} g, scattered to zc[patch * 6 + mode]; the slots of the
+// modes a 2D patch does not have are set to zero (G_apply reads all six)
 __global__ void __launch_bounds__(kBlock) k_coarse_finalize(const int* __restrict__ p0, const int* __restrict__ np,
                                                             const int* __restrict__ nmod, const int64_t* __restrict__ coff,
                                                             const int* __restrict__ cptr, const double* __restrict__ part,
@@ -1388,6 +1393,8 @@ __global__ void __launch_bounds__(kBlock) k_coarse_finalize(const int* __restric
         for (int j = 0; j < nc; ++j) s += C[(int64_t)e * nc + j] * g[j];
         zc[(patch0 + e / nm) * 6 + e % nm] = s;
     }
+    for (int e = threadIdx.x; e < npch * (6 - nm); e += blockDim.x)
+        zc[(patch0 + e / (6 - nm)) * 6 + nm + e % (6 - nm)] = 0.0;
 }
 
 // y = x - R coef over chunks of patch DOFs
@@ -1718,17 +1725,30 @@ void launch_mask_interior(const DevPatch* dp, const int4* rb, int nrb, double* y
     if (nrb) hipLaunchKernelGGL(k_mask_interior, dim3(nrb), dim3(kBlock), 0, s, dp, rb, y);
 }
 
-void launch_stiffness_mf(int p, const DevPatch* dp, const int4* bricks, int n_bricks, const int4* rb, int nrb,
-                         const double* tab, const double* x, double* ybuf, double* y, const int64_t* bp,
-                         const int* br, const double* bs, const double* t, const MinresState* mask, hipStream_t s) {
+void launch_mf_bricks(int p, const DevPatch* dp, const int4* bricks, int n_bricks, const double* tab,
+                      const double* x, double* ybuf, const MinresState* mask, hipStream_t s) {
     if (n_bricks == 0) return;
     switch (p) {
-        case 1: mf_t<1>(dp, bricks, n_bricks, rb, nrb, tab, x, ybuf, y, bp, br, bs, t, mask, s); break;
-        case 2: mf_t<2>(dp, bricks, n_bricks, rb, nrb, tab, x, ybuf, y, bp, br, bs, t, mask, s); break;
-        case 3: mf_t<3>(dp, bricks, n_bricks, rb, nrb, tab, x, ybuf, y, bp, br, bs, t, mask, s); break;
-        case 4: mf_t<4>(dp, bricks, n_bricks, rb, nrb, tab, x, ybuf, y, bp, br, bs, t, mask, s); break;
-        case 5: mf_t<5>(dp, bricks, n_bricks, rb, nrb, tab, x, ybuf, y, bp, br, bs, t, mask, s); break;
-        default: mf_t<6>(dp, bricks, n_bricks, rb, nrb, tab, x, ybuf, y, bp, br, bs, t, mask, s); break;
+        case 1: mf_bricks_t<1>(dp, bricks, n_bricks, tab, x, ybuf, mask, s); break;
+        case 2: mf_bricks_t<2>(dp, bricks, n_bricks, tab, x, ybuf, mask, s); break;
+        case 3: mf_bricks_t<3>(dp, bricks, n_bricks, tab, x, ybuf, mask, s); break;
+        case 4: mf_bricks_t<4>(dp, bricks, n_bricks, tab, x, ybuf, mask, s); break;
+        case 5: mf_bricks_t<5>(dp, bricks, n_bricks, tab, x, ybuf, mask, s); break;
+        default: mf_bricks_t<6>(dp, bricks, n_bricks, tab, x, ybuf, mask, s); break;
+    }
+}
+
+void launch_mf_gather(int p, const DevPatch* dp, const int4* rb, int nrb, const double* ybuf, double* y,
+                      const int64_t* bp, const int* br, const double* bs, const double* t, const MinresState* mask,
+                      hipStream_t s) {
+    if (nrb == 0) return;
+    switch (p) {
+        case 1: mf_gather_t<1>(dp, rb, nrb, ybuf, y, bp, br, bs, t, mask, s); break;
+        case 2: mf_gather_t<2>(dp, rb, nrb, ybuf, y, bp, br, bs, t, mask, s); break;
+        case 3: mf_gather_t<3>(dp, rb, nrb, ybuf, y, bp, br, bs, t, mask, s); break;
+        case 4: mf_gather_t<4>(dp, rb, nrb, ybuf, y, bp, br, bs, t, mask, s); break;
+        case 5: mf_gather_t<5>(dp, rb, nrb, ybuf, y, bp, br, bs, t, mask, s); break;
+        default: mf_gather_t<6>(dp, rb, nrb, ybuf, y, bp, br, bs, t, mask, s); break;
     }
 }
 
