@@ -89,10 +89,14 @@ struct afieti_handle {
     int64_t part_e_n = 0, part_m_n = 0;
     std::vector<int> fd_uoff, fd_doff;
     std::vector<RowClass> classes;
-    int4* d_ahat_slabs = nullptr;  // (patch, component, i3)
-    int n_ahat_slabs = 0;
-    int4* d_all_rb = nullptr;      // row blocks of every patch
-    int n_all_rb = 0;
+    struct AhatClass {             // patches of one degree
+        int p = 0, max_n12 = 0;
+        int4* d_slabs = nullptr;   // (patch, component, i3)
+        int n_slabs = 0;
+        int4* d_rb = nullptr;      // row blocks (patch, component, node0)
+        int n_rb = 0;
+    };
+    std::vector<AhatClass> ahat;
     double *ah1 = nullptr, *ah2 = nullptr;
     // FD
     double* d_u64 = nullptr;
@@ -387,18 +391,28 @@ void device_setup(afieti_handle* h, hipStream_t s) {
             for (int64_t n0 = 0; n0 < P.nodes; n0 += kBlock) v.push_back(make_int4(k, c, (int)n0, 0));
     }
     {
-        std::vector<int4> all, sl;
+        // A-hat classes by degree (the kernels are specialised on p)
+        std::map<int, std::pair<std::vector<int4>, std::vector<int4>>> byp;
+        std::map<int, int> n12;
         for (int k = 0; k < np; ++k) {
             const PatchPlan& P = pl.patches[k];
+            auto& e = byp[P.p];
+            n12[P.p] = std::max(n12[P.p], P.n[0] * P.n[1]);
             for (int c = 0; c < P.dim; ++c) {
-                for (int64_t n0 = 0; n0 < P.nodes; n0 += kBlock) all.push_back(make_int4(k, c, (int)n0, 0));
-                for (int i3 = 0; i3 < P.n[2]; ++i3) sl.push_back(make_int4(k, c, i3, 0));
+                for (int64_t n0 = 0; n0 < P.nodes; n0 += kBlock) e.second.push_back(make_int4(k, c, (int)n0, 0));
+                for (int i3 = 0; i3 < P.n[2]; ++i3) e.first.push_back(make_int4(k, c, i3, 0));
             }
         }
-        h->n_all_rb = (int)all.size();
-        h->d_all_rb = h->upload(all, s);
-        h->n_ahat_slabs = (int)sl.size();
-        h->d_ahat_slabs = h->upload(sl, s);
+        for (auto& kv : byp) {
+            afieti_handle::AhatClass ac;
+            ac.p = kv.first;
+            ac.max_n12 = n12[kv.first];
+            ac.n_slabs = (int)kv.second.first.size();
+            ac.d_slabs = h->upload(kv.second.first, s);
+            ac.n_rb = (int)kv.second.second.size();
+            ac.d_rb = h->upload(kv.second.second, s);
+            h->ahat.push_back(ac);
+        }
     }
     int64_t ybuf = 0;
     std::vector<double> mftab;
@@ -670,8 +684,9 @@ void op_mask_interior(afieti_handle* h, double* y, hipStream_t s) {
 }
 
 void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_t s) {
-    launch_ahat(h->d_patches, h->d_ahat_slabs, h->n_ahat_slabs, h->d_all_rb, h->n_all_rb, h->d_kband, h->d_mband, x,
-                h->ah1, h->ah2, y, use_h, h->mask, s);
+    for (const auto& ac : h->ahat)
+        launch_ahat(ac.p, h->d_patches, ac.d_slabs, ac.n_slabs, ac.d_rb, ac.n_rb, ac.max_n12, h->d_kband, h->d_mband,
+                    x, h->ah1, h->ah2, y, use_h, h->mask, s);
 }
 
 void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s, int ln = 0) {
@@ -706,36 +721,52 @@ void op_pu(afieti_handle* h, const double* x, double* out, hipStream_t s, int ln
     launch_rigid_update(h->d_patches, h->d_dof_chunks, h->n_dof_chunks, h->d_ctrl, L.coef, x, out, s);
 }
 
-// out = P_S y (Remark 1, non-redundant, or the plain variant)
-void op_ps(afieti_handle* h, const double* y, double* out, hipStream_t s, int ln = 0) {
+// out = P_S y (Remark 1, non-redundant, or the plain variant), in three
+// stages so that a caller can interleave them with other work:
+//   1: v0 = B^T W y on Gamma, t = A-hat v0
+//   2: v_I = -((A-hat)_II)^{-1} t_I  (interior FD, in place in v)
+//   3: out = W B (H^{d-2} A-hat v)
+void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipStream_t s, int ln) {
     const bool nr = h->opt.ps_variant == AFIETI_PS_NR;
-    const double* a = y;
-    if (nr) {
-        launch_W(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, y, h->c1, s);
-        a = h->c1;
-    }
-    launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, a, h->tv, s);
-    op_ahat(h, h->tv, h->tt, 0, s);
-    op_fd(h, h->fd_int, h->tt, h->tv, s, ln);  // v_I = -((A-hat)_II)^{-1} (A-hat v0)_I
-    op_ahat(h, h->tv, h->tt, 1, s);        // H^{d-2} A-hat v; B reads its Gamma part
-    if (nr) {
-        launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, h->tt, h->c2, s);
-        launch_W(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->c2, out, s);
+    if (stage == 1) {
+        const double* a = y;
+        if (nr) {
+            launch_W(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, y, h->c1, s);
+            a = h->c1;
+        }
+        launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, a, h->tv, s);
+        op_ahat(h, h->tv, h->tt, 0, s);
+    } else if (stage == 2) {
+        op_fd(h, h->fd_int, h->tt, h->tv, s, ln);
     } else {
-        launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, h->tt, out, s);
+        op_ahat(h, h->tv, h->tt, 1, s);  // B reads the Gamma part
+        if (nr) {
+            launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, h->tt, h->c2, s);
+            launch_W(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->c2, out, s);
+        } else {
+            launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, h->tt, out, s);
+        }
     }
+}
+
+void op_ps(afieti_handle* h, const double* y, double* out, hipStream_t s, int ln = 0) {
+    for (int stage = 1; stage <= 3; ++stage) op_ps_stage(h, stage, y, out, s, ln);
 }
 
 // z = [P_u P_A^{-1} P_u r_u ; P_chi P_S P_chi r_chi]: the two blocks are
 // independent and run concurrently (multiplier block on the side branch)
+// (the launches of the two blocks are interleaved: the graph executor
+// starts nodes in the order they were captured)
 void op_prec(afieti_handle* h, const double* r, double* z, hipStream_t s) {
     const Branch b = fork(h, s);
     op_pchi(h, r + h->n_dof, h->c3, b.s, b.ln);
-    op_ps(h, h->c3, h->c4, b.s, b.ln);
-    op_pchi(h, h->c4, z + h->n_dof, b.s, b.ln);
     op_pu(h, r, h->s1, s);
+    op_ps_stage(h, 1, h->c3, h->c4, b.s, b.ln);
     op_fd(h, h->fd_pa, h->s1, h->s2, s);
+    op_ps_stage(h, 2, h->c3, h->c4, b.s, b.ln);
     op_pu(h, h->s2, z, s);
+    op_ps_stage(h, 3, h->c3, h->c4, b.s, b.ln);
+    op_pchi(h, h->c4, z + h->n_dof, b.s, b.ln);
     join(h, s);
 }
 
@@ -744,10 +775,12 @@ void op_prec(afieti_handle* h, const double* r, double* z, hipStream_t s) {
 // B^T P_chi chi
 void op_saddle(afieti_handle* h, const double* x, double* y, hipStream_t s) {
     const Branch b = fork(h, s);
+    // the brick quadrature is enqueued first: the graph executor starts the
+    // branches in the order they were captured
+    op_stiffness_bricks(h, x, s);
     op_pchi(h, x + h->n_dof, h->c5, b.s, b.ln);
     launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, x, h->c6, b.s);
     op_pchi(h, h->c6, y + h->n_dof, b.s, b.ln);
-    op_stiffness_bricks(h, x, s);
     join(h, s);
     op_stiffness_rows(h, x, y, h->c5, s);
 }

@@ -59,6 +59,25 @@ __device__ inline void block_sum(double (&v)[NV], double* lds /* NV * 4 */) {
     }
 }
 
+// dst[e] = load(e) for e < n (n <= IT kBlock): every global load of a thread
+// is issued before its LDS stores, so their latencies overlap
+template <int IT, typename T, typename F>
+__device__ inline void batched_copy(T* dst, int n, F load) {
+    T v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + it * kBlock;
+        v[it] = e < n ? load(e) : (T)0;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + it * kBlock;
+        if (e < n) dst[e] = v[it];
+    }
+}
+
+constexpr int kSlabIt = (kMaxN * kMaxN + kBlock - 1) / kBlock;  // loads per thread of an n x n slab
+
 // =============================================================== FD kernels
 // Pass 1: per (tensor, slab i3): Y[a2][a1] = sum_{i2,i1} U2[i2][a2] X[i2][i1] U1[i1][a1]
 template <typename T>
@@ -74,11 +93,11 @@ __global__ void __launch_bounds__(kBlock) k_fd_fwd12(const FdTensor* __restrict_
     T* Y = X + kMaxN * kMaxN;
     T* U = Y + kMaxN * kMaxN;
     const double* src = in + t.in_off + (int64_t)i3 * t.s3;
-    for (int e = threadIdx.x; e < n12; e += kBlock) {
-        int i2 = e / n1, i1 = e - i2 * n1;
-        X[e] = (T)src[(int64_t)i2 * t.s2 + i1];
-    }
-    for (int e = threadIdx.x; e < n1 * n1; e += kBlock) U[e] = ut[t.u_off[0] + e];
+    batched_copy<kSlabIt>(X, n12, [&](int e) {
+        const int i2 = e / n1, i1 = e - i2 * n1;
+        return (T)src[(int64_t)i2 * t.s2 + i1];
+    });
+    batched_copy<kSlabIt>(U, n1 * n1, [&](int e) { return ut[t.u_off[0] + e]; });
     __syncthreads();
     for (int e = threadIdx.x; e < n12; e += kBlock) {  // Y[i2][a1]
         int i2 = e / n1, a1 = e - i2 * n1;
@@ -87,7 +106,7 @@ __global__ void __launch_bounds__(kBlock) k_fd_fwd12(const FdTensor* __restrict_
         Y[e] = acc;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < n2 * n2; e += kBlock) U[e] = ut[t.u_off[1] + e];
+    batched_copy<kSlabIt>(U, n2 * n2, [&](int e) { return ut[t.u_off[1] + e]; });
     __syncthreads();
     T* dst = tmp + t.tmp_off + (int64_t)i3 * n12;
     for (int e = threadIdx.x; e < n12; e += kBlock) {  // Z[a2][a1]
@@ -115,11 +134,11 @@ __global__ void __launch_bounds__(kBlock) k_fd_mid3(const FdTensor* __restrict__
     T* Zt = Z + kMaxN * NC;
     T* U = Zt + kMaxN * NC;
     T* base = tmp + t.tmp_off;
-    for (int e = threadIdx.x; e < n3 * NC; e += kBlock) {
-        int i3 = e / NC, c = e - i3 * NC, col = col0 + c;
-        Z[e] = col < n12 ? base[(int64_t)i3 * n12 + col] : (T)0;
-    }
-    for (int e = threadIdx.x; e < n3 * n3; e += kBlock) U[e] = ut[t.u_off[2] + e];
+    batched_copy<(kMaxN * NC + kBlock - 1) / kBlock>(Z, n3 * NC, [&](int e) {
+        const int i3 = e / NC, col = col0 + e - i3 * NC;
+        return col < n12 ? base[(int64_t)i3 * n12 + col] : (T)0;
+    });
+    batched_copy<kSlabIt>(U, n3 * n3, [&](int e) { return ut[t.u_off[2] + e]; });
     __syncthreads();
     const int c = threadIdx.x % NC, g = threadIdx.x / NC;  // 8 groups over a3
     const int col = col0 + c;
@@ -154,8 +173,8 @@ __global__ void __launch_bounds__(kBlock) k_fd_bwd12(const FdTensor* __restrict_
     T* Y = Z + kMaxN * kMaxN;
     T* U = Y + kMaxN * kMaxN;
     const T* src = tmp + t.tmp_off + (int64_t)i3 * n12;
-    for (int e = threadIdx.x; e < n12; e += kBlock) Z[e] = src[e];
-    for (int e = threadIdx.x; e < n1 * n1; e += kBlock) U[e] = ut[t.u_off[0] + e];
+    batched_copy<kSlabIt>(Z, n12, [&](int e) { return src[e]; });
+    batched_copy<kSlabIt>(U, n1 * n1, [&](int e) { return ut[t.u_off[0] + e]; });
     __syncthreads();
     for (int e = threadIdx.x; e < n12; e += kBlock) {  // Y[a2][i1] = sum_a1 Z[a2][a1] U1[i1][a1]
         int a2 = e / n1, i1 = e - a2 * n1;
@@ -164,7 +183,7 @@ __global__ void __launch_bounds__(kBlock) k_fd_bwd12(const FdTensor* __restrict_
         Y[e] = acc;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < n2 * n2; e += kBlock) U[e] = ut[t.u_off[1] + e];
+    batched_copy<kSlabIt>(U, n2 * n2, [&](int e) { return ut[t.u_off[1] + e]; });
     __syncthreads();
     double* dst = out + t.out_off + (int64_t)i3 * t.s3;
     for (int e = threadIdx.x; e < n12; e += kBlock) {  // X[i2][i1] = sum_a2 U2[i2][a2] Y[a2][i1]
@@ -239,15 +258,29 @@ __device__ inline typename MfmaK<MODE>::Acc mfma_tile(const typename MfmaK<MODE>
 }
 
 // stage a rows x cols block (row stride src_ld in global) into LDS as T,
-// zero padded to prow x pcol with leading dimension ld
+// zero padded to prow x pcol (prow * pcol <= 16 kBlock) with leading
+// dimension ld; every global load of a thread is issued before its stores
 template <typename T, typename S>
 __device__ inline void stage(T* dst, int ld, int prow, int pcol, const S* src, int64_t src_ld, int rows, int cols) {
-    for (int e = threadIdx.x; e < prow * pcol; e += kBlock) {
+    constexpr int IT = 16;
+    const int total = prow * pcol;
+    S v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + it * kBlock;
         const int i = e / pcol, j = e - i * pcol;
-        if constexpr (std::is_same<T, __bf16>::value)
-            dst[i * ld + j] = (i < rows && j < cols) ? (T)(float)src[(int64_t)i * src_ld + j] : (T)0.f;
-        else
-            dst[i * ld + j] = (i < rows && j < cols) ? (T)src[(int64_t)i * src_ld + j] : (T)0;
+        v[it] = (e < total && i < rows && j < cols) ? src[(int64_t)i * src_ld + j] : (S)0;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int e = threadIdx.x + it * kBlock;
+        if (e < total) {
+            const int i = e / pcol, j = e - i * pcol;
+            if constexpr (std::is_same<T, __bf16>::value)
+                dst[i * ld + j] = (T)(float)v[it];
+            else
+                dst[i * ld + j] = (T)v[it];
+        }
     }
 }
 
@@ -326,9 +359,21 @@ __global__ void __launch_bounds__(kBlock) k_fdm_mid3(const FdTensor* __restrict_
     const int p3 = pad16(n3), k3 = M::kpad(n3);
     const int col0 = it.y * NC;
     typename M::Tmp* base = tmp + t.tmp_off;
-    for (int e = threadIdx.x; e < k3 * NC; e += kBlock) {
-        const int i3 = e / NC, c = e - i3 * NC, col = col0 + c;
-        Zc[i3 * LDC + c] = (i3 < n3 && col < n12) ? (T)base[(int64_t)i3 * n12 + col] : (T)0.f;
+    {
+        constexpr int IT = KP * NC / kBlock;  // k3 <= KP
+        typename M::Tmp v[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * kBlock;
+            const int i3 = e / NC, c = e - i3 * NC, col = col0 + c;
+            v[it] = (i3 < n3 && col < n12) ? base[(int64_t)i3 * n12 + col] : (typename M::Tmp)0;
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * kBlock;
+            const int i3 = e / NC, c = e - i3 * NC;
+            if (i3 < k3) Zc[i3 * LDC + c] = (T)v[it];
+        }
     }
     stage(U3, LDU, k3, k3, ut + t.u_off[2], n3, n3, n3);
     for (int e = threadIdx.x; e < (k3 - p3) * LDC; e += kBlock) Zt[p3 * LDC + e] = (T)0.f;
@@ -1154,14 +1199,28 @@ __global__ void __launch_bounds__(kBlock) k_mf_gather(const DevPatch* __restrict
         lo[d] = l <= 0 ? 0 : (l + BE - 1) / BE;
         hi[d] = min(pa.nb[d] - 1, i[d] / BE);
     }
-    double acc = 0.0;
-    for (int b3 = lo[2]; b3 <= hi[2]; ++b3)
-        for (int b2 = lo[1]; b2 <= hi[1]; ++b2)
-            for (int b1 = lo[0]; b1 <= hi[0]; ++b1) {
-                const int64_t g = (int64_t)(b3 * pa.nb[1] + b2) * pa.nb[0] + b1;
-                const int t1 = i[0] - b1 * BE, t2 = i[1] - b2 * BE, t3 = i[2] - b3 * BE;
-                acc += ybuf[pa.ybuf_off + g * 3 * NB3 + c * NB3 + (t3 * NB + t2) * NB + t1];
+    // at most NR bricks per direction contain a node: all loads are issued
+    // before the sum, which runs in the fixed (b3, b2, b1) order
+    constexpr int NR = (NB + BE - 1) / BE;
+    double v[NR * NR * NR];
+#pragma unroll
+    for (int a3 = 0; a3 < NR; ++a3)
+#pragma unroll
+        for (int a2 = 0; a2 < NR; ++a2)
+#pragma unroll
+            for (int a1 = 0; a1 < NR; ++a1) {
+                const int b3 = lo[2] + a3, b2 = lo[1] + a2, b1 = lo[0] + a1;
+                double r = 0.0;
+                if (b3 <= hi[2] && b2 <= hi[1] && b1 <= hi[0]) {
+                    const int64_t g = (int64_t)(b3 * pa.nb[1] + b2) * pa.nb[0] + b1;
+                    const int t1 = i[0] - b1 * BE, t2 = i[1] - b2 * BE, t3 = i[2] - b3 * BE;
+                    r = ybuf[pa.ybuf_off + g * 3 * NB3 + c * NB3 + (t3 * NB + t2) * NB + t1];
+                }
+                v[(a3 * NR + a2) * NR + a1] = r;
             }
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < NR * NR * NR; ++a) acc += v[a];
     const int64_t row = pa.dof_off + (int64_t)c * pa.nodes + node;
     if (t) {
         for (int64_t e = bt_ptr[row]; e < bt_ptr[row + 1]; ++e) acc += bt_sign[e] * t[bt_row[e]];
@@ -1188,28 +1247,32 @@ void mf_gather_t(const DevPatch* dp, const int4* rb, int nrb, const double* ybuf
 // pass 2 (per node): y = scale (M3 P + kappa_3 K3 C)     (direction 3).
 // Univariate K, M are banded (half-bandwidth p) and stored as [i][t],
 // t = j - i + p.
+// P > 0: degree known at compile time (loops unrolled); P == 0: any degree
+template <int P>
 __global__ void __launch_bounds__(kBlock) k_ahat12(const DevPatch* __restrict__ dps, const int4* __restrict__ slabs,
                                                    const double* __restrict__ kb, const double* __restrict__ mb,
-                                                   const double* __restrict__ x, double* __restrict__ P,
-                                                   double* __restrict__ Cm, const MinresState* __restrict__ mask) {
+                                                   const double* __restrict__ x, double* __restrict__ P_,
+                                                   double* __restrict__ Cm, int max_n12,
+                                                   const MinresState* __restrict__ mask) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int4 it = slabs[blockIdx.x];
     const DevPatch& pa = dps[it.x];
     if (mask && mask[pa.prob].stop) return;
     const int l = it.y, i3 = it.z;
     const int n1 = pa.n[0], n2 = pa.n[1], n12 = n1 * n2;
-    const int p = pa.p, W = 2 * p + 1;
+    const int p = P > 0 ? P : pa.p, W = 2 * p + 1;
     double* X = reinterpret_cast<double*>(smem);
-    double* T1 = X + kMaxN * kMaxN;
-    double* M1 = T1 + kMaxN * kMaxN;
+    double* T1 = X + max_n12;
+    double* M1 = T1 + max_n12;
     const int64_t base = pa.dof_off + (int64_t)l * pa.nodes + (int64_t)i3 * n12;
-    for (int e = threadIdx.x; e < n12; e += kBlock) X[e] = x[base + e];
+    batched_copy<kSlabIt>(X, n12, [&](int e) { return x[base + e]; });
     __syncthreads();
     const double* K1 = kb + pa.band_off[0];
     const double* Mb1 = mb + pa.band_off[0];
     for (int e = threadIdx.x; e < n12; e += kBlock) {
         const int i2 = e / n1, i1 = e - i2 * n1;
         double t = 0.0, m = 0.0;
+#pragma unroll
         for (int o = -p; o <= p; ++o) {
             const int j1 = i1 + o;
             if ((unsigned)j1 < (unsigned)n1) {
@@ -1229,6 +1292,7 @@ __global__ void __launch_bounds__(kBlock) k_ahat12(const DevPatch* __restrict__ 
     for (int e = threadIdx.x; e < n12; e += kBlock) {
         const int i2 = e / n1, i1 = e - i2 * n1;
         double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
         for (int o = -p; o <= p; ++o) {
             const int j2 = i2 + o;
             if ((unsigned)j2 < (unsigned)n2) {
@@ -1238,14 +1302,15 @@ __global__ void __launch_bounds__(kBlock) k_ahat12(const DevPatch* __restrict__ 
                 c += mk * M1[j2 * n1 + i1];
             }
         }
-        P[base + e] = k1 * a + k2 * b;
+        P_[base + e] = k1 * a + k2 * b;
         Cm[base + e] = c;
     }
 }
 
+template <int P>
 __global__ void __launch_bounds__(kBlock) k_ahat3(const DevPatch* __restrict__ dps, const int4* __restrict__ rb,
                                                   const double* __restrict__ kb, const double* __restrict__ mb,
-                                                  const double* __restrict__ P, const double* __restrict__ Cm,
+                                                  const double* __restrict__ P_, const double* __restrict__ Cm,
                                                   double* __restrict__ y, int use_h, const MinresState* __restrict__ mask) {
     const int4 b = rb[blockIdx.x];
     const DevPatch& pa = dps[b.x];
@@ -1253,7 +1318,7 @@ __global__ void __launch_bounds__(kBlock) k_ahat3(const DevPatch* __restrict__ d
     const int64_t node = (int64_t)b.z + threadIdx.x;
     if (node >= pa.nodes) return;
     const int l = b.y;
-    const int p = pa.p, W = 2 * p + 1;
+    const int p = P > 0 ? P : pa.p, W = 2 * p + 1;
     const int64_t n12 = (int64_t)pa.n[0] * pa.n[1];
     const int i3 = (int)(node / n12);
     const int64_t rem = node - i3 * n12;
@@ -1262,11 +1327,22 @@ __global__ void __launch_bounds__(kBlock) k_ahat3(const DevPatch* __restrict__ d
     const double* M3 = mb + pa.band_off[2] + i3 * W;
     const int64_t base = pa.dof_off + (int64_t)l * pa.nodes + rem;
     double acc = 0.0;
+#pragma unroll
     for (int o = -p; o <= p; ++o) {
         const int j3 = i3 + o;
-        if ((unsigned)j3 < (unsigned)pa.n[2]) acc += M3[o + p] * P[base + j3 * n12] + k3 * K3[o + p] * Cm[base + j3 * n12];
+        if ((unsigned)j3 < (unsigned)pa.n[2]) acc += M3[o + p] * P_[base + j3 * n12] + k3 * K3[o + p] * Cm[base + j3 * n12];
     }
     y[base + i3 * n12] = (use_h ? pa.hscale : 1.0) * acc;
+}
+
+template <int P>
+void ahat_t(const DevPatch* dp, const int4* slabs, int n_slabs, const int4* rb, int nrb, int max_n12, const double* kb,
+            const double* mb, const double* x, double* Pb, double* Cm, double* y, int use_h, const MinresState* mask,
+            hipStream_t s) {
+    if (n_slabs)
+        hipLaunchKernelGGL(k_ahat12<P>, dim3(n_slabs), dim3(kBlock), 3 * (size_t)max_n12 * sizeof(double), s, dp,
+                           slabs, kb, mb, x, Pb, Cm, max_n12, mask);
+    if (nrb) hipLaunchKernelGGL(k_ahat3<P>, dim3(nrb), dim3(kBlock), 0, s, dp, rb, kb, mb, Pb, Cm, y, use_h, mask);
 }
 
 __global__ void k_B(const int64_t* __restrict__ plus, const int64_t* __restrict__ minus, int64_t n_c, double alpha,
@@ -1369,31 +1445,56 @@ __global__ void __launch_bounds__(kBlock) k_rigid_finalize(const int* __restrict
 // wave per entry, lanes strided over the chunks, fixed shuffle tree),
 // zc = (G^T G)^{-1} g, scattered to zc[patch * 6 + mode]; the slots of the
 // modes a 2D patch does not have are set to zero (G_apply reads all six)
-__global__ void __launch_bounds__(kBlock) k_coarse_finalize(const int* __restrict__ p0, const int* __restrict__ np,
-                                                            const int* __restrict__ nmod, const int64_t* __restrict__ coff,
-                                                            const int* __restrict__ cptr, const double* __restrict__ part,
-                                                            const double* __restrict__ cinv, double* __restrict__ zc) {
+constexpr int kFinBlock = 1024;  // threads of the coarse finalisation (16 wavefronts)
+constexpr int kFinSub = 16;      // lanes per row of the (G^T G)^{-1} product
+
+__global__ void __launch_bounds__(kFinBlock) k_coarse_finalize(const int* __restrict__ p0, const int* __restrict__ np,
+                                                               const int* __restrict__ nmod,
+                                                               const int64_t* __restrict__ coff,
+                                                               const int* __restrict__ cptr,
+                                                               const double* __restrict__ part,
+                                                               const double* __restrict__ cinv,
+                                                               double* __restrict__ zc) {
     extern __shared__ __align__(16) unsigned char smem[];
     double* g = reinterpret_cast<double*>(smem);
+    constexpr int NWV = kFinBlock / 64, U = 4;
     const int pr = blockIdx.x;
     const int nm = nmod[pr], npch = np[pr], patch0 = p0[pr];
     const int nc = nm * npch;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int e = wave; e < nc; e += kBlock / 64) {
-        const int k = patch0 + e / nm, m = e % nm;
-        double s = 0.0;
-        for (int c = cptr[k] + lane; c < cptr[k + 1]; c += 64) s += part[(int64_t)c * 6 + m];
-        s = wave_sum(s);
-        if (lane == 0) g[e] = s;
+    // U entries per wavefront at a time, so that their loads overlap
+    for (int e0 = wave; e0 < nc; e0 += U * NWV) {
+        double s[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * NWV;
+            s[u] = 0.0;
+            if (e < nc) {
+                const int k = patch0 + e / nm, m = e % nm;
+                for (int c = cptr[k] + lane; c < cptr[k + 1]; c += 64) s[u] += part[(int64_t)c * 6 + m];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double t = wave_sum(s[u]);
+            if (lane == 0 && e0 + u * NWV < nc) g[e0 + u * NWV] = t;
+        }
     }
     __syncthreads();
+    // zc = C g: kFinSub lanes per row, partial sums over j = sub (mod kFinSub),
+    // then a fixed butterfly over the kFinSub lanes
     const double* C = cinv + coff[pr];
-    for (int e = threadIdx.x; e < nc; e += blockDim.x) {
+    const int sub = threadIdx.x % kFinSub;
+    for (int base = 0; base < nc; base += kFinBlock / kFinSub) {
+        const int e = base + threadIdx.x / kFinSub;
         double s = 0.0;
-        for (int j = 0; j < nc; ++j) s += C[(int64_t)e * nc + j] * g[j];
-        zc[(patch0 + e / nm) * 6 + e % nm] = s;
+        if (e < nc)
+            for (int j = sub; j < nc; j += kFinSub) s += C[(int64_t)e * nc + j] * g[j];
+#pragma unroll
+        for (int o = kFinSub / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (sub == 0 && e < nc) zc[(patch0 + e / nm) * 6 + e % nm] = s;
     }
-    for (int e = threadIdx.x; e < npch * (6 - nm); e += blockDim.x)
+    for (int e = threadIdx.x; e < npch * (6 - nm); e += kFinBlock)
         zc[(patch0 + e / (6 - nm)) * 6 + nm + e % (6 - nm)] = 0.0;
 }
 
@@ -1712,13 +1813,18 @@ void launch_stiffness_dp(int dim, int p, const DevPatch* dp, const int4* rb, int
     }
 }
 
-void launch_ahat(const DevPatch* dp, const int4* slabs, int n_slabs, const int4* rb, int nrb, const double* kb,
-                 const double* mb, const double* x, double* P, double* Cm, double* y, int use_h,
+void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, const int4* rb, int nrb, int max_n12,
+                 const double* kb, const double* mb, const double* x, double* Pb, double* Cm, double* y, int use_h,
                  const MinresState* mask, hipStream_t s) {
-    if (n_slabs)
-        hipLaunchKernelGGL(k_ahat12, dim3(n_slabs), dim3(kBlock), 3 * kMaxN * kMaxN * sizeof(double), s, dp, slabs, kb,
-                           mb, x, P, Cm, mask);
-    if (nrb) hipLaunchKernelGGL(k_ahat3, dim3(nrb), dim3(kBlock), 0, s, dp, rb, kb, mb, P, Cm, y, use_h, mask);
+    switch (p) {
+        case 1: ahat_t<1>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
+        case 2: ahat_t<2>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
+        case 3: ahat_t<3>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
+        case 4: ahat_t<4>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
+        case 5: ahat_t<5>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
+        case 6: ahat_t<6>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
+        default: ahat_t<0>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
+    }
 }
 
 void launch_mask_interior(const DevPatch* dp, const int4* rb, int nrb, double* y, hipStream_t s) {
@@ -1794,8 +1900,8 @@ void launch_rigid_finalize(const int* cptr, int n_patches, const double* partial
 void launch_coarse_finalize(const int* p0, const int* np, const int* nm, const int64_t* coff, int n_probs,
                             const int* cptr, const double* partials, const double* Cinv, double* zc, int max_nc,
                             hipStream_t s) {
-    hipLaunchKernelGGL(k_coarse_finalize, dim3(n_probs), dim3(kBlock), max_nc * sizeof(double), s, p0, np, nm, coff,
-                       cptr, partials, Cinv, zc);
+    hipLaunchKernelGGL(k_coarse_finalize, dim3(n_probs), dim3(kFinBlock), max_nc * sizeof(double), s, p0, np, nm,
+                       coff, cptr, partials, Cinv, zc);
 }
 
 void launch_rigid_update(const DevPatch* dp, const Chunk* chunks, int n_chunks, const double* ctrl, const double* coef,
