@@ -222,37 +222,47 @@ struct MfmaK {
     using Tmp = typename std::conditional<MODE == 2, double, float>::type;  // between passes
     using U = typename std::conditional<MODE == 2, double, float>::type;    // eigenvector table
     __device__ static inline int row(int g, int q) { return MODE == 2 ? g + 4 * q : 4 * g + q; }
-    __device__ static inline int kpad(int n) { return MODE == 1 ? (n + 31) & ~31 : (n + 15) & ~15; }
 };
 
-// C tile (16x16 at rows m0, cols n0) += sum_k A(m, k) B(k, n) with
-// A(m, k) = At ? a[k * lda + m] : a[m * lda + k], B(k, n) = Bt ? b[n * ldb + k] : b[k * ldb + n]
+// C tile (16x16 at rows m0, cols n0) = sum_{k < KP} A(m, k) B(k, n) with
+// A(m, k) = At ? a[k * lda + m] : a[m * lda + k], B(k, n) = Bt ? b[n * ldb + k] : b[k * ldb + n].
+// The depth is the padded KP of the mode (operands zero beyond the true
+// size), so the loop unrolls and every operand read is issued before the
+// chain of matrix instructions.
 template <int MODE, bool At, bool Bt>
 __device__ inline typename MfmaK<MODE>::Acc mfma_tile(const typename MfmaK<MODE>::T* __restrict__ a, int lda,
                                                       const typename MfmaK<MODE>::T* __restrict__ b, int ldb, int m0,
-                                                      int n0, int kdim) {
+                                                      int n0) {
+    using M = MfmaK<MODE>;
+    constexpr int KP = M::KP, STEPS = KP / M::K;
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
-    typename MfmaK<MODE>::Acc acc = {0, 0, 0, 0};
+    typename M::Acc acc = {0, 0, 0, 0};
     if constexpr (MODE != 1) {
-        for (int k0 = 0; k0 < kdim; k0 += 4) {
-            const int k = k0 + g;
-            const auto av = At ? a[k * lda + m0 + r] : a[(m0 + r) * lda + k];
-            const auto bv = Bt ? b[(n0 + r) * ldb + k] : b[k * ldb + n0 + r];
-            if constexpr (MODE == 0) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
-            else acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        typename M::T av[STEPS], bv[STEPS];
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            const int k = 4 * s + g;
+            av[s] = At ? a[k * lda + m0 + r] : a[(m0 + r) * lda + k];
+            bv[s] = Bt ? b[(n0 + r) * ldb + k] : b[k * ldb + n0 + r];
+        }
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            if constexpr (MODE == 0) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc, 0, 0, 0);
+            else acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
         }
     } else {
-        for (int k0 = 0; k0 < kdim; k0 += 32) {
-            bf16x8 av, bv;
+        bf16x8 av[STEPS], bv[STEPS];
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s)
 #pragma unroll
             for (int v = 0; v < 8; ++v) {
-                const int k = k0 + 8 * g + v;
-                av[v] = At ? a[k * lda + m0 + r] : a[(m0 + r) * lda + k];
-                bv[v] = Bt ? b[(n0 + r) * ldb + k] : b[k * ldb + n0 + r];
+                const int k = 32 * s + 8 * g + v;
+                av[s][v] = At ? a[k * lda + m0 + r] : a[(m0 + r) * lda + k];
+                bv[s][v] = Bt ? b[(n0 + r) * ldb + k] : b[k * ldb + n0 + r];
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
-        }
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[s], bv[s], acc, 0, 0, 0);
     }
     return acc;
 }
@@ -306,27 +316,26 @@ __global__ void __launch_bounds__(kBlock) k_fdm_fwd12(const FdTensor* __restrict
     if (mask && mask[t.prob].stop) return;
     const int i3 = it.y, n1 = t.n1, n2 = t.n2;
     const int p1 = pad16(n1), p2 = pad16(n2);
-    const int k1 = M::kpad(n1), k2 = M::kpad(n2);
-    stage(X, LDK, p2, k1, in + t.in_off + (int64_t)i3 * t.s3, t.s2, n2, n1);
-    stage(U1, kLD, k1, p1, ut + t.u_off[0], n1, n1, n1);
-    stage(U2, kLD, k2, p2, ut + t.u_off[1], n2, n2, n2);
+    stage(X, LDK, p2, KP, in + t.in_off + (int64_t)i3 * t.s3, t.s2, n2, n1);
+    stage(U1, kLD, KP, p1, ut + t.u_off[0], n1, n1, n1);
+    stage(U2, kLD, KP, p2, ut + t.u_off[1], n2, n2, n2);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
     const int t1 = p1 / 16, tiles1 = (p2 / 16) * t1;
     for (int tl = wave; tl < tiles1; tl += kBlock / 64) {
         const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
-        auto acc = mfma_tile<MODE, false, false>(X, LDK, U1, kLD, m0, n0, k1);
+        auto acc = mfma_tile<MODE, false, false>(X, LDK, U1, kLD, m0, n0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) Y[(m0 + M::row(g, q)) * kLD + n0 + r] = (T)acc[q];
     }
-    for (int e = threadIdx.x; e < (k2 - p2) * kLD; e += kBlock) Y[p2 * kLD + e] = (T)0.f;  // depth padding
+    for (int e = threadIdx.x; e < (KP - p2) * kLD; e += kBlock) Y[p2 * kLD + e] = (T)0.f;  // depth padding
     __syncthreads();
     typename M::Tmp* dst = tmp + t.tmp_off + (int64_t)i3 * n1 * n2;
     const int tiles2 = (p2 / 16) * t1;
     for (int tl = wave; tl < tiles2; tl += kBlock / 64) {
         const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
-        auto acc = mfma_tile<MODE, true, false>(U2, kLD, Y, kLD, m0, n0, k2);
+        auto acc = mfma_tile<MODE, true, false>(U2, kLD, Y, kLD, m0, n0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int a2 = m0 + M::row(g, q), a1 = n0 + r;
@@ -356,7 +365,7 @@ __global__ void __launch_bounds__(kBlock) k_fdm_mid3(const FdTensor* __restrict_
     const FdTensor t = tens[it.x];
     if (mask && mask[t.prob].stop) return;
     const int n1 = t.n1, n3 = t.n3, n12 = t.n1 * t.n2;
-    const int p3 = pad16(n3), k3 = M::kpad(n3);
+    const int p3 = pad16(n3);
     const int col0 = it.y * NC;
     typename M::Tmp* base = tmp + t.tmp_off;
     {
@@ -372,18 +381,18 @@ __global__ void __launch_bounds__(kBlock) k_fdm_mid3(const FdTensor* __restrict_
         for (int it = 0; it < IT; ++it) {
             const int e = threadIdx.x + it * kBlock;
             const int i3 = e / NC, c = e - i3 * NC;
-            if (i3 < k3) Zc[i3 * LDC + c] = (T)v[it];
+            Zc[i3 * LDC + c] = (T)v[it];
         }
     }
-    stage(U3, LDU, k3, k3, ut + t.u_off[2], n3, n3, n3);
-    for (int e = threadIdx.x; e < (k3 - p3) * LDC; e += kBlock) Zt[p3 * LDC + e] = (T)0.f;
+    stage(U3, LDU, KP, KP, ut + t.u_off[2], n3, n3, n3);
+    for (int e = threadIdx.x; e < (KP - p3) * LDC; e += kBlock) Zt[p3 * LDC + e] = (T)0.f;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
     const int tiles = (p3 / 16) * (NC / 16);
     for (int tl = wave; tl < tiles; tl += kBlock / 64) {
         const int m0 = (tl / (NC / 16)) * 16, n0 = (tl % (NC / 16)) * 16;
-        auto acc = mfma_tile<MODE, true, false>(U3, LDU, Zc, LDC, m0, n0, k3);
+        auto acc = mfma_tile<MODE, true, false>(U3, LDU, Zc, LDC, m0, n0);
         const int col = col0 + n0 + r;
         const int a2 = col / n1, a1 = col - a2 * n1;
         double lam12 = 0.0;
@@ -399,7 +408,7 @@ __global__ void __launch_bounds__(kBlock) k_fdm_mid3(const FdTensor* __restrict_
     __syncthreads();
     for (int tl = wave; tl < tiles; tl += kBlock / 64) {
         const int m0 = (tl / (NC / 16)) * 16, n0 = (tl % (NC / 16)) * 16;
-        auto acc = mfma_tile<MODE, false, false>(U3, LDU, Zt, LDC, m0, n0, k3);
+        auto acc = mfma_tile<MODE, false, false>(U3, LDU, Zt, LDC, m0, n0);
         const int col = col0 + n0 + r;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -428,18 +437,17 @@ __global__ void __launch_bounds__(kBlock) k_fdm_bwd12(const FdTensor* __restrict
     if (mask && mask[t.prob].stop) return;
     const int i3 = it.y, n1 = t.n1, n2 = t.n2;
     const int p1 = pad16(n1), p2 = pad16(n2);
-    const int k1 = M::kpad(n1), k2 = M::kpad(n2);
-    stage(Z, LDK, p2, k1, tmp + t.tmp_off + (int64_t)i3 * n1 * n2, n1, n2, n1);
-    stage(U1, LDK, p1, k1, ut + t.u_off[0], n1, n1, n1);
-    stage(U2, LDK, p2, k2, ut + t.u_off[1], n2, n2, n2);
-    for (int e = threadIdx.x; e < (k2 - p2) * kLD; e += kBlock) Y[p2 * kLD + e] = (T)0.f;
+    stage(Z, LDK, p2, KP, tmp + t.tmp_off + (int64_t)i3 * n1 * n2, n1, n2, n1);
+    stage(U1, LDK, p1, KP, ut + t.u_off[0], n1, n1, n1);
+    stage(U2, LDK, p2, KP, ut + t.u_off[1], n2, n2, n2);
+    for (int e = threadIdx.x; e < (KP - p2) * kLD; e += kBlock) Y[p2 * kLD + e] = (T)0.f;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
     const int t1 = p1 / 16, tiles = (p2 / 16) * t1;
     for (int tl = wave; tl < tiles; tl += kBlock / 64) {
         const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
-        auto acc = mfma_tile<MODE, false, true>(Z, LDK, U1, LDK, m0, n0, k1);
+        auto acc = mfma_tile<MODE, false, true>(Z, LDK, U1, LDK, m0, n0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) Y[(m0 + M::row(g, q)) * kLD + n0 + r] = (T)acc[q];
     }
@@ -447,7 +455,7 @@ __global__ void __launch_bounds__(kBlock) k_fdm_bwd12(const FdTensor* __restrict
     double* dst = out + t.out_off + (int64_t)i3 * t.s3;
     for (int tl = wave; tl < tiles; tl += kBlock / 64) {
         const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
-        auto acc = mfma_tile<MODE, false, false>(U2, LDK, Y, kLD, m0, n0, k2);
+        auto acc = mfma_tile<MODE, false, false>(U2, LDK, Y, kLD, m0, n0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int i2 = m0 + M::row(g, q), i1 = n0 + r;
