@@ -429,7 +429,6 @@ void device_setup(afieti_handle* h, hipStream_t s) {
             for (int k = 0; k < np; ++k) {
                 DevPatch& d = h->h_patches[k];
                 if (!d.mf || d.p != rc.p) continue;
-                d.brick_off = (int64_t)bricks.size();
                 d.ybuf_off = ybuf;
                 // per-brick tables: V[q][t], D[q][t] of basis b be + t at the
                 // brick's Gauss point q (zero off the support and past the
@@ -461,6 +460,20 @@ void device_setup(afieti_handle* h, hipStream_t s) {
                     for (int b2 = 0; b2 < d.nb[1]; ++b2)
                         for (int b1 = 0; b1 < d.nb[0]; ++b1) bricks.push_back(make_int4(k, b1, b2, b3));
                 ybuf += (int64_t)d.nb[0] * d.nb[1] * d.nb[2] * 3 * nbd * nbd * nbd;
+            }
+            // launch order: workgroups are handed to the 8 XCDs in turn, so
+            // workgroup w gets brick (w % 8) * ceil(n / 8) + w / 8 -- each XCD
+            // then sweeps a contiguous run of bricks, and the neighbouring
+            // bricks that share nodes and brick-buffer lines meet in its L2
+            {
+                const int n = (int)bricks.size(), per = (n + 7) / 8;
+                std::vector<int4> order;
+                order.reserve(n);
+                for (int w = 0; w < 8 * per; ++w) {
+                    const int g = (w % 8) * per + w / 8;
+                    if (g < n) order.push_back(bricks[g]);
+                }
+                bricks.swap(order);
             }
             rc.n_bricks = (int)bricks.size();
             rc.d_bricks = h->upload(bricks, s);

@@ -30,7 +30,6 @@ struct DevPatch {
     double jcoef[36];            // dF_x/deta_a = c0 + c1 eta_b + c2 eta_c + c3 eta_b eta_c, [a][x][4]
     int nb[3];                   // matrix-free bricks per direction
     int mf;                      // 1: stiffness applied matrix-free
-    int64_t brick_off;           // first brick of the patch in the brick list
     int64_t ybuf_off;            // offset (in doubles) of its bricks' partial results
     int64_t tab_off[3];          // offsets (in doubles) of its per-brick univariate tables
 };

@@ -1164,7 +1164,10 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
     }
     __syncthreads();
     // ---- B1: rows (c, t3, t2), written to the brick buffer
-    double* yb = ybuf + pa.ybuf_off + (int64_t)(blockIdx.x - pa.brick_off) * 3 * NB3;
+    // brick buffer layout [c][t3][t2][t1][brick] (brick fastest, bricks in
+    // (b3, b2, b1) order): the per-node gather reads runs of consecutive bricks
+    const int64_t nbr = (int64_t)pa.nb[0] * pa.nb[1] * pa.nb[2];
+    double* yb = ybuf + pa.ybuf_off + ((int64_t)br.w * pa.nb[1] + br.z) * pa.nb[0] + br.y;
     for (int row = tid; row < 3 * NB * NB; row += NT) {
         const double* s = sA + row * QA;
         double sd[QB], sv[QB];
@@ -1178,7 +1181,7 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
             double v = 0.0;
 #pragma unroll
             for (int q = 0; q < QB; ++q) v += T1[OD + q * NB + t] * sd[q] + T1[q * NB + t] * sv[q];
-            yb[row * NB + t] = v;
+            yb[(row * NB + t) * nbr] = v;
         }
     }
 }
@@ -1207,6 +1210,7 @@ __global__ void __launch_bounds__(kBlock) k_mf_gather(const DevPatch* __restrict
         lo[d] = l <= 0 ? 0 : (l + BE - 1) / BE;
         hi[d] = min(pa.nb[d] - 1, i[d] / BE);
     }
+    const int64_t nbr = (int64_t)pa.nb[0] * pa.nb[1] * pa.nb[2];
     // at most NR bricks per direction contain a node: all loads are issued
     // before the sum, which runs in the fixed (b3, b2, b1) order
     constexpr int NR = (NB + BE - 1) / BE;
@@ -1222,7 +1226,7 @@ __global__ void __launch_bounds__(kBlock) k_mf_gather(const DevPatch* __restrict
                 if (b3 <= hi[2] && b2 <= hi[1] && b1 <= hi[0]) {
                     const int64_t g = (int64_t)(b3 * pa.nb[1] + b2) * pa.nb[0] + b1;
                     const int t1 = i[0] - b1 * BE, t2 = i[1] - b2 * BE, t3 = i[2] - b3 * BE;
-                    r = ybuf[pa.ybuf_off + g * 3 * NB3 + c * NB3 + (t3 * NB + t2) * NB + t1];
+                    r = ybuf[pa.ybuf_off + ((int64_t)((c * NB + t3) * NB + t2) * NB + t1) * nbr + g];
                 }
                 v[(a3 * NR + a2) * NR + a1] = r;
             }
