@@ -22,6 +22,12 @@ import sys
 import time
 
 METRIC = "AF-IETI solve s to 1e-8 rel.res (FP32-FD vs FP64-FD); FD-apply DOF/s"
+# HBM bytes of one stiffness-operator application (k_mf_brick + k_mf_gather)
+# read from the FETCH_SIZE / WRITE_SIZE counters (scaled by a 1 GiB device
+# copy's readings): profiles/k_mf_stiffness_c2_traffic.md.  Valid for the
+# kernels that were measured; None for workloads without such a run.
+MEASURED_TRAFFIC = {"c2": 231.1e6}
+FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
@@ -45,7 +51,7 @@ def workload(name):
         desc = ("ragged batch of 32 3D problems: patch grids in {1,2,3}^3, 8..40 elements per direction, "
                 "p in {2,3,4}, lognormal Lame, 8 trig modes, u=0 on z=0")
     elif name.startswith("c3"):
-        p = int(name[3:]) if len(name) > 3 else 3
+        p = int(name[2:]) if len(name) > 2 else 3
         prob = W.make_c3(seed=0, p=p)
         desc = f"3D unit cube, 4x4x4 patches, p={p} C^{p-1}, 24^3 elements/patch, lognormal Lame, 8 trig modes"
     else:
@@ -91,6 +97,8 @@ def mf_flops(prob):
     (2, 3, 3 products of length NB per output in directions 1, 2, 3), the
     same number of transposed ones, and 238 flops per Gauss point for the
     Jacobian of the trilinear map, its inverse, the stress and the flux."""
+    if isinstance(prob, list):
+        return sum(mf_flops(q) for q in prob)
     total = 0
     for pd in prob["patches"]:
         p = pd["p"]
@@ -209,6 +217,8 @@ def main():
         out[f"fd_apply_ms_{name}"] = ms
         out[f"fd_apply_dof_per_s_{name}"] = s.n_dof / (ms * 1e-3)
         out[f"fd_apply_tflops_{name}"] = flops / (ms * 1e-3) / 1e12
+        if name == "fp32":
+            out["fd_apply_frac_fp32_mfma_peak"] = flops / (ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS
         log(f"FD apply {name}: {ms*1e3:.1f} us, {s.n_dof/(ms*1e-3)/1e9:.2f} GDOF/s")
 
     # stiffness matvec: the dominant kernel of every MINRES iteration
@@ -222,7 +232,7 @@ def main():
         tfs = mv_flops / (mv_ms * 1e-3) / 1e12
         log(f"stiffness matvec (matrix-free): {mv_ms:.3f} ms, {tfs:.2f} TFLOP/s FP64")
         roof = dict(bound="alu", achieved=tfs, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=tfs / FP64_PEAK_TFLOPS,
-                    traffic=None, kernel="stiffness operator: k_mf_brick + k_mf_gather",
+                    traffic=MEASURED_TRAFFIC.get(args.workload), kernel="stiffness operator: k_mf_brick + k_mf_gather",
                     flops_per_launch=mv_flops, ms_per_launch=mv_ms)
     else:
         mv_bytes = s32.stiffness_bytes + 2 * 8 * s32.n_dof
