@@ -93,11 +93,8 @@ struct afieti_handle {
         int p = 0, max_n12 = 0;
         int4* d_slabs = nullptr;   // (patch, component, i3)
         int n_slabs = 0;
-        int4* d_rb = nullptr;      // row blocks (patch, component, node0)
-        int n_rb = 0;
     };
     std::vector<AhatClass> ahat;
-    double *ah1 = nullptr, *ah2 = nullptr;
     // FD
     double* d_u64 = nullptr;
     float* d_u32 = nullptr;
@@ -392,25 +389,21 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     }
     {
         // A-hat classes by degree (the kernels are specialised on p)
-        std::map<int, std::pair<std::vector<int4>, std::vector<int4>>> byp;
+        std::map<int, std::vector<int4>> byp;
         std::map<int, int> n12;
         for (int k = 0; k < np; ++k) {
             const PatchPlan& P = pl.patches[k];
             auto& e = byp[P.p];
             n12[P.p] = std::max(n12[P.p], P.n[0] * P.n[1]);
-            for (int c = 0; c < P.dim; ++c) {
-                for (int64_t n0 = 0; n0 < P.nodes; n0 += kBlock) e.second.push_back(make_int4(k, c, (int)n0, 0));
-                for (int i3 = 0; i3 < P.n[2]; ++i3) e.first.push_back(make_int4(k, c, i3, 0));
-            }
+            for (int c = 0; c < P.dim; ++c)
+                for (int i3 = 0; i3 < P.n[2]; ++i3) e.push_back(make_int4(k, c, i3, 0));
         }
         for (auto& kv : byp) {
             afieti_handle::AhatClass ac;
             ac.p = kv.first;
             ac.max_n12 = n12[kv.first];
-            ac.n_slabs = (int)kv.second.first.size();
-            ac.d_slabs = h->upload(kv.second.first, s);
-            ac.n_rb = (int)kv.second.second.size();
-            ac.d_rb = h->upload(kv.second.second, s);
+            ac.n_slabs = (int)kv.second.size();
+            ac.d_slabs = h->upload(kv.second, s);
             h->ahat.push_back(ac);
         }
     }
@@ -616,8 +609,6 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     h->s2 = h->dalloc<double>(pl.n_dof);
     h->tv = h->dalloc<double>(pl.n_dof);
     h->tt = h->dalloc<double>(pl.n_dof);
-    h->ah1 = h->dalloc<double>(pl.n_dof);
-    h->ah2 = h->dalloc<double>(pl.n_dof);
     h->c1 = h->dalloc<double>(pl.n_c);
     h->c2 = h->dalloc<double>(pl.n_c);
     h->c3 = h->dalloc<double>(pl.n_c);
@@ -698,8 +689,8 @@ void op_mask_interior(afieti_handle* h, double* y, hipStream_t s) {
 
 void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_t s) {
     for (const auto& ac : h->ahat)
-        launch_ahat(ac.p, h->d_patches, ac.d_slabs, ac.n_slabs, ac.d_rb, ac.n_rb, ac.max_n12, h->d_kband, h->d_mband,
-                    x, h->ah1, h->ah2, y, use_h, h->mask, s);
+        launch_ahat(ac.p, h->d_patches, ac.d_slabs, ac.n_slabs, ac.max_n12, h->d_kband, h->d_mband, x, y, use_h,
+                    h->mask, s);
 }
 
 void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s, int ln = 0) {

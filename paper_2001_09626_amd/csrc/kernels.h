@@ -75,12 +75,10 @@ void launch_Bt(const int64_t* bt_ptr, const int* bt_row, const double* bt_sign, 
 void launch_W(const int* blk_start, const int* blk_size, const int* blk_dir, int64_t n_c,
               const double* y, double* z, hipStream_t s);
 // y = scale_k * A-hat x per patch and component for the patches of degree p
-// (banded Kronecker form, two sum-factorised passes through the DOF-sized
-// scratch vectors Pb and Cm).  slabs: (patch, component, i3); rb: row blocks
-// (patch, component, node0); max_n12: largest n1 n2 of those patches.
-void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, const int4* rb, int nrb, int max_n12,
-                 const double* kb, const double* mb, const double* x, double* Pb, double* Cm, double* y, int use_h,
-                 const MinresState* mask, hipStream_t s);
+// (banded Kronecker form, sum-factorised, one workgroup per slab).  slabs:
+// (patch, component, i3); max_n12: largest n1 n2 of those patches (LDS size).
+void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, const double* kb,
+                 const double* mb, const double* x, double* y, int use_h, const MinresState* mask, hipStream_t s);
 // partial sums of R^T x over patch DOF chunks (nm values per chunk)
 void launch_rigid_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks,
                           const double* ctrl, const double* x, double* partials, hipStream_t s);

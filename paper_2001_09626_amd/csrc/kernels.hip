@@ -1254,107 +1254,98 @@ void mf_gather_t(const DevPatch* dp, const int4* rb, int nrb, const double* ybuf
 
 // A-hat_l x = kappa_1 (M3 x M2 x K1) x + kappa_2 (M3 x K2 x M1) x
 //           + kappa_3 (K3 x M2 x M1) x           (Kronecker form, Section 5.2)
-// by sum factorisation in two passes.  Pass 1 (per slab i3, in LDS):
-//   P = kappa_1 M2 K1 x + kappa_2 K2 M1 x,  C = M2 M1 x   (directions 1, 2);
-// pass 2 (per node): y = scale (M3 P + kappa_3 K3 C)     (direction 3).
-// Univariate K, M are banded (half-bandwidth p) and stored as [i][t],
-// t = j - i + p.
-// P > 0: degree known at compile time (loops unrolled); P == 0: any degree
+//         = M2 (kappa_1 K1 u + kappa_3 M1 v) + kappa_2 K2 (M1 u),
+//           u = M3 x, v = K3 x,
+// by sum factorisation, one workgroup per slab i3 of a patch and component:
+// u, v on the slab (direction 3, read from global memory), then direction 1
+// (a = kappa_1 K1 u + kappa_3 M1 v, b = M1 u) and direction 2 in LDS
+// (four slab arrays).  Univariate K, M are banded (half-bandwidth p) and
+// stored as [i][t], t = j - i + p.
+// P > 0: degree known at compile time (loops unrolled); P == 0: any degree.
 template <int P>
-__global__ void __launch_bounds__(kBlock) k_ahat12(const DevPatch* __restrict__ dps, const int4* __restrict__ slabs,
-                                                   const double* __restrict__ kb, const double* __restrict__ mb,
-                                                   const double* __restrict__ x, double* __restrict__ P_,
-                                                   double* __restrict__ Cm, int max_n12,
-                                                   const MinresState* __restrict__ mask) {
+__global__ void __launch_bounds__(kBlock) k_ahat(const DevPatch* __restrict__ dps, const int4* __restrict__ slabs,
+                                                 const double* __restrict__ kb, const double* __restrict__ mb,
+                                                 const double* __restrict__ x, double* __restrict__ y, int max_n12,
+                                                 int use_h, const MinresState* __restrict__ mask) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int4 it = slabs[blockIdx.x];
     const DevPatch& pa = dps[it.x];
     if (mask && mask[pa.prob].stop) return;
     const int l = it.y, i3 = it.z;
-    const int n1 = pa.n[0], n2 = pa.n[1], n12 = n1 * n2;
+    const int n1 = pa.n[0], n2 = pa.n[1], n3 = pa.n[2], n12 = n1 * n2;
     const int p = P > 0 ? P : pa.p, W = 2 * p + 1;
-    double* X = reinterpret_cast<double*>(smem);
-    double* T1 = X + max_n12;
-    double* M1 = T1 + max_n12;
-    const int64_t base = pa.dof_off + (int64_t)l * pa.nodes + (int64_t)i3 * n12;
-    batched_copy<kSlabIt>(X, n12, [&](int e) { return x[base + e]; });
+    double* U = reinterpret_cast<double*>(smem);
+    double* V = U + max_n12;
+    double* A = V + max_n12;
+    double* Bm = A + max_n12;
+    const int64_t base = pa.dof_off + (int64_t)l * pa.nodes;
+    // direction 3
+    const double* K3 = kb + pa.band_off[2] + i3 * W;
+    const double* M3 = mb + pa.band_off[2] + i3 * W;
+    for (int e = threadIdx.x; e < n12; e += kBlock) {
+        double u = 0.0, v = 0.0;
+#pragma unroll
+        for (int o = -p; o <= p; ++o) {
+            const int j3 = i3 + o;
+            const double xx = (unsigned)j3 < (unsigned)n3 ? x[base + (int64_t)j3 * n12 + e] : 0.0;
+            u += M3[o + p] * xx;
+            v += K3[o + p] * xx;
+        }
+        U[e] = u;
+        V[e] = v;
+    }
     __syncthreads();
+    // direction 1
+    const double k1 = l == 0 ? 2 * pa.mu + pa.lam : pa.mu;
+    const double k2 = l == 1 ? 2 * pa.mu + pa.lam : pa.mu;
+    const double k3 = l == 2 ? 2 * pa.mu + pa.lam : pa.mu;
     const double* K1 = kb + pa.band_off[0];
     const double* Mb1 = mb + pa.band_off[0];
     for (int e = threadIdx.x; e < n12; e += kBlock) {
         const int i2 = e / n1, i1 = e - i2 * n1;
-        double t = 0.0, m = 0.0;
+        double ku = 0.0, mu_ = 0.0, mv = 0.0;
 #pragma unroll
         for (int o = -p; o <= p; ++o) {
             const int j1 = i1 + o;
             if ((unsigned)j1 < (unsigned)n1) {
-                const double v = X[i2 * n1 + j1];
-                t += K1[i1 * W + o + p] * v;
-                m += Mb1[i1 * W + o + p] * v;
+                const double uu = U[i2 * n1 + j1], vv = V[i2 * n1 + j1];
+                const double kk = K1[i1 * W + o + p], mm = Mb1[i1 * W + o + p];
+                ku += kk * uu;
+                mu_ += mm * uu;
+                mv += mm * vv;
             }
         }
-        T1[e] = t;
-        M1[e] = m;
+        A[e] = k1 * ku + k3 * mv;
+        Bm[e] = mu_;
     }
     __syncthreads();
-    const double k1 = l == 0 ? 2 * pa.mu + pa.lam : pa.mu;
-    const double k2 = l == 1 ? 2 * pa.mu + pa.lam : pa.mu;
+    // direction 2
+    const double sc = use_h ? pa.hscale : 1.0;
     const double* K2 = kb + pa.band_off[1];
     const double* Mb2 = mb + pa.band_off[1];
     for (int e = threadIdx.x; e < n12; e += kBlock) {
         const int i2 = e / n1, i1 = e - i2 * n1;
-        double a = 0.0, b = 0.0, c = 0.0;
+        double a = 0.0, b = 0.0;
 #pragma unroll
         for (int o = -p; o <= p; ++o) {
             const int j2 = i2 + o;
             if ((unsigned)j2 < (unsigned)n2) {
-                const double mk = Mb2[i2 * W + o + p], kk = K2[i2 * W + o + p];
-                a += mk * T1[j2 * n1 + i1];
-                b += kk * M1[j2 * n1 + i1];
-                c += mk * M1[j2 * n1 + i1];
+                a += Mb2[i2 * W + o + p] * A[j2 * n1 + i1];
+                b += K2[i2 * W + o + p] * Bm[j2 * n1 + i1];
             }
         }
-        P_[base + e] = k1 * a + k2 * b;
-        Cm[base + e] = c;
+        y[base + (int64_t)i3 * n12 + e] = sc * (a + k2 * b);
     }
 }
 
 template <int P>
-__global__ void __launch_bounds__(kBlock) k_ahat3(const DevPatch* __restrict__ dps, const int4* __restrict__ rb,
-                                                  const double* __restrict__ kb, const double* __restrict__ mb,
-                                                  const double* __restrict__ P_, const double* __restrict__ Cm,
-                                                  double* __restrict__ y, int use_h, const MinresState* __restrict__ mask) {
-    const int4 b = rb[blockIdx.x];
-    const DevPatch& pa = dps[b.x];
-    if (mask && mask[pa.prob].stop) return;
-    const int64_t node = (int64_t)b.z + threadIdx.x;
-    if (node >= pa.nodes) return;
-    const int l = b.y;
-    const int p = P > 0 ? P : pa.p, W = 2 * p + 1;
-    const int64_t n12 = (int64_t)pa.n[0] * pa.n[1];
-    const int i3 = (int)(node / n12);
-    const int64_t rem = node - i3 * n12;
-    const double k3 = l == 2 ? 2 * pa.mu + pa.lam : pa.mu;
-    const double* K3 = kb + pa.band_off[2] + i3 * W;
-    const double* M3 = mb + pa.band_off[2] + i3 * W;
-    const int64_t base = pa.dof_off + (int64_t)l * pa.nodes + rem;
-    double acc = 0.0;
-#pragma unroll
-    for (int o = -p; o <= p; ++o) {
-        const int j3 = i3 + o;
-        if ((unsigned)j3 < (unsigned)pa.n[2]) acc += M3[o + p] * P_[base + j3 * n12] + k3 * K3[o + p] * Cm[base + j3 * n12];
-    }
-    y[base + i3 * n12] = (use_h ? pa.hscale : 1.0) * acc;
-}
-
-template <int P>
-void ahat_t(const DevPatch* dp, const int4* slabs, int n_slabs, const int4* rb, int nrb, int max_n12, const double* kb,
-            const double* mb, const double* x, double* Pb, double* Cm, double* y, int use_h, const MinresState* mask,
-            hipStream_t s) {
-    if (n_slabs)
-        hipLaunchKernelGGL(k_ahat12<P>, dim3(n_slabs), dim3(kBlock), 3 * (size_t)max_n12 * sizeof(double), s, dp,
-                           slabs, kb, mb, x, Pb, Cm, max_n12, mask);
-    if (nrb) hipLaunchKernelGGL(k_ahat3<P>, dim3(nrb), dim3(kBlock), 0, s, dp, rb, kb, mb, Pb, Cm, y, use_h, mask);
+void ahat_t(const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, const double* kb, const double* mb,
+            const double* x, double* y, int use_h, const MinresState* mask, hipStream_t s) {
+    if (!n_slabs) return;
+    const size_t lds = 4 * (size_t)max_n12 * sizeof(double);  // <= 4 * 48^2 * 8 = 73,728 bytes
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void*)k_ahat<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_ahat<P>, dim3(n_slabs), dim3(kBlock), lds, s, dp, slabs, kb, mb, x, y, max_n12, use_h, mask);
 }
 
 __global__ void k_B(const int64_t* __restrict__ plus, const int64_t* __restrict__ minus, int64_t n_c, double alpha,
@@ -1825,17 +1816,16 @@ void launch_stiffness_dp(int dim, int p, const DevPatch* dp, const int4* rb, int
     }
 }
 
-void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, const int4* rb, int nrb, int max_n12,
-                 const double* kb, const double* mb, const double* x, double* Pb, double* Cm, double* y, int use_h,
-                 const MinresState* mask, hipStream_t s) {
+void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, const double* kb,
+                 const double* mb, const double* x, double* y, int use_h, const MinresState* mask, hipStream_t s) {
     switch (p) {
-        case 1: ahat_t<1>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
-        case 2: ahat_t<2>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
-        case 3: ahat_t<3>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
-        case 4: ahat_t<4>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
-        case 5: ahat_t<5>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
-        case 6: ahat_t<6>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
-        default: ahat_t<0>(dp, slabs, n_slabs, rb, nrb, max_n12, kb, mb, x, Pb, Cm, y, use_h, mask, s); break;
+        case 1: ahat_t<1>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
+        case 2: ahat_t<2>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
+        case 3: ahat_t<3>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
+        case 4: ahat_t<4>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
+        case 5: ahat_t<5>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
+        case 6: ahat_t<6>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
+        default: ahat_t<0>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
     }
 }
 
