@@ -963,8 +963,8 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
     constexpr int AK = 3 * NB * NB * QA;  // offset of A1 / SV in sA
     constexpr int BK = NB * NCB;          // stride of the k index in sB
     constexpr int OD = QB * NB, OW = 2 * QB * NB, OE = 2 * QB * NB + QB;  // D, W, E within a table
-    __shared__ double sA[2 * AK];         // [A0|A1] (later [SD|SV]) [c][t3][t2][q1]
-    __shared__ double sB[9 * BK];         // [c][k][t3][q2 QB + q1]: B00, B10, B01, later P1, P2, P3
+    __shared__ double sB[9 * BK];         // [c][k][t3][q2 QB + q1]: B00, B10, B01, then P1, P2, P3, then S
+    static_assert(2 * AK <= 9 * BK, "S must fit in the B / P buffer");
     const int4 br = bricks[blockIdx.x];
     const DevPatch& pa = dps[br.x];
     if (mask && mask[pa.prob].stop) return;
@@ -973,38 +973,36 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
     const double* __restrict__ T2 = tab + pa.tab_off[1] + (int64_t)br.z * TS;
     const double* __restrict__ T3 = tab + pa.tab_off[2] + (int64_t)br.w * TS;
     const int i1 = br.y * BE, i2 = br.z * BE, i3 = br.w * BE;  // first basis function of the brick
-    // ---- F1: rows (c, t3, t2)
-    for (int row = tid; row < 3 * NB * NB; row += NT) {
-        const int c = row / (NB * NB), t3 = (row / NB) % NB, t2 = row % NB;
-        const bool rin = i2 + t2 < pa.n[1] && i3 + t3 < pa.n[2];
-        const double* xr = x + pa.dof_off + (int64_t)c * pa.nodes +
-                           (int64_t)pa.n[0] * ((i2 + t2) + (int64_t)pa.n[1] * (i3 + t3)) + i1;
-        double xl[NB];
-#pragma unroll
-        for (int t = 0; t < NB; ++t) xl[t] = (rin && i1 + t < pa.n[0]) ? xr[t] : 0.0;
-        double* a = sA + row * QA;
-#pragma unroll
-        for (int q = 0; q < QB; ++q) {
-            double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-            for (int t = 0; t < NB; ++t) {
-                a0 += T1[q * NB + t] * xl[t];
-                a1 += T1[OD + q * NB + t] * xl[t];
-            }
-            a[q] = a0;
-            a[AK + q] = a1;
-        }
-    }
-    __syncthreads();
-    // ---- F2: rows (c, t3, q1)
+    // ---- F: rows (c, t3, q1): A0 = V1 x, A1 = D1 x along direction 1 for
+    // this q1 (each A value is formed by exactly one thread, from the NB x NB
+    // coefficients of the row's (c, t3) plane, read through the cache), then
+    // B00 = V2 A0, B10 = D2 A0, B01 = V2 A1 along direction 2
     for (int row = tid; row < 3 * NB * QB; row += NT) {
         const int c = row / (NB * QB), t3 = (row / QB) % NB, q1 = row % QB;
-        const double* a = sA + (c * NB + t3) * NB * QA + q1;
-        double a0[NB], a1[NB];
+        const bool pin = i3 + t3 < pa.n[2];
+        const double* xp = x + pa.dof_off + (int64_t)c * pa.nodes + (int64_t)pa.n[0] * pa.n[1] * (i3 + t3) + i1;
+        double v1[NB], d1[NB];
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
-            a0[t] = a[t * QA];
-            a1[t] = a[AK + t * QA];
+            v1[t] = T1[q1 * NB + t];
+            d1[t] = T1[OD + q1 * NB + t];
+        }
+        double a0[NB], a1[NB];
+#pragma unroll
+        for (int t2 = 0; t2 < NB; ++t2) {
+            const bool rin = pin && i2 + t2 < pa.n[1];
+            const double* xr = xp + (int64_t)pa.n[0] * (i2 + t2);
+            double xl[NB];
+#pragma unroll
+            for (int t = 0; t < NB; ++t) xl[t] = (rin && i1 + t < pa.n[0]) ? xr[t] : 0.0;
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int t = 0; t < NB; ++t) {
+                s0 += v1[t] * xl[t];
+                s1 += d1[t] * xl[t];
+            }
+            a0[t2] = s0;
+            a1[t2] = s1;
         }
         double* b = sB + (c * 3 * NB + t3) * NCB + q1;
 #pragma unroll
@@ -1138,8 +1136,14 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
             __syncthreads();
         }
     }
-    // ---- B2: rows (c, t3, q1)
-    for (int row = tid; row < 3 * NB * QB; row += NT) {
+    // ---- B2: rows (c, t3, q1): SD = V2^T P1, SV = D2^T P2 + V2^T P3; once
+    // every thread has read its P, S overwrites the start of sB
+    constexpr int RB2 = (3 * NB * QB + NT - 1) / NT;  // B2 rows per thread
+    double sd[RB2][NB], sv[RB2][NB];
+#pragma unroll
+    for (int rr = 0; rr < RB2; ++rr) {
+        const int row = tid + rr * NT;
+        if (row >= 3 * NB * QB) continue;
         const int c = row / (NB * QB), t3 = (row / QB) % NB, q1 = row % QB;
         const double* pp = sB + (c * 3 * NB + t3) * NCB + q1;
         double p1[QB], p2[QB], p3[QB];
@@ -1149,17 +1153,30 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
             p2[q] = pp[BK + q * QB];
             p3[q] = pp[2 * BK + q * QB];
         }
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            double a = 0.0, b = 0.0;
+#pragma unroll
+            for (int q = 0; q < QB; ++q) {
+                a += T2[q * NB + t] * p1[q];
+                b += T2[OD + q * NB + t] * p2[q] + T2[q * NB + t] * p3[q];
+            }
+            sd[rr][t] = a;
+            sv[rr][t] = b;
+        }
+    }
+    __syncthreads();
+    double* const sA = sB;  // S: [SD|SV][c][t3][t2][q1], rows of QA doubles
+#pragma unroll
+    for (int rr = 0; rr < RB2; ++rr) {
+        const int row = tid + rr * NT;
+        if (row >= 3 * NB * QB) continue;
+        const int c = row / (NB * QB), t3 = (row / QB) % NB, q1 = row % QB;
         double* s = sA + (c * NB + t3) * NB * QA + q1;
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
-            double sd = 0.0, sv = 0.0;
-#pragma unroll
-            for (int q = 0; q < QB; ++q) {
-                sd += T2[q * NB + t] * p1[q];
-                sv += T2[OD + q * NB + t] * p2[q] + T2[q * NB + t] * p3[q];
-            }
-            s[t * QA] = sd;
-            s[AK + t * QA] = sv;
+            s[t * QA] = sd[rr][t];
+            s[AK + t * QA] = sv[rr][t];
         }
     }
     __syncthreads();
