@@ -831,7 +831,11 @@ void minres_iteration(afieti_handle* h, hipStream_t s, MinresBufs& b) {
     op_prec(h, b.v_new, b.z_new, s);
     launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, b.z_new, b.v_new, h->d_part2, s);
     launch_minres_givens(h->d_state, h->d_vec_cptr, np, h->d_part2, s);
-    launch_minres_dx(h->d_state, h->d_vec_chunks, h->n_vec_chunks, b.z, b.d_old, b.d, b.d_new, x, s);
+    // the d and x updates run on the side branch, off the critical path; the
+    // next saddle operator joins that branch before anything reads the state
+    // again or overwrites z
+    const Branch bd = fork(h, s);
+    launch_minres_dx(h->d_state, h->d_vec_chunks, h->n_vec_chunks, b.z, b.d_old, b.d, b.d_new, x, bd.s);
     double* t = b.v_old;
     b.v_old = b.v;
     b.v = b.v_new;
@@ -880,6 +884,7 @@ int run_minres(afieti_handle* h, hipStream_t s, afieti_stats* st) {
             } guard{h};
             h->capturing = true;
             for (int r = 0; r < kGraphIters; ++r) minres_iteration(h, g, bc);
+            join(h, g);  // the last d/x update
             h->capturing = false;
             HIP_OK(hipStreamEndCapture(g, &graph));
             HIP_OK(hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0));
