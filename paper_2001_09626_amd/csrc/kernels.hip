@@ -948,6 +948,15 @@ struct MfShape {
     static constexpr int NW = AFIETI_MF_WAVES;              // wavefronts per brick
     static constexpr int QPG = (QB + NW - 1) / NW;          // q3 values per wavefront
     static constexpr int NT = 64 * NW;                      // threads per brick
+    // support: at brick Gauss point q (element q / (P + 1)) only basis
+    // functions tlo(q)..thi(q) are nonzero; basis t is nonzero at the Gauss
+    // points qlo(t) <= q < qhi(t).  The contractions skip the known zeros.
+    static constexpr int tlo(int q) { return q / (P + 1); }
+    static constexpr int thi(int q) { return q / (P + 1) + P; }
+    static constexpr int qlo(int t) { return (t > P ? t - P : 0) * (P + 1); }
+    static constexpr int qhi(int t) { return ((t < BE - 1 ? t : BE - 1) + 1) * (P + 1); }
+    // each wavefront's q3 range is exactly one element (BE = NW, QPG = P + 1)
+    static constexpr bool WAVE_ELEM = NW == BE && QPG == P + 1;
 };
 
 template <int P>
@@ -1009,7 +1018,7 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
         for (int q = 0; q < QB; ++q) {
             double b00 = 0.0, b10 = 0.0, b01 = 0.0;
 #pragma unroll
-            for (int t = 0; t < NB; ++t) {
+            for (int t = S::tlo(q); t <= S::thi(q); ++t) {
                 b00 += T2[q * NB + t] * a0[t];
                 b10 += T2[OD + q * NB + t] * a0[t];
                 b01 += T2[q * NB + t] * a1[t];
@@ -1031,26 +1040,38 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
         const bool act = col < NCOL;
         double F[3][3][QPG];  // [c][a][j]: gradient d u_c / d eta_a, then flux
         if (act) {
+            // E: the element of this wavefront's q3 range (its basis functions
+            // E..E+P), or -1 for all basis functions
+            auto grads = [&](auto Ec) {
+                constexpr int E = decltype(Ec)::value;
+                constexpr int TA = E < 0 ? 0 : E, TZ = E < 0 ? NB - 1 : E + P;
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
+                for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    double bv[NB];
+                    for (int k = 0; k < 3; ++k) {
+                        double bv[NB];
 #pragma unroll
-                    for (int t = 0; t < NB; ++t) bv[t] = sB[(c * 3 + k) * BK + t * NCB + col];
-                    // B00 -> d/deta_3 (D3), B10 -> d/deta_2 (V3), B01 -> d/deta_1 (V3)
-                    const int a = 2 - k;
-                    const int o = k == 0 ? OD : 0;
+                        for (int t = TA; t <= TZ; ++t) bv[t] = sB[(c * 3 + k) * BK + t * NCB + col];
+                        // B00 -> d/deta_3 (D3), B10 -> d/deta_2 (V3), B01 -> d/deta_1 (V3)
+                        const int a = 2 - k;
+                        const int o = k == 0 ? OD : 0;
 #pragma unroll
-                    for (int j = 0; j < QPG; ++j) {
-                        double g = 0.0;
-                        if (has(j)) {
+                        for (int j = 0; j < QPG; ++j) {
+                            double g = 0.0;
+                            if (has(j)) {
 #pragma unroll
-                            for (int t = 0; t < NB; ++t) g += T3[o + (q3a + j) * NB + t] * bv[t];
+                                for (int t = TA; t <= TZ; ++t) g += T3[o + (q3a + j) * NB + t] * bv[t];
+                            }
+                            F[c][a][j] = g;
                         }
-                        F[c][a][j] = g;
                     }
-                }
+            };
+            if constexpr (S::WAVE_ELEM) {
+                if (w == 0) grads(std::integral_constant<int, 0>{});
+                else grads(std::integral_constant<int, 1>{});
+            } else {
+                grads(std::integral_constant<int, -1>{});
+            }
             const int q1 = col % QB, q2 = col / QB;
             const double w12 = T1[OW + q1] * T2[OW + q2];
             const double e1 = T1[OE + q1], e2 = T2[OE + q2];
@@ -1114,13 +1135,17 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
             return v;
         };
         __syncthreads();  // every wavefront has read B
+        // (with one element per wavefront, wavefront r touches only basis
+        // functions r..r+P: the first writes zeros beyond P, the others add
+        // their range)
         if (w == 0 && act) {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
-                    for (int t = 0; t < NB; ++t) sB[(c * 3 + a) * BK + t * NCB + col] = partial(c, a, t);
+                    for (int t = 0; t < NB; ++t)
+                        sB[(c * 3 + a) * BK + t * NCB + col] = (!S::WAVE_ELEM || t <= P) ? partial(c, a, t) : 0.0;
         }
         __syncthreads();
 #pragma unroll 1
@@ -1131,7 +1156,9 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
 #pragma unroll
                     for (int a = 0; a < 3; ++a)
 #pragma unroll
-                        for (int t = 0; t < NB; ++t) sB[(c * 3 + a) * BK + t * NCB + col] += partial(c, a, t);
+                        for (int t = 0; t < NB; ++t)
+                            if (!S::WAVE_ELEM || (t >= r && t <= r + P))
+                                sB[(c * 3 + a) * BK + t * NCB + col] += partial(c, a, t);
             }
             __syncthreads();
         }
@@ -1157,7 +1184,7 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
         for (int t = 0; t < NB; ++t) {
             double a = 0.0, b = 0.0;
 #pragma unroll
-            for (int q = 0; q < QB; ++q) {
+            for (int q = S::qlo(t); q < S::qhi(t); ++q) {
                 a += T2[q * NB + t] * p1[q];
                 b += T2[OD + q * NB + t] * p2[q] + T2[q * NB + t] * p3[q];
             }
@@ -1197,7 +1224,7 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
         for (int t = 0; t < NB; ++t) {
             double v = 0.0;
 #pragma unroll
-            for (int q = 0; q < QB; ++q) v += T1[OD + q * NB + t] * sd[q] + T1[q * NB + t] * sv[q];
+            for (int q = S::qlo(t); q < S::qhi(t); ++q) v += T1[OD + q * NB + t] * sd[q] + T1[q * NB + t] * sv[q];
             yb[(row * NB + t) * nbr] = v;
         }
     }
