@@ -93,21 +93,23 @@ def mf_flops(prob):
     """Algorithmic FP64 flops of one matrix-free stiffness application
     (sum-factorised quadrature, Section 3 bilinear form): per element brick
     of BE^3 elements with NB = BE + p basis functions and QB = BE (p + 1)
-    Gauss points per direction, the forward gradient contractions
-    (2, 3, 3 products of length NB per output in directions 1, 2, 3), the
-    same number of transposed ones, and 238 flops per Gauss point for the
-    Jacobian of the trilinear map, its inverse, the stress and the flux."""
+    Gauss points per direction, six univariate passes each way -- a
+    multiply-add per Gauss point and supported basis function (p + 1 of
+    them): 2 products along direction 1 on 3 NB^2 lines, 3 along direction 2
+    on 3 NB QB lines, 3 along direction 3 on 3 QB^2 lines, forward and
+    transposed -- plus 238 flops per Gauss point for the Jacobian of the
+    trilinear map, its inverse, the stress and the flux."""
     if isinstance(prob, list):
         return sum(mf_flops(q) for q in prob)
     total = 0
     for pd in prob["patches"]:
         p = pd["p"]
-        BE = 2 if p <= 3 else 1
+        BE = 2 if p <= 4 else 1
         NB, QB = BE + p, BE * (p + 1)
         nb = 1
         for e in pd["n_el"]:
             nb *= -(-e // BE)
-        fma = 3 * (2 * NB * NB * QB * NB + 3 * NB * QB * QB * NB + 3 * QB * QB * QB * NB)
+        fma = 3 * QB * (p + 1) * (2 * NB * NB + 3 * NB * QB + 3 * QB * QB)
         total += nb * (2 * 2 * fma + 238 * QB ** 3)
     return total
 

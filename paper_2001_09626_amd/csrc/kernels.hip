@@ -935,7 +935,7 @@ __global__ void __launch_bounds__(kBlock) k_stiffness(const DevPatch* __restrict
 // it in a fixed order (deterministic, no atomics).
 template <int P>
 struct MfShape {
-    static constexpr int BE = P <= 3 ? 2 : 1;               // elements per brick direction
+    static constexpr int BE = P <= 4 ? 2 : 1;               // elements per brick direction
     static constexpr int NB = BE + P;                       // basis functions per brick direction
     static constexpr int QB = BE * (P + 1);                 // Gauss points per brick direction
     static constexpr int NCOL = QB * QB;                    // Gauss columns (q1, q2)
@@ -1904,7 +1904,7 @@ void launch_mf_gather(int p, const DevPatch* dp, const int4* rb, int nrb, const 
     }
 }
 
-int mf_brick_elems(int p) { return p <= 3 ? 2 : 1; }
+int mf_brick_elems(int p) { return p <= 4 ? 2 : 1; }
 
 int mf_table_doubles(int p) {
     const int be = mf_brick_elems(p), nb = be + p, qb = be * (p + 1);
