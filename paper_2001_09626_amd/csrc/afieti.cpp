@@ -745,8 +745,7 @@ void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipS
     } else {
         op_ahat(h, h->tv, h->tt, 1, s);  // B reads the Gamma part
         if (nr) {
-            launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, h->tt, h->c2, s);
-            launch_W(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->c2, out, s);
+            launch_BW(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->d_cplus, h->d_cminus, h->tt, out, s);
         } else {
             launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, h->tt, out, s);
         }
@@ -763,9 +762,26 @@ void op_ps(afieti_handle* h, const double* y, double* out, hipStream_t s, int ln
 // starts nodes in the order they were captured)
 void op_prec(afieti_handle* h, const double* r, double* z, hipStream_t s) {
     const Branch b = fork(h, s);
-    op_pchi(h, r + h->n_dof, h->c3, b.s, b.ln);
+    const bool nr = h->opt.ps_variant == AFIETI_PS_NR;
+    if (nr) {  // P_chi r_chi folded into the first (B B^T)^{-1} of P_S: c1 = W P_chi r_chi
+        const Lane& L = h->lane[b.ln];
+        launch_gamma_partial(h->d_patches, h->d_gam_chunks, h->n_gam_chunks, h->d_ctrl, h->d_gam, h->d_btptr,
+                             h->d_btrow, h->d_btsgn, r + h->n_dof, L.part, b.s);
+        launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_gam_cptr, L.part,
+                               h->d_cinv, L.zc, h->max_nc, b.s);
+    } else {
+        op_pchi(h, r + h->n_dof, h->c3, b.s, b.ln);
+    }
     op_pu(h, r, h->s1, s);
-    op_ps_stage(h, 1, h->c3, h->c4, b.s, b.ln);
+    if (nr) {
+        const Lane& L = h->lane[b.ln];
+        launch_GW(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, L.zc,
+                  r + h->n_dof, h->c1, b.s);
+        launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, h->c1, h->tv, b.s);
+        op_ahat(h, h->tv, h->tt, 0, b.s);
+    } else {
+        op_ps_stage(h, 1, h->c3, h->c4, b.s, b.ln);
+    }
     op_fd(h, h->fd_pa, h->s1, h->s2, s);
     op_ps_stage(h, 2, h->c3, h->c4, b.s, b.ln);
     op_pu(h, h->s2, z, s);

@@ -79,6 +79,13 @@ void launch_W(const int* blk_start, const int* blk_size, const int* blk_dir, int
 // (patch, component, i3); max_n12: largest n1 n2 of those patches (LDS size).
 void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, const double* kb,
                  const double* mb, const double* x, double* y, int use_h, const MinresState* mask, hipStream_t s);
+// z = (B B^T)^{-1} (B x), and z = (B B^T)^{-1} (y - G zc), with the B and the
+// G rows computed inside the block solve
+void launch_BW(const int* blk_start, const int* blk_size, const int* blk_dir, int64_t n_c, const int64_t* plus,
+               const int64_t* minus, const double* x, double* z, hipStream_t s);
+void launch_GW(const int* blk_start, const int* blk_size, const int* blk_dir, int64_t n_c, const int* patch_plus,
+               const int* patch_minus, const double* g_plus, const double* g_minus, const double* zc,
+               const double* y, double* z, hipStream_t s);
 // partial sums of R^T x over patch DOF chunks (nm values per chunk)
 void launch_rigid_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks,
                           const double* ctrl, const double* x, double* partials, hipStream_t s);

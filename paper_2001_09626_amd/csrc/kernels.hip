@@ -1425,6 +1425,47 @@ __global__ void k_W(const int* __restrict__ bs, const int* __restrict__ bn, cons
     z[r] = y[r] - sum / (sz + 1);
 }
 
+// The same block solve applied to values computed row by row on the fly:
+// z = (B B^T)^{-1} (B x) (k_BW) and z = (B B^T)^{-1} (y - G zc) (k_GW); the
+// arithmetic of every row value equals k_B / k_G_apply.
+template <typename RowValue>
+__device__ inline void w_rows(const int* __restrict__ bs, const int* __restrict__ bn, const int* __restrict__ bd,
+                              int64_t n_c, double* __restrict__ z, RowValue val) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_c) return;
+    if (bd[r]) {
+        z[r] = val(r);
+        return;
+    }
+    const int s0 = bs[r], sz = bn[r];
+    double sum = 0.0;
+    for (int j = 0; j < sz; ++j) sum += val(s0 + j);
+    z[r] = val(r) - sum / (sz + 1);
+}
+
+__global__ void k_BW(const int* __restrict__ bs, const int* __restrict__ bn, const int* __restrict__ bd, int64_t n_c,
+                     const int64_t* __restrict__ plus, const int64_t* __restrict__ minus, const double* __restrict__ x,
+                     double* __restrict__ z) {
+    w_rows(bs, bn, bd, n_c, z, [&](int64_t q) {
+        const int64_t m = minus[q];
+        return 1.0 * (x[plus[q]] - (m >= 0 ? x[m] : 0.0));
+    });
+}
+
+__global__ void k_GW(const int* __restrict__ bs, const int* __restrict__ bn, const int* __restrict__ bd, int64_t n_c,
+                     const int* __restrict__ pp, const int* __restrict__ pm, const double* __restrict__ gp,
+                     const double* __restrict__ gm, const double* __restrict__ zc, const double* __restrict__ y,
+                     double* __restrict__ z) {
+    w_rows(bs, bn, bd, n_c, z, [&](int64_t q) {
+        const int a = pp[q], b = pm[q];
+        double s = 0.0;
+        for (int m = 0; m < 6; ++m) s += gp[q * 6 + m] * zc[a * 6 + m];
+        if (b >= 0)
+            for (int m = 0; m < 6; ++m) s -= gm[q * 6 + m] * zc[b * 6 + m];
+        return 1.0 * y[q] + -1.0 * s;
+    });
+}
+
 // partial sums of R^T x over chunks of one patch's DOFs
 __global__ void __launch_bounds__(kBlock) k_rigid_partial(const DevPatch* __restrict__ dps, const Chunk* __restrict__ ch,
                                                           const double* __restrict__ ctrl, const double* __restrict__ x,
@@ -1923,6 +1964,17 @@ void launch_Bt(const int64_t* bt_ptr, const int* bt_row, const double* bt_sign, 
 
 void launch_W(const int* bs, const int* bn, const int* bd, int64_t n_c, const double* y, double* z, hipStream_t s) {
     if (n_c) hipLaunchKernelGGL(k_W, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, bs, bn, bd, n_c, y, z);
+}
+
+void launch_BW(const int* bs, const int* bn, const int* bd, int64_t n_c, const int64_t* plus, const int64_t* minus,
+               const double* x, double* z, hipStream_t s) {
+    if (n_c) hipLaunchKernelGGL(k_BW, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, bs, bn, bd, n_c, plus, minus, x, z);
+}
+
+void launch_GW(const int* bs, const int* bn, const int* bd, int64_t n_c, const int* pp, const int* pm,
+               const double* gp, const double* gm, const double* zc, const double* y, double* z, hipStream_t s) {
+    if (n_c)
+        hipLaunchKernelGGL(k_GW, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, bs, bn, bd, n_c, pp, pm, gp, gm, zc, y, z);
 }
 
 void launch_rigid_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks, const double* ctrl, const double* x,
