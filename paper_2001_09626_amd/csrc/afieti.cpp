@@ -687,10 +687,12 @@ void op_mask_interior(afieti_handle* h, double* y, hipStream_t s) {
     for (const auto& rc : h->classes) launch_mask_interior(h->d_patches, rc.d_rb, rc.n, y, s);
 }
 
-void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_t s) {
+// y = A-hat x (H^{d-2} A-hat x with use_h); bnd_in: x is zero away from the
+// patch boundaries (B^T of a multiplier vector, or a masked vector)
+void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_t s, bool bnd_in = false) {
     for (const auto& ac : h->ahat)
         launch_ahat(ac.p, h->d_patches, ac.d_slabs, ac.n_slabs, ac.max_n12, h->d_kband, h->d_mband, x, y, use_h,
-                    h->mask, s);
+                    bnd_in ? 1 : 0, h->mask, s);
 }
 
 void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s, int ln = 0) {
@@ -739,7 +741,7 @@ void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipS
             a = h->c1;
         }
         launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, a, h->tv, s);
-        op_ahat(h, h->tv, h->tt, 0, s);
+        op_ahat(h, h->tv, h->tt, 0, s, true);
     } else if (stage == 2) {
         op_fd(h, h->fd_int, h->tt, h->tv, s, ln);
     } else {
@@ -778,7 +780,7 @@ void op_prec(afieti_handle* h, const double* r, double* z, hipStream_t s) {
         launch_GW(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, L.zc,
                   r + h->n_dof, h->c1, b.s);
         launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, h->c1, h->tv, b.s);
-        op_ahat(h, h->tv, h->tt, 0, b.s);
+        op_ahat(h, h->tv, h->tt, 0, b.s, true);
     } else {
         op_ps_stage(h, 1, h->c3, h->c4, b.s, b.ln);
     }
@@ -818,7 +820,7 @@ void op_mass(afieti_handle* h, const double* x, double* y, hipStream_t s) {
 void op_shat(afieti_handle* h, const double* x, double* y, hipStream_t s) {
     launch_copy(x, h->tv, h->n_dof, s);
     op_mask_interior(h, h->tv, s);
-    op_ahat(h, h->tv, h->tt, 0, s);
+    op_ahat(h, h->tv, h->tt, 0, s, true);
     op_fd(h, h->fd_int, h->tt, h->tv, s);
     op_ahat(h, h->tv, y, 1, s);
     op_mask_interior(h, y, s);

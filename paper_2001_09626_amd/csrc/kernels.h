@@ -76,9 +76,11 @@ void launch_W(const int* blk_start, const int* blk_size, const int* blk_dir, int
               const double* y, double* z, hipStream_t s);
 // y = scale_k * A-hat x per patch and component for the patches of degree p
 // (banded Kronecker form, sum-factorised, one workgroup per slab).  slabs:
-// (patch, component, i3); max_n12: largest n1 n2 of those patches (LDS size).
+// (patch, component, i3); max_n12: largest n1 n2 of those patches (LDS size);
+// bnd_in != 0 promises that x is zero away from the patch boundary.
 void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, const double* kb,
-                 const double* mb, const double* x, double* y, int use_h, const MinresState* mask, hipStream_t s);
+                 const double* mb, const double* x, double* y, int use_h, int bnd_in, const MinresState* mask,
+                 hipStream_t s);
 // z = (B B^T)^{-1} (B x), and z = (B B^T)^{-1} (y - G zc), with the B and the
 // G rows computed inside the block solve
 void launch_BW(const int* blk_start, const int* blk_size, const int* blk_dir, int64_t n_c, const int64_t* plus,

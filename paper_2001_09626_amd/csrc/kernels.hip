@@ -1310,7 +1310,7 @@ template <int P>
 __global__ void __launch_bounds__(kBlock) k_ahat(const DevPatch* __restrict__ dps, const int4* __restrict__ slabs,
                                                  const double* __restrict__ kb, const double* __restrict__ mb,
                                                  const double* __restrict__ x, double* __restrict__ y, int max_n12,
-                                                 int use_h, const MinresState* __restrict__ mask) {
+                                                 int use_h, int bnd_in, const MinresState* __restrict__ mask) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int4 it = slabs[blockIdx.x];
     const DevPatch& pa = dps[it.x];
@@ -1326,14 +1326,20 @@ __global__ void __launch_bounds__(kBlock) k_ahat(const DevPatch* __restrict__ dp
     // direction 3
     const double* K3 = kb + pa.band_off[2] + i3 * W;
     const double* M3 = mb + pa.band_off[2] + i3 * W;
+    // bnd_in: x vanishes away from the patch boundary, so on slabs more than
+    // p layers from the i3 faces only the outer ring of the slab can be nonzero
+    const bool ring_only = bnd_in && i3 > p && i3 < n3 - 1 - p;
     for (int e = threadIdx.x; e < n12; e += kBlock) {
+        const int i2 = e / n1, i1 = e - i2 * n1;
         double u = 0.0, v = 0.0;
+        if (!ring_only || i1 == 0 || i1 == n1 - 1 || i2 == 0 || i2 == n2 - 1) {
 #pragma unroll
-        for (int o = -p; o <= p; ++o) {
-            const int j3 = i3 + o;
-            const double xx = (unsigned)j3 < (unsigned)n3 ? x[base + (int64_t)j3 * n12 + e] : 0.0;
-            u += M3[o + p] * xx;
-            v += K3[o + p] * xx;
+            for (int o = -p; o <= p; ++o) {
+                const int j3 = i3 + o;
+                const double xx = (unsigned)j3 < (unsigned)n3 ? x[base + (int64_t)j3 * n12 + e] : 0.0;
+                u += M3[o + p] * xx;
+                v += K3[o + p] * xx;
+            }
         }
         U[e] = u;
         V[e] = v;
@@ -1384,12 +1390,13 @@ __global__ void __launch_bounds__(kBlock) k_ahat(const DevPatch* __restrict__ dp
 
 template <int P>
 void ahat_t(const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, const double* kb, const double* mb,
-            const double* x, double* y, int use_h, const MinresState* mask, hipStream_t s) {
+            const double* x, double* y, int use_h, int bnd_in, const MinresState* mask, hipStream_t s) {
     if (!n_slabs) return;
     const size_t lds = 4 * (size_t)max_n12 * sizeof(double);  // <= 4 * 48^2 * 8 = 73,728 bytes
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_ahat<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_ahat<P>, dim3(n_slabs), dim3(kBlock), lds, s, dp, slabs, kb, mb, x, y, max_n12, use_h, mask);
+    hipLaunchKernelGGL(k_ahat<P>, dim3(n_slabs), dim3(kBlock), lds, s, dp, slabs, kb, mb, x, y, max_n12, use_h, bnd_in,
+                       mask);
 }
 
 __global__ void k_B(const int64_t* __restrict__ plus, const int64_t* __restrict__ minus, int64_t n_c, double alpha,
@@ -1902,15 +1909,16 @@ void launch_stiffness_dp(int dim, int p, const DevPatch* dp, const int4* rb, int
 }
 
 void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, const double* kb,
-                 const double* mb, const double* x, double* y, int use_h, const MinresState* mask, hipStream_t s) {
+                 const double* mb, const double* x, double* y, int use_h, int bnd_in, const MinresState* mask,
+                 hipStream_t s) {
     switch (p) {
-        case 1: ahat_t<1>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
-        case 2: ahat_t<2>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
-        case 3: ahat_t<3>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
-        case 4: ahat_t<4>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
-        case 5: ahat_t<5>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
-        case 6: ahat_t<6>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
-        default: ahat_t<0>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, mask, s); break;
+        case 1: ahat_t<1>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
+        case 2: ahat_t<2>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
+        case 3: ahat_t<3>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
+        case 4: ahat_t<4>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
+        case 5: ahat_t<5>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
+        case 6: ahat_t<6>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
+        default: ahat_t<0>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
     }
 }
 
