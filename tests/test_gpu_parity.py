@@ -205,3 +205,25 @@ def test_solve_with_rhs(pair):
     print(f"  rhs: iterations {st['iterations']} / {ref['iters']}; diff {diff:.2e} own {own:.2e}")
     assert same_iterations(st["iterations"], ref, 1e-8)
     assert diff <= 0.25 * own
+
+
+@pytest.mark.parametrize("case", ["c1_small", "c2_small"])
+def test_plain_ps_variant_matches_oracle(case):
+    """The plain inexact P_S (no (B B^T)^{-1} scaling) as a switch: P_S and the
+    preconditioner against the oracle's "plain" variant, and the solve."""
+    torch = _torch()
+    from paper_2001_09626_amd import Solver
+    prob = CASES[case]()
+    o = AFIETI(prob)
+    s = Solver(prob, tol=1e-8, ps_variant="plain")
+    y = W.random_vector(o.n_c, 31)
+    _close(_host(s.apply("P_S", _dev(torch, y))), o.apply_PS(y, "plain"), 1e-11)
+    r = W.random_vector(o.n_dof + o.n_c, 32)
+    _close(_host(s.apply("prec", _dev(torch, r))), o.apply_prec(r, "plain"), 1e-11)
+    ref = o.solve(variant="plain")
+    u, lam, st = s.solve()
+    diff = np.linalg.norm(_host(u) - ref["u"]) / np.linalg.norm(ref["u"])
+    print(f"  plain P_S: {st['iterations']} it (oracle {ref['iters']}), rel diff u {diff:.2e}", flush=True)
+    assert st["converged"] and same_iterations(st["iterations"], ref, 1e-8)
+    assert diff <= 1e-8
+    s.close()
