@@ -90,7 +90,7 @@ struct afieti_handle {
     std::vector<int> fd_uoff, fd_doff;
     std::vector<RowClass> classes;
     struct AhatClass {             // patches of one degree
-        int p = 0, max_n12 = 0;
+        int p = 0, max_n12 = 0, max_n1n2 = 0;
         int4* d_slabs = nullptr;   // (patch, component, i3)
         int n_slabs = 0;
     };
@@ -179,6 +179,20 @@ int fail_with(afieti_handle* h, const SetupError& e) {
 }
 
 thread_local std::string g_setup_err;
+
+// launch order of a work list: workgroups are handed to the 8 XCDs in turn,
+// so workgroup w gets item (w % 8) * ceil(n / 8) + w / 8 and each XCD sweeps
+// a contiguous run of the list
+void xcd_order(std::vector<int4>& items) {
+    const int n = (int)items.size(), per = (n + 7) / 8;
+    std::vector<int4> order;
+    order.reserve(n);
+    for (int w = 0; w < 8 * per; ++w) {
+        const int g = (w % 8) * per + w / 8;
+        if (g < n) order.push_back(items[g]);
+    }
+    items.swap(order);
+}
 
 // chunk table over [begin, end) ranges of segments
 void add_chunks(std::vector<Chunk>& out, int64_t b, int64_t e, int seg, int size = kChunk) {
@@ -390,11 +404,12 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     {
         // A-hat classes by degree (the kernels are specialised on p)
         std::map<int, std::vector<int4>> byp;
-        std::map<int, int> n12;
+        std::map<int, int> n12, n1n2;
         for (int k = 0; k < np; ++k) {
             const PatchPlan& P = pl.patches[k];
             auto& e = byp[P.p];
             n12[P.p] = std::max(n12[P.p], P.n[0] * P.n[1]);
+            n1n2[P.p] = std::max(n1n2[P.p], P.n[0] + P.n[1]);
             for (int c = 0; c < P.dim; ++c)
                 for (int i3 = 0; i3 < P.n[2]; ++i3) e.push_back(make_int4(k, c, i3, 0));
         }
@@ -402,6 +417,8 @@ void device_setup(afieti_handle* h, hipStream_t s) {
             afieti_handle::AhatClass ac;
             ac.p = kv.first;
             ac.max_n12 = n12[kv.first];
+            ac.max_n1n2 = n1n2[kv.first];
+            xcd_order(kv.second);  // neighbouring slabs share 2p of their 2p + 1 input slabs
             ac.n_slabs = (int)kv.second.size();
             ac.d_slabs = h->upload(kv.second, s);
             h->ahat.push_back(ac);
@@ -454,20 +471,9 @@ void device_setup(afieti_handle* h, hipStream_t s) {
                         for (int b1 = 0; b1 < d.nb[0]; ++b1) bricks.push_back(make_int4(k, b1, b2, b3));
                 ybuf += (int64_t)d.nb[0] * d.nb[1] * d.nb[2] * 3 * nbd * nbd * nbd;
             }
-            // launch order: workgroups are handed to the 8 XCDs in turn, so
-            // workgroup w gets brick (w % 8) * ceil(n / 8) + w / 8 -- each XCD
-            // then sweeps a contiguous run of bricks, and the neighbouring
-            // bricks that share nodes and brick-buffer lines meet in its L2
-            {
-                const int n = (int)bricks.size(), per = (n + 7) / 8;
-                std::vector<int4> order;
-                order.reserve(n);
-                for (int w = 0; w < 8 * per; ++w) {
-                    const int g = (w % 8) * per + w / 8;
-                    if (g < n) order.push_back(bricks[g]);
-                }
-                bricks.swap(order);
-            }
+            // the neighbouring bricks that share nodes and brick-buffer
+            // lines meet in one XCD's L2
+            xcd_order(bricks);
             rc.n_bricks = (int)bricks.size();
             rc.d_bricks = h->upload(bricks, s);
         }
@@ -688,11 +694,13 @@ void op_mask_interior(afieti_handle* h, double* y, hipStream_t s) {
 }
 
 // y = A-hat x (H^{d-2} A-hat x with use_h); bnd_in: x is zero away from the
-// patch boundaries (B^T of a multiplier vector, or a masked vector)
-void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_t s, bool bnd_in = false) {
+// patch boundaries (B^T of a multiplier vector, or a masked vector);
+// bnd_out: only the patch-boundary entries of y are written
+void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_t s, bool bnd_in = false,
+             bool bnd_out = false) {
     for (const auto& ac : h->ahat)
-        launch_ahat(ac.p, h->d_patches, ac.d_slabs, ac.n_slabs, ac.max_n12, h->d_kband, h->d_mband, x, y, use_h,
-                    bnd_in ? 1 : 0, h->mask, s);
+        launch_ahat(ac.p, h->d_patches, ac.d_slabs, ac.n_slabs, ac.max_n12, ac.max_n1n2, h->d_kband, h->d_mband, x, y, use_h,
+                    bnd_in ? 1 : 0, bnd_out ? 1 : 0, h->mask, s);
 }
 
 void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s, int ln = 0) {
@@ -745,7 +753,7 @@ void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipS
     } else if (stage == 2) {
         op_fd(h, h->fd_int, h->tt, h->tv, s, ln);
     } else {
-        op_ahat(h, h->tv, h->tt, 1, s);  // B reads the Gamma part
+        op_ahat(h, h->tv, h->tt, 1, s, false, true);  // B reads only the Gamma part
         if (nr) {
             launch_BW(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->d_cplus, h->d_cminus, h->tt, out, s);
         } else {
@@ -822,7 +830,7 @@ void op_shat(afieti_handle* h, const double* x, double* y, hipStream_t s) {
     op_mask_interior(h, h->tv, s);
     op_ahat(h, h->tv, h->tt, 0, s, true);
     op_fd(h, h->fd_int, h->tt, h->tv, s);
-    op_ahat(h, h->tv, y, 1, s);
+    op_ahat(h, h->tv, y, 1, s, false, true);  // the interior of y is zeroed next
     op_mask_interior(h, y, s);
 }
 

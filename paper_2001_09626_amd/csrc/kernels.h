@@ -77,10 +77,13 @@ void launch_W(const int* blk_start, const int* blk_size, const int* blk_dir, int
 // y = scale_k * A-hat x per patch and component for the patches of degree p
 // (banded Kronecker form, sum-factorised, one workgroup per slab).  slabs:
 // (patch, component, i3); max_n12: largest n1 n2 of those patches (LDS size);
-// bnd_in != 0 promises that x is zero away from the patch boundary.
-void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, const double* kb,
-                 const double* mb, const double* x, double* y, int use_h, int bnd_in, const MinresState* mask,
-                 hipStream_t s);
+// bnd_in != 0 promises that x is zero away from the patch boundary;
+// bnd_out != 0 asks only for the patch-boundary entries of y (the others are
+// left as they were).
+void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, int max_n1n2,
+                 const double* kb,
+                 const double* mb, const double* x, double* y, int use_h, int bnd_in, int bnd_out,
+                 const MinresState* mask, hipStream_t s);
 // z = (B B^T)^{-1} (B x), and z = (B B^T)^{-1} (y - G zc), with the B and the
 // G rows computed inside the block solve
 void launch_BW(const int* blk_start, const int* blk_size, const int* blk_dir, int64_t n_c, const int64_t* plus,

@@ -61,17 +61,17 @@ __device__ inline void block_sum(double (&v)[NV], double* lds /* NV * 4 */) {
 
 // dst[e] = load(e) for e < n (n <= IT kBlock): every global load of a thread
 // is issued before its LDS stores, so their latencies overlap
-template <int IT, typename T, typename F>
+template <int IT, int BS = kBlock, typename T, typename F>
 __device__ inline void batched_copy(T* dst, int n, F load) {
     T v[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        const int e = threadIdx.x + it * kBlock;
+        const int e = threadIdx.x + it * BS;
         v[it] = e < n ? load(e) : (T)0;
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        const int e = threadIdx.x + it * kBlock;
+        const int e = threadIdx.x + it * BS;
         if (e < n) dst[e] = v[it];
     }
 }
@@ -1306,11 +1306,20 @@ void mf_gather_t(const DevPatch* dp, const int4* rb, int nrb, const double* ybuf
 // (four slab arrays).  Univariate K, M are banded (half-bandwidth p) and
 // stored as [i][t], t = j - i + p.
 // P > 0: degree known at compile time (loops unrolled); P == 0: any degree.
+constexpr int kAhBlock = 512;  // threads of the A-hat slab kernel
+constexpr int kAhE = 3;        // slab entries per thread whose loads are in flight together
+
+// One workgroup per slab (patch, component l, i3): y = A-hat x on that slab
+// (H^{d-2} A-hat x with use_h).  Direction 3 is taken from global memory
+// (2p + 1 slabs of x), directions 1 and 2 from LDS; the band rows of
+// directions 1 and 2 are staged in LDS first.  LDS: U, V (direction-3
+// products), then A, Bm overwrite them, then the band rows.
 template <int P>
-__global__ void __launch_bounds__(kBlock) k_ahat(const DevPatch* __restrict__ dps, const int4* __restrict__ slabs,
-                                                 const double* __restrict__ kb, const double* __restrict__ mb,
-                                                 const double* __restrict__ x, double* __restrict__ y, int max_n12,
-                                                 int use_h, int bnd_in, const MinresState* __restrict__ mask) {
+__global__ void __launch_bounds__(kAhBlock) k_ahat(const DevPatch* __restrict__ dps, const int4* __restrict__ slabs,
+                                                   const double* __restrict__ kb, const double* __restrict__ mb,
+                                                   const double* __restrict__ x, double* __restrict__ y, int max_n12,
+                                                   int use_h, int bnd_in, int bnd_out,
+                                                   const MinresState* __restrict__ mask) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int4 it = slabs[blockIdx.x];
     const DevPatch& pa = dps[it.x];
@@ -1320,39 +1329,107 @@ __global__ void __launch_bounds__(kBlock) k_ahat(const DevPatch* __restrict__ dp
     const int p = P > 0 ? P : pa.p, W = 2 * p + 1;
     double* U = reinterpret_cast<double*>(smem);
     double* V = U + max_n12;
-    double* A = V + max_n12;
-    double* Bm = A + max_n12;
+    const int nb1 = n1 * W, nb2 = n2 * W;
+    // band rows of directions 1 and 2: staged in LDS for the specialised
+    // degrees, read from global memory by the generic kernel
+    const double* K1 = kb + pa.band_off[0];
+    const double* Mb1 = mb + pa.band_off[0];
+    const double* K2 = kb + pa.band_off[1];
+    const double* Mb2 = mb + pa.band_off[1];
+    if constexpr (P > 0) {
+        double* T = V + max_n12;  // K1 | M1 (n1 x W), K2 | M2 (n2 x W)
+        batched_copy<(4 * kMaxN * (2 * P + 1) + kAhBlock - 1) / kAhBlock, kAhBlock>(
+            T, 2 * (nb1 + nb2), [&](int e) {
+                if (e < nb1) return K1[e];
+                e -= nb1;
+                if (e < nb1) return Mb1[e];
+                e -= nb1;
+                if (e < nb2) return K2[e];
+                return Mb2[e - nb2];
+            });
+        K1 = T;
+        Mb1 = T + nb1;
+        K2 = T + 2 * nb1;
+        Mb2 = K2 + nb2;
+    }
     const int64_t base = pa.dof_off + (int64_t)l * pa.nodes;
-    // direction 3
+    // bnd_in: x vanishes away from the patch boundary, so on slabs more than
+    // p layers from the i3 faces only the outer ring of the slab can be nonzero.
+    // bnd_out: only the patch-boundary entries of y are wanted, so on the
+    // slabs between the i3 faces direction 2 is needed on the outer ring
+    // only, direction 1 on the bands of p + 1 rows and the two edge columns it
+    // reads, direction 3 on the frame of width p + 1 those read.
+    const bool ring_only = bnd_in && i3 > p && i3 < n3 - 1 - p;
+    const bool thin = bnd_out && i3 > 0 && i3 < n3 - 1;
+    // direction 3: the band row of i3 is uniform over the workgroup
     const double* K3 = kb + pa.band_off[2] + i3 * W;
     const double* M3 = mb + pa.band_off[2] + i3 * W;
-    // bnd_in: x vanishes away from the patch boundary, so on slabs more than
-    // p layers from the i3 faces only the outer ring of the slab can be nonzero
-    const bool ring_only = bnd_in && i3 > p && i3 < n3 - 1 - p;
-    for (int e = threadIdx.x; e < n12; e += kBlock) {
-        const int i2 = e / n1, i1 = e - i2 * n1;
-        double u = 0.0, v = 0.0;
-        if (!ring_only || i1 == 0 || i1 == n1 - 1 || i2 == 0 || i2 == n2 - 1) {
+    for (int e0 = threadIdx.x; e0 < n12; e0 += kAhBlock * kAhE) {
+        bool need[kAhE], load[kAhE];
 #pragma unroll
-            for (int o = -p; o <= p; ++o) {
-                const int j3 = i3 + o;
-                const double xx = (unsigned)j3 < (unsigned)n3 ? x[base + (int64_t)j3 * n12 + e] : 0.0;
-                u += M3[o + p] * xx;
-                v += K3[o + p] * xx;
+        for (int u = 0; u < kAhE; ++u) {
+            const int e = e0 + u * kAhBlock;
+            const int i2 = e / n1, i1 = e - i2 * n1;
+            need[u] = e < n12 && (!thin || i2 <= p || i2 >= n2 - 1 - p || i1 <= p || i1 >= n1 - 1 - p);
+            load[u] = need[u] && (!ring_only || i1 == 0 || i1 == n1 - 1 || i2 == 0 || i2 == n2 - 1);
+        }
+        if constexpr (P > 0) {
+            double xv[kAhE][2 * P + 1];
+#pragma unroll
+            for (int u = 0; u < kAhE; ++u)
+#pragma unroll
+                for (int o = 0; o < 2 * P + 1; ++o) {
+                    const int j3 = i3 + o - P;
+                    xv[u][o] = load[u] && (unsigned)j3 < (unsigned)n3
+                                   ? x[base + (int64_t)j3 * n12 + e0 + u * kAhBlock]
+                                   : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < kAhE; ++u) {
+                double uu = 0.0, vv = 0.0;
+#pragma unroll
+                for (int o = 0; o < 2 * P + 1; ++o) {
+                    uu += M3[o] * xv[u][o];
+                    vv += K3[o] * xv[u][o];
+                }
+                if (need[u]) {
+                    U[e0 + u * kAhBlock] = uu;
+                    V[e0 + u * kAhBlock] = vv;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kAhE; ++u) {
+                const int e = e0 + u * kAhBlock;
+                double uu = 0.0, vv = 0.0;
+                if (load[u])
+                    for (int o = -p; o <= p; ++o) {
+                        const int j3 = i3 + o;
+                        const double xx = (unsigned)j3 < (unsigned)n3 ? x[base + (int64_t)j3 * n12 + e] : 0.0;
+                        uu += M3[o + p] * xx;
+                        vv += K3[o + p] * xx;
+                    }
+                if (need[u]) {
+                    U[e] = uu;
+                    V[e] = vv;
+                }
             }
         }
-        U[e] = u;
-        V[e] = v;
     }
     __syncthreads();
-    // direction 1
+    // direction 1 (results held in registers until every thread has read U, V)
     const double k1 = l == 0 ? 2 * pa.mu + pa.lam : pa.mu;
     const double k2 = l == 1 ? 2 * pa.mu + pa.lam : pa.mu;
     const double k3 = l == 2 ? 2 * pa.mu + pa.lam : pa.mu;
-    const double* K1 = kb + pa.band_off[0];
-    const double* Mb1 = mb + pa.band_off[0];
-    for (int e = threadIdx.x; e < n12; e += kBlock) {
+    constexpr int kR = (kMaxN * kMaxN + kAhBlock - 1) / kAhBlock;
+    double ra[kR], rb[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int e = threadIdx.x + r * kAhBlock;
+        ra[r] = rb[r] = 0.0;
+        if (e >= n12) continue;
         const int i2 = e / n1, i1 = e - i2 * n1;
+        if (thin && !(i2 <= p || i2 >= n2 - 1 - p || i1 == 0 || i1 == n1 - 1)) continue;
         double ku = 0.0, mu_ = 0.0, mv = 0.0;
 #pragma unroll
         for (int o = -p; o <= p; ++o) {
@@ -1365,16 +1442,26 @@ __global__ void __launch_bounds__(kBlock) k_ahat(const DevPatch* __restrict__ dp
                 mv += mm * vv;
             }
         }
-        A[e] = k1 * ku + k3 * mv;
-        Bm[e] = mu_;
+        ra[r] = k1 * ku + k3 * mv;
+        rb[r] = mu_;
+    }
+    __syncthreads();
+    double* A = U;
+    double* Bm = V;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int e = threadIdx.x + r * kAhBlock;
+        if (e < n12) {
+            A[e] = ra[r];
+            Bm[e] = rb[r];
+        }
     }
     __syncthreads();
     // direction 2
     const double sc = use_h ? pa.hscale : 1.0;
-    const double* K2 = kb + pa.band_off[1];
-    const double* Mb2 = mb + pa.band_off[1];
-    for (int e = threadIdx.x; e < n12; e += kBlock) {
+    for (int e = threadIdx.x; e < n12; e += kAhBlock) {
         const int i2 = e / n1, i1 = e - i2 * n1;
+        if (thin && !(i2 == 0 || i2 == n2 - 1 || i1 == 0 || i1 == n1 - 1)) continue;
         double a = 0.0, b = 0.0;
 #pragma unroll
         for (int o = -p; o <= p; ++o) {
@@ -1389,14 +1476,17 @@ __global__ void __launch_bounds__(kBlock) k_ahat(const DevPatch* __restrict__ dp
 }
 
 template <int P>
-void ahat_t(const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, const double* kb, const double* mb,
-            const double* x, double* y, int use_h, int bnd_in, const MinresState* mask, hipStream_t s) {
+void ahat_t(const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, int max_n1n2, const double* kb,
+            const double* mb, const double* x, double* y, int use_h, int bnd_in, int bnd_out, const MinresState* mask,
+            hipStream_t s) {
     if (!n_slabs) return;
-    const size_t lds = 4 * (size_t)max_n12 * sizeof(double);  // <= 4 * 48^2 * 8 = 73,728 bytes
+    const size_t W = P > 0 ? 2 * P + 1 : 0;  // the generic kernel stages no band rows
+    // <= (2 * 48^2 + 2 * 13 * 96) * 8 = 56,832 bytes
+    const size_t lds = (2 * (size_t)max_n12 + 2 * W * max_n1n2) * sizeof(double);
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)k_ahat<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_ahat<P>, dim3(n_slabs), dim3(kBlock), lds, s, dp, slabs, kb, mb, x, y, max_n12, use_h, bnd_in,
-                       mask);
+    hipLaunchKernelGGL(k_ahat<P>, dim3(n_slabs), dim3(kAhBlock), lds, s, dp, slabs, kb, mb, x, y, max_n12, use_h,
+                       bnd_in, bnd_out, mask);
 }
 
 __global__ void k_B(const int64_t* __restrict__ plus, const int64_t* __restrict__ minus, int64_t n_c, double alpha,
@@ -1474,21 +1564,46 @@ __global__ void k_GW(const int* __restrict__ bs, const int* __restrict__ bn, con
 }
 
 // partial sums of R^T x over chunks of one patch's DOFs
+// a chunk of patch DOFs as one thread sees it: kChunk / kBlock entries, with
+// every load issued before any use
+struct RigidRows {
+    static_assert(kChunk % kBlock == 0, "whole rounds of a DOF chunk per thread");
+    static constexpr int kIt = kChunk / kBlock;
+    bool ok[kIt];
+    int comp[kIt];
+    double X[kIt][3];
+    __device__ RigidRows(const DevPatch& pa, const Chunk& c, const double* __restrict__ ctrl) {
+        const int nodes = (int)pa.nodes;
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int64_t i = c.begin + threadIdx.x + it * kBlock;
+            ok[it] = i < c.end;
+            const int loc = ok[it] ? (int)(i - pa.dof_off) : 0;
+            comp[it] = loc / nodes;
+            const double* P = ctrl + pa.ctrl_off + (int64_t)(loc - comp[it] * nodes) * 3;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) X[it][a] = ok[it] ? P[a] : 0.0;
+        }
+    }
+};
+
 __global__ void __launch_bounds__(kBlock) k_rigid_partial(const DevPatch* __restrict__ dps, const Chunk* __restrict__ ch,
                                                           const double* __restrict__ ctrl, const double* __restrict__ x,
                                                           double* __restrict__ part) {
     __shared__ double lds[6 * 4];
     const Chunk c = ch[blockIdx.x];
     const DevPatch& pa = dps[c.seg];
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
-        const int64_t loc = i - pa.dof_off;
-        const int comp = (int)(loc / pa.nodes);
-        const int64_t nd = loc - comp * pa.nodes;
-        const double* X = ctrl + pa.ctrl_off + nd * 3;
-        const double v = x[i];
-        for (int m = 0; m < pa.nmodes; ++m) acc[m] += rigid_mode_value(pa.dim, m, comp, X) * v;
+    double v[RigidRows::kIt];
+#pragma unroll
+    for (int it = 0; it < RigidRows::kIt; ++it) {
+        const int64_t i = c.begin + threadIdx.x + it * kBlock;
+        v[it] = i < c.end ? x[i] : 0.0;
     }
+    const RigidRows r(pa, c, ctrl);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int it = 0; it < RigidRows::kIt; ++it)
+        for (int m = 0; m < pa.nmodes; ++m) acc[m] += rigid_mode_value(pa.dim, m, r.comp[it], r.X[it]) * v[it];
     block_sum<6>(acc, lds);
     if (threadIdx.x == 0)
         for (int m = 0; m < 6; ++m) part[(int64_t)blockIdx.x * 6 + m] = acc[m];
@@ -1599,16 +1714,20 @@ __global__ void __launch_bounds__(kBlock) k_rigid_update(const DevPatch* __restr
                                                          const double* __restrict__ x, double* __restrict__ y) {
     const Chunk c = ch[blockIdx.x];
     const DevPatch& pa = dps[c.seg];
+    double v[RigidRows::kIt];
+#pragma unroll
+    for (int it = 0; it < RigidRows::kIt; ++it) {
+        const int64_t i = c.begin + threadIdx.x + it * kBlock;
+        v[it] = i < c.end ? x[i] : 0.0;
+    }
+    const RigidRows r(pa, c, ctrl);
     double cf[6];
     for (int m = 0; m < 6; ++m) cf[m] = coef[c.seg * 6 + m];
-    for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) {
-        const int64_t loc = i - pa.dof_off;
-        const int comp = (int)(loc / pa.nodes);
-        const int64_t nd = loc - comp * pa.nodes;
-        const double* X = ctrl + pa.ctrl_off + nd * 3;
-        double r = 0.0;
-        for (int m = 0; m < pa.nmodes; ++m) r += rigid_mode_value(pa.dim, m, comp, X) * cf[m];
-        y[i] = x[i] - r;
+#pragma unroll
+    for (int it = 0; it < RigidRows::kIt; ++it) {
+        double s = 0.0;
+        for (int m = 0; m < pa.nmodes; ++m) s += rigid_mode_value(pa.dim, m, r.comp[it], r.X[it]) * cf[m];
+        if (r.ok[it]) y[c.begin + threadIdx.x + it * kBlock] = v[it] - s;
     }
 }
 
@@ -1908,17 +2027,17 @@ void launch_stiffness_dp(int dim, int p, const DevPatch* dp, const int4* rb, int
     }
 }
 
-void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, const double* kb,
-                 const double* mb, const double* x, double* y, int use_h, int bnd_in, const MinresState* mask,
-                 hipStream_t s) {
+void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, int max_n1n2, const double* kb,
+                 const double* mb, const double* x, double* y, int use_h, int bnd_in, int bnd_out,
+                 const MinresState* mask, hipStream_t s) {
     switch (p) {
-        case 1: ahat_t<1>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
-        case 2: ahat_t<2>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
-        case 3: ahat_t<3>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
-        case 4: ahat_t<4>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
-        case 5: ahat_t<5>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
-        case 6: ahat_t<6>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
-        default: ahat_t<0>(dp, slabs, n_slabs, max_n12, kb, mb, x, y, use_h, bnd_in, mask, s); break;
+        case 1: ahat_t<1>(dp, slabs, n_slabs, max_n12, max_n1n2, kb, mb, x, y, use_h, bnd_in, bnd_out, mask, s); break;
+        case 2: ahat_t<2>(dp, slabs, n_slabs, max_n12, max_n1n2, kb, mb, x, y, use_h, bnd_in, bnd_out, mask, s); break;
+        case 3: ahat_t<3>(dp, slabs, n_slabs, max_n12, max_n1n2, kb, mb, x, y, use_h, bnd_in, bnd_out, mask, s); break;
+        case 4: ahat_t<4>(dp, slabs, n_slabs, max_n12, max_n1n2, kb, mb, x, y, use_h, bnd_in, bnd_out, mask, s); break;
+        case 5: ahat_t<5>(dp, slabs, n_slabs, max_n12, max_n1n2, kb, mb, x, y, use_h, bnd_in, bnd_out, mask, s); break;
+        case 6: ahat_t<6>(dp, slabs, n_slabs, max_n12, max_n1n2, kb, mb, x, y, use_h, bnd_in, bnd_out, mask, s); break;
+        default: ahat_t<0>(dp, slabs, n_slabs, max_n12, max_n1n2, kb, mb, x, y, use_h, bnd_in, bnd_out, mask, s); break;
     }
 }
 
