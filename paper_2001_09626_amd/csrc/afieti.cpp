@@ -109,7 +109,9 @@ struct afieti_handle {
     int64_t* d_btptr = nullptr;
     int* d_btrow = nullptr;
     double* d_btsgn = nullptr;
-    int64_t* d_gam = nullptr;
+    int* d_mc_row = nullptr;       // multiplier copies touching each patch (patch-major)
+    double* d_mc_val = nullptr;    // their signed rigid-mode values, [mode][copy]
+    int64_t n_mc = 0;
     double* d_rtr = nullptr;
     double* d_cinv = nullptr;
     int *d_pr_p0 = nullptr, *d_pr_np = nullptr, *d_pr_nm = nullptr;
@@ -118,6 +120,7 @@ struct afieti_handle {
     // chunk tables
     Chunk *d_dof_chunks = nullptr, *d_gam_chunks = nullptr, *d_vec_chunks = nullptr;
     int n_dof_chunks = 0, n_gam_chunks = 0, n_vec_chunks = 0;
+    std::vector<int64_t> mc_ptr;   // per patch start in the multiplier-copy list
     int *d_dof_cptr = nullptr, *d_gam_cptr = nullptr, *d_vec_cptr = nullptr;
     // work
     double *d_part = nullptr, *d_part2 = nullptr;
@@ -562,7 +565,33 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     h->d_btptr = h->upload(pl.bt_ptr, s);
     h->d_btrow = h->upload(pl.bt_row, s);
     h->d_btsgn = h->upload(pl.bt_sign, s);
-    h->d_gam = h->upload(pl.gam_dof, s);
+    {
+        // G^T y = sum over multipliers r of y_r (R(plus copy) - R(minus copy)):
+        // the copies of each patch listed with their signed mode values
+        std::vector<std::vector<int64_t>> by(np);
+        for (int64_t r = 0; r < pl.n_c; ++r) {
+            by[pl.c_patch_plus[r]].push_back(r);
+            if (pl.c_patch_minus[r] >= 0) by[pl.c_patch_minus[r]].push_back(~r);
+        }
+        std::vector<int> row;
+        std::vector<int64_t> mptr{0};
+        for (int k = 0; k < np; ++k) {
+            for (int64_t e : by[k]) row.push_back((int)(e >= 0 ? e : ~e));
+            mptr.push_back((int64_t)row.size());
+        }
+        h->n_mc = (int64_t)row.size();
+        std::vector<double> val(6 * std::max<int64_t>(h->n_mc, 1), 0.0);
+        int64_t i = 0;
+        for (int k = 0; k < np; ++k)
+            for (int64_t e : by[k]) {
+                for (int m = 0; m < 6; ++m)
+                    val[m * h->n_mc + i] = e >= 0 ? pl.g_plus[e * 6 + m] : -pl.g_minus[~e * 6 + m];
+                ++i;
+            }
+        h->d_mc_row = h->upload(row.empty() ? std::vector<int>{0} : row, s);
+        h->d_mc_val = h->upload(val, s);
+        h->mc_ptr = mptr;
+    }
     h->d_rtr = h->upload(pl.RtR_inv, s);
     std::vector<double> cinv;
     std::vector<int> p0, npch, nm;
@@ -587,7 +616,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
         const PatchPlan& P = pl.patches[k];
         add_chunks(dch, P.dof_off, P.dof_off + P.dim * P.nodes, k);
         dptr.push_back((int)dch.size());
-        add_chunks(gch, pl.gam_ptr[k], pl.gam_ptr[k + 1], k, kGamChunk);
+        add_chunks(gch, h->mc_ptr[k], h->mc_ptr[k + 1], k, kGamChunk);
         gptr.push_back((int)gch.size());
     }
     for (int j = 0; j < (int)pl.probs.size(); ++j) {
@@ -720,8 +749,7 @@ void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hi
 // out = P_chi y  (in place allowed)
 void op_pchi(afieti_handle* h, const double* y, double* out, hipStream_t s, int ln = 0) {
     const Lane& L = h->lane[ln];
-    launch_gamma_partial(h->d_patches, h->d_gam_chunks, h->n_gam_chunks, h->d_ctrl, h->d_gam, h->d_btptr, h->d_btrow,
-                         h->d_btsgn, y, L.part, s);
+    launch_gamma_partial(h->d_gam_chunks, h->n_gam_chunks, h->d_mc_row, h->d_mc_val, h->n_mc, y, L.part, s);
     launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_gam_cptr, L.part,
                            h->d_cinv, L.zc, h->max_nc, s);
     launch_G_apply(h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, h->n_c, L.zc, -1.0, 1.0, y, out, s);
@@ -775,8 +803,7 @@ void op_prec(afieti_handle* h, const double* r, double* z, hipStream_t s) {
     const bool nr = h->opt.ps_variant == AFIETI_PS_NR;
     if (nr) {  // P_chi r_chi folded into the first (B B^T)^{-1} of P_S: c1 = W P_chi r_chi
         const Lane& L = h->lane[b.ln];
-        launch_gamma_partial(h->d_patches, h->d_gam_chunks, h->n_gam_chunks, h->d_ctrl, h->d_gam, h->d_btptr,
-                             h->d_btrow, h->d_btsgn, r + h->n_dof, L.part, b.s);
+        launch_gamma_partial(h->d_gam_chunks, h->n_gam_chunks, h->d_mc_row, h->d_mc_val, h->n_mc, r + h->n_dof, L.part, b.s);
         launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_gam_cptr, L.part,
                                h->d_cinv, L.zc, h->max_nc, b.s);
     } else {
@@ -972,8 +999,7 @@ int solve_impl(afieti_handle* h, const double* f, double* u, double* lambda, afi
     // recovery: u = w - R (G^T G)^{-1} G^T B w,  lambda = lambda_0 + chi
     const double* w = h->vec[8];
     launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, w, h->c1, s);
-    launch_gamma_partial(h->d_patches, h->d_gam_chunks, h->n_gam_chunks, h->d_ctrl, h->d_gam, h->d_btptr, h->d_btrow,
-                         h->d_btsgn, h->c1, h->d_part, s);
+    launch_gamma_partial(h->d_gam_chunks, h->n_gam_chunks, h->d_mc_row, h->d_mc_val, h->n_mc, h->c1, h->d_part, s);
     launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_gam_cptr, h->d_part,
                            h->d_cinv, h->d_zc, h->max_nc, s);
     launch_rigid_update(h->d_patches, h->d_dof_chunks, h->n_dof_chunks, h->d_ctrl, h->d_zc, w, u, s);

@@ -94,11 +94,10 @@ void launch_GW(const int* blk_start, const int* blk_size, const int* blk_dir, in
 // partial sums of R^T x over patch DOF chunks (nm values per chunk)
 void launch_rigid_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks,
                           const double* ctrl, const double* x, double* partials, hipStream_t s);
-// partial sums of R^T (B^T y) over the Gamma DOF chunks
-void launch_gamma_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks,
-                          const double* ctrl, const int64_t* gam_dof, const int64_t* bt_ptr,
-                          const int* bt_row, const double* bt_sign, const double* y,
-                          double* partials, hipStream_t s);
+// partial sums of G^T y = R^T (B^T y) over chunks of the per-patch lists of
+// multiplier copies (row, signed rigid-mode values [mode][copy], n_mc copies)
+void launch_gamma_partial(const Chunk* chunks, int n_chunks, const int* mc_row, const double* mc_val,
+                          int64_t n_mc, const double* y, double* partials, hipStream_t s);
 // coef[k] = RtR_inv[k] * sum(partials of patch k)
 void launch_rigid_finalize(const int* patch_chunk_ptr, int n_patches, const double* partials,
                            const double* RtR_inv, double* coef, hipStream_t s);

@@ -1354,7 +1354,10 @@ __global__ void __launch_bounds__(kAhBlock) k_ahat(const DevPatch* __restrict__ 
     }
     const int64_t base = pa.dof_off + (int64_t)l * pa.nodes;
     // bnd_in: x vanishes away from the patch boundary, so on slabs more than
-    // p layers from the i3 faces only the outer ring of the slab can be nonzero.
+    // p layers from the i3 faces only the outer ring of the slab can be
+    // nonzero, after direction 1 only the two edge rows and the edge column
+    // bands of width p + 1, and y only on the frame of width p + 1 (zero
+    // elsewhere).
     // bnd_out: only the patch-boundary entries of y are wanted, so on the
     // slabs between the i3 faces direction 2 is needed on the outer ring
     // only, direction 1 on the bands of p + 1 rows and the two edge columns it
@@ -1430,6 +1433,7 @@ __global__ void __launch_bounds__(kAhBlock) k_ahat(const DevPatch* __restrict__ 
         if (e >= n12) continue;
         const int i2 = e / n1, i1 = e - i2 * n1;
         if (thin && !(i2 <= p || i2 >= n2 - 1 - p || i1 == 0 || i1 == n1 - 1)) continue;
+        if (ring_only && !(i2 == 0 || i2 == n2 - 1 || i1 <= p || i1 >= n1 - 1 - p)) continue;
         double ku = 0.0, mu_ = 0.0, mv = 0.0;
 #pragma unroll
         for (int o = -p; o <= p; ++o) {
@@ -1463,12 +1467,14 @@ __global__ void __launch_bounds__(kAhBlock) k_ahat(const DevPatch* __restrict__ 
         const int i2 = e / n1, i1 = e - i2 * n1;
         if (thin && !(i2 == 0 || i2 == n2 - 1 || i1 == 0 || i1 == n1 - 1)) continue;
         double a = 0.0, b = 0.0;
+        if (!ring_only || i2 <= p || i2 >= n2 - 1 - p || i1 <= p || i1 >= n1 - 1 - p) {
 #pragma unroll
-        for (int o = -p; o <= p; ++o) {
-            const int j2 = i2 + o;
-            if ((unsigned)j2 < (unsigned)n2) {
-                a += Mb2[i2 * W + o + p] * A[j2 * n1 + i1];
-                b += K2[i2 * W + o + p] * Bm[j2 * n1 + i1];
+            for (int o = -p; o <= p; ++o) {
+                const int j2 = i2 + o;
+                if ((unsigned)j2 < (unsigned)n2) {
+                    a += Mb2[i2 * W + o + p] * A[j2 * n1 + i1];
+                    b += K2[i2 * W + o + p] * Bm[j2 * n1 + i1];
+                }
             }
         }
         y[base + (int64_t)i3 * n12 + e] = sc * (a + k2 * b);
@@ -1609,25 +1615,20 @@ __global__ void __launch_bounds__(kBlock) k_rigid_partial(const DevPatch* __rest
         for (int m = 0; m < 6; ++m) part[(int64_t)blockIdx.x * 6 + m] = acc[m];
 }
 
-// partial sums of R^T (B^T y) over chunks of one patch's Gamma DOF list
-__global__ void __launch_bounds__(kBlock) k_gamma_partial(const DevPatch* __restrict__ dps, const Chunk* __restrict__ ch,
-                                                          const double* __restrict__ ctrl, const int64_t* __restrict__ gam,
-                                                          const int64_t* __restrict__ ptr, const int* __restrict__ row,
-                                                          const double* __restrict__ sgn, const double* __restrict__ y,
-                                                          double* __restrict__ part) {
+// partial sums of G^T y over chunks of one patch's multiplier copies: copy e
+// of row r adds y_r times its signed rigid-mode values (one copy per thread)
+__global__ void __launch_bounds__(kBlock) k_gamma_partial(const Chunk* __restrict__ ch, const int* __restrict__ row,
+                                                          const double* __restrict__ val, int64_t n_mc,
+                                                          const double* __restrict__ y, double* __restrict__ part) {
+    static_assert(kGamChunk == kBlock, "one multiplier copy per thread");
     __shared__ double lds[6 * 4];
     const Chunk c = ch[blockIdx.x];
-    const DevPatch& pa = dps[c.seg];
+    const int64_t e = c.begin + threadIdx.x;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t e = c.begin + threadIdx.x; e < c.end; e += kBlock) {
-        const int64_t i = gam[e];
-        double v = 0.0;
-        for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) v += sgn[q] * y[row[q]];
-        const int64_t loc = i - pa.dof_off;
-        const int comp = (int)(loc / pa.nodes);
-        const int64_t nd = loc - comp * pa.nodes;
-        const double* X = ctrl + pa.ctrl_off + nd * 3;
-        for (int m = 0; m < pa.nmodes; ++m) acc[m] += rigid_mode_value(pa.dim, m, comp, X) * v;
+    if (e < c.end) {
+        const double v = y[row[e]];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) acc[m] = val[m * n_mc + e] * v;
     }
     block_sum<6>(acc, lds);
     if (threadIdx.x == 0)
@@ -2109,12 +2110,11 @@ void launch_rigid_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks,
     if (n_chunks) hipLaunchKernelGGL(k_rigid_partial, dim3(n_chunks), dim3(kBlock), 0, s, dp, chunks, ctrl, x, partials);
 }
 
-void launch_gamma_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks, const double* ctrl,
-                          const int64_t* gam_dof, const int64_t* bt_ptr, const int* bt_row, const double* bt_sign,
+void launch_gamma_partial(const Chunk* chunks, int n_chunks, const int* mc_row, const double* mc_val, int64_t n_mc,
                           const double* y, double* partials, hipStream_t s) {
     if (n_chunks)
-        hipLaunchKernelGGL(k_gamma_partial, dim3(n_chunks), dim3(kBlock), 0, s, dp, chunks, ctrl, gam_dof, bt_ptr,
-                           bt_row, bt_sign, y, partials);
+        hipLaunchKernelGGL(k_gamma_partial, dim3(n_chunks), dim3(kBlock), 0, s, chunks, mc_row, mc_val, n_mc, y,
+                           partials);
 }
 
 void launch_rigid_finalize(const int* cptr, int n_patches, const double* partials, const double* RtR_inv,
