@@ -139,7 +139,7 @@ struct afieti_handle {
     // partials, coarse coefficients and FD intermediate buffer.
     Lane lane[2];
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_mid = nullptr;
     bool capturing = false;  // the branches fork only while the iteration graph is captured
     hipGraphExec_t graph_exec = nullptr;
 
@@ -169,6 +169,7 @@ struct afieti_handle {
         if (ev_b) (void)hipEventDestroy(ev_b);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
+        if (ev_mid) (void)hipEventDestroy(ev_mid);
         if (side) (void)hipStreamDestroy(side);
         if (gstream) (void)hipStreamDestroy(gstream);
     }
@@ -664,6 +665,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     HIP_OK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&h->ev_mid, hipEventDisableTiming));
     HIP_OK(hipStreamSynchronize(s));
     HIP_OK(hipGetLastError());
 }
@@ -716,6 +718,13 @@ void join(afieti_handle* h, hipStream_t s) {
     if (!h->capturing) return;
     HIP_OK(hipEventRecord(h->ev_join, h->side));
     HIP_OK(hipStreamWaitEvent(s, h->ev_join, 0));
+}
+
+// the side branch continues after the work enqueued on s so far
+void sync_side(afieti_handle* h, hipStream_t s) {
+    if (!h->capturing) return;
+    HIP_OK(hipEventRecord(h->ev_mid, s));
+    HIP_OK(hipStreamWaitEvent(h->side, h->ev_mid, 0));
 }
 
 void op_mask_interior(afieti_handle* h, double* y, hipStream_t s) {
@@ -798,8 +807,7 @@ void op_ps(afieti_handle* h, const double* y, double* out, hipStream_t s, int ln
 // independent and run concurrently (multiplier block on the side branch)
 // (the launches of the two blocks are interleaved: the graph executor
 // starts nodes in the order they were captured)
-void op_prec(afieti_handle* h, const double* r, double* z, hipStream_t s) {
-    const Branch b = fork(h, s);
+void op_prec_branches(afieti_handle* h, const double* r, double* z, hipStream_t s, const Branch& b) {
     const bool nr = h->opt.ps_variant == AFIETI_PS_NR;
     if (nr) {  // P_chi r_chi folded into the first (B B^T)^{-1} of P_S: c1 = W P_chi r_chi
         const Lane& L = h->lane[b.ln];
@@ -824,20 +832,30 @@ void op_prec(afieti_handle* h, const double* r, double* z, hipStream_t s) {
     op_pu(h, h->s2, z, s);
     op_ps_stage(h, 3, h->c3, h->c4, b.s, b.ln);
     op_pchi(h, h->c4, z + h->n_dof, b.s, b.ln);
+}
+
+void op_prec(afieti_handle* h, const double* r, double* z, hipStream_t s) {
+    const Branch b = fork(h, s);
+    op_prec_branches(h, r, z, s, b);
     join(h, s);
 }
 
 // y = [A w + B^T P_chi chi ; P_chi B w]: the multiplier work runs on the
 // side branch while the brick quadrature of A w runs; the gathers then add
 // B^T P_chi chi
+// the multiplier part of the saddle operator: c5 = P_chi chi, y_chi = P_chi B w
+void op_saddle_side(afieti_handle* h, const double* x, double* y, hipStream_t s, int ln) {
+    op_pchi(h, x + h->n_dof, h->c5, s, ln);
+    launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, x, h->c6, s);
+    op_pchi(h, h->c6, y + h->n_dof, s, ln);
+}
+
 void op_saddle(afieti_handle* h, const double* x, double* y, hipStream_t s) {
     const Branch b = fork(h, s);
     // the brick quadrature is enqueued first: the graph executor starts the
     // branches in the order they were captured
     op_stiffness_bricks(h, x, s);
-    op_pchi(h, x + h->n_dof, h->c5, b.s, b.ln);
-    launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, x, h->c6, b.s);
-    op_pchi(h, h->c6, y + h->n_dof, b.s, b.ln);
+    op_saddle_side(h, x, y, b.s, b.ln);
     join(h, s);
     op_stiffness_rows(h, x, y, h->c5, s);
 }
@@ -873,22 +891,36 @@ MinresBufs initial_bufs(afieti_handle* h) {
 
 // One MINRES iteration (Lanczos step with the saddle operator and the block
 // preconditioner, Givens update, d and x updates), then buffer rotation.
-void minres_iteration(afieti_handle* h, hipStream_t s, MinresBufs& b) {
+// One MINRES iteration.  The saddle operator on z is split: its brick
+// quadrature (which reads only the displacement part of z) and its multiplier
+// part are issued by the iteration before (`next`) or here (`start`).  The
+// preconditioner's displacement block (P_u P_A^{-1} P_u) ends before its
+// multiplier block (P_chi P_S P_chi), so the next brick quadrature starts as
+// soon as that block is done, while the side branch finishes P_S, takes the
+// Lanczos norm and the Givens step, updates d and x, and applies the
+// multiplier part of the next saddle operator.
+void minres_iteration(afieti_handle* h, hipStream_t s, MinresBufs& b, bool start, bool next) {
     double* x = h->vec[8];
     double* q = h->vec[9];
     const int np = h->n_probs;
-    op_saddle(h, b.z, q, s);
+    if (start) {
+        op_stiffness_bricks(h, b.z, s);
+        const Branch bs = fork(h, s);
+        op_saddle_side(h, b.z, q, bs.s, bs.ln);
+    }
+    join(h, s);
+    op_stiffness_rows(h, b.z, q, h->c5, s);
     launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, q, b.z, h->d_part2, s);
     launch_minres_delta(h->d_state, h->d_vec_cptr, np, h->d_part2, s);
     launch_minres_v(h->d_state, h->d_vec_chunks, h->n_vec_chunks, q, b.v, b.v_old, b.v_new, s);
-    op_prec(h, b.v_new, b.z_new, s);
-    launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, b.z_new, b.v_new, h->d_part2, s);
-    launch_minres_givens(h->d_state, h->d_vec_cptr, np, h->d_part2, s);
-    // the d and x updates run on the side branch, off the critical path; the
-    // next saddle operator joins that branch before anything reads the state
-    // again or overwrites z
-    const Branch bd = fork(h, s);
-    launch_minres_dx(h->d_state, h->d_vec_chunks, h->n_vec_chunks, b.z, b.d_old, b.d, b.d_new, x, bd.s);
+    const Branch bp = fork(h, s);
+    op_prec_branches(h, b.v_new, b.z_new, s, bp);
+    sync_side(h, s);  // the displacement part of z_new is complete
+    if (next) op_stiffness_bricks(h, b.z_new, s);
+    launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, b.z_new, b.v_new, h->d_part2, bp.s);
+    launch_minres_givens(h->d_state, h->d_vec_cptr, np, h->d_part2, bp.s);
+    launch_minres_dx(h->d_state, h->d_vec_chunks, h->n_vec_chunks, b.z, b.d_old, b.d, b.d_new, x, bp.s);
+    if (next) op_saddle_side(h, b.z_new, q, bp.s, bp.ln);
     double* t = b.v_old;
     b.v_old = b.v;
     b.v = b.v_new;
@@ -936,7 +968,7 @@ int run_minres(afieti_handle* h, hipStream_t s, afieti_stats* st) {
                 ~Capturing() { h->capturing = false; }
             } guard{h};
             h->capturing = true;
-            for (int r = 0; r < kGraphIters; ++r) minres_iteration(h, g, bc);
+            for (int r = 0; r < kGraphIters; ++r) minres_iteration(h, g, bc, r == 0, r + 1 < kGraphIters);
             join(h, g);  // the last d/x update
             h->capturing = false;
             HIP_OK(hipStreamEndCapture(g, &graph));
@@ -955,7 +987,7 @@ int run_minres(afieti_handle* h, hipStream_t s, afieti_stats* st) {
     } else {
         const int every = std::max(1, h->opt.check_every);
         for (int it = 0; it < h->opt.maxit; ++it) {
-            minres_iteration(h, s, b);
+            minres_iteration(h, s, b, true, false);
             if (((it + 1) % every == 0 || it + 1 == h->opt.maxit) && all_stopped(h, s)) break;
         }
     }
