@@ -16,6 +16,8 @@ LIB = os.path.join(HERE, "libafieti.so")
 SOURCES = ["plan.cpp", "afieti.cpp", "kernels.hip"]
 HIP_FLAGS = [
     "-std=c++17", "-O3", "-fPIC", "-shared", "--offload-arch=gfx950",
+    # every symbol resolved at link time (a missing definition fails the build)
+    "-Wl,--no-undefined",
     # no packed FP32 instructions in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -911,8 +911,8 @@ void minres_iteration(afieti_handle* h, hipStream_t s, MinresBufs& b, bool start
     join(h, s);
     op_stiffness_rows(h, b.z, q, h->c5, s);
     launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, q, b.z, h->d_part2, s);
-    launch_minres_delta(h->d_state, h->d_vec_cptr, np, h->d_part2, s);
-    launch_minres_v(h->d_state, h->d_vec_chunks, h->n_vec_chunks, q, b.v, b.v_old, b.v_new, s);
+    launch_minres_dv(h->d_state, h->d_vec_chunks, h->n_vec_chunks, h->d_vec_cptr, h->d_part2, q, b.v, b.v_old,
+                     b.v_new, s);
     const Branch bp = fork(h, s);
     op_prec_branches(h, b.v_new, b.z_new, s, bp);
     sync_side(h, s);  // the displacement part of z_new is complete

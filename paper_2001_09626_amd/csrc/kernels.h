@@ -98,14 +98,14 @@ void launch_rigid_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks,
 // multiplier copies (row, signed rigid-mode values [mode][copy], n_mc copies)
 void launch_gamma_partial(const Chunk* chunks, int n_chunks, const int* mc_row, const double* mc_val,
                           int64_t n_mc, const double* y, double* partials, hipStream_t s);
-// coef[k] = RtR_inv[k] * sum(partials of patch k)
-void launch_rigid_finalize(const int* patch_chunk_ptr, int n_patches, const double* partials,
-                           const double* RtR_inv, double* coef, hipStream_t s);
 // per problem: g = sum partials; zc = Cinv g (coefficients per patch)
 void launch_coarse_finalize(const int* prob_patch0, const int* prob_npatch, const int* prob_nmodes,
                             const int64_t* prob_cinv_off, int n_probs, const int* patch_chunk_ptr,
                             const double* partials, const double* Cinv, double* zc, int max_nc,
                             hipStream_t s);
+// coef[k] = RtR_inv[k] * sum(partials of patch k)
+void launch_rigid_finalize(const int* patch_chunk_ptr, int n_patches, const double* partials,
+                           const double* RtR_inv, double* coef, hipStream_t s);
 // y = x - R coef (all DOFs)
 void launch_rigid_update(const DevPatch* dp, const Chunk* chunks, int n_chunks, const double* ctrl,
                          const double* coef, const double* x, double* y, hipStream_t s);
@@ -122,15 +122,15 @@ void launch_axpby(double a, const double* x, double b, const double* y, double* 
 void launch_dot_partial(const Chunk* chunks, int n_chunks, const double* x, const double* y,
                         double* partials, hipStream_t s);
 // MINRES scalar steps (one thread per problem)
-void launch_minres_delta(MinresState* st, const int* prob_chunk_ptr, int n_probs,
-                         const double* partials, hipStream_t s);
 void launch_minres_givens(MinresState* st, const int* prob_chunk_ptr, int n_probs,
                           const double* partials, hipStream_t s);
 void launch_minres_init(MinresState* st, const int* prob_chunk_ptr, int n_probs,
                         const double* partials, double tol, int maxit, hipStream_t s);
-// v_new = cv_q q + cv_v v + cv_vold v_old   (skipped for stopped problems)
-void launch_minres_v(const MinresState* st, const Chunk* chunks, int n_chunks, const double* q,
-                     const double* v, const double* v_old, double* v_new, hipStream_t s);
+// delta_j from the chunk partials of <A z_j, z_j> (cptr: per-problem chunk
+// ranges), then v_new = cv_q q + cv_v v + cv_vold v_old, in one launch
+// (skipped for stopped problems)
+void launch_minres_dv(MinresState* st, const Chunk* chunks, int n_chunks, const int* cptr, const double* part,
+                      const double* q, const double* v, const double* v_old, double* v_new, hipStream_t s);
 // d_new = cd_z z + cd_dold d_old + cd_d d; x += cx d_new   (only when upd)
 void launch_minres_dx(const MinresState* st, const Chunk* chunks, int n_chunks, const double* z,
                       const double* d_old, const double* d, double* d_new, double* x, hipStream_t s);

@@ -1803,21 +1803,6 @@ __global__ void __launch_bounds__(kBlock) k_minres_init(MinresState* st, const i
     st[blockIdx.x] = s;
 }
 
-// delta_j = <A z_j, z_j> with z_j = zraw / gamma_j, and the v-update weights
-__global__ void __launch_bounds__(kBlock) k_minres_delta(MinresState* st, const int* cptr, const double* part) {
-    __shared__ double lds[4];
-    const double sum = block_chunk_sum(cptr, part, lds);
-    if (threadIdx.x != 0) return;
-    MinresState& s = st[blockIdx.x];
-    s.upd = 0;
-    if (s.stop) return;
-    const double g = s.gamma;
-    s.delta = sum / (g * g);
-    s.cv_q = 1.0 / g;
-    s.cv_v = -s.delta / g;
-    s.cv_vold = -g / s.gamma_old;
-}
-
 // gamma_{j+1}, the Givens rotation and the d/x-update weights
 __global__ void __launch_bounds__(kBlock) k_minres_givens(MinresState* st, const int* cptr, const double* part) {
     __shared__ double lds[4];
@@ -1853,13 +1838,38 @@ __global__ void __launch_bounds__(kBlock) k_minres_givens(MinresState* st, const
     else if (s.its >= s.maxit) s.stop = 3;
 }
 
-__global__ void __launch_bounds__(kBlock) k_minres_v(const MinresState* __restrict__ st, const Chunk* __restrict__ ch,
-                                                     const double* __restrict__ q, const double* __restrict__ v,
-                                                     const double* __restrict__ vo, double* __restrict__ vn) {
+// delta_j = <A z_j, z_j> with z_j = zraw / gamma_j, the v-update weights and
+// v_{j+1} in one launch: every block sums the chunk partials of its problem
+// in the same fixed order (so all blocks hold the same delta), and the first
+// block of the problem records delta and the weights in the state
+__global__ void __launch_bounds__(kBlock) k_minres_dv(MinresState* __restrict__ st, const Chunk* __restrict__ ch,
+                                                      const int* __restrict__ cptr, const double* __restrict__ part,
+                                                      const double* __restrict__ q, const double* __restrict__ v,
+                                                      const double* __restrict__ vo, double* __restrict__ vn) {
+    __shared__ double lds[4];
+    __shared__ double sum_s;
     const Chunk c = ch[blockIdx.x];
-    const MinresState& s = st[c.seg];
+    const int pr = c.seg;
+    MinresState& s = st[pr];
+    const bool first = (int)blockIdx.x == cptr[pr];
+    if (first && threadIdx.x == 0) s.upd = 0;
     if (s.stop) return;
-    const double a = s.cv_q, b = s.cv_v, d = s.cv_vold;
+    {
+        double acc[1] = {0.0};
+        for (int j = cptr[pr] + threadIdx.x; j < cptr[pr + 1]; j += kBlock) acc[0] += part[j];
+        block_sum<1>(acc, lds);
+        if (threadIdx.x == 0) sum_s = acc[0];
+        __syncthreads();
+    }
+    const double g = s.gamma;
+    const double delta = sum_s / (g * g);
+    const double a = 1.0 / g, b = -delta / g, d = -g / s.gamma_old;
+    if (first && threadIdx.x == 0) {
+        s.delta = delta;
+        s.cv_q = a;
+        s.cv_v = b;
+        s.cv_vold = d;
+    }
     for (int64_t i = c.begin + threadIdx.x; i < c.end; i += kBlock) vn[i] = a * q[i] + b * v[i] + d * vo[i];
 }
 
@@ -2117,16 +2127,16 @@ void launch_gamma_partial(const Chunk* chunks, int n_chunks, const int* mc_row, 
                            partials);
 }
 
-void launch_rigid_finalize(const int* cptr, int n_patches, const double* partials, const double* RtR_inv,
-                           double* coef, hipStream_t s) {
-    hipLaunchKernelGGL(k_rigid_finalize, dim3(n_patches), dim3(kBlock), 0, s, cptr, partials, RtR_inv, coef);
-}
-
 void launch_coarse_finalize(const int* p0, const int* np, const int* nm, const int64_t* coff, int n_probs,
                             const int* cptr, const double* partials, const double* Cinv, double* zc, int max_nc,
                             hipStream_t s) {
     hipLaunchKernelGGL(k_coarse_finalize, dim3(n_probs), dim3(kFinBlock), max_nc * sizeof(double), s, p0, np, nm,
                        coff, cptr, partials, Cinv, zc);
+}
+
+void launch_rigid_finalize(const int* cptr, int n_patches, const double* partials, const double* RtR_inv,
+                           double* coef, hipStream_t s) {
+    hipLaunchKernelGGL(k_rigid_finalize, dim3(n_patches), dim3(kBlock), 0, s, cptr, partials, RtR_inv, coef);
 }
 
 void launch_rigid_update(const DevPatch* dp, const Chunk* chunks, int n_chunks, const double* ctrl, const double* coef,
@@ -2157,16 +2167,15 @@ void launch_minres_init(MinresState* st, const int* cptr, int n, const double* p
                         hipStream_t s) {
     hipLaunchKernelGGL(k_minres_init, dim3(n), dim3(kBlock), 0, s, st, cptr, part, tol, maxit);
 }
-void launch_minres_delta(MinresState* st, const int* cptr, int n, const double* part, hipStream_t s) {
-    hipLaunchKernelGGL(k_minres_delta, dim3(n), dim3(kBlock), 0, s, st, cptr, part);
-}
 void launch_minres_givens(MinresState* st, const int* cptr, int n, const double* part, hipStream_t s) {
     hipLaunchKernelGGL(k_minres_givens, dim3(n), dim3(kBlock), 0, s, st, cptr, part);
 }
-void launch_minres_v(const MinresState* st, const Chunk* chunks, int n_chunks, const double* q, const double* v,
-                     const double* v_old, double* v_new, hipStream_t s) {
-    if (n_chunks) hipLaunchKernelGGL(k_minres_v, dim3(n_chunks), dim3(kBlock), 0, s, st, chunks, q, v, v_old, v_new);
+void launch_minres_dv(MinresState* st, const Chunk* chunks, int n_chunks, const int* cptr, const double* part,
+                      const double* q, const double* v, const double* v_old, double* v_new, hipStream_t s) {
+    if (n_chunks)
+        hipLaunchKernelGGL(k_minres_dv, dim3(n_chunks), dim3(kBlock), 0, s, st, chunks, cptr, part, q, v, v_old, v_new);
 }
+
 void launch_minres_dx(const MinresState* st, const Chunk* chunks, int n_chunks, const double* z, const double* d_old,
                       const double* d, double* d_new, double* x, hipStream_t s) {
     if (n_chunks) hipLaunchKernelGGL(k_minres_dx, dim3(n_chunks), dim3(kBlock), 0, s, st, chunks, z, d_old, d, d_new, x);
