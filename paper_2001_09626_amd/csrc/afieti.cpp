@@ -141,7 +141,13 @@ struct afieti_handle {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_mid = nullptr;
     bool capturing = false;  // the branches fork only while the iteration graph is captured
-    hipGraphExec_t graph_exec = nullptr;
+    // the iteration graph in two forms (pipelined, classic): each is timed
+    // on one replay during the first solve and the faster one is kept
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    int graph_pick = -1;          // chosen form, -1 while on trial
+    int trial_n = 0;              // trial replays so far
+    float trial_ms[2] = {0, 0};   // their timed sums per form
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
 
     template <typename T>
     T* dalloc(int64_t n) {
@@ -160,7 +166,10 @@ struct afieti_handle {
         return p;
     }
     ~afieti_handle() {
-        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        for (auto& ge : graph_exec)
+            if (ge) (void)hipGraphExecDestroy(ge);
+        if (ev_t0) (void)hipEventDestroy(ev_t0);
+        if (ev_t1) (void)hipEventDestroy(ev_t1);
         if (gstream) (void)hipStreamSynchronize(gstream);
         if (side) (void)hipStreamSynchronize(side);
         for (void* p : allocs) (void)hipFree(p);
@@ -666,6 +675,8 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     HIP_OK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&h->ev_mid, hipEventDisableTiming));
+    HIP_OK(hipEventCreate(&h->ev_t0));
+    HIP_OK(hipEventCreate(&h->ev_t1));
     HIP_OK(hipStreamSynchronize(s));
     HIP_OK(hipGetLastError());
 }
@@ -893,19 +904,27 @@ MinresBufs initial_bufs(afieti_handle* h) {
 // preconditioner, Givens update, d and x updates), then buffer rotation.
 // One MINRES iteration.  The saddle operator on z is split: its brick
 // quadrature (which reads only the displacement part of z) and its multiplier
-// part are issued by the iteration before (`next`) or here (`start`).  The
-// preconditioner's displacement block (P_u P_A^{-1} P_u) ends before its
-// multiplier block (P_chi P_S P_chi), so the next brick quadrature starts as
-// soon as that block is done, while the side branch finishes P_S, takes the
-// Lanczos norm and the Givens step, updates d and x, and applies the
-// multiplier part of the next saddle operator.
-void minres_iteration(afieti_handle* h, hipStream_t s, MinresBufs& b, bool start, bool next) {
+// part are issued by the iteration before (`next`) or here (`start`).
+// Pipelined form: the preconditioner's displacement block (P_u P_A^{-1} P_u)
+// ends before its multiplier block (P_chi P_S P_chi), so the next brick
+// quadrature starts as soon as that block is done, while the side branch
+// finishes P_S, takes the Lanczos norm and the Givens step, updates d and x,
+// and applies the multiplier part of the next saddle operator.  Classic form
+// (`pipelined` false, with `start` and without `next`): both blocks of the
+// preconditioner are joined, the norm and the Givens step follow on s, and
+// only the d/x update runs beside the next brick quadrature.  Both forms run
+// the same kernels on the same buffers.
+void minres_iteration(afieti_handle* h, hipStream_t s, MinresBufs& b, bool start, bool next,
+                      bool pipelined = true) {
     double* x = h->vec[8];
     double* q = h->vec[9];
     const int np = h->n_probs;
     if (start) {
-        op_stiffness_bricks(h, b.z, s);
+        // fork before the bricks are enqueued (the side branch does not wait
+        // for them); the bricks are captured first, and the graph executor
+        // starts the branches in the order they were captured
         const Branch bs = fork(h, s);
+        op_stiffness_bricks(h, b.z, s);
         op_saddle_side(h, b.z, q, bs.s, bs.ln);
     }
     join(h, s);
@@ -915,12 +934,20 @@ void minres_iteration(afieti_handle* h, hipStream_t s, MinresBufs& b, bool start
                      b.v_new, s);
     const Branch bp = fork(h, s);
     op_prec_branches(h, b.v_new, b.z_new, s, bp);
-    sync_side(h, s);  // the displacement part of z_new is complete
-    if (next) op_stiffness_bricks(h, b.z_new, s);
-    launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, b.z_new, b.v_new, h->d_part2, bp.s);
-    launch_minres_givens(h->d_state, h->d_vec_cptr, np, h->d_part2, bp.s);
-    launch_minres_dx(h->d_state, h->d_vec_chunks, h->n_vec_chunks, b.z, b.d_old, b.d, b.d_new, x, bp.s);
-    if (next) op_saddle_side(h, b.z_new, q, bp.s, bp.ln);
+    if (pipelined) {
+        sync_side(h, s);  // the displacement part of z_new is complete
+        if (next) op_stiffness_bricks(h, b.z_new, s);
+        launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, b.z_new, b.v_new, h->d_part2, bp.s);
+        launch_minres_givens(h->d_state, h->d_vec_cptr, np, h->d_part2, bp.s);
+        launch_minres_dx(h->d_state, h->d_vec_chunks, h->n_vec_chunks, b.z, b.d_old, b.d, b.d_new, x, bp.s);
+        if (next) op_saddle_side(h, b.z_new, q, bp.s, bp.ln);
+    } else {
+        join(h, s);
+        launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, b.z_new, b.v_new, h->d_part2, s);
+        launch_minres_givens(h->d_state, h->d_vec_cptr, np, h->d_part2, s);
+        const Branch bd = fork(h, s);
+        launch_minres_dx(h->d_state, h->d_vec_chunks, h->n_vec_chunks, b.z, b.d_old, b.d, b.d_new, x, bd.s);
+    }
     double* t = b.v_old;
     b.v_old = b.v;
     b.v = b.v_new;
@@ -959,7 +986,8 @@ int run_minres(afieti_handle* h, hipStream_t s, afieti_stats* st) {
     h->mask = h->d_state;
     if (h->opt.use_graph) {
         hipStream_t g = h->gstream;
-        if (!h->graph_exec) {
+        for (int f = 0; f < 2 && !h->graph_exec[f]; ++f) {
+            const bool pipelined = f == 0;
             hipGraph_t graph;
             HIP_OK(hipStreamBeginCapture(g, hipStreamCaptureModeThreadLocal));
             MinresBufs bc = initial_bufs(h);
@@ -968,19 +996,36 @@ int run_minres(afieti_handle* h, hipStream_t s, afieti_stats* st) {
                 ~Capturing() { h->capturing = false; }
             } guard{h};
             h->capturing = true;
-            for (int r = 0; r < kGraphIters; ++r) minres_iteration(h, g, bc, r == 0, r + 1 < kGraphIters);
+            for (int r = 0; r < kGraphIters; ++r)
+                minres_iteration(h, g, bc, r == 0 || !pipelined, pipelined && r + 1 < kGraphIters, pipelined);
             join(h, g);  // the last d/x update
             h->capturing = false;
             HIP_OK(hipStreamEndCapture(g, &graph));
-            HIP_OK(hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0));
+            HIP_OK(hipGraphInstantiate(&h->graph_exec[f], graph, nullptr, nullptr, 0));
             HIP_OK(hipGraphDestroy(graph));
         }
         HIP_OK(hipEventRecord(h->ev_a, s));
         HIP_OK(hipStreamWaitEvent(g, h->ev_a, 0));
         const int every = std::max(1, h->opt.check_every / kGraphIters);
         for (int it = 0, launches = 0; it < h->opt.maxit; it += kGraphIters) {
-            HIP_OK(hipGraphLaunch(h->graph_exec, g));
-            if (++launches % every == 0 && all_stopped(h, g)) break;
+            // trial: the forms alternate; the first replay of each is a
+            // warm-up, the next two of each are timed, then the faster form
+            // is kept for this and every later solve of the handle
+            const bool trial = h->graph_pick < 0;
+            const int f = trial ? h->trial_n % 2 : h->graph_pick;
+            if (trial) HIP_OK(hipEventRecord(h->ev_t0, g));
+            HIP_OK(hipGraphLaunch(h->graph_exec[f], g));
+            ++launches;
+            if (trial) {
+                HIP_OK(hipEventRecord(h->ev_t1, g));
+                if (all_stopped(h, g)) break;  // (a replay that stops the solve is not timed)
+                float ms = 0;
+                HIP_OK(hipEventElapsedTime(&ms, h->ev_t0, h->ev_t1));
+                if (h->trial_n >= 2) h->trial_ms[f] += ms;
+                if (++h->trial_n == 6) h->graph_pick = h->trial_ms[0] <= h->trial_ms[1] ? 0 : 1;
+                continue;
+            }
+            if (launches % every == 0 && all_stopped(h, g)) break;
         }
         HIP_OK(hipEventRecord(h->ev_b, g));
         HIP_OK(hipStreamWaitEvent(s, h->ev_b, 0));
