@@ -658,14 +658,6 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
             plan.bt_sign[b] = -1.0;
         }
     }
-    // ---- Gamma DOF lists per patch (DOFs with B^T entries)
-    plan.gam_ptr.assign(plan.patches.size() + 1, 0);
-    for (size_t k = 0; k < plan.patches.size(); ++k) {
-        const PatchPlan& P = plan.patches[k];
-        for (int64_t i = P.dof_off; i < P.dof_off + P.dim * P.nodes; ++i)
-            if (plan.bt_ptr[i + 1] > plan.bt_ptr[i]) plan.gam_dof.push_back(i);
-        plan.gam_ptr[k + 1] = (int64_t)plan.gam_dof.size();
-    }
     // ---- rigid modes: G rows, R^T R per patch, G^T G per problem
     plan.g_plus.assign(plan.n_c * 6, 0.0);
     plan.g_minus.assign(plan.n_c * 6, 0.0);

@@ -73,9 +73,6 @@ struct Plan {
     std::vector<int64_t> bt_ptr;
     std::vector<int> bt_row;
     std::vector<double> bt_sign;
-    // Gamma DOFs per patch (sorted), for G^T y = R^T (B^T y)
-    std::vector<int64_t> gam_dof;
-    std::vector<int64_t> gam_ptr;   // per patch start in gam_dof
     // rigid-mode values of G rows: G[r][m] for plus and minus copies
     std::vector<double> g_plus, g_minus;  // [r][6]
     std::vector<int> c_patch_plus, c_patch_minus;  // patch of each copy (-1)
