@@ -748,8 +748,8 @@ void op_mask_interior(afieti_handle* h, double* y, hipStream_t s) {
 void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_t s, bool bnd_in = false,
              bool bnd_out = false) {
     for (const auto& ac : h->ahat)
-        launch_ahat(ac.p, h->d_patches, ac.d_slabs, ac.n_slabs, ac.max_n12, ac.max_n1n2, h->d_kband, h->d_mband, x, y, use_h,
-                    bnd_in ? 1 : 0, bnd_out ? 1 : 0, h->mask, s);
+        launch_ahat(ac.p, h->d_patches, ac.d_slabs, ac.n_slabs, ac.max_n12, ac.max_n1n2, h->d_kband, h->d_mband, x,
+                    y, use_h, bnd_in ? 1 : 0, bnd_out ? 1 : 0, h->mask, s);
 }
 
 void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s, int ln = 0) {
@@ -822,7 +822,8 @@ void op_prec_branches(afieti_handle* h, const double* r, double* z, hipStream_t 
     const bool nr = h->opt.ps_variant == AFIETI_PS_NR;
     if (nr) {  // P_chi r_chi folded into the first (B B^T)^{-1} of P_S: c1 = W P_chi r_chi
         const Lane& L = h->lane[b.ln];
-        launch_gamma_partial(h->d_gam_chunks, h->n_gam_chunks, h->d_mc_row, h->d_mc_val, h->n_mc, r + h->n_dof, L.part, b.s);
+        launch_gamma_partial(h->d_gam_chunks, h->n_gam_chunks, h->d_mc_row, h->d_mc_val, h->n_mc, r + h->n_dof,
+                             L.part, b.s);
         launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_gam_cptr, L.part,
                                h->d_cinv, L.zc, h->max_nc, b.s);
     } else {
