@@ -119,7 +119,12 @@ typedef struct {
     int host_only;       /* 1: build the host plan only, no device work    */
     int use_graph;       /* 1: replay MINRES iterations as a captured HIP
                             graph (6 iterations per launch) on a stream the
-                            handle owns; 0: enqueue kernels one by one     */
+                            handle owns; the graph exists in two schedules
+                            (pipelined, classic) with identical results,
+                            the first solve of a handle times both (with a
+                            host synchronisation per launch while it does)
+                            and later solves use the faster;
+                            0: enqueue kernels one by one                  */
     int stiffness;       /* AFIETI_STIFFNESS_*                             */
 } afieti_options;
 
