@@ -139,7 +139,7 @@ struct afieti_handle {
     // partials, coarse coefficients and FD intermediate buffer.
     Lane lane[2];
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_mid = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_mid = nullptr, ev_ps = nullptr;
     bool capturing = false;  // the branches fork only while the iteration graph is captured
     // the iteration graph in two forms (pipelined, classic): each is timed
     // on one replay during the first solve and the faster one is kept
@@ -179,6 +179,7 @@ struct afieti_handle {
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (ev_mid) (void)hipEventDestroy(ev_mid);
+        if (ev_ps) (void)hipEventDestroy(ev_ps);
         if (side) (void)hipStreamDestroy(side);
         if (gstream) (void)hipStreamDestroy(gstream);
     }
@@ -675,6 +676,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     HIP_OK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&h->ev_mid, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&h->ev_ps, hipEventDisableTiming));
     HIP_OK(hipEventCreate(&h->ev_t0));
     HIP_OK(hipEventCreate(&h->ev_t1));
     HIP_OK(hipStreamSynchronize(s));
@@ -787,7 +789,8 @@ void op_pu(afieti_handle* h, const double* x, double* out, hipStream_t s, int ln
 // stages so that a caller can interleave them with other work:
 //   1: v0 = B^T W y on Gamma, t = A-hat v0
 //   2: v_I = -((A-hat)_II)^{-1} t_I  (interior FD, in place in v)
-//   3: out = W B (H^{d-2} A-hat v)
+//   3: out = W B (H^{d-2} A-hat v)  (4: the same without the A-hat, when
+//      the caller has applied it)
 void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipStream_t s, int ln) {
     const bool nr = h->opt.ps_variant == AFIETI_PS_NR;
     if (stage == 1) {
@@ -801,7 +804,7 @@ void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipS
     } else if (stage == 2) {
         op_fd(h, h->fd_int, h->tt, h->tv, s, ln);
     } else {
-        op_ahat(h, h->tv, h->tt, 1, s, false, true);  // B reads only the Gamma part
+        if (stage == 3) op_ahat(h, h->tv, h->tt, 1, s, false, true);  // B reads only the Gamma part
         if (nr) {
             launch_BW(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->d_cplus, h->d_cminus, h->tt, out, s);
         } else {
@@ -842,7 +845,11 @@ void op_prec_branches(afieti_handle* h, const double* r, double* z, hipStream_t 
     op_fd(h, h->fd_pa, h->s1, h->s2, s);
     op_ps_stage(h, 2, h->c3, h->c4, b.s, b.ln);
     op_pu(h, h->s2, z, s);
-    op_ps_stage(h, 3, h->c3, h->c4, b.s, b.ln);
+    op_ahat(h, h->tv, h->tt, 1, b.s, false, true);
+    // the last LDS-heavy kernel of P_S (a pipelined graph starts the next
+    // brick quadrature after it)
+    if (h->capturing) HIP_OK(hipEventRecord(h->ev_ps, b.s));
+    op_ps_stage(h, 4, h->c3, h->c4, b.s, b.ln);
     op_pchi(h, h->c4, z + h->n_dof, b.s, b.ln);
 }
 
@@ -937,7 +944,13 @@ void minres_iteration(afieti_handle* h, hipStream_t s, MinresBufs& b, bool start
     op_prec_branches(h, b.v_new, b.z_new, s, bp);
     if (pipelined) {
         sync_side(h, s);  // the displacement part of z_new is complete
-        if (next) op_stiffness_bricks(h, b.z_new, s);
+        if (next) {
+            // the brick quadrature fills the LDS of every CU: started while
+            // the second A-hat of P_S is still pending, it holds that kernel
+            // back until the bricks drain, so it waits for it
+            if (h->capturing) HIP_OK(hipStreamWaitEvent(s, h->ev_ps, 0));
+            op_stiffness_bricks(h, b.z_new, s);
+        }
         launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, b.z_new, b.v_new, h->d_part2, bp.s);
         launch_minres_givens(h->d_state, h->d_vec_cptr, np, h->d_part2, bp.s);
         launch_minres_dx(h->d_state, h->d_vec_chunks, h->n_vec_chunks, b.z, b.d_old, b.d, b.d_new, x, bp.s);

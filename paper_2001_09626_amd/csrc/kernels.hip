@@ -1570,6 +1570,17 @@ __global__ void k_GW(const int* __restrict__ bs, const int* __restrict__ bn, con
 }
 
 // partial sums of R^T x over chunks of one patch's DOFs
+// f(integral_constant<int, dim>) for the dimension of a patch (uniform per
+// workgroup): with the dimension and the mode index known at compile time the
+// mode values reduce to selects (no branches per DOF and mode)
+template <typename F>
+__device__ inline void with_dim(int dim, F f) {
+    if (dim == 3)
+        f(std::integral_constant<int, 3>{});
+    else
+        f(std::integral_constant<int, 2>{});
+}
+
 // a chunk of patch DOFs as one thread sees it: kChunk / kBlock entries, with
 // every load issued before any use
 struct RigidRows {
@@ -1607,9 +1618,13 @@ __global__ void __launch_bounds__(kBlock) k_rigid_partial(const DevPatch* __rest
     }
     const RigidRows r(pa, c, ctrl);
     double acc[6] = {0, 0, 0, 0, 0, 0};
+    with_dim(pa.dim, [&](auto D) {
+        constexpr int DIM = decltype(D)::value, NM = DIM == 3 ? 6 : 3;
 #pragma unroll
-    for (int it = 0; it < RigidRows::kIt; ++it)
-        for (int m = 0; m < pa.nmodes; ++m) acc[m] += rigid_mode_value(pa.dim, m, r.comp[it], r.X[it]) * v[it];
+        for (int it = 0; it < RigidRows::kIt; ++it)
+#pragma unroll
+            for (int m = 0; m < NM; ++m) acc[m] += rigid_mode_value(DIM, m, r.comp[it], r.X[it]) * v[it];
+    });
     block_sum<6>(acc, lds);
     if (threadIdx.x == 0)
         for (int m = 0; m < 6; ++m) part[(int64_t)blockIdx.x * 6 + m] = acc[m];
@@ -1724,12 +1739,16 @@ __global__ void __launch_bounds__(kBlock) k_rigid_update(const DevPatch* __restr
     const RigidRows r(pa, c, ctrl);
     double cf[6];
     for (int m = 0; m < 6; ++m) cf[m] = coef[c.seg * 6 + m];
+    with_dim(pa.dim, [&](auto D) {
+        constexpr int DIM = decltype(D)::value, NM = DIM == 3 ? 6 : 3;
 #pragma unroll
-    for (int it = 0; it < RigidRows::kIt; ++it) {
-        double s = 0.0;
-        for (int m = 0; m < pa.nmodes; ++m) s += rigid_mode_value(pa.dim, m, r.comp[it], r.X[it]) * cf[m];
-        if (r.ok[it]) y[c.begin + threadIdx.x + it * kBlock] = v[it] - s;
-    }
+        for (int it = 0; it < RigidRows::kIt; ++it) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < NM; ++m) s += rigid_mode_value(DIM, m, r.comp[it], r.X[it]) * cf[m];
+            if (r.ok[it]) y[c.begin + threadIdx.x + it * kBlock] = v[it] - s;
+        }
+    });
 }
 
 // y[r] = beta x[r] + alpha (G zc)[r],  G row = R(plus copy) - R(minus copy)
