@@ -76,12 +76,17 @@ __device__ inline void batched_copy(T* dst, int n, F load) {
     }
 }
 
-constexpr int kSlabIt = (kMaxN * kMaxN + kBlock - 1) / kBlock;  // loads per thread of an n x n slab
 
 // =============================================================== FD kernels
+// threads of the FD kernels (vector ALU and matrix cores): eight wavefronts
+// per slab or column block; four workgroups of the matrix-core kernels, two
+// of the FP64 vector-ALU kernels fit in the LDS of a CU
+constexpr int kFdBlock = 512;
+constexpr int kFdSlabIt = (kMaxN * kMaxN + kFdBlock - 1) / kFdBlock;  // loads per thread of an n x n slab
+
 // Pass 1: per (tensor, slab i3): Y[a2][a1] = sum_{i2,i1} U2[i2][a2] X[i2][i1] U1[i1][a1]
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_fd_fwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
+__global__ void __launch_bounds__(kFdBlock) k_fd_fwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
                                                      const T* __restrict__ ut, const double* __restrict__ in,
                                                      T* __restrict__ tmp, const MinresState* __restrict__ mask) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -93,23 +98,23 @@ __global__ void __launch_bounds__(kBlock) k_fd_fwd12(const FdTensor* __restrict_
     T* Y = X + kMaxN * kMaxN;
     T* U = Y + kMaxN * kMaxN;
     const double* src = in + t.in_off + (int64_t)i3 * t.s3;
-    batched_copy<kSlabIt>(X, n12, [&](int e) {
+    batched_copy<kFdSlabIt, kFdBlock>(X, n12, [&](int e) {
         const int i2 = e / n1, i1 = e - i2 * n1;
         return (T)src[(int64_t)i2 * t.s2 + i1];
     });
-    batched_copy<kSlabIt>(U, n1 * n1, [&](int e) { return ut[t.u_off[0] + e]; });
+    batched_copy<kFdSlabIt, kFdBlock>(U, n1 * n1, [&](int e) { return ut[t.u_off[0] + e]; });
     __syncthreads();
-    for (int e = threadIdx.x; e < n12; e += kBlock) {  // Y[i2][a1]
+    for (int e = threadIdx.x; e < n12; e += kFdBlock) {  // Y[i2][a1]
         int i2 = e / n1, a1 = e - i2 * n1;
         T acc = 0;
         for (int i1 = 0; i1 < n1; ++i1) acc += X[i2 * n1 + i1] * U[i1 * n1 + a1];
         Y[e] = acc;
     }
     __syncthreads();
-    batched_copy<kSlabIt>(U, n2 * n2, [&](int e) { return ut[t.u_off[1] + e]; });
+    batched_copy<kFdSlabIt, kFdBlock>(U, n2 * n2, [&](int e) { return ut[t.u_off[1] + e]; });
     __syncthreads();
     T* dst = tmp + t.tmp_off + (int64_t)i3 * n12;
-    for (int e = threadIdx.x; e < n12; e += kBlock) {  // Z[a2][a1]
+    for (int e = threadIdx.x; e < n12; e += kFdBlock) {  // Z[a2][a1]
         int a2 = e / n1, a1 = e - a2 * n1;
         T acc = 0;
         for (int i2 = 0; i2 < n2; ++i2) acc += U[i2 * n2 + a2] * Y[i2 * n1 + a1];
@@ -120,7 +125,7 @@ __global__ void __launch_bounds__(kBlock) k_fd_fwd12(const FdTensor* __restrict_
 // Pass 2: per (tensor, block of 32 columns (a1,a2)): mode-3 product with U3^T,
 // divide by the Kronecker-sum eigenvalues Lambda, mode-3 product with U3.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_fd_mid3(const FdTensor* __restrict__ tens, const int2* __restrict__ cols,
+__global__ void __launch_bounds__(kFdBlock) k_fd_mid3(const FdTensor* __restrict__ tens, const int2* __restrict__ cols,
                                                     const T* __restrict__ ut, const double* __restrict__ dt,
                                                     T* __restrict__ tmp, const MinresState* __restrict__ mask) {
     constexpr int NC = 32;
@@ -134,25 +139,25 @@ __global__ void __launch_bounds__(kBlock) k_fd_mid3(const FdTensor* __restrict__
     T* Zt = Z + kMaxN * NC;
     T* U = Zt + kMaxN * NC;
     T* base = tmp + t.tmp_off;
-    batched_copy<(kMaxN * NC + kBlock - 1) / kBlock>(Z, n3 * NC, [&](int e) {
+    batched_copy<(kMaxN * NC + kFdBlock - 1) / kFdBlock, kFdBlock>(Z, n3 * NC, [&](int e) {
         const int i3 = e / NC, col = col0 + e - i3 * NC;
         return col < n12 ? base[(int64_t)i3 * n12 + col] : (T)0;
     });
-    batched_copy<kSlabIt>(U, n3 * n3, [&](int e) { return ut[t.u_off[2] + e]; });
+    batched_copy<kFdSlabIt, kFdBlock>(U, n3 * n3, [&](int e) { return ut[t.u_off[2] + e]; });
     __syncthreads();
     const int c = threadIdx.x % NC, g = threadIdx.x / NC;  // 8 groups over a3
     const int col = col0 + c;
     const int a2 = col / n1, a1 = col - a2 * n1;
     double lam12 = 0;
     if (col < n12) lam12 = t.mass + t.kappa[0] * dt[t.d_off[0] + a1] + t.kappa[1] * dt[t.d_off[1] + a2];
-    for (int a3 = g; a3 < n3; a3 += kBlock / NC) {
+    for (int a3 = g; a3 < n3; a3 += kFdBlock / NC) {
         T acc = 0;
         for (int i3 = 0; i3 < n3; ++i3) acc += U[i3 * n3 + a3] * Z[i3 * NC + c];
         double lam = t.scale * (lam12 + t.kappa[2] * dt[t.d_off[2] + a3]);
         Zt[a3 * NC + c] = (col < n12) ? (T)((double)acc / lam) : (T)0;
     }
     __syncthreads();
-    for (int i3 = g; i3 < n3; i3 += kBlock / NC) {
+    for (int i3 = g; i3 < n3; i3 += kFdBlock / NC) {
         T acc = 0;
         for (int a3 = 0; a3 < n3; ++a3) acc += U[i3 * n3 + a3] * Zt[a3 * NC + c];
         if (col < n12) base[(int64_t)i3 * n12 + col] = acc;
@@ -161,7 +166,7 @@ __global__ void __launch_bounds__(kBlock) k_fd_mid3(const FdTensor* __restrict__
 
 // Pass 3: per (tensor, slab i3): X[i2][i1] = alpha sum_{a2,a1} U2[i2][a2] Z[a2][a1] U1[i1][a1]
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_fd_bwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
+__global__ void __launch_bounds__(kFdBlock) k_fd_bwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
                                                      const T* __restrict__ ut, const T* __restrict__ tmp,
                                                      double* __restrict__ out, const MinresState* __restrict__ mask) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -173,20 +178,20 @@ __global__ void __launch_bounds__(kBlock) k_fd_bwd12(const FdTensor* __restrict_
     T* Y = Z + kMaxN * kMaxN;
     T* U = Y + kMaxN * kMaxN;
     const T* src = tmp + t.tmp_off + (int64_t)i3 * n12;
-    batched_copy<kSlabIt>(Z, n12, [&](int e) { return src[e]; });
-    batched_copy<kSlabIt>(U, n1 * n1, [&](int e) { return ut[t.u_off[0] + e]; });
+    batched_copy<kFdSlabIt, kFdBlock>(Z, n12, [&](int e) { return src[e]; });
+    batched_copy<kFdSlabIt, kFdBlock>(U, n1 * n1, [&](int e) { return ut[t.u_off[0] + e]; });
     __syncthreads();
-    for (int e = threadIdx.x; e < n12; e += kBlock) {  // Y[a2][i1] = sum_a1 Z[a2][a1] U1[i1][a1]
+    for (int e = threadIdx.x; e < n12; e += kFdBlock) {  // Y[a2][i1] = sum_a1 Z[a2][a1] U1[i1][a1]
         int a2 = e / n1, i1 = e - a2 * n1;
         T acc = 0;
         for (int a1 = 0; a1 < n1; ++a1) acc += Z[a2 * n1 + a1] * U[i1 * n1 + a1];
         Y[e] = acc;
     }
     __syncthreads();
-    batched_copy<kSlabIt>(U, n2 * n2, [&](int e) { return ut[t.u_off[1] + e]; });
+    batched_copy<kFdSlabIt, kFdBlock>(U, n2 * n2, [&](int e) { return ut[t.u_off[1] + e]; });
     __syncthreads();
     double* dst = out + t.out_off + (int64_t)i3 * t.s3;
-    for (int e = threadIdx.x; e < n12; e += kBlock) {  // X[i2][i1] = sum_a2 U2[i2][a2] Y[a2][i1]
+    for (int e = threadIdx.x; e < n12; e += kFdBlock) {  // X[i2][i1] = sum_a2 U2[i2][a2] Y[a2][i1]
         int i2 = e / n1, i1 = e - i2 * n1;
         T acc = 0;
         for (int a2 = 0; a2 < n2; ++a2) acc += U[i2 * n2 + a2] * Y[a2 * n1 + i1];
@@ -268,22 +273,22 @@ __device__ inline typename MfmaK<MODE>::Acc mfma_tile(const typename MfmaK<MODE>
 }
 
 // stage a rows x cols block (row stride src_ld in global) into LDS as T,
-// zero padded to prow x pcol (prow * pcol <= 16 kBlock) with leading
+// zero padded to prow x pcol (prow * pcol <= 4096) with leading
 // dimension ld; every global load of a thread is issued before its stores
 template <typename T, typename S>
 __device__ inline void stage(T* dst, int ld, int prow, int pcol, const S* src, int64_t src_ld, int rows, int cols) {
-    constexpr int IT = 16;
+    constexpr int IT = 4096 / kFdBlock;
     const int total = prow * pcol;
     S v[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        const int e = threadIdx.x + it * kBlock;
+        const int e = threadIdx.x + it * kFdBlock;
         const int i = e / pcol, j = e - i * pcol;
         v[it] = (e < total && i < rows && j < cols) ? src[(int64_t)i * src_ld + j] : (S)0;
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-        const int e = threadIdx.x + it * kBlock;
+        const int e = threadIdx.x + it * kFdBlock;
         if (e < total) {
             const int i = e / pcol, j = e - i * pcol;
             if constexpr (std::is_same<T, __bf16>::value)
@@ -298,7 +303,7 @@ __device__ inline int pad16(int n) { return (n + 15) & ~15; }
 
 // Pass 1: Y = X U1 (rows i2, cols a1), Z = U2^T Y, per slab i3 -> tmp
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_fdm_fwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
+__global__ void __launch_bounds__(kFdBlock) k_fdm_fwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
                                                       const typename MfmaK<MODE>::U* __restrict__ ut,
                                                       const double* __restrict__ in,
                                                       typename MfmaK<MODE>::Tmp* __restrict__ tmp,
@@ -323,17 +328,17 @@ __global__ void __launch_bounds__(kBlock) k_fdm_fwd12(const FdTensor* __restrict
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
     const int t1 = p1 / 16, tiles1 = (p2 / 16) * t1;
-    for (int tl = wave; tl < tiles1; tl += kBlock / 64) {
+    for (int tl = wave; tl < tiles1; tl += kFdBlock / 64) {
         const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
         auto acc = mfma_tile<MODE, false, false>(X, LDK, U1, kLD, m0, n0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) Y[(m0 + M::row(g, q)) * kLD + n0 + r] = (T)acc[q];
     }
-    for (int e = threadIdx.x; e < (KP - p2) * kLD; e += kBlock) Y[p2 * kLD + e] = (T)0.f;  // depth padding
+    for (int e = threadIdx.x; e < (KP - p2) * kLD; e += kFdBlock) Y[p2 * kLD + e] = (T)0.f;  // depth padding
     __syncthreads();
     typename M::Tmp* dst = tmp + t.tmp_off + (int64_t)i3 * n1 * n2;
     const int tiles2 = (p2 / 16) * t1;
-    for (int tl = wave; tl < tiles2; tl += kBlock / 64) {
+    for (int tl = wave; tl < tiles2; tl += kFdBlock / 64) {
         const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
         auto acc = mfma_tile<MODE, true, false>(U2, kLD, Y, kLD, m0, n0);
 #pragma unroll
@@ -347,7 +352,7 @@ __global__ void __launch_bounds__(kBlock) k_fdm_fwd12(const FdTensor* __restrict
 // Pass 2: per block of 64 columns c = (a2, a1): Zt = U3^T Zc, divide by Lambda,
 // W = U3 Zt, written back in place
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_fdm_mid3(const FdTensor* __restrict__ tens, const int2* __restrict__ cols,
+__global__ void __launch_bounds__(kFdBlock) k_fdm_mid3(const FdTensor* __restrict__ tens, const int2* __restrict__ cols,
                                                      const typename MfmaK<MODE>::U* __restrict__ ut,
                                                      const double* __restrict__ dt,
                                                      typename MfmaK<MODE>::Tmp* __restrict__ tmp,
@@ -369,28 +374,28 @@ __global__ void __launch_bounds__(kBlock) k_fdm_mid3(const FdTensor* __restrict_
     const int col0 = it.y * NC;
     typename M::Tmp* base = tmp + t.tmp_off;
     {
-        constexpr int IT = KP * NC / kBlock;  // k3 <= KP
+        constexpr int IT = KP * NC / kFdBlock;  // k3 <= KP
         typename M::Tmp v[IT];
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
-            const int e = threadIdx.x + it * kBlock;
+            const int e = threadIdx.x + it * kFdBlock;
             const int i3 = e / NC, c = e - i3 * NC, col = col0 + c;
             v[it] = (i3 < n3 && col < n12) ? base[(int64_t)i3 * n12 + col] : (typename M::Tmp)0;
         }
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
-            const int e = threadIdx.x + it * kBlock;
+            const int e = threadIdx.x + it * kFdBlock;
             const int i3 = e / NC, c = e - i3 * NC;
             Zc[i3 * LDC + c] = (T)v[it];
         }
     }
     stage(U3, LDU, KP, KP, ut + t.u_off[2], n3, n3, n3);
-    for (int e = threadIdx.x; e < (KP - p3) * LDC; e += kBlock) Zt[p3 * LDC + e] = (T)0.f;
+    for (int e = threadIdx.x; e < (KP - p3) * LDC; e += kFdBlock) Zt[p3 * LDC + e] = (T)0.f;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
     const int tiles = (p3 / 16) * (NC / 16);
-    for (int tl = wave; tl < tiles; tl += kBlock / 64) {
+    for (int tl = wave; tl < tiles; tl += kFdBlock / 64) {
         const int m0 = (tl / (NC / 16)) * 16, n0 = (tl % (NC / 16)) * 16;
         auto acc = mfma_tile<MODE, true, false>(U3, LDU, Zc, LDC, m0, n0);
         const int col = col0 + n0 + r;
@@ -406,7 +411,7 @@ __global__ void __launch_bounds__(kBlock) k_fdm_mid3(const FdTensor* __restrict_
         }
     }
     __syncthreads();
-    for (int tl = wave; tl < tiles; tl += kBlock / 64) {
+    for (int tl = wave; tl < tiles; tl += kFdBlock / 64) {
         const int m0 = (tl / (NC / 16)) * 16, n0 = (tl % (NC / 16)) * 16;
         auto acc = mfma_tile<MODE, false, false>(U3, LDU, Zt, LDC, m0, n0);
         const int col = col0 + n0 + r;
@@ -420,7 +425,7 @@ __global__ void __launch_bounds__(kBlock) k_fdm_mid3(const FdTensor* __restrict_
 
 // Pass 3: Y = Z U1^T (rows a2, cols i1), X = U2 Y, alpha X -> FP64 output
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_fdm_bwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
+__global__ void __launch_bounds__(kFdBlock) k_fdm_bwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
                                                       const typename MfmaK<MODE>::U* __restrict__ ut,
                                                       const typename MfmaK<MODE>::Tmp* __restrict__ tmp,
                                                       double* __restrict__ out, const MinresState* __restrict__ mask) {
@@ -440,12 +445,12 @@ __global__ void __launch_bounds__(kBlock) k_fdm_bwd12(const FdTensor* __restrict
     stage(Z, LDK, p2, KP, tmp + t.tmp_off + (int64_t)i3 * n1 * n2, n1, n2, n1);
     stage(U1, LDK, p1, KP, ut + t.u_off[0], n1, n1, n1);
     stage(U2, LDK, p2, KP, ut + t.u_off[1], n2, n2, n2);
-    for (int e = threadIdx.x; e < (KP - p2) * kLD; e += kBlock) Y[p2 * kLD + e] = (T)0.f;
+    for (int e = threadIdx.x; e < (KP - p2) * kLD; e += kFdBlock) Y[p2 * kLD + e] = (T)0.f;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
     const int t1 = p1 / 16, tiles = (p2 / 16) * t1;
-    for (int tl = wave; tl < tiles; tl += kBlock / 64) {
+    for (int tl = wave; tl < tiles; tl += kFdBlock / 64) {
         const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
         auto acc = mfma_tile<MODE, false, true>(Z, LDK, U1, LDK, m0, n0);
 #pragma unroll
@@ -453,7 +458,7 @@ __global__ void __launch_bounds__(kBlock) k_fdm_bwd12(const FdTensor* __restrict
     }
     __syncthreads();
     double* dst = out + t.out_off + (int64_t)i3 * t.s3;
-    for (int tl = wave; tl < tiles; tl += kBlock / 64) {
+    for (int tl = wave; tl < tiles; tl += kFdBlock / 64) {
         const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
         auto acc = mfma_tile<MODE, false, false>(U2, LDK, Y, kLD, m0, n0);
 #pragma unroll
@@ -470,9 +475,9 @@ void fdm_launch(const FdTensor* tens, const int2* slabs, int n_slabs, const int2
     using M = MfmaK<MODE>;
     const auto* u = static_cast<const typename M::U*>(ut);
     auto* tp = static_cast<typename M::Tmp*>(tmp);
-    hipLaunchKernelGGL(k_fdm_fwd12<MODE>, dim3(n_slabs), dim3(kBlock), 0, s, tens, slabs, u, in, tp, mask);
-    hipLaunchKernelGGL(k_fdm_mid3<MODE>, dim3(n_cols), dim3(kBlock), 0, s, tens, cols, u, dt, tp, mask);
-    hipLaunchKernelGGL(k_fdm_bwd12<MODE>, dim3(n_slabs), dim3(kBlock), 0, s, tens, slabs, u, tp, out, mask);
+    hipLaunchKernelGGL(k_fdm_fwd12<MODE>, dim3(n_slabs), dim3(kFdBlock), 0, s, tens, slabs, u, in, tp, mask);
+    hipLaunchKernelGGL(k_fdm_mid3<MODE>, dim3(n_cols), dim3(kFdBlock), 0, s, tens, cols, u, dt, tp, mask);
+    hipLaunchKernelGGL(k_fdm_bwd12<MODE>, dim3(n_slabs), dim3(kFdBlock), 0, s, tens, slabs, u, tp, out, mask);
 }
 
 // ============================================================ setup kernels
@@ -1942,11 +1947,11 @@ void launch_fd(int prec, const FdTensor* tens, int n_tensors, const int2* slabs,
     if (prec == 0) {
         const size_t sh12 = 3 * kMaxN * kMaxN * sizeof(double);
         const size_t sh3 = (2 * kMaxN * 32 + kMaxN * kMaxN) * sizeof(double);
-        hipLaunchKernelGGL(k_fd_fwd12<double>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
+        hipLaunchKernelGGL(k_fd_fwd12<double>, dim3(n_slabs), dim3(kFdBlock), sh12, s, tens, slabs,
                            (const double*)ut, in, (double*)tmp, mask);
-        hipLaunchKernelGGL(k_fd_mid3<double>, dim3(n_colblocks), dim3(kBlock), sh3, s, tens, cols,
+        hipLaunchKernelGGL(k_fd_mid3<double>, dim3(n_colblocks), dim3(kFdBlock), sh3, s, tens, cols,
                            (const double*)ut, dt, (double*)tmp, mask);
-        hipLaunchKernelGGL(k_fd_bwd12<double>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
+        hipLaunchKernelGGL(k_fd_bwd12<double>, dim3(n_slabs), dim3(kFdBlock), sh12, s, tens, slabs,
                            (const double*)ut, (const double*)tmp, out, mask);
     } else if (prec == 2 || prec == 3 || prec == 4) {
         // MFMA: 2 = FP32 operands, 3 = BF16 operands, 4 = FP64; 64-column blocks in pass 2
@@ -1956,11 +1961,11 @@ void launch_fd(int prec, const FdTensor* tens, int n_tensors, const int2* slabs,
     } else {
         const size_t sh12 = 3 * kMaxN * kMaxN * sizeof(float);
         const size_t sh3 = (2 * kMaxN * 32 + kMaxN * kMaxN) * sizeof(float);
-        hipLaunchKernelGGL(k_fd_fwd12<float>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
+        hipLaunchKernelGGL(k_fd_fwd12<float>, dim3(n_slabs), dim3(kFdBlock), sh12, s, tens, slabs,
                            (const float*)ut, in, (float*)tmp, mask);
-        hipLaunchKernelGGL(k_fd_mid3<float>, dim3(n_colblocks), dim3(kBlock), sh3, s, tens, cols,
+        hipLaunchKernelGGL(k_fd_mid3<float>, dim3(n_colblocks), dim3(kFdBlock), sh3, s, tens, cols,
                            (const float*)ut, dt, (float*)tmp, mask);
-        hipLaunchKernelGGL(k_fd_bwd12<float>, dim3(n_slabs), dim3(kBlock), sh12, s, tens, slabs,
+        hipLaunchKernelGGL(k_fd_bwd12<float>, dim3(n_slabs), dim3(kFdBlock), sh12, s, tens, slabs,
                            (const float*)ut, (const float*)tmp, out, mask);
     }
 }
