@@ -1574,7 +1574,6 @@ __global__ void k_GW(const int* __restrict__ bs, const int* __restrict__ bn, con
     });
 }
 
-// partial sums of R^T x over chunks of one patch's DOFs
 // f(integral_constant<int, dim>) for the dimension of a patch (uniform per
 // workgroup): with the dimension and the mode index known at compile time the
 // mode values reduce to selects (no branches per DOF and mode)
@@ -1609,6 +1608,7 @@ struct RigidRows {
     }
 };
 
+// partial sums of R^T x over chunks of one patch's DOFs
 __global__ void __launch_bounds__(kBlock) k_rigid_partial(const DevPatch* __restrict__ dps, const Chunk* __restrict__ ch,
                                                           const double* __restrict__ ctrl, const double* __restrict__ x,
                                                           double* __restrict__ part) {
