@@ -1101,7 +1101,12 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
                 const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
                 const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
                 const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-                const double id = 1.0 / det;
+                // 1/det: hardware reciprocal refined by two Newton-Raphson
+                // steps (e <- e + e (1 - det e)), within an ulp or so of the
+                // correctly rounded quotient at half its instruction count
+                double id = __builtin_amdgcn_rcp(det);
+                id = fma(fma(-det, id, 1.0), id, id);
+                id = fma(fma(-det, id, 1.0), id, id);
                 double Ji[3][3];  // Ji[a][x] = d eta_a / d x_x
                 Ji[0][0] = c00 * id;
                 Ji[1][0] = c01 * id;
