@@ -26,7 +26,7 @@ METRIC = "AF-IETI solve s to 1e-8 rel.res (FP32-FD vs FP64-FD); FD-apply DOF/s"
 # read from the FETCH_SIZE / WRITE_SIZE counters (scaled by a 1 GiB device
 # copy's readings): profiles/k_mf_stiffness_c2_traffic.md.  Valid for the
 # kernels that were measured; None for workloads without such a run.
-MEASURED_TRAFFIC = {"c2": 231.0e6}
+MEASURED_TRAFFIC = {"c2": 231.1e6}
 FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
