@@ -859,9 +859,6 @@ void op_prec(afieti_handle* h, const double* r, double* z, hipStream_t s) {
     join(h, s);
 }
 
-// y = [A w + B^T P_chi chi ; P_chi B w]: the multiplier work runs on the
-// side branch while the brick quadrature of A w runs; the gathers then add
-// B^T P_chi chi
 // the multiplier part of the saddle operator: c5 = P_chi chi, y_chi = P_chi B w
 void op_saddle_side(afieti_handle* h, const double* x, double* y, hipStream_t s, int ln) {
     op_pchi(h, x + h->n_dof, h->c5, s, ln);
@@ -869,6 +866,9 @@ void op_saddle_side(afieti_handle* h, const double* x, double* y, hipStream_t s,
     op_pchi(h, h->c6, y + h->n_dof, s, ln);
 }
 
+// y = [A w + B^T P_chi chi ; P_chi B w]: the multiplier work runs on the
+// side branch while the brick quadrature of A w runs; the gathers then add
+// B^T P_chi chi
 void op_saddle(afieti_handle* h, const double* x, double* y, hipStream_t s) {
     const Branch b = fork(h, s);
     // the brick quadrature is enqueued first: the graph executor starts the
@@ -910,7 +910,7 @@ MinresBufs initial_bufs(afieti_handle* h) {
 
 // One MINRES iteration (Lanczos step with the saddle operator and the block
 // preconditioner, Givens update, d and x updates), then buffer rotation.
-// One MINRES iteration.  The saddle operator on z is split: its brick
+// The saddle operator on z is split: its brick
 // quadrature (which reads only the displacement part of z) and its multiplier
 // part are issued by the iteration before (`next`) or here (`start`).
 // Pipelined form: the preconditioner's displacement block (P_u P_A^{-1} P_u)
@@ -949,6 +949,10 @@ void minres_iteration(afieti_handle* h, hipStream_t s, MinresBufs& b, bool start
             // the second A-hat of P_S is still pending, it holds that kernel
             // back until the bricks drain, so it waits for it
             if (h->capturing) HIP_OK(hipStreamWaitEvent(s, h->ev_ps, 0));
+            // (it reads the stop flags while the Givens step below may set
+            // them: a problem that has just stopped is then either skipped
+            // or computed, and the gather, which runs after the join, skips
+            // it in both cases)
             op_stiffness_bricks(h, b.z_new, s);
         }
         launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, b.z_new, b.v_new, h->d_part2, bp.s);
