@@ -152,8 +152,8 @@ def main():
     ap.add_argument("--only-fp32", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the method shards by patch; see DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the method would shard by patch). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
