@@ -3,7 +3,7 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
-Readings of points the paper leaves open (each also listed in the design doc):
+Readings of points the paper leaves open:
   * Jump matrix B: the paper only requires Bv = 0 <=> continuity and
     homogeneous Dirichlet data, with no redundant rows.  Reading: a "star"
     to the lowest patch index.  For every geometric node with copies
