@@ -13,7 +13,7 @@ solve with right-hand side dJ/du, and
   dJ/da_j   =  psi^T F_j.
 
 Pinned by central finite differences of J through full solves
-(tests/test_oracle_adjoint.py).
+(tests/test_oracle_solve.py, test_adjoint_gradient_central_differences).
 """
 from __future__ import annotations
 

@@ -241,6 +241,7 @@ def _autograd():
             u, _, _ = solver.solve(want_lambda=False)
             ctx.solver = solver
             ctx.params = (lam_np, amp_np)
+            ctx.like = ((lame.device, lame.dtype), (amps.device, amps.dtype))
             ctx.save_for_backward(u)
             return u
 
@@ -252,8 +253,9 @@ def _autograd():
             if not (np.array_equal(lam_np, solver.lame) and np.array_equal(amp_np, solver.amps)):
                 solver.set_parameters(lam_np, amp_np)
             _, dlam, dmu, damp, _ = solver.solve_adjoint(grad_u.contiguous(), u)
-            g_lame = torch.from_numpy(np.stack([dlam, dmu], axis=1))
-            g_amps = torch.from_numpy(damp)
+            (ld, lt), (ad, at) = ctx.like
+            g_lame = torch.from_numpy(np.stack([dlam, dmu], axis=1)).to(device=ld, dtype=lt)
+            g_amps = torch.from_numpy(damp).to(device=ad, dtype=at)
             return g_lame, g_amps, None
 
     class _MassNorm(torch.autograd.Function):

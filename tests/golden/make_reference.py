@@ -1,0 +1,73 @@
+"""Write oracle reference solutions of full-size workloads for the GPU
+parity tests (tests/test_gpu_reference.py).
+
+    python tests/golden/make_reference.py c2            # C2 at tol 1e-8 and 1e-12
+    python tests/golden/make_reference.py c4 0 3 5 ...  # problems of the C4 batch
+
+Only the oracle (``oracle/``) and the seeded workload generators are called.
+Each output file holds, per tolerance: the MINRES iteration count and the
+history of |eta| / gamma_1, the norms of u and lambda, u and lambda at a
+seeded sample of indices, and the projections of u onto seeded N(0, 1)
+vectors (``workloads.random_vector(n_dof, seed)``), so that a test can
+compare the whole solution without storing it.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+from oracle.afieti import AFIETI  # noqa: E402
+
+N_SAMPLES = 4096
+PROJ_SEEDS = (101, 102, 103)
+
+
+def summarise(o, res, tol):
+    rng = np.random.default_rng(1234)
+    iu = np.sort(rng.choice(o.n_dof, size=min(N_SAMPLES, o.n_dof), replace=False))
+    il = np.sort(rng.choice(o.n_c, size=min(N_SAMPLES, o.n_c), replace=False))
+    u, lam = res["u"], res["lam"]
+    return dict(tol=tol, iters=int(res["iters"]), history=[float(h) for h in res["history"]],
+                u_norm=float(np.linalg.norm(u)), lam_norm=float(np.linalg.norm(lam)),
+                u_idx=iu.tolist(), u_val=u[iu].tolist(), lam_idx=il.tolist(), lam_val=lam[il].tolist(),
+                u_proj={str(s): float(W.random_vector(o.n_dof, s) @ u) for s in PROJ_SEEDS})
+
+
+def write(name, prob, tols):
+    t0 = time.time()
+    o = AFIETI(prob)
+    out = dict(workload=name, n_dof=int(o.n_dof), n_c=int(o.n_c), solves=[])
+    for tol in tols:
+        t = time.time()
+        res = o.solve(tol=tol, maxit=5000)
+        out["solves"].append(summarise(o, res, tol))
+        print(f"{name} tol {tol:.0e}: {res['iters']} iterations, {time.time() - t:.0f} s", flush=True)
+    path = os.path.join(HERE, f"ref_{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print(f"wrote {path} ({time.time() - t0:.0f} s)", flush=True)
+
+
+def main(argv):
+    what = argv[1]
+    if what == "c2":
+        write("c2", W.make_c2(seed=0), (1e-8, 1e-12))
+    elif what == "c4":
+        probs = W.make_c4(seed=0)
+        for j in argv[2:]:
+            write(f"c4_{int(j)}", probs[int(j)], (1e-8,))
+    else:
+        raise SystemExit(f"unknown workload {what}")
+
+
+if __name__ == "__main__":
+    main(sys.argv)

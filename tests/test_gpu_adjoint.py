@@ -115,20 +115,45 @@ def test_autograd_function():
     assert np.abs(amps.grad.numpy() - g["damp"]).max() <= 1e-8 * np.abs(g["damp"]).max()
 
 
+def test_autograd_with_device_parameters():
+    """Parameters living on the GPU get their gradients on the GPU, with
+    the same values as for CPU parameters."""
+    torch = _torch()
+    from paper_2001_09626_amd import Solver, AfietiSolve, mass_norm_loss
+    prob = _small_c5(seed=4)
+    target = W.redraw_parameters(prob, seed=5)
+    u_t = _dev(torch, AFIETI(target).solve(tol=1e-13)["u"])
+    s = Solver(prob, tol=1e-13)
+    grads = []
+    for dev in ("cpu", "cuda"):
+        lame = torch.tensor([[p["lam"], p["mu"]] for p in prob["patches"]], dtype=torch.float64,
+                            device=dev, requires_grad=True)
+        amps = torch.tensor([m[1] for m in prob["load"]], dtype=torch.float64, device=dev, requires_grad=True)
+        J = mass_norm_loss(AfietiSolve(lame, amps, s) - u_t, s)
+        J.backward()
+        assert lame.grad.device.type == dev and amps.grad.device.type == dev
+        grads.append((lame.grad.cpu(), amps.grad.cpu()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+    s.close()
+
+
 def test_central_differences_full_c5():
     """Full adjoint workload (3x3x3 patches, 32^3 elements, p=3): adjoint
     gradient against central differences with step 1e-6 (relative for the
-    Lame parameters, absolute for the load amplitudes), forward solves at
-    tol 1e-12, for a few parameters."""
+    Lame parameters, absolute for the load amplitudes) for every Lame
+    parameter and eight load amplitudes, to 1e-6 relative.  The forward
+    solves run to tol 1e-13: with the step 1e-6 a relative error e of J
+    becomes an error of about e / 1e-6 in the difference quotient, and the
+    solves' own error, not the truncation (1e-12), sets the floor."""
     torch = _torch()
     from paper_2001_09626_amd import Solver
     prob = W.make_c5(seed=0)
     target = W.redraw_parameters(prob, seed=1)
     print("\n[c5 full: setup]", flush=True)
-    st_ = Solver(target, tol=1e-12)
+    st_ = Solver(target, tol=1e-13)
     u_t, _, _ = st_.solve(want_lambda=False)
     st_.close()
-    s = Solver(prob, tol=1e-12)
+    s = Solver(prob, tol=1e-13)
     lame0 = s.lame.copy()
     amps0 = s.amps.copy()
 
@@ -142,7 +167,9 @@ def test_central_differences_full_c5():
     Me = s.apply("mass", u0 - u_t)
     _, dlam, dmu, damp, its = s.solve_adjoint(Me, u0)
     print(f"  J={J0:.6e}  forward {st0['iterations']} it ({st0['ms']:.0f} ms), adjoint {its} it", flush=True)
-    checks = [("mu", 13), ("lam", 4), ("amp", 0), ("amp", 17)]
+    checks = [(kind, k) for k in range(len(prob["patches"])) for kind in ("lam", "mu")]
+    checks += [("amp", j) for j in range(0, 64, 8)]
+    worst = 0.0
     for kind, idx in checks:
         lp, lm = lame0.copy(), lame0.copy()
         ap, am = amps0.copy(), amps0.copy()
@@ -159,6 +186,8 @@ def test_central_differences_full_c5():
             ref = (dlam if kind == "lam" else dmu)[idx]
         fd = (J_of(lp, ap)[0] - J_of(lm, am)[0]) / (2 * h)
         rel = abs(ref - fd) / abs(fd)
+        worst = max(worst, rel)
         print(f"  d J / d {kind}[{idx}]: adjoint {ref:.9e}  central diff {fd:.9e}  rel {rel:.2e}", flush=True)
-        assert rel <= 1e-5
+        assert rel <= 1e-6
+    print(f"  worst relative difference {worst:.2e} over {len(checks)} parameters", flush=True)
     s.set_parameters(lame0, amps0)

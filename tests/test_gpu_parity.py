@@ -4,10 +4,14 @@ element.  FP64 operators to 1e-12 relative to the largest entry (sums of at
 most a few thousand products in a different order).
 
 Solves: at tolerance 1e-8 the GPU and the oracle take the same number of
-MINRES iterations and their iterates differ by less than a quarter of the
-iterate's own distance to the converged solution (the part of the error
-that rounding decides is much smaller than the part the tolerance leaves);
-at tolerance 1e-12 the two solutions agree to 1e-10 relative."""
+MINRES iterations (or one apart where the oracle's own stopping estimate
+sits within 10 % of the tolerance, tests/minres_band.py) and their iterates
+differ by less than a tenth of the iterate's own distance to the converged
+solution: the part of the error that rounding decides is much smaller than
+the part the tolerance leaves (measured: at most 0.035 of it, 5e-10
+relative after 259 iterations); at tolerance 1e-12 the two solutions agree
+to 1e-10 relative (measured: at most 2e-13) with iteration counts under the
+same rule."""
 import numpy as np
 import pytest
 
@@ -146,7 +150,7 @@ def test_solve_matches_oracle(pair):
           f"|u_or-u*| {own:.2e}, |lam-lam_or| {dl:.2e}", flush=True)
     assert st["converged"]
     assert same_iterations(st["iterations"], ref, 1e-8)
-    assert diff <= 0.25 * own and diff <= 1e-8
+    assert diff <= 0.1 * own and diff <= 1e-8
     assert dl <= 1e-7
 
 
@@ -161,7 +165,7 @@ def test_solve_tight_matches_oracle_1e10(pair):
     dl = np.linalg.norm(lam - ref["lam"]) / np.linalg.norm(ref["lam"])
     print(f"  tol 1e-12: iterations gpu {st['iterations']} oracle {ref['iters']}; rel diff u {diff:.2e} "
           f"lam {dl:.2e}", flush=True)
-    assert abs(st["iterations"] - ref["iters"]) <= 1
+    assert same_iterations(st["iterations"], ref, 1e-12)
     assert diff <= 1e-10 and dl <= 1e-9
     st_.close()
 
@@ -204,7 +208,7 @@ def test_solve_with_rhs(pair):
     own = np.linalg.norm(ref["u"] - tight["u"]) / nu
     print(f"  rhs: iterations {st['iterations']} / {ref['iters']}; diff {diff:.2e} own {own:.2e}")
     assert same_iterations(st["iterations"], ref, 1e-8)
-    assert diff <= 0.25 * own
+    assert diff <= 0.1 * own
 
 
 @pytest.mark.parametrize("case", ["c1_small", "c2_small"])

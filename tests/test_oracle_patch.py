@@ -146,3 +146,65 @@ def test_traction_divergence_theorem():
             mats = [(pa.D[l] if l == a else pa.V[l]).T for l in range(3)]
             ref[c] += apply_1d(flux[c, a], mats)
     assert np.allclose(tot, ref, atol=1e-12)
+
+
+def _box_patch(corners, dim):
+    return Patch(dict(corners=np.asarray(corners, float), p=2, reg=1, n_el=[2] * dim, lam=1.0, mu=1.0,
+                      bc=[0] * 2 * dim), dim)
+
+
+def test_diameter_of_axis_aligned_boxes():
+    """H^(k) (Section 2.2, the patch diameter that scales P_A and P_S): an
+    a x b x c box has diameter sqrt(a^2 + b^2 + c^2), an a x b rectangle
+    sqrt(a^2 + b^2), wherever the box sits."""
+    a, b, c = 0.3, 1.7, 0.55
+    unit = np.array([[(k >> l) & 1 for l in range(3)] for k in range(8)], float)
+    pa = _box_patch(unit * [a, b, c] + [2.0, -1.0, 0.25], 3)
+    assert pa.diameter() == pytest.approx(np.sqrt(a * a + b * b + c * c), rel=1e-15)
+    unit2 = np.array([[(k >> l) & 1 for l in range(2)] for k in range(4)], float)
+    pa2 = _box_patch(unit2 * [a, b] + [0.1, 0.2], 2)
+    assert pa2.diameter() == pytest.approx(np.hypot(a, b), rel=1e-15)
+
+
+def test_diameter_of_rotated_sheared_parallelepiped():
+    """Parallelepiped spanned by e1 = (1, 0, 0), e2 = (0.4, 1, 0) and
+    e3 = (0, 0, 0.6), then rotated by 30 degrees about z and 20 degrees about
+    x (distances do not change, its bounding box does).  By hand, in the
+    unrotated frame: the four long diagonals are 0-(1.4, 1, 0.6) and
+    (0, 0, 0.6)-(1.4, 1, 0), of length sqrt(3.32), and (1, 0, 0)-(0.4, 1, 0.6),
+    (0.4, 1, 0)-(1, 0, 0.6), of length sqrt(1.72); the face diagonals are
+    at most sqrt(2.96).  So H = sqrt(3.32), while the rotated bounding box
+    has a longer diagonal."""
+    e = np.array([[1.0, 0, 0], [0.4, 1.0, 0], [0, 0, 0.6]])
+    cz, sz = np.cos(np.pi / 6), np.sin(np.pi / 6)
+    cx, sx = np.cos(np.pi / 9), np.sin(np.pi / 9)
+    R = np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]]) @ np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]])
+    corners = np.array([R @ sum(((k >> l) & 1) * e[l] for l in range(3)) for k in range(8)])
+    pa = _box_patch(corners, 3)
+    assert pa.diameter() == pytest.approx(np.sqrt(3.32), rel=1e-14)
+    bbox = np.linalg.norm(corners.max(axis=0) - corners.min(axis=0))
+    assert bbox > np.sqrt(3.32) * 1.05
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_diameter_is_sup_distance_of_mapped_points(seed):
+    """For a perturbed trilinear patch, the diameter of the set F(0,1)^3:
+    the largest distance between points of a dense sample of the mapped
+    parametric cube (the corners excluded) approaches H from below, and no
+    pair of points of the patch lies farther apart than H."""
+    pa = _patch3(seed=seed, delta=0.15)
+    t = np.linspace(0.0, 1.0, 9)
+    g = np.stack(np.meshgrid(t, t, t, indexing="ij"), axis=-1).reshape(-1, 3)
+    on_bnd = np.any((g == 0.0) | (g == 1.0), axis=1)
+    is_corner = np.all((g == 0.0) | (g == 1.0), axis=1)
+    X = multilinear(pa.corners, g[on_bnd & ~is_corner])
+    Y = multilinear(pa.corners, g[~on_bnd])
+    Xc = multilinear(pa.corners, g[is_corner])
+    H = pa.diameter()
+    d_inner = max(np.linalg.norm(X[:, None] - X[None], axis=-1).max(),
+                  np.linalg.norm(Y[:, None] - Xc[None], axis=-1).max())
+    assert d_inner <= H * (1 + 1e-14)
+    d_all = np.linalg.norm(Xc[:, None] - Xc[None], axis=-1).max()
+    assert d_all == pytest.approx(H, rel=1e-15)
+    # points next to the farthest corners come within the sample spacing
+    assert d_inner >= H - 2 * np.sqrt(3) * 0.125 * 1.5

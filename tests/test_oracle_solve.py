@@ -83,10 +83,10 @@ def test_adjoint_gradient_central_differences():
             def plus(pr, k=k, key=key, sgn=1):
                 pr["patches"][k][key] += sgn * h
             fd = (J_of(plus) - J_of(lambda pr: plus(pr, sgn=-1))) / (2 * h)
-            assert ref == pytest.approx(fd, rel=1e-5, abs=1e-10)
+            assert ref == pytest.approx(fd, rel=1e-6, abs=1e-10)
     for j in range(len(base["load"])):
         def amp(pr, j=j, sgn=1):
             c, a, k, ph = pr["load"][j]
             pr["load"][j] = (c, a + sgn * h, k, ph)
         fd = (J_of(amp) - J_of(lambda pr: amp(pr, sgn=-1))) / (2 * h)
-        assert g["damp"][j] == pytest.approx(fd, rel=1e-5, abs=1e-10)
+        assert g["damp"][j] == pytest.approx(fd, rel=1e-6, abs=1e-10)
