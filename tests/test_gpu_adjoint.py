@@ -141,10 +141,15 @@ def test_central_differences_full_c5():
     """Full adjoint workload (3x3x3 patches, 32^3 elements, p=3): adjoint
     gradient against central differences with step 1e-6 (relative for the
     Lame parameters, absolute for the load amplitudes) for every Lame
-    parameter and eight load amplitudes, to 1e-6 relative.  The forward
-    solves run to tol 1e-13: with the step 1e-6 a relative error e of J
-    becomes an error of about e / 1e-6 in the difference quotient, and the
-    solves' own error, not the truncation (1e-12), sets the floor."""
+    parameter and eight load amplitudes.  Per family (lambda, mu, load
+    amplitudes) the two gradient vectors agree to 1e-6 relative, and every
+    entry to 1e-6 of itself up to the rounding floor of the difference
+    quotient.  The forward solves run to tol 1e-13; what remains is the
+    rounding of J itself (a sum over 3.5 M products after the solves, with
+    error of order log2(N) eps |J| = 22 eps |J|), which the step h turns into
+    an absolute floor of 50 eps |J| / h in each quotient (measured: at most
+    11 eps |J| / h); it exceeds 1e-6 relative only for entries below
+    about 5e-5 of the largest."""
     torch = _torch()
     from paper_2001_09626_amd import Solver
     prob = W.make_c5(seed=0)
@@ -166,10 +171,10 @@ def test_central_differences_full_c5():
     J0, u0, st0 = J_of(lame0, amps0)
     Me = s.apply("mass", u0 - u_t)
     _, dlam, dmu, damp, its = s.solve_adjoint(Me, u0)
-    print(f"  J={J0:.6e}  forward {st0['iterations']} it ({st0['ms']:.0f} ms), adjoint {its} it", flush=True)
+    print(f"  J={J0:.9e}  forward {st0['iterations']} it ({st0['ms']:.0f} ms), adjoint {its} it", flush=True)
     checks = [(kind, k) for k in range(len(prob["patches"])) for kind in ("lam", "mu")]
     checks += [("amp", j) for j in range(0, 64, 8)]
-    worst = 0.0
+    fam = {"lam": [], "mu": [], "amp": []}
     for kind, idx in checks:
         lp, lm = lame0.copy(), lame0.copy()
         ap, am = amps0.copy(), amps0.copy()
@@ -185,9 +190,18 @@ def test_central_differences_full_c5():
             lm[idx, col] -= h
             ref = (dlam if kind == "lam" else dmu)[idx]
         fd = (J_of(lp, ap)[0] - J_of(lm, am)[0]) / (2 * h)
-        rel = abs(ref - fd) / abs(fd)
-        worst = max(worst, rel)
-        print(f"  d J / d {kind}[{idx}]: adjoint {ref:.9e}  central diff {fd:.9e}  rel {rel:.2e}", flush=True)
-        assert rel <= 1e-6
-    print(f"  worst relative difference {worst:.2e} over {len(checks)} parameters", flush=True)
+        fam[kind].append((ref, fd, h))
+        print(f"  d J / d {kind}[{idx}]: adjoint {ref:.9e}  central diff {fd:.9e}  "
+              f"abs {abs(ref - fd):.2e} rel {abs(ref - fd) / abs(fd):.2e}", flush=True)
+    eps = np.finfo(np.float64).eps
+    for kind, vals in fam.items():
+        g = np.array(vals)
+        err = np.abs(g[:, 0] - g[:, 1])
+        vec = np.linalg.norm(g[:, 0] - g[:, 1]) / np.linalg.norm(g[:, 1])
+        floor = 50 * eps * abs(J0) / g[:, 2]
+        excess = (err / (1e-6 * np.abs(g[:, 1]) + floor)).max()
+        print(f"  {kind}: |g_adj - g_fd| / |g_fd| = {vec:.2e}; max error / (1e-6 |fd| + 50 eps |J| / h) "
+              f"= {excess:.2f}; largest error {err.max():.2e}", flush=True)
+        assert vec <= 1e-6
+        assert excess <= 1.0
     s.set_parameters(lame0, amps0)
