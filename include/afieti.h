@@ -178,6 +178,23 @@ int afieti_get_offsets(const afieti_handle* h, int64_t* dof_off, int64_t* c_off)
 int afieti_apply_fd(afieti_handle* h, const double* r, double* z, void* stream);
 
 /*
+ * The same z = (P_A^inex)^{-1} r as afieti_apply_fd (same kernels, bitwise
+ * equal results), for callers that cannot allocate during the call: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  The FD intermediate tensor lives in a fixed device array of
+ * AFIETI_NOALLOC_SCRATCH_BYTES (8 MiB) per GPU, held until the process ends,
+ * instead of handle memory; the call allocates nothing (no hipMalloc, no
+ * hipFree, no allocating library routine).  The handle's device must be
+ * current.  Returns AFIETI_EUNSUPPORTED when the handle's intermediate
+ * (one FP64 entry per DOF for the FP64 precisions, one FP32 entry for the
+ * others) exceeds the array.  Every call on one GPU shares the array: calls
+ * that overlap in time on one GPU (other streams, threads or handles) race
+ * on it.  Nothing of a previous call's contents is read.
+ */
+#define AFIETI_NOALLOC_SCRATCH_BYTES (8 << 20)
+int afieti_apply_fd_noalloc(afieti_handle* h, const double* r, double* z, void* stream);
+
+/*
  * AF-IETI solve (Section 4): MINRES on the preconditioned projected saddle
  * system, then u = (I - R (G^T G)^{-1} G^T B) w and lambda = lambda_0 + chi.
  * rhs: device DOF vector, or NULL for the assembled body-force load.

@@ -62,6 +62,7 @@ struct afieti_handle {
     afieti_options opt{};
     std::string err;
     bool host_only = false;
+    int device = -1;                 // GPU the handle's memory lives on
     std::vector<void*> allocs;
     int64_t bytes = 0, stencil_bytes = 0;
     int n_probs = 0, n_patches = 0;
@@ -303,6 +304,13 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     Plan& pl = h->plan;
     const int np = (int)pl.patches.size();
     h->n_patches = np;
+    HIP_OK(hipGetDevice(&h->device));
+    {
+        // the fixed scratch array of afieti_apply_fd_noalloc: its device
+        // address on this GPU is resolved here, once per device
+        hipError_t e = hipSuccess;
+        if (!noalloc_scratch_acquire(&e)) HIP_OK(e);
+    }
     // ---- patch descriptors and univariate tables
     std::vector<double> ctrl, qval, qder, qw, qx, kband, mband;
     std::vector<int> qfirst, elf, ell;
@@ -754,7 +762,8 @@ void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_
                     y, use_h, bnd_in ? 1 : 0, bnd_out ? 1 : 0, h->mask, s);
 }
 
-void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s, int ln = 0) {
+// the launch precision code of the configured FD precision
+int fd_prec(const afieti_handle* h) {
     int prec = 0;
     switch (h->opt.fd_precision) {
         case AFIETI_FD_FP32: prec = 2; break;       // MFMA, FP32 operands
@@ -763,9 +772,24 @@ void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hi
         case AFIETI_FD_FP64_MFMA: prec = 4; break;  // MFMA, FP64
         default: prec = 0;                          // vector ALU, FP64 (measured faster)
     }
+    return prec;
+}
+
+// bytes of the FD intermediate tensor of a set in the configured precision
+int64_t fd_tmp_bytes(const afieti_handle* h, const FdSet& set) {
+    const int prec = fd_prec(h);
+    return set.tmp_elems * (int64_t)(prec == 0 || prec == 4 ? sizeof(double) : sizeof(float));
+}
+
+void op_fd_tmp(afieti_handle* h, const FdSet& set, const double* in, double* out, void* tmp, hipStream_t s) {
+    const int prec = fd_prec(h);
     const bool f64 = prec == 0 || prec == 4;
     launch_fd(prec, set.d_t, set.n_t, set.d_slabs, set.n_slabs, set.d_cols, set.n_cols, set.d_cols64, set.n_cols64,
-              f64 ? (const void*)h->d_u64 : (const void*)h->d_u32, h->d_dtab, in, out, h->lane[ln].fdtmp, h->mask, s);
+              f64 ? (const void*)h->d_u64 : (const void*)h->d_u32, h->d_dtab, in, out, tmp, h->mask, s);
+}
+
+void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s, int ln = 0) {
+    op_fd_tmp(h, set, in, out, h->lane[ln].fdtmp, s);
 }
 
 // out = P_chi y  (in place allowed)
@@ -1227,6 +1251,40 @@ int afieti_apply_fd(afieti_handle* h, const double* r, double* z, void* stream) 
     } catch (const SetupError& e) {
         return fail_with(h, e);
     }
+}
+
+int afieti_apply_fd_noalloc(afieti_handle* h, const double* r, double* z, void* stream) {
+    int c = need_device(h);
+    if (c) return c;
+    if (!r || !z || r == z) {
+        h->err = "apply_fd_noalloc needs distinct input and output";
+        return AFIETI_EINVAL;
+    }
+    const int64_t need = fd_tmp_bytes(h, h->fd_pa);
+    if (need > (int64_t)kNoAllocScratchBytes) {
+        h->err = "FD intermediate of " + std::to_string(need) + " bytes exceeds the fixed scratch of " +
+                 std::to_string(kNoAllocScratchBytes) + " bytes";
+        return AFIETI_EUNSUPPORTED;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != h->device) {
+        h->err = "apply_fd_noalloc must run with the handle's device current";
+        return AFIETI_EINVAL;
+    }
+    void* tmp = noalloc_scratch_ptr(dev);
+    if (!tmp) {
+        h->err = "fixed scratch not resolved on this device";
+        return AFIETI_EHIP;
+    }
+    // the passes write every intermediate entry before reading it: nothing
+    // of the previous call's contents is read
+    op_fd_tmp(h, h->fd_pa, r, z, tmp, (hipStream_t)stream);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        h->err = std::string("kernel launch: ") + hipGetErrorString(e);
+        return AFIETI_EHIP;
+    }
+    return AFIETI_OK;
 }
 
 int afieti_apply(afieti_handle* h, int op, const double* x, double* y, void* stream) {

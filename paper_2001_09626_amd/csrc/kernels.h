@@ -17,6 +17,17 @@ void launch_fd(int prec, const FdTensor* d_tensors, int n_tensors,
                const int2* d_cols64, int n_colblocks64, const void* u_table, const double* d_table,
                const double* in, double* out, void* tmp, const MinresState* mask, hipStream_t s);
 
+// ---- fixed scratch for callers that cannot allocate
+// Bytes of the file-scope device array that afieti_apply_fd_noalloc uses for
+// the FD intermediate tensor (one copy per GPU, held until the process ends).
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+// Resolve the array's device address on the current device (once per
+// device; later calls return the stored address).  Returns nullptr and sets
+// *err when the runtime call fails.
+void* noalloc_scratch_acquire(hipError_t* err);
+// The address resolved for `device` by an earlier acquire, or nullptr.
+void* noalloc_scratch_ptr(int device);
+
 // ---- setup kernels
 void launch_geometry(const DevPatch* dp, int k, const DevPatch& hp, const double* ctrl,
                      const double* qval, const double* qder, const int* qfirst, const double* qw,

@@ -17,6 +17,7 @@
 // identical.  No atomics.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "device.h"
@@ -1939,6 +1940,48 @@ void stiffness_t(const DevPatch* dp, const int4* rb, int nrb, const double* A, c
 }
 
 }  // namespace
+
+// ====================================================== fixed scratch array
+// FD intermediate tensor of afieti_apply_fd_noalloc: a file-scope device
+// array, so that the entry point calls no allocator.  In host code its name
+// is only a stand-in for the symbol: every host use goes through the device
+// address that hipGetSymbolAddress returns for the current device, kept per
+// device (each GPU holds its own copy of the array).
+__device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+}  // namespace
+
+void* noalloc_scratch_acquire(hipError_t* err) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && (dev < 0 || dev >= kMaxDevices)) e = hipErrorInvalidDevice;
+    if (e != hipSuccess) {
+        if (err) *err = e;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            if (err) *err = e;
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    if (err) *err = hipSuccess;
+    return g_scratch_ptr[dev];
+}
+
+void* noalloc_scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 // ======================================================== launch wrappers
 void launch_fd(int prec, const FdTensor* tens, int n_tensors, const int2* slabs, int n_slabs, const int2* cols,
