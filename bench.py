@@ -89,9 +89,26 @@ def fd_flops(solver_prob):
     return total
 
 
+def stiffness_alg_flops(prob):
+    """Algorithmic flops of one stiffness product A w: the assembled
+    operator's 2 flops per stored coefficient, each row (component, node)
+    coupling to the d (2p+1)^d coefficients of its stencil (Section 3, local
+    matrices): 2 d (2p+1)^d per DOF."""
+    if isinstance(prob, list):
+        return sum(stiffness_alg_flops(q) for q in prob)
+    d = prob["dim"]
+    total = 0
+    for pd in prob["patches"]:
+        N = 1
+        for e in pd["n_el"][:d]:
+            N *= e * (pd["p"] - pd["reg"]) + pd["reg"] + 1
+        total += d * N * 2 * d * (2 * pd["p"] + 1) ** d
+    return total
+
+
 def mf_flops(prob):
-    """Algorithmic FP64 flops of one matrix-free stiffness application
-    (sum-factorised quadrature, Section 3 bilinear form): per element brick
+    """FP64 flops the matrix-free stiffness kernel executes per application
+    (sum-factorised quadrature of the Section 3 bilinear form): per element brick
     of BE^3 elements with NB = BE + p basis functions and QB = BE (p + 1)
     Gauss points per direction, six univariate passes each way -- a
     multiply-add per Gauss point and supported basis function (p + 1 of
@@ -114,10 +131,23 @@ def mf_flops(prob):
     return total
 
 
-def cpu_baseline(prob, gpu_iters):
-    """The oracle, untouched, on the host: one MINRES iteration of the same
-    problem (saddle operator + preconditioner + the vector recurrences),
-    scaled by the GPU iteration count."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, gpu_iters, n_iters=2):
+    """The oracle, untouched, on the host: ``n_iters`` MINRES iterations of
+    the same problem (saddle operator, preconditioner, inner products and
+    vector updates as in the oracle's MINRES), timed and scaled by the GPU
+    iteration count (an extrapolated full solve); plus one full oracle solve
+    of the small 2D workload (C1), timed end to end."""
     import numpy as np
     from threadpoolctl import threadpool_info
     import workloads as W
@@ -126,18 +156,24 @@ def cpu_baseline(prob, gpu_iters):
     x = W.random_vector(o.n_dof + o.n_c, 5)
     o.apply_op(x)  # geometry tables (setup, not timed)
     t0 = time.perf_counter()
-    q = o.apply_op(x)
-    z = o.apply_prec(q)
-    d = float(q @ x) + float(z @ q)
-    v = q - 0.5 * x - 0.25 * z
-    x = x + 1e-3 * v + d * 0.0
-    t1 = time.perf_counter()
-    per_it = t1 - t0
-    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    return dict(value=per_it * gpu_iters, unit="s", cores=threads, kind="oracle",
-                sample=f"one MINRES iteration of the oracle on this workload ({per_it:.2f} s: saddle "
-                       f"operator, preconditioner, dots, updates), x {gpu_iters} iterations",
-                per_iteration_s=per_it)
+    for _ in range(n_iters):
+        q = o.apply_op(x)
+        z = o.apply_prec(q)
+        d = float(q @ x) + float(z @ q)
+        v = q - 0.5 * x - 0.25 * z
+        x = x + 1e-3 * v + d * 0.0
+    per_it = (time.perf_counter() - t0) / n_iters
+    blas = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    oc1 = AFIETI(W.make_c1(seed=0))
+    t0 = time.perf_counter()
+    r1 = oc1.solve(tol=1e-8)
+    c1_s = time.perf_counter() - t0
+    return dict(value=per_it * gpu_iters, unit="s", cores=blas, kind="oracle",
+                sample=f"{n_iters} MINRES iterations of the oracle on this workload ({per_it:.2f} s each: saddle "
+                       f"operator, preconditioner, dots, updates), x {gpu_iters} iterations (extrapolated)",
+                extrapolated=True, per_iteration_s=per_it, nproc=os.cpu_count(), cpu_model=_cpu_model(),
+                threads="BLAS threads (dense FD products); the quadrature and sparse products run on one thread",
+                c1_full_solve_s=c1_s, c1_iterations=int(r1["iters"]))
 
 
 def main():
@@ -223,25 +259,63 @@ def main():
             out["fd_apply_frac_fp32_mfma_peak"] = flops / (ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS
         log(f"FD apply {name}: {ms*1e3:.1f} us, {s.n_dof/(ms*1e-3)/1e9:.2f} GDOF/s")
 
-    # stiffness matvec: the dominant kernel of every MINRES iteration
+    # stiffness matvec: the dominant kernel of every MINRES iteration,
+    # timed with HIP events on the stream its kernels are launched on
     x = torch.from_numpy(W.random_vector(s32.n_dof, 4)).cuda()
     y = torch.empty_like(x)
     s32.apply("stiffness", x, y)
     mv_ms = time_events(lambda: s32.apply("stiffness", x, y), args.mv_reps)
+    alg = stiffness_alg_flops(prob)
     if s32.stiffness_bytes == 0:
-        # matrix-free: bound by FP64 vector arithmetic
-        mv_flops = mf_flops(prob)
-        tfs = mv_flops / (mv_ms * 1e-3) / 1e12
-        log(f"stiffness matvec (matrix-free): {mv_ms:.3f} ms, {tfs:.2f} TFLOP/s FP64")
+        # matrix-free: bound by FP64 vector arithmetic; achieved counts the
+        # method's algorithmic flops (2 d (2p+1)^d per DOF), the flops the
+        # quadrature kernel executes are reported beside them
+        impl = mf_flops(prob)
+        tfs = alg / (mv_ms * 1e-3) / 1e12
+        log(f"stiffness matvec (matrix-free): {mv_ms:.3f} ms, {tfs:.2f} TFLOP/s algorithmic FP64, "
+            f"{impl / (mv_ms * 1e-3) / 1e12:.2f} TFLOP/s executed")
         roof = dict(bound="alu", achieved=tfs, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s", frac=tfs / FP64_PEAK_TFLOPS,
                     traffic=MEASURED_TRAFFIC.get(args.workload), kernel="stiffness operator: k_mf_brick + k_mf_gather",
-                    flops_per_launch=mv_flops, ms_per_launch=mv_ms)
+                    flops_per_launch=alg, ms_per_launch=mv_ms,
+                    executed_flops_per_launch=impl,
+                    executed_tflops=impl / (mv_ms * 1e-3) / 1e12,
+                    executed_frac=impl / (mv_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                    algorithmic_bytes=16 * s32.n_dof,
+                    note="achieved = 2 d (2p+1)^d flops per DOF (assembled-operator count) / time; "
+                         "executed = the quadrature kernel's own flops")
     else:
         mv_bytes = s32.stiffness_bytes + 2 * 8 * s32.n_dof
         gbs = mv_bytes / (mv_ms * 1e-3) / 1e9
         log(f"stiffness matvec (assembled): {mv_ms:.3f} ms, {gbs:.0f} GB/s")
         roof = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS,
-                    traffic=None, kernel="k_stiffness", bytes_per_launch=mv_bytes, ms_per_launch=mv_ms)
+                    traffic=None, kernel="k_stiffness", bytes_per_launch=mv_bytes, ms_per_launch=mv_ms,
+                    flops_per_launch=alg)
+
+    # FD apply against the FP32 matrix-core peak (4 d n flops per DOF)
+    fd_roof = None
+    if "fd_apply_ms_fp32" in out:
+        a = flops / (out["fd_apply_ms_fp32"] * 1e-3) / 1e12
+        fd_roof = dict(bound="mfma", achieved=a, peak=FP32_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                       frac=a / FP32_MFMA_PEAK_TFLOPS, kernel="FD apply, FP32 on the matrix cores",
+                       flops_per_launch=flops, ms_per_launch=out["fd_apply_ms_fp32"],
+                       algorithmic_bytes=16 * s32.n_dof)
+
+    # jump operator and projection: bandwidth-bound, algorithmic bytes of
+    # their index and value streams
+    bx = s32.export("B")
+    nnz = int(len(bx) + np.count_nonzero(bx[:, 2] >= 0))
+    c = torch.from_numpy(W.random_vector(s32.n_c, 6)).cuda()
+    yc = torch.empty_like(c)
+    jump = {}
+    for name, src, dst, nbytes in (
+            ("B", x, yc, s32.n_c * (8 + 8 + 8) + nnz * 8),          # plus/minus index, x values, y
+            ("Bt", c, y, (s32.n_dof + 1) * 8 + nnz * (4 + 8 + 8) + s32.n_dof * 8),  # CSR ptr, (row, sign, x), y
+            ("P_u", x, y, s32.n_dof * (8 + 8 + 8 + 8))):            # x twice, control points, y
+        s32.apply(name, src, dst)
+        ms = time_events(lambda: s32.apply(name, src, dst), args.mv_reps)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        jump[name] = dict(ms=ms, bytes=nbytes, gbs=gbs, frac=gbs / HBM_PEAK_GBS)
+        log(f"{name}: {ms * 1e3:.1f} us, {gbs:.0f} GB/s ({100 * gbs / HBM_PEAK_GBS:.1f} % of HBM)")
 
     cpu = None
     if not args.no_cpu_baseline and args.workload != "c4":
@@ -269,6 +343,8 @@ def main():
         "fp32_fd_solve_s": ms32 / 1e3,
         **out,
         "roofline": roof,
+        "fd_roofline": fd_roof,
+        "jump_hbm": jump,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -57,15 +57,14 @@ extern "C" {
 #define AFIETI_FACE_DIRICHLET 1  /* homogeneous Dirichlet u = 0              */
 
 /* precision of the FD mode products (Section 5.2.1, Algorithm 1); the
- * Krylov vectors, residuals and projections are always FP64.  FP32 and BF16
- * run on the matrix cores with FP32 accumulation; FP64 runs on the vector
- * ALU (measured faster than FP64 on the matrix cores at these sizes, which
- * FP64_MFMA selects); FP32_VALU is the FP32 vector-ALU path. */
+ * Krylov vectors, residuals and projections are always FP64.  FP64, FP32
+ * and BF16 run on the matrix cores (FP32 accumulation for BF16);
+ * FP64_VALU and FP32_VALU are the vector-ALU paths. */
 #define AFIETI_FD_FP64 0
 #define AFIETI_FD_FP32 1
 #define AFIETI_FD_BF16 2
 #define AFIETI_FD_FP32_VALU 3
-#define AFIETI_FD_FP64_MFMA 4
+#define AFIETI_FD_FP64_VALU 4
 
 /* choice of P_S: non-redundant inexact (Remark 1, default) or plain
  * inexact (Section 5.2, eq. inexact_SP) */
@@ -126,6 +125,15 @@ typedef struct {
                             and later solves use the faster;
                             0: enqueue kernels one by one                  */
     int stiffness;       /* AFIETI_STIFFNESS_*                             */
+    int fd_tune;         /* launch shape of the matrix-core FD kernels
+                            (FP64, FP32, BF16): -1 = autotune at setup
+                            (every shape timed on the handle's tensors, the
+                            choice kept per tensor shapes for the process),
+                            0..3 = fixed: layout (0 the d components of a
+                            patch together, 1 one per workgroup) * 2 +
+                            (0: 64, 1: 128 columns per block of the mode-3
+                            pass).  All shapes give bitwise identical
+                            results.                                       */
 } afieti_options;
 
 typedef struct {

@@ -78,7 +78,7 @@ class Solver:
     """One handle over one or more independent problems."""
 
     def __init__(self, problems, tol=1e-8, maxit=5000, fd_precision="fp64", ps_variant="nr",
-                 check_every=12, host_only=False, use_graph=True, stiffness="auto"):
+                 check_every=12, host_only=False, use_graph=True, stiffness="auto", fd_tune=-1):
         L = N.lib()
         self._L = L
         arr, keep = to_c_problems(problems)
@@ -92,6 +92,7 @@ class Solver:
         opt.host_only = 1 if host_only else 0
         opt.use_graph = 1 if use_graph else 0
         opt.stiffness = N.STIFFNESS[stiffness]
+        opt.fd_tune = int(fd_tune)
         self.host_only = host_only
         h = C.c_void_p()
         stream = C.c_void_p(0) if host_only else _stream()

@@ -13,7 +13,7 @@ NOT_CONVERGED = 1
 ERRORS = {-1: "EINVAL", -2: "EGEOM", -3: "ESINGULAR", -4: "EBREAKDOWN",
           -5: "ENOMEM", -6: "EHIP", -7: "EUNSUPPORTED"}
 
-FD_PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "fp32_valu": 3, "fp64_mfma": 4}
+FD_PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "fp32_valu": 3, "fp64_valu": 4}
 PS_VARIANT = {"nr": 0, "plain": 1}
 STIFFNESS = {"auto": 0, "assembled": 1, "matrix_free": 2}
 
@@ -42,7 +42,7 @@ class Problem(C.Structure):
 class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("fd_precision", C.c_int),
                 ("ps_variant", C.c_int), ("check_every", C.c_int), ("host_only", C.c_int),
-                ("use_graph", C.c_int), ("stiffness", C.c_int)]
+                ("use_graph", C.c_int), ("stiffness", C.c_int), ("fd_tune", C.c_int)]
 
 
 class Info(C.Structure):

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -47,12 +48,17 @@ struct Lane {           // scratch of one concurrent branch
 };
 
 struct FdSet {          // tensors of one FD operator (P_A or interior)
-    FdTensor* d_t = nullptr;
+    FdTensor* d_t = nullptr;   // one per (patch, component): vector-ALU kernels
     int2* d_slabs = nullptr;
     int2* d_cols = nullptr;    // 32-column blocks (VALU pass 2)
-    int2* d_cols64 = nullptr;  // 64-column blocks (MFMA pass 2)
-    int n_t = 0, n_slabs = 0, n_cols = 0, n_cols64 = 0;
+    int n_t = 0, n_slabs = 0, n_cols = 0;
     int64_t tmp_elems = 0;
+    // matrix-core kernels: groups of the d components of a patch (layout 0)
+    // or one component per group (layout 1)
+    FdGroupSet gs[2];
+    FdGroup* d_groups[2] = {nullptr, nullptr};
+    std::vector<FdGroup> h_groups[2];
+    int tune = 0;              // chosen layout * kFdVariants + variant
 };
 
 }  // namespace
@@ -217,36 +223,51 @@ void add_chunks(std::vector<Chunk>& out, int64_t b, int64_t e, int seg, int size
 void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector<int>& u_off,
                   const std::vector<int>& d_off, hipStream_t s) {
     std::vector<FdTensor> ts;
-    std::vector<int2> slabs, cols, cols64;
+    std::vector<int2> slabs, cols;
+    std::vector<FdGroup> groups[2];
+    std::vector<int2> gslabs[2], gcols64[2], gcols128[2];
     int64_t tmp = 0;
     for (size_t k = 0; k < h->plan.patches.size(); ++k) {
         const PatchPlan& P = h->plan.patches[k];
         const int dim = P.dim;
+        int sh[3], off[3];
+        for (int m = 0; m < 3; ++m) {
+            bool active = m < dim;
+            sh[m] = interior && active ? P.n[m] - 2 : P.n[m];
+            off[m] = interior && active ? 1 : 0;
+        }
+        const int64_t n123 = (int64_t)sh[0] * sh[1] * sh[2];
+        const int64_t base0 = P.dof_off + off[0] + (int64_t)off[1] * P.n[0] + (int64_t)off[2] * P.n[0] * P.n[1];
+        FdGroup g{};
+        g.in_off = g.out_off = base0;
+        g.cstride = P.nodes;
+        g.tmp_off = tmp;
+        g.n1 = sh[0];
+        g.n2 = sh[1];
+        g.n3 = sh[2];
+        g.nc = dim;
+        g.s2 = P.n[0];
+        g.s3 = P.n[0] * P.n[1];
         for (int l = 0; l < dim; ++l) {
             FdTensor t{};
-            int sh[3], off[3];
-            for (int m = 0; m < 3; ++m) {
-                bool active = m < dim;
-                sh[m] = interior && active ? P.n[m] - 2 : P.n[m];
-                off[m] = interior && active ? 1 : 0;
-            }
             t.n1 = sh[0];
             t.n2 = sh[1];
             t.n3 = sh[2];
             t.s2 = P.n[0];
             t.s3 = P.n[0] * P.n[1];
-            int64_t base = P.dof_off + (int64_t)l * P.nodes + off[0] + (int64_t)off[1] * t.s2 + (int64_t)off[2] * t.s3;
-            t.in_off = base;
-            t.out_off = base;
+            t.in_off = t.out_off = base0 + (int64_t)l * P.nodes;
             t.tmp_off = tmp;
-            tmp += (int64_t)t.n1 * t.n2 * t.n3;
+            tmp += n123;
             for (int m = 0; m < 3; ++m) {
                 int idx = (int)k * 3 + m;
                 t.u_off[m] = u_off[idx * 2 + (interior ? 1 : 0)];
                 t.d_off[m] = d_off[idx * 2 + (interior ? 1 : 0)];
                 t.kappa[m] = (m == l) ? 2 * P.mu + P.lam : P.mu;
+                g.u_off[m] = t.u_off[m];
+                g.d_off[m] = t.d_off[m];
             }
             if (dim == 2) t.kappa[2] = 0.0;
+            for (int m = 0; m < 3; ++m) g.kappa[l][m] = t.kappa[m];
             t.scale = interior ? 1.0 : P.hscale;
             t.mass = interior ? 0.0 : 1.0;
             t.alpha = interior ? -1.0 : 1.0;
@@ -256,12 +277,40 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
             for (int i3 = 0; i3 < t.n3; ++i3) slabs.push_back(make_int2(ti, i3));
             int ncb = (t.n1 * t.n2 + 31) / 32;
             for (int cb = 0; cb < ncb; ++cb) cols.push_back(make_int2(ti, cb));
-            int ncb64 = (t.n1 * t.n2 + 63) / 64;
-            for (int cb = 0; cb < ncb64; ++cb) cols64.push_back(make_int2(ti, cb));
+        }
+        g.scale = interior ? 1.0 : P.hscale;
+        g.mass = interior ? 0.0 : 1.0;
+        g.alpha = interior ? -1.0 : 1.0;
+        g.prob = P.prob;
+        // layout 0: the patch's components together; layout 1: one each
+        for (int lay = 0; lay < 2; ++lay) {
+            for (int part = 0; part < (lay == 0 ? 1 : dim); ++part) {
+                FdGroup q = g;
+                if (lay == 1) {
+                    q.nc = 1;
+                    q.in_off = q.out_off = g.in_off + (int64_t)part * g.cstride;
+                    q.tmp_off = g.tmp_off + (int64_t)part * n123;
+                    for (int m = 0; m < 3; ++m) {
+                        q.kappa[0][m] = g.kappa[part][m];
+                        q.kappa[1][m] = q.kappa[2][m] = 0.0;
+                    }
+                }
+                const int gi = (int)groups[lay].size();
+                groups[lay].push_back(q);
+                for (int i3 = 0; i3 < q.n3; ++i3) gslabs[lay].push_back(make_int2(gi, i3));
+                const int ncol = q.nc * q.n1 * q.n2;
+                for (int cb = 0; cb < (ncol + 63) / 64; ++cb) gcols64[lay].push_back(make_int2(gi, cb));
+                for (int cb = 0; cb < (ncol + 127) / 128; ++cb) gcols128[lay].push_back(make_int2(gi, cb));
+            }
         }
     }
     if (set.d_t) {  // parameters changed: rewrite the descriptors in place
         HIP_OK(hipMemcpyAsync(set.d_t, ts.data(), ts.size() * sizeof(FdTensor), hipMemcpyHostToDevice, s));
+        for (int lay = 0; lay < 2; ++lay) {
+            set.h_groups[lay] = groups[lay];
+            HIP_OK(hipMemcpyAsync(set.d_groups[lay], set.h_groups[lay].data(), groups[lay].size() * sizeof(FdGroup),
+                                  hipMemcpyHostToDevice, s));
+        }
         HIP_OK(hipStreamSynchronize(s));
         return;
     }
@@ -272,8 +321,25 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
     set.d_t = h->upload(ts, s);
     set.d_slabs = h->upload(slabs, s);
     set.d_cols = h->upload(cols, s);
-    set.n_cols64 = (int)cols64.size();
-    set.d_cols64 = h->upload(cols64, s);
+    for (int lay = 0; lay < 2; ++lay) {
+        FdGroupSet& G = set.gs[lay];
+        set.h_groups[lay] = groups[lay];
+        set.d_groups[lay] = h->upload(set.h_groups[lay], s);
+        G.groups = set.d_groups[lay];
+        G.slabs = h->upload(gslabs[lay], s);
+        G.cols64 = h->upload(gcols64[lay], s);
+        G.cols128 = h->upload(gcols128[lay], s);
+        G.n_groups = (int)groups[lay].size();
+        G.n_slabs = (int)gslabs[lay].size();
+        G.n_cols64 = (int)gcols64[lay].size();
+        G.n_cols128 = (int)gcols128[lay].size();
+        for (const FdGroup& q : groups[lay]) {
+            G.max_n1 = std::max(G.max_n1, q.n1);
+            G.max_n2 = std::max(G.max_n2, q.n2);
+            G.max_n3 = std::max(G.max_n3, q.n3);
+            G.max_nc = std::max(G.max_nc, q.nc);
+        }
+    }
 }
 
 // stiffness stencils of every patch (Gauss-point geometry, then assembly)
@@ -298,6 +364,63 @@ void combine_load(afieti_handle* h, hipStream_t s) {
         for (size_t m = 0; m < h->amps[j].size(); ++m)
             launch_axpby(h->amps[j][m], h->d_F[j] + (int64_t)m * pr.n_dof, 1.0, f, f, pr.n_dof, s);
     }
+}
+
+int fd_prec(const afieti_handle* h);
+void op_fd_tmp(afieti_handle* h, const FdSet& set, const double* in, double* out, void* tmp, hipStream_t s);
+
+constexpr int64_t kLdsBytes = 160 * 1024;  // LDS of one gfx950 compute unit
+
+// LDS bytes of a (layout, variant) choice of a set in the configured precision
+int64_t fd_choice_lds(const afieti_handle* h, const FdSet& set, int choice) {
+    return fd_lds_bytes(fd_prec(h) - 2, choice % kFdVariants, set.gs[choice / kFdVariants]);
+}
+
+// FD autotuner: the launch shape of the matrix-core FD kernels (layout of
+// the components x mode-3 column block), chosen by
+// timing every choice that fits the LDS on this handle's tensors.  All
+// choices give bitwise identical results.  Choices are kept for the
+// process per (precision, tensor shapes), so handles of the same shapes
+// reuse them.
+int tune_fd(afieti_handle* h, FdSet& set, const double* in, double* out, hipStream_t s) {
+    static std::mutex mu;
+    static std::map<std::string, int> cache;
+    std::string key = std::to_string(fd_prec(h)) + ":";
+    for (const FdGroup& g : set.h_groups[0])
+        key += std::to_string(g.n1) + "," + std::to_string(g.n2) + "," + std::to_string(g.n3) + "," +
+               std::to_string(g.nc) + ";";
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    int best = -1;
+    float best_ms = 0;
+    for (int c = 0; c < 2 * kFdVariants; ++c) {
+        if (fd_choice_lds(h, set, c) > kLdsBytes) continue;
+        set.tune = c;
+        op_fd_tmp(h, set, in, out, h->d_fdtmp, s);  // warm-up
+        HIP_OK(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r) op_fd_tmp(h, set, in, out, h->d_fdtmp, s);
+        HIP_OK(hipEventRecord(e1, s));
+        HIP_OK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+        if (best < 0 || ms < best_ms) {
+            best = c;
+            best_ms = ms;
+        }
+    }
+    HIP_OK(hipEventDestroy(e0));
+    HIP_OK(hipEventDestroy(e1));
+    HIP_OK(hipGetLastError());
+    if (best < 0) throw SetupError{AFIETI_EUNSUPPORTED, "FD tensors too large for the matrix-core kernels' LDS"};
+    std::lock_guard<std::mutex> lock(mu);
+    cache[key] = best;
+    return best;
 }
 
 void device_setup(afieti_handle* h, hipStream_t s) {
@@ -687,6 +810,19 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     HIP_OK(hipEventCreateWithFlags(&h->ev_ps, hipEventDisableTiming));
     HIP_OK(hipEventCreate(&h->ev_t0));
     HIP_OK(hipEventCreate(&h->ev_t1));
+    if (fd_prec(h) >= 2) {
+        // matrix-core FD: launch shapes from the options or the autotuner
+        for (FdSet* set : {&h->fd_pa, &h->fd_int}) {
+            if (h->opt.fd_tune >= 0) {
+                if (h->opt.fd_tune >= 2 * kFdVariants || fd_choice_lds(h, *set, h->opt.fd_tune) > kLdsBytes)
+                    throw SetupError{AFIETI_EUNSUPPORTED, "FD launch shape does not fit these tensors"};
+                set->tune = h->opt.fd_tune;
+            } else {
+                launch_fill(h->s1, 1.0, h->n_dof, s);
+                set->tune = tune_fd(h, *set, h->s1, h->s2, s);
+            }
+        }
+    }
     HIP_OK(hipStreamSynchronize(s));
     HIP_OK(hipGetLastError());
 }
@@ -766,11 +902,11 @@ void op_ahat(afieti_handle* h, const double* x, double* y, int use_h, hipStream_
 int fd_prec(const afieti_handle* h) {
     int prec = 0;
     switch (h->opt.fd_precision) {
-        case AFIETI_FD_FP32: prec = 2; break;       // MFMA, FP32 operands
-        case AFIETI_FD_BF16: prec = 3; break;       // MFMA, BF16 operands
+        case AFIETI_FD_FP32: prec = 2; break;       // matrix cores, FP32 operands
+        case AFIETI_FD_BF16: prec = 3; break;       // matrix cores, BF16 operands
         case AFIETI_FD_FP32_VALU: prec = 1; break;  // vector ALU, FP32
-        case AFIETI_FD_FP64_MFMA: prec = 4; break;  // MFMA, FP64
-        default: prec = 0;                          // vector ALU, FP64 (measured faster)
+        case AFIETI_FD_FP64_VALU: prec = 0; break;  // vector ALU, FP64
+        default: prec = 4;                          // matrix cores, FP64
     }
     return prec;
 }
@@ -781,11 +917,18 @@ int64_t fd_tmp_bytes(const afieti_handle* h, const FdSet& set) {
     return set.tmp_elems * (int64_t)(prec == 0 || prec == 4 ? sizeof(double) : sizeof(float));
 }
 
+// FD launch: the vector-ALU kernels per tensor (FP64, FP32 VALU) or the
+// matrix-core kernels per group in the tuned layout and launch shape
 void op_fd_tmp(afieti_handle* h, const FdSet& set, const double* in, double* out, void* tmp, hipStream_t s) {
     const int prec = fd_prec(h);
     const bool f64 = prec == 0 || prec == 4;
-    launch_fd(prec, set.d_t, set.n_t, set.d_slabs, set.n_slabs, set.d_cols, set.n_cols, set.d_cols64, set.n_cols64,
-              f64 ? (const void*)h->d_u64 : (const void*)h->d_u32, h->d_dtab, in, out, tmp, h->mask, s);
+    const void* ut = f64 ? (const void*)h->d_u64 : (const void*)h->d_u32;
+    if (prec >= 2)
+        launch_fd_groups(prec - 2, set.tune % kFdVariants, set.gs[set.tune / kFdVariants], ut, h->d_dtab, in, out, tmp,
+                         h->mask, s);
+    else
+        launch_fd(prec, set.d_t, set.n_t, set.d_slabs, set.n_slabs, set.d_cols, set.n_cols, ut, h->d_dtab, in, out,
+                  tmp, h->mask, s);
 }
 
 void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s, int ln = 0) {
@@ -1149,6 +1292,7 @@ void afieti_default_options(afieti_options* opt) {
     opt->host_only = 0;
     opt->use_graph = 1;
     opt->stiffness = AFIETI_STIFFNESS_AUTO;
+    opt->fd_tune = -1;
 }
 
 const char* afieti_strerror(int code) {
@@ -1178,8 +1322,9 @@ int afieti_setup(const afieti_problem* probs, int n_problems, const afieti_optio
         if (opt) h->opt = *opt;
         else afieti_default_options(&h->opt);
         if (!(h->opt.tol > 0) || h->opt.maxit < 1 ||
-            (h->opt.fd_precision < AFIETI_FD_FP64 || h->opt.fd_precision > AFIETI_FD_FP64_MFMA) ||
-            (h->opt.ps_variant != AFIETI_PS_NR && h->opt.ps_variant != AFIETI_PS_PLAIN))
+            (h->opt.fd_precision < AFIETI_FD_FP64 || h->opt.fd_precision > AFIETI_FD_FP64_VALU) ||
+            (h->opt.ps_variant != AFIETI_PS_NR && h->opt.ps_variant != AFIETI_PS_PLAIN) ||
+            h->opt.fd_tune < -1 || h->opt.fd_tune >= 2 * kFdVariants)
             throw SetupError{AFIETI_EINVAL, "invalid options"};
         h->plan = build_plan(probs, n_problems);
         h->n_probs = (int)h->plan.probs.size();

@@ -50,6 +50,27 @@ struct FdTensor {
     int pad;
 };
 
+// The d component tensors of one patch in one FD operator (or their
+// interiors): they share the univariate eigenvectors U_m, so the matrix-core
+// FD kernels process them together.  Component c of the group starts at
+// in_off + c cstride (out_off + c cstride) in the FP64 vectors and at
+// tmp_off + c n1 n2 n3 in the intermediate buffer.
+struct FdGroup {
+    int64_t in_off, out_off;     // component 0 in the FP64 input / output vector
+    int64_t cstride;             // offset between components in the vectors
+    int64_t tmp_off;             // component 0 in the intermediate buffer
+    int n1, n2, n3, nc;          // tensor sizes, number of components
+    int s2, s3;                  // strides of directions 2 and 3 in the vectors
+    int u_off[3];                // U_m (n_m x n_m, U[i*n + a]) in the eigenvector table
+    int d_off[3];                // D_m in the eigenvalue table
+    double kappa[3][3];          // Kronecker coefficients kappa_{c,m} per component
+    double scale;                // (H^(k))^{d-2} for P_A, 1 for the interior solve
+    double mass;                 // 1 for P_A (mass term), 0 for the interior solve
+    double alpha;                // output = alpha * solution
+    int prob;                    // problem index (for the stop mask)
+    int pad;
+};
+
 struct Chunk {                   // contiguous range inside one segment
     int64_t begin, end;
     int seg;                     // patch or problem index

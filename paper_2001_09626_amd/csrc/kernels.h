@@ -7,15 +7,39 @@
 
 namespace afieti {
 
-// ---- Fast Diagonalization (Algorithm 1): three passes over the tensors.
-// Kernels of problems whose MINRES has
-// stopped (mask[prob].stop != 0) return at once; mask may be NULL.
-// prec 0: FP64 (VALU); 1: FP32 (VALU); 2: FP32 on MFMA; 3: BF16 on MFMA (FP32
-// accumulation); 4: FP64 on MFMA.  d_cols: 32-column blocks (VALU), d_cols64: 64-column blocks (MFMA).
+// ---- Fast Diagonalization (Algorithm 1) on the vector ALU: three passes
+// over the tensors.  Kernels of problems whose MINRES has stopped
+// (mask[prob].stop != 0) return at once; mask may be NULL.  prec 0: FP64;
+// 1: FP32.  d_cols: 32-column blocks of the mode-3 pass.
 void launch_fd(int prec, const FdTensor* d_tensors, int n_tensors,
                const int2* d_slabs, int n_slabs, const int2* d_cols, int n_colblocks,
-               const int2* d_cols64, int n_colblocks64, const void* u_table, const double* d_table,
+               const void* u_table, const double* d_table,
                const double* in, double* out, void* tmp, const MinresState* mask, hipStream_t s);
+
+// ---- Fast Diagonalization on the matrix cores (fd.hip): the d component
+// tensors of a patch (a group) share U_m and are transformed together (or
+// one per group, the per-component layout).  Device lists: slabs (group,
+// i3), column blocks (group, block) of 64 and of 128 columns.
+struct FdGroupSet {
+    const FdGroup* groups = nullptr;
+    const int2* slabs = nullptr;
+    const int2* cols64 = nullptr;
+    const int2* cols128 = nullptr;
+    int n_groups = 0, n_slabs = 0, n_cols64 = 0, n_cols128 = 0;
+    int max_n1 = 1, max_n2 = 1, max_n3 = 1, max_nc = 1;
+};
+// launch shapes the autotuner picks from (bitwise identical results): per
+// layout, variant 0 or 1 = 64 or 128 columns per mode-3 block
+constexpr int kFdVariants = 2;
+int fd_variant_ncb(int variant);
+// compile-time depth extent (28, 36 or 48) the kernels use for a set
+int fd_depth_extent(const FdGroupSet& set);
+// LDS bytes of the larger pass of a set for a variant
+int64_t fd_lds_bytes(int mode, int variant, const FdGroupSet& set);
+// mode 0: FP32 operands, 1: BF16 operands (FP32 accumulation), 2: FP64.
+// tmp holds one FP32 (FP64 for mode 2) entry per tensor element.
+void launch_fd_groups(int mode, int variant, const FdGroupSet& set, const void* ut, const double* dt,
+                      const double* in, double* out, void* tmp, const MinresState* mask, hipStream_t s);
 
 // ---- fixed scratch for callers that cannot allocate
 // Bytes of the file-scope device array that afieti_apply_fd_noalloc uses for

@@ -1,8 +1,9 @@
 // HIP kernels of the inexact AF-IETI hot path for gfx950 (wave64).
 //
-//  * FD (Algorithm 1 of Section 5.2.1): mode products with the univariate
-//    generalised eigenvectors in three passes (modes 1+2 per slab, mode 3
-//    with the eigenvalue divide fused, modes 2+1 per slab), tiles in LDS.
+//  * FD (Algorithm 1 of Section 5.2.1) on the vector ALU (FP64, FP32): mode
+//    products with the univariate generalised eigenvectors in three passes
+//    (modes 1+2 per slab, mode 3 with the eigenvalue divide fused, modes 2+1
+//    per slab), tiles in LDS; the matrix-core variants are in fd.hip.
 //  * stiffness stencil assembly (Gauss quadrature of the bilinear form of
 //    Section 3) and the matrix-vector product with the assembled stencil,
 //    with B^T t fused into its epilogue (first block row of the projected
@@ -198,287 +199,6 @@ __global__ void __launch_bounds__(kFdBlock) k_fd_bwd12(const FdTensor* __restric
         for (int a2 = 0; a2 < n2; ++a2) acc += U[i2 * n2 + a2] * Y[a2 * n1 + i1];
         dst[(int64_t)i2 * t.s2 + i1] = t.alpha * (double)acc;
     }
-}
-
-// ================================================== FD on MFMA (FP32, BF16)
-// The same three passes with the slab and column GEMMs on the matrix cores:
-// v_mfma_f32_16x16x4_f32 (FP32 operands) or v_mfma_f32_16x16x32_bf16 (BF16
-// operands), FP32 accumulation.  Operand tiles are staged in LDS, zero
-// padded to multiples of 16 (rows/columns) and of the MFMA depth K, so the
-// inner loops carry no bounds checks.  Lane layout (wave64): A element
-// (row l%16, k-group l/16), B element (k-group l/16, column l%16), result
-// rows 4(l/16)+r, column l%16 in accumulator register r.
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-constexpr int kNP = 48;       // padded tile rows/columns (n <= 48)
-constexpr int kLD = kNP + 4;  // LDS leading dimension (bank spread)
-
-// MODE 0: FP32 operands (v_mfma_f32_16x16x4_f32), 1: BF16 operands
-// (v_mfma_f32_16x16x32_bf16), 2: FP64 (v_mfma_f64_16x16x4_f64).  Result row
-// of accumulator register q in lane group g: 4g + q (FP32 accumulators) or
-// g + 4q (FP64 accumulators).
-template <int MODE>
-struct MfmaK {
-    static constexpr int K = MODE == 1 ? 32 : 4;    // depth of one instruction
-    static constexpr int KP = MODE == 1 ? 64 : kNP; // padded depth of a 48-wide contraction
-    using T = typename std::conditional<MODE == 0, float, typename std::conditional<MODE == 1, __bf16, double>::type>::type;
-    using Acc = typename std::conditional<MODE == 2, doublex4, floatx4>::type;
-    using Tmp = typename std::conditional<MODE == 2, double, float>::type;  // between passes
-    using U = typename std::conditional<MODE == 2, double, float>::type;    // eigenvector table
-    __device__ static inline int row(int g, int q) { return MODE == 2 ? g + 4 * q : 4 * g + q; }
-};
-
-// C tile (16x16 at rows m0, cols n0) = sum_{k < KP} A(m, k) B(k, n) with
-// A(m, k) = At ? a[k * lda + m] : a[m * lda + k], B(k, n) = Bt ? b[n * ldb + k] : b[k * ldb + n].
-// The depth is the padded KP of the mode (operands zero beyond the true
-// size), so the loop unrolls and every operand read is issued before the
-// chain of matrix instructions.
-template <int MODE, bool At, bool Bt>
-__device__ inline typename MfmaK<MODE>::Acc mfma_tile(const typename MfmaK<MODE>::T* __restrict__ a, int lda,
-                                                      const typename MfmaK<MODE>::T* __restrict__ b, int ldb, int m0,
-                                                      int n0) {
-    using M = MfmaK<MODE>;
-    constexpr int KP = M::KP, STEPS = KP / M::K;
-    const int lane = threadIdx.x & 63;
-    const int r = lane & 15, g = lane >> 4;
-    typename M::Acc acc = {0, 0, 0, 0};
-    if constexpr (MODE != 1) {
-        typename M::T av[STEPS], bv[STEPS];
-#pragma unroll
-        for (int s = 0; s < STEPS; ++s) {
-            const int k = 4 * s + g;
-            av[s] = At ? a[k * lda + m0 + r] : a[(m0 + r) * lda + k];
-            bv[s] = Bt ? b[(n0 + r) * ldb + k] : b[k * ldb + n0 + r];
-        }
-#pragma unroll
-        for (int s = 0; s < STEPS; ++s) {
-            if constexpr (MODE == 0) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc, 0, 0, 0);
-            else acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
-        }
-    } else {
-        bf16x8 av[STEPS], bv[STEPS];
-#pragma unroll
-        for (int s = 0; s < STEPS; ++s)
-#pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                const int k = 32 * s + 8 * g + v;
-                av[s][v] = At ? a[k * lda + m0 + r] : a[(m0 + r) * lda + k];
-                bv[s][v] = Bt ? b[(n0 + r) * ldb + k] : b[k * ldb + n0 + r];
-            }
-#pragma unroll
-        for (int s = 0; s < STEPS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[s], bv[s], acc, 0, 0, 0);
-    }
-    return acc;
-}
-
-// stage a rows x cols block (row stride src_ld in global) into LDS as T,
-// zero padded to prow x pcol (prow * pcol <= 4096) with leading
-// dimension ld; every global load of a thread is issued before its stores
-template <typename T, typename S>
-__device__ inline void stage(T* dst, int ld, int prow, int pcol, const S* src, int64_t src_ld, int rows, int cols) {
-    constexpr int IT = 4096 / kFdBlock;
-    const int total = prow * pcol;
-    S v[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int e = threadIdx.x + it * kFdBlock;
-        const int i = e / pcol, j = e - i * pcol;
-        v[it] = (e < total && i < rows && j < cols) ? src[(int64_t)i * src_ld + j] : (S)0;
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int e = threadIdx.x + it * kFdBlock;
-        if (e < total) {
-            const int i = e / pcol, j = e - i * pcol;
-            if constexpr (std::is_same<T, __bf16>::value)
-                dst[i * ld + j] = (T)(float)v[it];
-            else
-                dst[i * ld + j] = (T)v[it];
-        }
-    }
-}
-
-__device__ inline int pad16(int n) { return (n + 15) & ~15; }
-
-// Pass 1: Y = X U1 (rows i2, cols a1), Z = U2^T Y, per slab i3 -> tmp
-template <int MODE>
-__global__ void __launch_bounds__(kFdBlock) k_fdm_fwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
-                                                      const typename MfmaK<MODE>::U* __restrict__ ut,
-                                                      const double* __restrict__ in,
-                                                      typename MfmaK<MODE>::Tmp* __restrict__ tmp,
-                                                      const MinresState* __restrict__ mask) {
-    using M = MfmaK<MODE>;
-    using T = typename M::T;
-    constexpr int KP = M::KP;
-    constexpr int LDK = KP + 4;
-    __shared__ T X[kNP * LDK];      // [i2][i1]
-    __shared__ T Y[KP * kLD];       // [i2][a1]  (rows padded to the depth of the next GEMM)
-    __shared__ T U1[KP * kLD];      // [i1][a1]
-    __shared__ T U2[KP * kLD];      // [i2][a2]
-    const int2 it = slabs[blockIdx.x];
-    const FdTensor t = tens[it.x];
-    if (mask && mask[t.prob].stop) return;
-    const int i3 = it.y, n1 = t.n1, n2 = t.n2;
-    const int p1 = pad16(n1), p2 = pad16(n2);
-    stage(X, LDK, p2, KP, in + t.in_off + (int64_t)i3 * t.s3, t.s2, n2, n1);
-    stage(U1, kLD, KP, p1, ut + t.u_off[0], n1, n1, n1);
-    stage(U2, kLD, KP, p2, ut + t.u_off[1], n2, n2, n2);
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r = lane & 15, g = lane >> 4;
-    const int t1 = p1 / 16, tiles1 = (p2 / 16) * t1;
-    for (int tl = wave; tl < tiles1; tl += kFdBlock / 64) {
-        const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
-        auto acc = mfma_tile<MODE, false, false>(X, LDK, U1, kLD, m0, n0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Y[(m0 + M::row(g, q)) * kLD + n0 + r] = (T)acc[q];
-    }
-    for (int e = threadIdx.x; e < (KP - p2) * kLD; e += kFdBlock) Y[p2 * kLD + e] = (T)0.f;  // depth padding
-    __syncthreads();
-    typename M::Tmp* dst = tmp + t.tmp_off + (int64_t)i3 * n1 * n2;
-    const int tiles2 = (p2 / 16) * t1;
-    for (int tl = wave; tl < tiles2; tl += kFdBlock / 64) {
-        const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
-        auto acc = mfma_tile<MODE, true, false>(U2, kLD, Y, kLD, m0, n0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int a2 = m0 + M::row(g, q), a1 = n0 + r;
-            if (a2 < n2 && a1 < n1) dst[a2 * n1 + a1] = acc[q];
-        }
-    }
-}
-
-// Pass 2: per block of 64 columns c = (a2, a1): Zt = U3^T Zc, divide by Lambda,
-// W = U3 Zt, written back in place
-template <int MODE>
-__global__ void __launch_bounds__(kFdBlock) k_fdm_mid3(const FdTensor* __restrict__ tens, const int2* __restrict__ cols,
-                                                     const typename MfmaK<MODE>::U* __restrict__ ut,
-                                                     const double* __restrict__ dt,
-                                                     typename MfmaK<MODE>::Tmp* __restrict__ tmp,
-                                                     const MinresState* __restrict__ mask) {
-    using M = MfmaK<MODE>;
-    using T = typename M::T;
-    constexpr int NC = 64;
-    constexpr int KP = M::KP;
-    constexpr int LDC = NC + 4;
-    constexpr int LDU = KP + 4;  // U3 is read along both indices up to the depth KP
-    __shared__ T Zc[KP * LDC];   // [i3][c]
-    __shared__ T Zt[KP * LDC];   // [a3][c]
-    __shared__ T U3[KP * LDU];   // [i3][a3]
-    const int2 it = cols[blockIdx.x];
-    const FdTensor t = tens[it.x];
-    if (mask && mask[t.prob].stop) return;
-    const int n1 = t.n1, n3 = t.n3, n12 = t.n1 * t.n2;
-    const int p3 = pad16(n3);
-    const int col0 = it.y * NC;
-    typename M::Tmp* base = tmp + t.tmp_off;
-    {
-        constexpr int IT = KP * NC / kFdBlock;  // k3 <= KP
-        typename M::Tmp v[IT];
-#pragma unroll
-        for (int it = 0; it < IT; ++it) {
-            const int e = threadIdx.x + it * kFdBlock;
-            const int i3 = e / NC, c = e - i3 * NC, col = col0 + c;
-            v[it] = (i3 < n3 && col < n12) ? base[(int64_t)i3 * n12 + col] : (typename M::Tmp)0;
-        }
-#pragma unroll
-        for (int it = 0; it < IT; ++it) {
-            const int e = threadIdx.x + it * kFdBlock;
-            const int i3 = e / NC, c = e - i3 * NC;
-            Zc[i3 * LDC + c] = (T)v[it];
-        }
-    }
-    stage(U3, LDU, KP, KP, ut + t.u_off[2], n3, n3, n3);
-    for (int e = threadIdx.x; e < (KP - p3) * LDC; e += kFdBlock) Zt[p3 * LDC + e] = (T)0.f;
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r = lane & 15, g = lane >> 4;
-    const int tiles = (p3 / 16) * (NC / 16);
-    for (int tl = wave; tl < tiles; tl += kFdBlock / 64) {
-        const int m0 = (tl / (NC / 16)) * 16, n0 = (tl % (NC / 16)) * 16;
-        auto acc = mfma_tile<MODE, true, false>(U3, LDU, Zc, LDC, m0, n0);
-        const int col = col0 + n0 + r;
-        const int a2 = col / n1, a1 = col - a2 * n1;
-        double lam12 = 0.0;
-        if (col < n12) lam12 = t.mass + t.kappa[0] * dt[t.d_off[0] + a1] + t.kappa[1] * dt[t.d_off[1] + a2];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int a3 = m0 + M::row(g, q);
-            double v = 0.0;
-            if (a3 < n3 && col < n12) v = (double)acc[q] / (t.scale * (lam12 + t.kappa[2] * dt[t.d_off[2] + a3]));
-            Zt[a3 * LDC + n0 + r] = (T)v;
-        }
-    }
-    __syncthreads();
-    for (int tl = wave; tl < tiles; tl += kFdBlock / 64) {
-        const int m0 = (tl / (NC / 16)) * 16, n0 = (tl % (NC / 16)) * 16;
-        auto acc = mfma_tile<MODE, false, false>(U3, LDU, Zt, LDC, m0, n0);
-        const int col = col0 + n0 + r;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i3 = m0 + M::row(g, q);
-            if (i3 < n3 && col < n12) base[(int64_t)i3 * n12 + col] = acc[q];
-        }
-    }
-}
-
-// Pass 3: Y = Z U1^T (rows a2, cols i1), X = U2 Y, alpha X -> FP64 output
-template <int MODE>
-__global__ void __launch_bounds__(kFdBlock) k_fdm_bwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
-                                                      const typename MfmaK<MODE>::U* __restrict__ ut,
-                                                      const typename MfmaK<MODE>::Tmp* __restrict__ tmp,
-                                                      double* __restrict__ out, const MinresState* __restrict__ mask) {
-    using M = MfmaK<MODE>;
-    using T = typename M::T;
-    constexpr int KP = M::KP;
-    constexpr int LDK = KP + 4;
-    __shared__ T Z[kNP * LDK];     // [a2][a1]
-    __shared__ T Y[KP * kLD];      // [a2][i1]
-    __shared__ T U1[kNP * LDK];    // [i1][a1]
-    __shared__ T U2[kNP * LDK];    // [i2][a2]
-    const int2 it = slabs[blockIdx.x];
-    const FdTensor t = tens[it.x];
-    if (mask && mask[t.prob].stop) return;
-    const int i3 = it.y, n1 = t.n1, n2 = t.n2;
-    const int p1 = pad16(n1), p2 = pad16(n2);
-    stage(Z, LDK, p2, KP, tmp + t.tmp_off + (int64_t)i3 * n1 * n2, n1, n2, n1);
-    stage(U1, LDK, p1, KP, ut + t.u_off[0], n1, n1, n1);
-    stage(U2, LDK, p2, KP, ut + t.u_off[1], n2, n2, n2);
-    for (int e = threadIdx.x; e < (KP - p2) * kLD; e += kFdBlock) Y[p2 * kLD + e] = (T)0.f;
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r = lane & 15, g = lane >> 4;
-    const int t1 = p1 / 16, tiles = (p2 / 16) * t1;
-    for (int tl = wave; tl < tiles; tl += kFdBlock / 64) {
-        const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
-        auto acc = mfma_tile<MODE, false, true>(Z, LDK, U1, LDK, m0, n0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Y[(m0 + M::row(g, q)) * kLD + n0 + r] = (T)acc[q];
-    }
-    __syncthreads();
-    double* dst = out + t.out_off + (int64_t)i3 * t.s3;
-    for (int tl = wave; tl < tiles; tl += kFdBlock / 64) {
-        const int m0 = (tl / t1) * 16, n0 = (tl % t1) * 16;
-        auto acc = mfma_tile<MODE, false, false>(U2, LDK, Y, kLD, m0, n0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i2 = m0 + M::row(g, q), i1 = n0 + r;
-            if (i2 < n2 && i1 < n1) dst[(int64_t)i2 * t.s2 + i1] = t.alpha * (double)acc[q];
-        }
-    }
-}
-
-template <int MODE>
-void fdm_launch(const FdTensor* tens, const int2* slabs, int n_slabs, const int2* cols, int n_cols, const void* ut,
-                const double* dt, const double* in, double* out, void* tmp, const MinresState* mask, hipStream_t s) {
-    using M = MfmaK<MODE>;
-    const auto* u = static_cast<const typename M::U*>(ut);
-    auto* tp = static_cast<typename M::Tmp*>(tmp);
-    hipLaunchKernelGGL(k_fdm_fwd12<MODE>, dim3(n_slabs), dim3(kFdBlock), 0, s, tens, slabs, u, in, tp, mask);
-    hipLaunchKernelGGL(k_fdm_mid3<MODE>, dim3(n_cols), dim3(kFdBlock), 0, s, tens, cols, u, dt, tp, mask);
-    hipLaunchKernelGGL(k_fdm_bwd12<MODE>, dim3(n_slabs), dim3(kFdBlock), 0, s, tens, slabs, u, tp, out, mask);
 }
 
 // ============================================================ setup kernels
@@ -1985,13 +1705,10 @@ void* noalloc_scratch_ptr(int device) {
 
 // ======================================================== launch wrappers
 void launch_fd(int prec, const FdTensor* tens, int n_tensors, const int2* slabs, int n_slabs, const int2* cols,
-               int n_colblocks, const int2* cols64, int n_colblocks64, const void* ut, const double* dt,
-               const double* in, double* out, void* tmp, const MinresState* mask, hipStream_t s) {
+               int n_colblocks, const void* ut, const double* dt, const double* in, double* out, void* tmp,
+               const MinresState* mask, hipStream_t s) {
     (void)n_tensors;
-    if (prec >= 2) {
-        cols = cols64;
-        n_colblocks = n_colblocks64;
-    }
+    if (n_slabs == 0) return;
     if (prec == 0) {
         const size_t sh12 = 3 * kMaxN * kMaxN * sizeof(double);
         const size_t sh3 = (2 * kMaxN * 32 + kMaxN * kMaxN) * sizeof(double);
@@ -2001,11 +1718,6 @@ void launch_fd(int prec, const FdTensor* tens, int n_tensors, const int2* slabs,
                            (const double*)ut, dt, (double*)tmp, mask);
         hipLaunchKernelGGL(k_fd_bwd12<double>, dim3(n_slabs), dim3(kFdBlock), sh12, s, tens, slabs,
                            (const double*)ut, (const double*)tmp, out, mask);
-    } else if (prec == 2 || prec == 3 || prec == 4) {
-        // MFMA: 2 = FP32 operands, 3 = BF16 operands, 4 = FP64; 64-column blocks in pass 2
-        if (prec == 2) fdm_launch<0>(tens, slabs, n_slabs, cols, n_colblocks, ut, dt, in, out, tmp, mask, s);
-        else if (prec == 3) fdm_launch<1>(tens, slabs, n_slabs, cols, n_colblocks, ut, dt, in, out, tmp, mask, s);
-        else fdm_launch<2>(tens, slabs, n_slabs, cols, n_colblocks, ut, dt, in, out, tmp, mask, s);
     } else {
         const size_t sh12 = 3 * kMaxN * kMaxN * sizeof(float);
         const size_t sh3 = (2 * kMaxN * 32 + kMaxN * kMaxN) * sizeof(float);
