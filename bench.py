@@ -27,6 +27,9 @@ METRIC = "AF-IETI solve s to 1e-8 rel.res (FP32-FD vs FP64-FD); FD-apply DOF/s"
 # copy's readings): profiles/k_mf_stiffness_c2_traffic.md.  Valid for the
 # kernels that were measured; None for workloads without such a run.
 MEASURED_TRAFFIC = {"c2": 231.1e6}
+# HBM bytes of one FP32 P_A^{-1} application (k_fdg_fwd + k_fdg_mid +
+# k_fdg_bwd), from the same counters: profiles/fd_c2_fp32_counters.md
+MEASURED_FD_TRAFFIC = {"c2": 36.98e6}
 FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
@@ -297,6 +300,7 @@ def main():
         a = flops / (out["fd_apply_ms_fp32"] * 1e-3) / 1e12
         fd_roof = dict(bound="mfma", achieved=a, peak=FP32_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
                        frac=a / FP32_MFMA_PEAK_TFLOPS, kernel="FD apply, FP32 on the matrix cores",
+                       traffic=MEASURED_FD_TRAFFIC.get(args.workload),
                        flops_per_launch=flops, ms_per_launch=out["fd_apply_ms_fp32"],
                        algorithmic_bytes=16 * s32.n_dof)
 
