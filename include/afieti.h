@@ -6,10 +6,13 @@
  *
  * Problem statement (paper Sections 2.2 and 3): patches Omega^(k) given by a
  * multilinear map of their corners (the spline map F^(k) with control
- * points at the Greville images), splines of degree p and continuity C^reg
- * on uniform open knot vectors, Lame parameters per patch, a body force,
- * homogeneous Dirichlet data on marked faces, natural conditions elsewhere.
- * Interfaces are found by matching patch faces; they must be conforming.
+ * points at the Greville images), splines of degree p on open knot vectors
+ * (uniform with continuity C^reg, or given explicitly), Lame parameters per
+ * patch, a body force f (trigonometric modes and/or a callback), a traction
+ * g on faces marked AFIETI_FACE_TRACTION (Gamma_N), Dirichlet data u = g_D
+ * on faces marked AFIETI_FACE_DIRICHLET (homogeneous, or from a callback),
+ * natural conditions elsewhere.  Interfaces are found by matching patch
+ * faces; they must be conforming (equal knot vectors).
  *
  * Vector layouts (all double precision, device memory, caller owned):
  *   DOF vector   patch-stacked (Section 4): for each problem, for each
@@ -54,7 +57,10 @@ extern "C" {
 #define AFIETI_EUNSUPPORTED (-7)
 
 #define AFIETI_FACE_FREE 0       /* natural condition or interface (auto)    */
-#define AFIETI_FACE_DIRICHLET 1  /* homogeneous Dirichlet u = 0              */
+#define AFIETI_FACE_DIRICHLET 1  /* Dirichlet u = g_D (g_D = 0 without the
+                                    problem's dirichlet callback)            */
+#define AFIETI_FACE_TRACTION 2   /* boundary face with the problem's traction
+                                    callback (Gamma_N); not an interface      */
 
 /* precision of the FD mode products (Section 5.2.1, Algorithm 1); the
  * Krylov vectors, residuals and projections are always FP64.  FP64, FP32
@@ -83,14 +89,21 @@ extern "C" {
 /* One patch (Section 2.2).  Corner index a1 + 2 a2 + 4 a3 (a_l in {0,1}),
  * coordinates corners[3*index + x] (2D: only the first 4 corners and x < 2
  * are read).  face_bc order: (dir1 min, dir1 max, dir2 min, dir2 max, dir3
- * min, dir3 max). */
+ * min, dir3 max).  Knot vectors (Section 2.1): with knots[l] == NULL,
+ * direction l has the uniform open vector of n_el[l] elements and interior
+ * multiplicity p - reg; otherwise knots[l] (host, n_knots[l] entries, read
+ * during afieti_setup) is an open vector on [0, 1]: p + 1 zeros, p + 1
+ * ones, non-decreasing, interior knots of multiplicity at most p (so the
+ * splines are continuous); n_el[l] and reg are then ignored for l. */
 typedef struct {
     int p;             /* degree, 1..8                                     */
-    int reg;           /* continuity C^reg, 0 <= reg < p                   */
+    int reg;           /* continuity C^reg, 0 <= reg < p (uniform knots)   */
     int n_el[3];       /* elements per parametric direction (>= 1)         */
     double corners[24];
     double lambda, mu; /* Lame parameters (> 0)                            */
-    int face_bc[6];
+    int face_bc[6];    /* AFIETI_FACE_*                                    */
+    const double* knots[3];  /* explicit open knot vectors, or NULL         */
+    int n_knots[3];
 } afieti_patch;
 
 /* body force f_comp(x) += amp * prod_d sin(pi k[d] x_d + phase[d]) */
@@ -101,12 +114,33 @@ typedef struct {
     double phase[3];
 } afieti_load_mode;
 
+/* Host callbacks of a problem, each called during afieti_setup with n
+ * points at a time (x: [n][dim] physical coordinates, row major), filling
+ * [n][dim] outputs; they may be NULL.
+ *   body_force  f(x): added to the load modes, integrated by the Gauss rule
+ *               of the stiffness (p+1 points per element and direction).
+ *   traction    g(x, normal): on the faces marked AFIETI_FACE_TRACTION,
+ *               normal the outward unit normal, integrated by the face
+ *               Gauss rule (Section 3, the boundary term of the load).
+ *   dirichlet   g_D(x): at the control point of every basis function on a
+ *               face marked AFIETI_FACE_DIRICHLET; the constraint rows of
+ *               those functions read B u = g_D(control point): the
+ *               data's values at the control points serve as its spline
+ *               coefficients (exact for linear data, second order in h
+ *               otherwise). */
+typedef void (*afieti_field_fn)(int64_t n, const double* x, double* out, void* ctx);
+typedef void (*afieti_traction_fn)(int64_t n, const double* x, const double* normal, double* out, void* ctx);
+
 typedef struct {
     int dim;                          /* 2 or 3                          */
     int n_patches;
     const afieti_patch* patches;
     int n_load_modes;
     const afieti_load_mode* load_modes;
+    afieti_field_fn body_force;       /* may be NULL                     */
+    afieti_traction_fn traction;      /* may be NULL                     */
+    afieti_field_fn dirichlet;        /* may be NULL (homogeneous)       */
+    void* ctx;                        /* passed to the callbacks         */
 } afieti_problem;
 
 typedef struct {
@@ -205,9 +239,12 @@ int afieti_apply_fd_noalloc(afieti_handle* h, const double* r, double* z, void* 
 /*
  * AF-IETI solve (Section 4): MINRES on the preconditioned projected saddle
  * system, then u = (I - R (G^T G)^{-1} G^T B) w and lambda = lambda_0 + chi.
- * rhs: device DOF vector, or NULL for the assembled body-force load.
- * u: device DOF vector (out); lambda: device multiplier vector or NULL.
- * st may be NULL.
+ * With Dirichlet data (B u = c, c the g_D values of the Dirichlet rows) the
+ * solve runs on u_0 = u - u_D, u_D = B^T (B B^T)^{-1} c, with right-hand
+ * side rhs - A u_D and homogeneous constraints, and returns u_0 + u_D.
+ * rhs: device DOF vector, or NULL for the assembled load (modes, body
+ * force, tractions).  u: device DOF vector (out); lambda: device multiplier
+ * vector or NULL.  st may be NULL.
  */
 int afieti_solve(afieti_handle* h, const double* rhs, double* u, double* lambda,
                  afieti_stats* st, void* stream);
@@ -215,13 +252,18 @@ int afieti_solve(afieti_handle* h, const double* rhs, double* u, double* lambda,
 /*
  * Adjoint gradients of a scalar J(u) (follows from the symmetric saddle
  * system of Section 4): psi solves the same system with right-hand side
- * dJdu (device DOF vector); u is the forward solution (device DOF vector).
- * psi (out, device, may be NULL); dJ_dlame (out, host, 2 per patch in
- * problem-stacked patch order: dJ/dlambda_k, dJ/dmu_k);
- * dJ_damp (out, host, one per load mode of each problem, stacked).
+ * dJdu (device DOF vector) and homogeneous constraints (the Dirichlet data
+ * do not depend on the parameters); u is the forward solution (device DOF
+ * vector).  psi (out, device, may be NULL); dJ_dlame (out, host, 2 per
+ * patch in problem-stacked patch order: dJ/dlambda_k, dJ/dmu_k);
+ * dJ_damp (out, host, one per load mode of each problem, stacked);
+ * load_vectors (device, n_load_vectors x n_dof, row major, may be NULL):
+ * loads F_j of the caller, with dJ_dload[j] = psi^T F_j (host, out) the
+ * derivative of J with respect to the coefficient c_j of a load sum_j c_j F_j.
  */
 int afieti_solve_adjoint(afieti_handle* h, const double* dJdu, const double* u,
                          double* psi, double* dJ_dlame, double* dJ_damp,
+                         int n_load_vectors, const double* load_vectors, double* dJ_dload,
                          afieti_stats* st, void* stream);
 
 /*
@@ -250,15 +292,21 @@ int afieti_set_parameters(afieti_handle* h, const double* lame, const double* am
                                    boundary of y zero (DOF -> DOF) eq. fac_schur      */
 #define AFIETI_OP_AHAT 10       /* y = A-hat x per patch/component (DOF -> DOF)      */
 #define AFIETI_OP_MASS 11       /* y = M x, physical mass (DOF -> DOF) eq. le_local_MS */
-#define AFIETI_OP_LOAD 12       /* y = assembled body force (x ignored, DOF)         */
+#define AFIETI_OP_LOAD 12       /* y = assembled load: modes, body force, tractions
+                                   (x ignored, DOF)                                  */
+#define AFIETI_OP_DIRICHLET_LIFT 13 /* y = u_D = B^T (B B^T)^{-1} c, the Dirichlet
+                                   data as a DOF vector (x ignored)                  */
 int afieti_apply(afieti_handle* h, int op, const double* x, double* y, void* stream);
 
 /* Host copies of setup data, for checking (valid also with host_only):
  *  what = 0: B as triples, buf = [row, dof_plus, dof_minus(-1 if none)] x n_c int64
  *  what = 1: eigenvalues D of every patch and direction, concatenated (double)
  *  what = 2: diameters H^(k) (double, one per patch)
- *  what = 3: rigid-mode count per problem (int64) followed by G^T G of
- *            problem 0, row major (double reinterpreted)                     */
+ *  what = 3: G^T G of problem 0, row major (double)
+ *  what = 4: the load terms assembled on the host, body force and
+ *            tractions of every problem, DOF-ordered (double, n_dof)
+ *  what = 5: c, the right-hand side of B u = c: Dirichlet data on the
+ *            Dirichlet rows, zero elsewhere (double, n_c)                  */
 int afieti_export(const afieti_handle* h, int what, void* buf, int64_t buf_bytes);
 int64_t afieti_export_size(const afieti_handle* h, int what);
 

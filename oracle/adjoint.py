@@ -22,7 +22,9 @@ import numpy as np
 
 def gradients(sysm, u, dJdu, tol=1e-12):
     """Returns dict(psi, dmu[N_p], dlam[N_p], damp[n_modes])."""
-    res = sysm.solve(rhs=dJdu, tol=tol)
+    # the adjoint constraints are homogeneous: the Dirichlet data do not
+    # depend on the parameters
+    res = sysm.solve(rhs=dJdu, tol=tol, lift=False)
     psi = res["u"]
     dmu, dlam = [], []
     for k, pa in enumerate(sysm.patches):

@@ -23,6 +23,19 @@ Readings of points the paper leaves open:
   * MINRES: the preconditioned Lanczos/Givens form (Paige-Saunders), x0 = 0,
     stopped when the preconditioned residual norm |eta| drops below
     tol * gamma_1 (the residual norm is not stated in the paper).
+  * Non-homogeneous Dirichlet data (the paper only says the right-hand side
+    changes): the spline coefficients of the data are its values at the
+    control points (Schoenberg's variation-diminishing approximation; on
+    the multilinear patches here a control point is the image of its
+    Greville point), so the constraint row of a Dirichlet copy reads
+    u_i = g_D(X_i)[c] and B u = c.  This is exact for g_D linear and of
+    second order in h otherwise.  The solve lifts them: u_D = B^T (B B^T)^{-1} c satisfies
+    B u_D = c, the projected system of Section 4 is solved for u - u_D with
+    right-hand side f - A u_D and homogeneous constraints, and u_D is added
+    back.
+  * Loads: the trigonometric modes, a body force given as a function of
+    the point, and a traction g(x, n) on the faces marked 2 (Gamma_N), as in
+    the linear form of Section 3.
 """
 from __future__ import annotations
 
@@ -50,6 +63,9 @@ class AFIETI:
         self.dim = int(prob["dim"])
         self.patches = [Patch(pd, self.dim) for pd in prob["patches"]]
         self.load_modes = prob["load"]
+        self.body_force = prob.get("body_force")
+        self.traction = prob.get("traction")
+        self.dirichlet = prob.get("dirichlet")
         self.tol = float(prob.get("tol", 1e-8))
         sizes = [pa.n_dof for pa in self.patches]
         self.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
@@ -60,6 +76,7 @@ class AFIETI:
         self.A = [pa.stiffness_matrix() for pa in self.patches] if assembled else None
         self._build_numbering()
         self._build_B()
+        self._build_dirichlet_data()
         self._build_coarse()
         self._build_fd()
 
@@ -137,6 +154,7 @@ class AFIETI:
         self.dirichlet_class = [any(self._on_dirichlet(k, i) for (k, i) in cp)
                                 for cp in self.classes]
         r = 0
+        dir_rows = []  # (row, patch, node, component) of the Dirichlet rows
         for c in range(self.dim):
             for cp, isd in zip(self.classes, self.dirichlet_class):
                 if isd:
@@ -144,6 +162,7 @@ class AFIETI:
                         rows.append(r)
                         cols.append(self.dof(k, c, i))
                         vals.append(1.0)
+                        dir_rows.append((r, k, i, c))
                         r += 1
                 else:
                     k1, i1 = cp[0]
@@ -153,9 +172,21 @@ class AFIETI:
                         vals += [1.0, -1.0]
                         r += 1
         self.n_c = r
+        self._dir_rows = dir_rows
         self.B = sp.csr_matrix((vals, (rows, cols)), shape=(r, self.n_dof))
         self.BBt = (self.B @ self.B.T).tocsc()
         self._BBt_lu = spla.splu(self.BBt)
+
+    def _build_dirichlet_data(self):
+        """c: right-hand side of B u = c, g_D(X_i)[c] on the Dirichlet row of
+        copy (k, i) and component c, zero elsewhere; u_D = B^T (B B^T)^{-1} c."""
+        self.c = np.zeros(self.n_c)
+        if self.dirichlet is not None and self._dir_rows:
+            X = np.array([self.patches[k].ctrl.reshape(-1, self.dim)[i] for (_r, k, i, _c) in self._dir_rows])
+            g = np.asarray(self.dirichlet(X), dtype=float).reshape(len(X), self.dim)
+            for j, (r, _k, _i, c) in enumerate(self._dir_rows):
+                self.c[r] = g[j, c]
+        self.u_dir = self.B.T @ self._BBt_lu.solve(self.c)
 
     # ----------------------------------------------------------- coarse space
     def _build_coarse(self):
@@ -200,7 +231,18 @@ class AFIETI:
                           for pa, wk in zip(self.patches, self.split(w))])
 
     def load(self, amps=None):
-        return self.join([pa.body_force(self.load_modes, amps) for pa in self.patches])
+        """Assembled load: the trigonometric modes, the body-force function
+        and the tractions on the faces marked 2 (Section 3)."""
+        parts = []
+        for pa in self.patches:
+            F = pa.body_force(self.load_modes, amps)
+            if self.body_force is not None:
+                F = F + pa.body_force_field(self.body_force)
+            for f in range(2 * self.dim):
+                if pa.bc[f] == 2:
+                    F = F + pa.traction(f, self.traction)
+            parts.append(F)
+        return self.join(parts)
 
     def apply_op(self, x):
         """Projected saddle operator of Section 4: [A w + B^T P_chi chi;
@@ -319,11 +361,18 @@ class AFIETI:
         return np.concatenate([zw, zc])
 
     # --------------------------------------------------------------- solve
-    def solve(self, rhs=None, tol=None, maxit=2000, variant="nr"):
+    def solve(self, rhs=None, tol=None, maxit=2000, variant="nr", lift=True):
         """AF-IETI: MINRES on the preconditioned projected system, then the
-        recovery of (u, lambda) of Section 4.  Returns a dict."""
+        recovery of (u, lambda) of Section 4.  With Dirichlet data (and
+        ``lift``) the system is solved for u - u_D (module docstring).
+        Returns a dict."""
         f = self.load() if rhs is None else np.asarray(rhs, dtype=float)
         tol = self.tol if tol is None else tol
+        if lift and np.any(self.c != 0):
+            res = self.solve(rhs=f - self.apply_A(self.u_dir), tol=tol, maxit=maxit, variant=variant, lift=False)
+            res["u"] = res["u"] + self.u_dir
+            res["f"] = f
+            return res
         lam0 = self.lambda0(f)
         b = np.concatenate([f - self.B.T @ lam0, np.zeros(self.n_c)])
         x, its, hist = minres(self.apply_op, lambda r: self.apply_prec(r, variant),

@@ -48,12 +48,14 @@ def conforming_map(sysm) -> sp.csr_matrix:
 
 
 def solve_conforming(sysm, f=None):
-    """u = Z (Z^T A Z)^{-1} Z^T f with the assembled patch matrices."""
+    """u = Z (Z^T A Z)^{-1} Z^T (f - A u_D) + u_D with the assembled patch
+    matrices: the conforming unknowns away from the Dirichlet boundary, the
+    Dirichlet copies fixed at their data u_D (zero for homogeneous data)."""
     if not sysm.assembled:
         raise ValueError("direct solve needs assembled patch matrices")
     f = sysm.load() if f is None else f
     Z = conforming_map(sysm)
     A = sp.block_diag(sysm.A, format="csr")
     Ac = (Z.T @ A @ Z).tocsc()
-    uc = spla.spsolve(Ac, Z.T @ f)
-    return Z @ uc
+    uc = spla.spsolve(Ac, Z.T @ (f - A @ sysm.u_dir))
+    return Z @ uc + sysm.u_dir

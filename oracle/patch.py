@@ -69,8 +69,13 @@ class Patch:
         self.mu = float(pd["mu"])
         self.bc = list(pd["bc"])
         self.corners = np.asarray(pd["corners"], dtype=float)
-        self.knots = [bspline.open_uniform_knots(self.n_el[l], self.p, self.reg)
-                      for l in range(dim)]
+        if pd.get("knots") is not None:
+            # explicit open knot vectors (Section 2.1); elements = non-empty spans
+            self.knots = [np.asarray(pd["knots"][l], dtype=float) for l in range(dim)]
+            self.n_el = [len(np.unique(k)) - 1 for k in self.knots]
+        else:
+            self.knots = [bspline.open_uniform_knots(self.n_el[l], self.p, self.reg)
+                          for l in range(dim)]
         self.n = [bspline.n_functions(k, self.p) for k in self.knots]
         self.shape = tuple(reversed(self.n))  # (n_d, ..., n_1)
         self.n_nodes = int(np.prod(self.n))
@@ -262,13 +267,23 @@ class Patch:
             out[comp] += a * apply_1d(wdet * val, VT)
         return out
 
+    def body_force_field(self, fn) -> np.ndarray:
+        """f^(k)_(c,i) = int f_c B_i dx for a body force given as a function
+        f(x) of an array of points (n, dim) -> (n, dim) (Section 3, the load
+        term), by the Gauss rule of the patch."""
+        xq, wdet, _ = self.geometry()
+        dim = self.dim
+        f = np.asarray(fn(xq.reshape(-1, dim)), dtype=float).reshape(xq.shape)
+        VT = [v.T for v in self.V]
+        return np.array([apply_1d(wdet * f[..., c], VT) for c in range(dim)])
+
     def mode_loads(self, modes) -> np.ndarray:
         """Load vector of each mode with unit amplitude: (n_modes, dim, ...)."""
         return np.array([self.body_force([(c, 1.0, k, ph)]) for (c, _a, k, ph) in modes])
 
     def traction(self, face: int, gfun) -> np.ndarray:
         """int_face g . v ds for the face ``face`` (2*dir + side), g = gfun(x, n)
-        returning (..., dim); n is the outward unit normal."""
+        for arrays of points and outward unit normals (n, dim) -> (n, dim)."""
         dim = self.dim
         fd, side = face // 2, face % 2
         X = np.moveaxis(self.ctrl, -1, 0)
@@ -307,7 +322,8 @@ class Patch:
             shp = [1] * dim
             shp[dim - 1 - l] = -1
             w = w * wts[l].reshape(shp)
-        g = gfun(xq, nvec) * (w * area)[..., None]
+        g = np.asarray(gfun(xq.reshape(-1, dim), nvec.reshape(-1, dim)), dtype=float)
+        g = g.reshape(xq.shape) * (w * area)[..., None]
         VT = [m.T for m in mats_v]
         return np.array([apply_1d(g[..., c], VT) for c in range(dim)])
 

@@ -25,9 +25,29 @@ class AfietiError(RuntimeError):
         self.code = code
 
 
+def _field_cb(fn, dim):
+    """C callback over a batch of points for a Python f(x[n, dim]) -> [n, dim]."""
+    def cb(n, x, out, ctx):
+        X = np.ctypeslib.as_array(x, shape=(n, dim))
+        np.ctypeslib.as_array(out, shape=(n, dim))[:] = np.asarray(fn(X.copy()), dtype=np.float64).reshape(n, dim)
+    return N.FIELD_FN(cb)
+
+
+def _traction_cb(fn, dim):
+    """C callback for a Python g(x[n, dim], normal[n, dim]) -> [n, dim]."""
+    def cb(n, x, nrm, out, ctx):
+        X = np.ctypeslib.as_array(x, shape=(n, dim)).copy()
+        Nv = np.ctypeslib.as_array(nrm, shape=(n, dim)).copy()
+        np.ctypeslib.as_array(out, shape=(n, dim))[:] = np.asarray(fn(X, Nv), dtype=np.float64).reshape(n, dim)
+    return N.TRACTION_FN(cb)
+
+
 def to_c_problems(problems):
     """Convert ``workloads`` problem dictionaries into the C structs; returns
-    (array, keepalive)."""
+    (array, keepalive).  Optional entries: a patch's ``knots`` (explicit
+    open knot vectors per direction), a problem's ``body_force(x)``,
+    ``traction(x, normal)`` and ``dirichlet(x)`` callables (arrays of
+    points in, arrays of values out)."""
     if isinstance(problems, dict):
         problems = [problems]
     arr = (N.Problem * len(problems))()
@@ -49,6 +69,12 @@ def to_c_problems(problems):
             P.mu = float(pd["mu"])
             for f in range(2 * dim):
                 P.face_bc[f] = int(pd["bc"][f])
+            if pd.get("knots") is not None:
+                for l in range(dim):
+                    kv = np.ascontiguousarray(np.asarray(pd["knots"][l], dtype=np.float64))
+                    keep.append(kv)
+                    P.knots[l] = kv.ctypes.data_as(C.POINTER(C.c_double))
+                    P.n_knots[l] = len(kv)
         modes = (N.LoadMode * max(1, len(pr["load"])))()
         for m, (comp, amp, k, ph) in enumerate(pr["load"]):
             modes[m].comp = int(comp)
@@ -62,6 +88,11 @@ def to_c_problems(problems):
         arr[j].patches = pats
         arr[j].n_load_modes = len(pr["load"])
         arr[j].load_modes = modes
+        for key, make in (("body_force", _field_cb), ("traction", _traction_cb), ("dirichlet", _field_cb)):
+            if pr.get(key) is not None:
+                cb = make(pr[key], dim)
+                keep.append(cb)
+                setattr(arr[j], key, cb)
     return arr, keep
 
 
@@ -191,19 +222,26 @@ class Solver:
             self.amps = amps.copy()
         self.param_version += 1
 
-    def solve_adjoint(self, dJdu, u, psi=None, allow_not_converged=False):
+    def solve_adjoint(self, dJdu, u, psi=None, allow_not_converged=False, load_vectors=None):
         """psi = adjoint state; returns (psi, dJ/dlambda[n_patches],
-        dJ/dmu[n_patches], dJ/damp[n_modes], iterations)."""
+        dJ/dmu[n_patches], dJ/damp[n_modes], iterations), and with
+        ``load_vectors`` (device tensor [m, n_dof]) also dJ/dc[m] for a load
+        sum_j c_j F_j as a sixth entry."""
         psi = self._new(self.n_dof) if psi is None else psi
         dl = (C.c_double * (2 * self.n_patches))()
         n_modes = self.n_load_modes_total
         da = (C.c_double * max(1, n_modes))()
+        m = 0 if load_vectors is None else int(load_vectors.shape[0])
+        dv = (C.c_double * max(1, m))()
+        lvt = None if load_vectors is None else load_vectors.contiguous()
+        lv = C.c_void_p(0) if lvt is None else C.c_void_p(lvt.data_ptr())
         st = N.Stats()
         allow = (N.OK, N.NOT_CONVERGED) if allow_not_converged else (N.OK,)
-        self._check(self._L.afieti_solve_adjoint(self._h, _ptr(dJdu), _ptr(u), _ptr(psi), dl, da,
+        self._check(self._L.afieti_solve_adjoint(self._h, _ptr(dJdu), _ptr(u), _ptr(psi), dl, da, m, lv, dv,
                                                  C.byref(st), _stream()), allow)
         dl = np.array(dl[:]).reshape(-1, 2)
-        return psi, dl[:, 0], dl[:, 1], np.array(da[:n_modes]), st.iterations
+        out = (psi, dl[:, 0], dl[:, 1], np.array(da[:n_modes]), st.iterations)
+        return out + (np.array(dv[:m]),) if load_vectors is not None else out
 
     # ---------------------------------------------------------- exports
     def export(self, what):

@@ -18,15 +18,16 @@ PS_VARIANT = {"nr": 0, "plain": 1}
 STIFFNESS = {"auto": 0, "assembled": 1, "matrix_free": 2}
 
 OPS = {"stiffness": 0, "B": 1, "Bt": 2, "P_u": 3, "P_chi": 4, "Shat": 5, "P_S": 6,
-       "prec": 7, "saddle": 8, "fd_interior": 9, "Ahat": 10, "mass": 11, "load": 12}
+       "prec": 7, "saddle": 8, "fd_interior": 9, "Ahat": 10, "mass": 11, "load": 12,
+       "dirichlet_lift": 13}
 
-EXPORT = {"B": 0, "eig": 1, "H": 2, "GtG": 3}
+EXPORT = {"B": 0, "eig": 1, "H": 2, "GtG": 3, "fixed_load": 4, "dirichlet_c": 5}
 
 
 class Patch(C.Structure):
     _fields_ = [("p", C.c_int), ("reg", C.c_int), ("n_el", C.c_int * 3),
                 ("corners", C.c_double * 24), ("lam", C.c_double), ("mu", C.c_double),
-                ("face_bc", C.c_int * 6)]
+                ("face_bc", C.c_int * 6), ("knots", C.POINTER(C.c_double) * 3), ("n_knots", C.c_int * 3)]
 
 
 class LoadMode(C.Structure):
@@ -34,9 +35,16 @@ class LoadMode(C.Structure):
                 ("phase", C.c_double * 3)]
 
 
+FIELD_FN = C.CFUNCTYPE(None, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p)
+TRACTION_FN = C.CFUNCTYPE(None, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                          C.POINTER(C.c_double), C.c_void_p)
+
+
 class Problem(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_patches", C.c_int), ("patches", C.POINTER(Patch)),
-                ("n_load_modes", C.c_int), ("load_modes", C.POINTER(LoadMode))]
+                ("n_load_modes", C.c_int), ("load_modes", C.POINTER(LoadMode)),
+                ("body_force", FIELD_FN), ("traction", TRACTION_FN), ("dirichlet", FIELD_FN),
+                ("ctx", C.c_void_p)]
 
 
 class Options(C.Structure):
@@ -70,6 +78,7 @@ SYMBOLS = {
                                C.POINTER(Stats), C.c_void_p]),
     "afieti_solve_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.c_int, C.c_void_p, C.POINTER(C.c_double),
                                        C.POINTER(Stats), C.c_void_p]),
     "afieti_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "afieti_set_parameters": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),

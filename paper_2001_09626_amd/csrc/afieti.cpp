@@ -88,6 +88,10 @@ struct afieti_handle {
     double* d_mftab = nullptr; // matrix-free per-brick univariate tables
     double* d_geo = nullptr;
     double* d_load = nullptr;
+    double* d_fixed = nullptr;   // loads of the body-force / traction callbacks (or NULL)
+    double* d_udir = nullptr;    // Dirichlet lift u_D = B^T (B B^T)^{-1} c (or NULL)
+    double* d_part_u = nullptr;  // partials of the caller's load-vector products
+    int64_t part_u_n = 0;
     std::vector<double*> d_F;              // per problem: unit-amplitude mode loads [mode][dof]
     std::vector<std::vector<double>> amps; // per problem: load amplitudes
     std::vector<double*> d_unit_modes;     // per problem: modes with amplitude 1 (8 doubles each)
@@ -357,7 +361,8 @@ void assemble_all(afieti_handle* h, hipStream_t s) {
 
 // assembled load = sum_j amp_j F_j per problem
 void combine_load(afieti_handle* h, hipStream_t s) {
-    launch_fill(h->d_load, 0.0, h->n_dof, s);
+    if (h->d_fixed) launch_copy(h->d_fixed, h->d_load, h->n_dof, s);
+    else launch_fill(h->d_load, 0.0, h->n_dof, s);
     for (size_t j = 0; j < h->plan.probs.size(); ++j) {
         const ProblemPlan& pr = h->plan.probs[j];
         double* f = h->d_load + pr.dof_off;
@@ -538,6 +543,25 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     h->stencil_bytes = stencil * 8;
     h->d_geo = h->dalloc<double>(geo_max);
     h->d_load = h->dalloc<double>(pl.n_dof);
+    {
+        // loads of the callbacks, and the Dirichlet lift: B B^T is the
+        // identity on a Dirichlet row's block, so u_D = B^T c puts each
+        // row's value c_r on its DOF
+        bool fixed = false;
+        for (const auto& pr : pl.probs) fixed |= !pr.fixed_load.empty();
+        if (fixed) {
+            std::vector<double> fx(pl.n_dof, 0.0);
+            for (const auto& pr : pl.probs)
+                if (!pr.fixed_load.empty()) std::copy(pr.fixed_load.begin(), pr.fixed_load.end(), fx.begin() + pr.dof_off);
+            h->d_fixed = h->upload(fx, s);
+        }
+        if (!pl.c_rhs.empty()) {
+            std::vector<double> ud(pl.n_dof, 0.0);
+            for (int64_t r = 0; r < pl.n_c; ++r)
+                if (pl.c_minus[r] < 0) ud[pl.c_plus[r]] = pl.c_rhs[r];
+            h->d_udir = h->upload(ud, s);
+        }
+    }
     // row blocks by (dim, p, matrix-free)
     std::map<std::tuple<int, int, int>, std::vector<int4>> rbs;
     for (int k = 0; k < np; ++k) {
@@ -1243,11 +1267,21 @@ int run_minres(afieti_handle* h, hipStream_t s, afieti_stats* st) {
 }
 
 // Full AF-IETI solve for right-hand side f (device DOF vector).
-int solve_impl(afieti_handle* h, const double* f, double* u, double* lambda, afieti_stats* st, hipStream_t s) {
+// lift: the constraints read B u = c with the handle's Dirichlet data (the
+// solve runs on u - u_D with right-hand side f - A u_D); otherwise B u = 0
+int solve_impl(afieti_handle* h, const double* f, double* u, double* lambda, afieti_stats* st, hipStream_t s,
+               bool lift = true) {
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
     HIP_OK(hipEventRecord(e0, s));
+    lift = lift && h->d_udir;
+    if (lift) {
+        // tt, tv serve the preconditioner only once MINRES runs
+        op_stiffness(h, h->d_udir, h->tt, nullptr, s);
+        launch_axpby(1.0, f, -1.0, h->tt, h->tv, h->n_dof, s);
+        f = h->tv;
+    }
     // lambda_0 = G (G^T G)^{-1} R^T f  (minimal-norm solution of G^T lambda_0 = R^T f)
     launch_rigid_partial(h->d_patches, h->d_dof_chunks, h->n_dof_chunks, h->d_ctrl, f, h->d_part, s);
     launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_dof_cptr, h->d_part,
@@ -1265,6 +1299,7 @@ int solve_impl(afieti_handle* h, const double* f, double* u, double* lambda, afi
     launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_gam_cptr, h->d_part,
                            h->d_cinv, h->d_zc, h->max_nc, s);
     launch_rigid_update(h->d_patches, h->d_dof_chunks, h->n_dof_chunks, h->d_ctrl, h->d_zc, w, u, s);
+    if (lift) launch_axpby(1.0, u, 1.0, h->d_udir, u, h->n_dof, s);
     if (lambda) launch_axpby(1.0, h->lam0, 1.0, h->vec[8] + h->n_dof, lambda, h->n_c, s);
     HIP_OK(hipEventRecord(e1, s));
     HIP_OK(hipEventSynchronize(e1));
@@ -1435,7 +1470,7 @@ int afieti_apply_fd_noalloc(afieti_handle* h, const double* r, double* z, void* 
 int afieti_apply(afieti_handle* h, int op, const double* x, double* y, void* stream) {
     int c = need_device(h);
     if (c) return c;
-    if (!y || (op != AFIETI_OP_LOAD && (!x || x == y))) {
+    if (!y || (op != AFIETI_OP_LOAD && op != AFIETI_OP_DIRICHLET_LIFT && (!x || x == y))) {
         h->err = "apply needs distinct input and output";
         return AFIETI_EINVAL;
     }
@@ -1458,6 +1493,10 @@ int afieti_apply(afieti_handle* h, int op, const double* x, double* y, void* str
                 break;
             case AFIETI_OP_AHAT: op_ahat(h, x, y, 0, s); break;
             case AFIETI_OP_LOAD: launch_copy(h->d_load, y, h->n_dof, s); break;
+            case AFIETI_OP_DIRICHLET_LIFT:
+                if (h->d_udir) launch_copy(h->d_udir, y, h->n_dof, s);
+                else launch_fill(y, 0.0, h->n_dof, s);
+                break;
             case AFIETI_OP_MASS: op_mass(h, x, y, s); break;
             default: h->err = "unknown operator"; return AFIETI_EUNSUPPORTED;
         }
@@ -1483,11 +1522,16 @@ int afieti_solve(afieti_handle* h, const double* rhs, double* u, double* lambda,
 }
 
 int afieti_solve_adjoint(afieti_handle* h, const double* dJdu, const double* u, double* psi, double* dJ_dlame,
-                         double* dJ_damp, afieti_stats* st, void* stream) {
+                         double* dJ_damp, int n_load_vectors, const double* load_vectors, double* dJ_dload,
+                         afieti_stats* st, void* stream) {
     int c = need_device(h);
     if (c) return c;
     if (!dJdu || !u) {
         h->err = "dJdu and u are required";
+        return AFIETI_EINVAL;
+    }
+    if (n_load_vectors < 0 || (n_load_vectors > 0 && (!load_vectors || !dJ_dload))) {
+        h->err = "load vectors need n_load_vectors >= 0, the vectors and an output array";
         return AFIETI_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -1495,7 +1539,7 @@ int afieti_solve_adjoint(afieti_handle* h, const double* dJdu, const double* u, 
         double* ps = psi;
         if (!ps) ps = h->s2;  // scratch when the caller does not want psi
         // the saddle operator is symmetric: psi solves the forward system with rhs dJ/du
-        int code = solve_impl(h, dJdu, ps, nullptr, st, s);
+        int code = solve_impl(h, dJdu, ps, nullptr, st, s, false);
         if (code < 0) return code;
         if (dJ_dlame) {
             std::vector<double> part(h->part_e_n);
@@ -1531,6 +1575,24 @@ int afieti_solve_adjoint(afieti_handle* h, const double* dJdu, const double* u, 
                     for (int b = 0; b < nch; ++b) acc += part[(size_t)m * nch + b];
                     dJ_damp[out++] = acc;  // dJ/da_m = psi^T F_m
                 }
+            }
+        }
+        if (n_load_vectors > 0) {
+            // dJ/dc_j = psi^T F_j for the caller's load vectors
+            const int64_t nch = (h->n_dof + kChunk - 1) / kChunk;
+            if (h->part_u_n < nch * n_load_vectors) {
+                h->d_part_u = h->dalloc<double>(nch * n_load_vectors);
+                h->part_u_n = nch * n_load_vectors;
+            }
+            std::vector<double> part((size_t)nch * n_load_vectors);
+            const int got = launch_mdot(load_vectors, h->n_dof, n_load_vectors, 0, ps, h->d_part_u, s);
+            HIP_OK(hipMemcpyAsync(part.data(), h->d_part_u, (size_t)got * n_load_vectors * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+            HIP_OK(hipStreamSynchronize(s));
+            for (int m = 0; m < n_load_vectors; ++m) {
+                double acc = 0;
+                for (int b = 0; b < got; ++b) acc += part[(size_t)m * got + b];
+                dJ_dload[m] = acc;
             }
         }
         HIP_OK(hipGetLastError());
@@ -1610,6 +1672,8 @@ int64_t afieti_export_size(const afieti_handle* h, int what) {
             int64_t nc = (int64_t)pr.n_modes * pr.n_patches;
             return nc * nc * (int64_t)sizeof(double);
         }
+        case 4: return pl.n_dof * (int64_t)sizeof(double);
+        case 5: return pl.n_c * (int64_t)sizeof(double);
         default: return -1;
     }
 }
@@ -1632,8 +1696,17 @@ int afieti_export(const afieti_handle* h, int what, void* buf, int64_t buf_bytes
     } else if (what == 2) {
         double* o = static_cast<double*>(buf);
         for (const auto& P : pl.patches) *o++ = P.H;
-    } else {
+    } else if (what == 3) {
         std::memcpy(buf, pl.probs[0].CtC.data(), need);
+    } else if (what == 4) {
+        double* o = static_cast<double*>(buf);
+        std::fill(o, o + pl.n_dof, 0.0);
+        for (const auto& pr : pl.probs)
+            if (!pr.fixed_load.empty()) std::copy(pr.fixed_load.begin(), pr.fixed_load.end(), o + pr.dof_off);
+    } else {
+        double* o = static_cast<double*>(buf);
+        std::fill(o, o + pl.n_c, 0.0);
+        if (!pl.c_rhs.empty()) std::copy(pl.c_rhs.begin(), pl.c_rhs.end(), o);
     }
     return AFIETI_OK;
 }

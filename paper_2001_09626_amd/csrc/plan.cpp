@@ -81,9 +81,10 @@ double multilinear_coord(int dim, const double* corners, const double* eta, int 
     return s;
 }
 
-// det of the Jacobian of the multilinear corner map at eta
-double multilinear_det(int dim, const double* corners, const double* eta) {
-    double J[3][3] = {{0}};
+// Jacobian J[x][a] = dF_x / deta_a of the multilinear corner map at eta
+void multilinear_jac(int dim, const double* corners, const double* eta, double (&J)[3][3]) {
+    for (auto& row : J)
+        for (double& v : row) v = 0.0;
     for (int c = 0; c < (1 << dim); ++c) {
         for (int a = 0; a < dim; ++a) {
             double w = 1;
@@ -95,6 +96,12 @@ double multilinear_det(int dim, const double* corners, const double* eta) {
             for (int x = 0; x < dim; ++x) J[x][a] += w * corners[3 * c + x];
         }
     }
+}
+
+// det of the Jacobian of the multilinear corner map at eta
+double multilinear_det(int dim, const double* corners, const double* eta) {
+    double J[3][3];
+    multilinear_jac(dim, corners, eta, J);
     if (dim == 2) return J[0][0] * J[1][1] - J[0][1] * J[1][0];
     return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
            J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
@@ -118,10 +125,10 @@ struct UnionFind {
     }
 };
 
-void build_dir(Dir1D& d, int n_el, int p, int reg) {
+// univariate spline data of one direction from its open knot vector
+void build_dir(Dir1D& d, const std::vector<double>& knots, int p) {
     d.p = p;
-    d.n_el = n_el;
-    d.knots = open_uniform_knots(n_el, p, reg);
+    d.knots = knots;
     d.n = (int)d.knots.size() - p - 1;
     const int P = p + 1;
     std::vector<double> gx(P), gw(P);
@@ -129,7 +136,8 @@ void build_dir(Dir1D& d, int n_el, int p, int reg) {
     std::vector<double> brk;
     for (double t : d.knots)
         if (brk.empty() || t > brk.back()) brk.push_back(t);
-    if ((int)brk.size() - 1 != n_el) fail(AFIETI_EINVAL, "knot spans do not match n_el");
+    const int n_el = (int)brk.size() - 1;
+    d.n_el = n_el;
     d.nq = n_el * P;
     d.qx.resize(d.nq);
     d.qw.resize(d.nq);
@@ -192,6 +200,167 @@ void dummy_dir(Dir1D& d) {
     d.M = {1.0};
 }
 
+// The Gauss rule and nonzero basis values of one direction as the load
+// integrals read them; a direction the patch does not have (2D) is one
+// point of weight 1 where its single function is 1.
+struct QuadDir {
+    int nq, P;
+    const double *qx, *qw, *qval;
+    const int* qfirst;
+    double one_x = 0.0, one_w = 1.0, one_v = 1.0;
+    int one_f = 0;
+    explicit QuadDir(const Dir1D& d) {
+        if (d.nq > 0) {
+            nq = d.nq;
+            P = d.p + 1;
+            qx = d.qx.data();
+            qw = d.qw.data();
+            qval = d.qval.data();
+            qfirst = d.qfirst.data();
+        } else {
+            nq = 1;
+            P = 1;
+            qx = &one_x;
+            qw = &one_w;
+            qval = &one_v;
+            qfirst = &one_f;
+        }
+    }
+};
+
+// load of the body-force callback on one patch (Section 3: int f . v dx by
+// the Gauss rule of the stiffness): f at every Gauss point, weighted by
+// w |det J|, contracted with the basis direction by direction; added to
+// F[c * nodes + node]
+void add_body_force(const PatchPlan& P, afieti_field_fn fn, void* ctx, double* F) {
+    const int dim = P.dim;
+    QuadDir Q0(P.dir[0]), Q1(P.dir[1]), Q2(P.dir[2]);
+    const int64_t nq = (int64_t)Q0.nq * Q1.nq * Q2.nq;
+    std::vector<double> x((size_t)nq * dim), f((size_t)nq * dim, 0.0), W(nq);
+    for (int q3 = 0; q3 < Q2.nq; ++q3)
+        for (int q2 = 0; q2 < Q1.nq; ++q2)
+            for (int q1 = 0; q1 < Q0.nq; ++q1) {
+                const int64_t q = q1 + (int64_t)Q0.nq * (q2 + (int64_t)Q1.nq * q3);
+                const double eta[3] = {Q0.qx[q1], Q1.qx[q2], Q2.qx[q3]};
+                for (int c = 0; c < dim; ++c) x[q * dim + c] = multilinear_coord(dim, P.corners, eta, c);
+                W[q] = Q0.qw[q1] * Q1.qw[q2] * Q2.qw[q3] * std::fabs(multilinear_det(dim, P.corners, eta));
+            }
+    fn(nq, x.data(), f.data(), ctx);
+    for (double v : f)
+        if (!std::isfinite(v)) fail(AFIETI_EINVAL, "non-finite body force");
+    // contract direction 1, then 2, then 3
+    const int n1 = P.n[0], n2 = P.n[1], n3 = P.n[2];
+    std::vector<double> A1((size_t)dim * Q2.nq * Q1.nq * n1, 0.0), A2((size_t)dim * Q2.nq * n2 * n1, 0.0);
+    for (int c = 0; c < dim; ++c)
+        for (int q3 = 0; q3 < Q2.nq; ++q3)
+            for (int q2 = 0; q2 < Q1.nq; ++q2) {
+                double* a = &A1[(((size_t)c * Q2.nq + q3) * Q1.nq + q2) * n1];
+                for (int q1 = 0; q1 < Q0.nq; ++q1) {
+                    const int64_t q = q1 + (int64_t)Q0.nq * (q2 + (int64_t)Q1.nq * q3);
+                    const double v = W[q] * f[q * dim + c];
+                    for (int t = 0; t < Q0.P; ++t) a[Q0.qfirst[q1] + t] += Q0.qval[(size_t)q1 * Q0.P + t] * v;
+                }
+            }
+    for (int c = 0; c < dim; ++c)
+        for (int q3 = 0; q3 < Q2.nq; ++q3)
+            for (int q2 = 0; q2 < Q1.nq; ++q2) {
+                const double* a = &A1[(((size_t)c * Q2.nq + q3) * Q1.nq + q2) * n1];
+                for (int t = 0; t < Q1.P; ++t) {
+                    const double b = Q1.qval[(size_t)q2 * Q1.P + t];
+                    double* o = &A2[(((size_t)c * Q2.nq + q3) * n2 + Q1.qfirst[q2] + t) * n1];
+                    for (int i1 = 0; i1 < n1; ++i1) o[i1] += b * a[i1];
+                }
+            }
+    for (int c = 0; c < dim; ++c)
+        for (int q3 = 0; q3 < Q2.nq; ++q3)
+            for (int t = 0; t < Q2.P; ++t) {
+                const double b = Q2.qval[(size_t)q3 * Q2.P + t];
+                const int i3 = Q2.qfirst[q3] + t;
+                for (int i2 = 0; i2 < n2; ++i2) {
+                    const double* a = &A2[(((size_t)c * Q2.nq + q3) * n2 + i2) * n1];
+                    double* o = &F[(size_t)c * P.nodes + ((size_t)i3 * n2 + i2) * n1];
+                    for (int i1 = 0; i1 < n1; ++i1) o[i1] += b * a[i1];
+                }
+            }
+}
+
+// load of the traction callback on face `face` of a patch (Section 3: the
+// boundary term int_{Gamma_N} g . v ds) by the Gauss rule of the face's
+// directions; the face basis functions are the products of the tangential
+// ones (the normal direction's end function is 1 on the face)
+void add_traction(const PatchPlan& P, int face, afieti_traction_fn fn, void* ctx, double* F) {
+    const int dim = P.dim, fd = face / 2, side = face % 2;
+    int tan[2] = {0, 0}, nt = 0;
+    for (int l = 0; l < dim; ++l)
+        if (l != fd) tan[nt++] = l;
+    QuadDir Qa(P.dir[tan[0]]), Qb(dim == 3 ? P.dir[tan[1]] : P.dir[2]);
+    const int64_t nq = (int64_t)Qa.nq * Qb.nq;
+    std::vector<double> x((size_t)nq * dim), nrm((size_t)nq * dim), g((size_t)nq * dim, 0.0), wa(nq);
+    for (int qb = 0; qb < Qb.nq; ++qb)
+        for (int qa = 0; qa < Qa.nq; ++qa) {
+            const int64_t q = qa + (int64_t)Qa.nq * qb;
+            double eta[3] = {0, 0, 0};
+            eta[fd] = side ? 1.0 : 0.0;
+            eta[tan[0]] = Qa.qx[qa];
+            if (dim == 3) eta[tan[1]] = Qb.qx[qb];
+            double J[3][3];
+            multilinear_jac(dim, P.corners, eta, J);
+            double n[3] = {0, 0, 0};
+            if (dim == 3) {
+                const int a = tan[0], b = tan[1];
+                n[0] = J[1][a] * J[2][b] - J[2][a] * J[1][b];
+                n[1] = J[2][a] * J[0][b] - J[0][a] * J[2][b];
+                n[2] = J[0][a] * J[1][b] - J[1][a] * J[0][b];
+            } else {
+                n[0] = J[1][tan[0]];
+                n[1] = -J[0][tan[0]];
+            }
+            double area = 0;
+            for (int c = 0; c < dim; ++c) area += n[c] * n[c];
+            area = std::sqrt(area);
+            // outward: along the gradient of eta_fd on the max side, against
+            // it on the min side (the gradient is row fd of J^{-1}, i.e. the
+            // cofactors of column fd of J up to the sign of det J)
+            double grad[3] = {0, 0, 0};
+            if (dim == 3) {
+                const int a = (fd + 1) % 3, b = (fd + 2) % 3;
+                grad[0] = J[1][a] * J[2][b] - J[2][a] * J[1][b];
+                grad[1] = J[2][a] * J[0][b] - J[0][a] * J[2][b];
+                grad[2] = J[0][a] * J[1][b] - J[1][a] * J[0][b];
+            } else {
+                const int a = 1 - fd;
+                grad[0] = (fd == 0 ? 1.0 : -1.0) * J[1][a];
+                grad[1] = (fd == 0 ? -1.0 : 1.0) * J[0][a];
+            }
+            const double det = multilinear_det(dim, P.corners, eta);
+            double dot = 0;
+            for (int c = 0; c < dim; ++c) dot += grad[c] * n[c];
+            const double sgn = ((dot * det) >= 0 ? 1.0 : -1.0) * (side ? 1.0 : -1.0);
+            for (int c = 0; c < dim; ++c) {
+                x[q * dim + c] = multilinear_coord(dim, P.corners, eta, c);
+                nrm[q * dim + c] = sgn * n[c] / area;
+            }
+            wa[q] = Qa.qw[qa] * Qb.qw[qb] * area;
+        }
+    fn(nq, x.data(), nrm.data(), g.data(), ctx);
+    for (double v : g)
+        if (!std::isfinite(v)) fail(AFIETI_EINVAL, "non-finite traction");
+    for (int qb = 0; qb < Qb.nq; ++qb)
+        for (int qa = 0; qa < Qa.nq; ++qa) {
+            const int64_t q = qa + (int64_t)Qa.nq * qb;
+            for (int tb = 0; tb < Qb.P; ++tb)
+                for (int ta = 0; ta < Qa.P; ++ta) {
+                    int idx[3] = {0, 0, 0};
+                    idx[fd] = side ? P.n[fd] - 1 : 0;
+                    idx[tan[0]] = Qa.qfirst[qa] + ta;
+                    if (dim == 3) idx[tan[1]] = Qb.qfirst[qb] + tb;
+                    const double b = Qa.qval[(size_t)qa * Qa.P + ta] * Qb.qval[(size_t)qb * Qb.P + tb] * wa[q];
+                    const int64_t node = node_index(P.n, idx[0], idx[1], idx[2]);
+                    for (int c = 0; c < dim; ++c) F[(size_t)c * P.nodes + node] += b * g[q * dim + c];
+                }
+        }
+}
+
 bool on_face(const PatchPlan& pp, int64_t node, int face) {
     int fd = face / 2, side = face % 2;
     int64_t i1 = node % pp.n[0];
@@ -210,6 +379,22 @@ bool is_gamma(const PatchPlan& pp, int64_t node) {
 }  // namespace
 
 // ------------------------------------------------------------------ spline
+int check_open_knots(const std::vector<double>& t, int p) {
+    const int m = (int)t.size();
+    if (m < 2 * (p + 1)) fail(AFIETI_EINVAL, "knot vector too short for its degree");
+    for (int i = 0; i <= p; ++i)
+        if (t[i] != 0.0 || t[m - 1 - i] != 1.0) fail(AFIETI_EINVAL, "knot vector must be open on [0, 1]");
+    int mult = 0, worst = 0;
+    for (int i = p + 1; i < m - p - 1; ++i) {
+        if (!std::isfinite(t[i]) || t[i] < t[i - 1] || !(t[i] > 0.0) || !(t[i] < 1.0))
+            fail(AFIETI_EINVAL, "interior knots must be non-decreasing inside (0, 1)");
+        mult = (i > p + 1 && t[i] == t[i - 1]) ? mult + 1 : 1;
+        worst = std::max(worst, mult);
+    }
+    if (worst > p) fail(AFIETI_EINVAL, "interior knot multiplicity above the degree (discontinuous splines)");
+    return p - std::max(worst, 1);
+}
+
 std::vector<double> open_uniform_knots(int n_el, int p, int reg) {
     if (p < 1 || reg < 0 || reg >= p || n_el < 1) fail(AFIETI_EINVAL, "need p >= 1, 0 <= reg < p, n_el >= 1");
     std::vector<double> t(p + 1, 0.0);
@@ -431,11 +616,25 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
             }
             if (dim == 2)
                 for (int c = 0; c < 4; ++c) P.corners[3 * c + 2] = 0.0;
-            for (int f = 0; f < 6; ++f) P.bc[f] = f < 2 * dim ? in.face_bc[f] : 0;
+            for (int f = 0; f < 6; ++f) {
+                P.bc[f] = f < 2 * dim ? in.face_bc[f] : 0;
+                if (P.bc[f] < AFIETI_FACE_FREE || P.bc[f] > AFIETI_FACE_TRACTION) fail(AFIETI_EINVAL, "bad face condition");
+                if (P.bc[f] == AFIETI_FACE_TRACTION && !pr.traction)
+                    fail(AFIETI_EINVAL, "a traction face needs the problem's traction callback");
+            }
+            int reg_min = in.p;
             for (int l = 0; l < 3; ++l) {
                 if (l < dim) {
-                    if (in.n_el[l] < 1) fail(AFIETI_EINVAL, "n_el must be >= 1");
-                    build_dir(P.dir[l], in.n_el[l], in.p, in.reg);
+                    std::vector<double> kv;
+                    if (in.knots[l]) {
+                        kv.assign(in.knots[l], in.knots[l] + std::max(in.n_knots[l], 0));
+                        reg_min = std::min(reg_min, check_open_knots(kv, in.p));
+                    } else {
+                        if (in.n_el[l] < 1) fail(AFIETI_EINVAL, "n_el must be >= 1");
+                        kv = open_uniform_knots(in.n_el[l], in.p, in.reg);
+                        reg_min = std::min(reg_min, in.n_el[l] > 1 ? in.reg : in.p - 1);
+                    }
+                    build_dir(P.dir[l], kv, in.p);
                     if (P.dir[l].n < 3) fail(AFIETI_EINVAL, "need at least 3 basis functions per direction");
                     if (P.dir[l].n > 48) fail(AFIETI_EUNSUPPORTED, "at most 48 basis functions per direction");
                 } else {
@@ -443,6 +642,8 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
                 }
                 P.n[l] = P.dir[l].n;
             }
+            // smallest continuity across the patch's interior knots
+            P.reg = std::min(reg_min, in.p - 1);
             P.nodes = (int64_t)P.n[0] * P.n[1] * P.n[2];
             P.dof_off = dof;
             dof += dim * P.nodes;
@@ -489,6 +690,20 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
             plan.patches.push_back(std::move(P));
         }
         pp.n_dof = dof - pp.dof_off;
+        // ---- loads of the callbacks (body force, tractions)
+        bool any_traction = false;
+        for (int k = 0; k < pr.n_patches; ++k)
+            for (int f = 0; f < 2 * dim; ++f) any_traction |= plan.patches[pp.patch0 + k].bc[f] == AFIETI_FACE_TRACTION;
+        if (pr.body_force || any_traction) {
+            pp.fixed_load.assign(pp.n_dof, 0.0);
+            for (int k = 0; k < pr.n_patches; ++k) {
+                const PatchPlan& P = plan.patches[pp.patch0 + k];
+                double* F = pp.fixed_load.data() + (P.dof_off - pp.dof_off);
+                if (pr.body_force) add_body_force(P, pr.body_force, pr.ctx, F);
+                for (int f = 0; f < 2 * dim; ++f)
+                    if (P.bc[f] == AFIETI_FACE_TRACTION) add_traction(P, f, pr.traction, pr.ctx, F);
+            }
+        }
 
         // ---- node matching across faces (union-find over patch nodes)
         std::vector<int64_t> node_off(pr.n_patches + 1, 0);
@@ -545,10 +760,16 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
                             int jb = diff == 1 ? 0 : 1;
                             to[j] = tb[jb];
                             flip[j] = (u0 >> jb) & 1;
-                            if (A.n[ta[j]] != B.n[to[j]] || A.p != B.p || A.reg != B.reg ||
-                                A.dir[ta[j]].n_el != B.dir[to[j]].n_el)
-                                fail(AFIETI_EGEOM, "non-conforming interface");
+                            // equal knot vectors along the face (reversed where flipped)
+                            const std::vector<double>& ka = A.dir[ta[j]].knots;
+                            const std::vector<double>& kb = B.dir[to[j]].knots;
+                            bool same = A.p == B.p && ka.size() == kb.size();
+                            for (size_t i = 0; same && i < ka.size(); ++i)
+                                same = std::fabs(ka[i] - (flip[j] ? 1.0 - kb[kb.size() - 1 - i] : kb[i])) <= 1e-12;
+                            if (!same) fail(AFIETI_EGEOM, "non-conforming interface");
                         }
+                        if (A.bc[fa] == AFIETI_FACE_TRACTION || B.bc[fb] == AFIETI_FACE_TRACTION)
+                            fail(AFIETI_EGEOM, "a traction face is an interface");
                         // unite the face nodes
                         int na1 = A.n[ta[0]], na2 = dim == 3 ? A.n[ta[1]] : 1;
                         for (int s2 = 0; s2 < na2; ++s2)
@@ -630,10 +851,40 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
         crow = (int64_t)plan.c_plus.size();
         pp.n_c = crow - pp.c_off;
         if (pp.n_c == 0) fail(AFIETI_ESINGULAR, "no constraints: the problem has no Dirichlet boundary");
+        // ---- Dirichlet data: g_D at the control point of every Dirichlet
+        // copy, one call for the problem; rows of the Dirichlet nodes read
+        // B u = g_D
+        if (pr.dirichlet) {
+            std::vector<int64_t> rows;
+            std::vector<double> pts;
+            for (int64_t r = pp.c_off; r < crow; ++r) {
+                if (plan.c_minus[r] >= 0) continue;
+                const PatchPlan& P = plan.patches[plan.c_patch_plus[r]];
+                const int64_t loc = plan.c_plus[r] - P.dof_off;
+                const int64_t nd = loc % P.nodes;
+                rows.push_back(r);
+                for (int x = 0; x < dim; ++x) pts.push_back(P.ctrl[nd * 3 + x]);
+            }
+            std::vector<double> val(pts.size(), 0.0);
+            if (!rows.empty()) pr.dirichlet((int64_t)rows.size(), pts.data(), val.data(), pr.ctx);
+            if (plan.c_rhs.empty()) plan.c_rhs.assign(crow, 0.0);
+            plan.c_rhs.resize(crow, 0.0);
+            for (size_t i = 0; i < rows.size(); ++i) {
+                const int64_t r = rows[i];
+                const PatchPlan& P = plan.patches[plan.c_patch_plus[r]];
+                const int comp = (int)((plan.c_plus[r] - P.dof_off) / P.nodes);
+                const double v = val[i * dim + comp];
+                if (!std::isfinite(v)) fail(AFIETI_EINVAL, "non-finite Dirichlet data");
+                plan.c_rhs[r] = v;
+            }
+        } else if (!plan.c_rhs.empty()) {
+            plan.c_rhs.resize(crow, 0.0);
+        }
         plan.probs.push_back(std::move(pp));
     }
     plan.n_dof = dof;
     plan.n_c = crow;
+    if (!plan.c_rhs.empty()) plan.c_rhs.resize(crow, 0.0);
     if (plan.n_dof > (int64_t)INT32_MAX || plan.n_c > (int64_t)INT32_MAX)
         fail(AFIETI_EUNSUPPORTED, "more than 2^31 unknowns");
 

@@ -59,6 +59,9 @@ struct ProblemPlan {
     std::vector<double> Cinv;     // (G^T G)^{-1}, dense (n_modes*N_p)^2
     std::vector<double> CtC;      // G^T G (for export)
     std::vector<afieti_load_mode> load;
+    // load of the body-force and traction callbacks (n_dof of the problem,
+    // patch-stacked), empty without callbacks
+    std::vector<double> fixed_load;
 };
 
 struct Plan {
@@ -78,6 +81,9 @@ struct Plan {
     std::vector<int> c_patch_plus, c_patch_minus;  // patch of each copy (-1)
     // (R^(k)T R^(k))^{-1} per patch, [k][6][6]
     std::vector<double> RtR_inv;
+    // right-hand side of the constraints B u = c: the Dirichlet data of the
+    // Dirichlet rows (zero on interface rows); empty when all data are zero
+    std::vector<double> c_rhs;
 };
 
 // Build the host plan.  Throws SetupError.
@@ -85,6 +91,9 @@ Plan build_plan(const afieti_problem* probs, int n_problems);
 
 // Helpers exposed for testing.
 std::vector<double> open_uniform_knots(int n_el, int p, int reg);
+// checks an explicit open knot vector of degree p on [0, 1]; returns the
+// smallest continuity p - (largest interior multiplicity)
+int check_open_knots(const std::vector<double>& t, int p);
 void bspline_eval(const std::vector<double>& knots, int p, double x, int& first,
                   double* val, double* der);
 void gauss_legendre(int n, double* x, double* w);

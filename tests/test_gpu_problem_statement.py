@@ -1,0 +1,255 @@
+"""The general problem statement through the C ABI on the GPU: explicit
+knot vectors, a body force and tractions on Gamma_N given as host
+callbacks, non-homogeneous Dirichlet data (lifted), caller load vectors in
+the adjoint, and the weak-scaling workload (unit cube of k^3 patches with a
+manufactured solution).  Each against the CPU oracle on the same input;
+exactly representable fields also against the field itself."""
+import copy
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.afieti import AFIETI
+from oracle.direct import solve_conforming
+from minres_band import same_iterations
+from test_oracle_problem import _with_boundary_data, _at_gauss_points
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+    print(f"  max rel err {err:.3e}", flush=True)
+    return err
+
+
+def _linear(prob, seed):
+    d = prob["dim"]
+    rng = np.random.default_rng(seed)
+    a, G = rng.standard_normal(d), rng.standard_normal((d, d))
+    prob = _with_boundary_data(prob, lambda x: a + x @ G.T, lambda x: np.broadcast_to(G, (len(x), d, d)))
+    prob["body_force"] = None
+    return prob, a, G
+
+
+def _general(prob, seed=0):
+    """Load modes kept, plus a body force, tractions on the outer faces that
+    are not Dirichlet and Dirichlet data."""
+    d = prob["dim"]
+    rng = np.random.default_rng(seed)
+    A, b = rng.standard_normal((d, d)), rng.standard_normal(d)
+    modes = prob["load"]
+    lame = [(pd["lam"], pd["mu"]) for pd in prob["patches"]]
+    prob = _with_boundary_data(prob, lambda x: 0.1 * (x @ A + b * np.prod(x, axis=1, keepdims=True)),
+                               lambda x: np.zeros((len(x), d, d)))
+    prob["load"] = modes
+    for pd, (lam, mu) in zip(prob["patches"], lame):
+        pd["lam"], pd["mu"] = lam, mu
+    prob["body_force"] = lambda x: np.sin(x @ A.T) + b
+    prob["traction"] = lambda x, n: np.cos(x @ A) * n[:, ::-1] + x
+    return prob
+
+
+LINEAR = {
+    "c2_perturbed": lambda: W.make_c2(n_el=3, p=2, seed=5),
+    "c1_2d": lambda: W.make_c1(n_el=4, p=2, seed=9),
+    "c3_p3": lambda: W.make_c3(n_el=2, p=3, grid=(2, 1, 2), seed=1),
+}
+
+
+@pytest.mark.parametrize("name", list(LINEAR))
+def test_linear_field_patch_test(name):
+    """u* = a + G x with Dirichlet data u* and tractions sigma(u*) n: the
+    GPU solve reproduces u*'s coefficients (its values at the control
+    points)."""
+    torch = _torch()
+    from paper_2001_09626_amd import Solver
+    print(f"\n[linear field {name}]", flush=True)
+    prob, a, G = _linear(LINEAR[name](), 3)
+    o = AFIETI(prob)
+    ustar = o.join([np.moveaxis(a + pa.ctrl @ G.T, -1, 0) for pa in o.patches])
+    s = Solver(prob, tol=1e-12)
+    u, _, st = s.solve()
+    assert st["converged"]
+    assert _rel(_host(u), ustar) <= 1e-9
+    s.close()
+    del torch
+
+
+def test_quadratic_field_with_body_force():
+    """Affine cube patches, p = 2, u* = a + G x + z (H x): constant body
+    force, linear tractions, linear data on z = 0; the GPU solution equals
+    the oracle's direct solve and u* at the Gauss points."""
+    _torch()
+    from paper_2001_09626_amd import Solver
+    prob = W.make_c2(n_el=3, p=2, seed=0, delta=0.0)
+    rng = np.random.default_rng(4)
+    a, G, H = rng.standard_normal(3), rng.standard_normal((3, 3)), rng.standard_normal((3, 3))
+
+    def u_fn(x):
+        return a + x @ G.T + x[:, 2:3] * (x @ H.T)
+
+    def grad_fn(x):
+        g = np.array(G + x[:, 2, None, None] * H)
+        g[:, :, 2] += x @ H.T
+        return g
+
+    prob = _with_boundary_data(prob, u_fn, grad_fn)
+    o = AFIETI(prob)
+    s = Solver(prob, tol=1e-12)
+    u, _, st = s.solve()
+    u = _host(u)
+    assert st["converged"]
+    assert _rel(u, solve_conforming(o)) <= 1e-9
+    uq, xq = _at_gauss_points(o, u)
+    assert _rel(uq, u_fn(xq)) <= 1e-9
+    s.close()
+
+
+GENERAL = {
+    "c2": lambda: W.make_c2(n_el=4, p=3, seed=2),
+    "c1": lambda: W.make_c1(n_el=5, p=2, seed=3),
+    "c3_ragged": lambda: W.make_c3(n_el=3, p=2, grid=(2, 3, 2), seed=4),
+}
+
+
+@pytest.fixture(scope="module", params=list(GENERAL))
+def general(request):
+    _torch()
+    from paper_2001_09626_amd import Solver
+    print(f"\n[general problem {request.param}]", flush=True)
+    prob = _general(GENERAL[request.param]())
+    o = AFIETI(prob)
+    s = Solver(prob, tol=1e-8)
+    yield prob, o, s
+    s.close()
+
+
+def test_load_and_dirichlet_lift(general):
+    """The assembled load (modes, body force, tractions) and the lift u_D
+    equal the oracle's to FP64 rounding."""
+    prob, o, s = general
+    assert _rel(_host(s.apply("load")), o.load()) <= 1e-12
+    ud = _host(s.apply("dirichlet_lift"))
+    assert np.count_nonzero(o.u_dir) > 0
+    assert _rel(ud, o.u_dir) <= 1e-12
+
+
+def test_general_solve_parity(general):
+    """Tolerance 1e-8: iteration counts under the band rule; tolerance
+    1e-12: the solutions agree to 1e-10 and both equal the direct
+    conforming solve to 1e-9."""
+    prob, o, s = general
+    ref = o.solve(tol=1e-8)
+    u, lam, st = s.solve()
+    print(f"  iterations gpu {st['iterations']} oracle {ref['iters']}", flush=True)
+    assert same_iterations(st["iterations"], ref, 1e-8)
+    from paper_2001_09626_amd import Solver
+    s12 = Solver(prob, tol=1e-12)
+    u12, _, st12 = s12.solve()
+    u12 = _host(u12)
+    ref12 = o.solve(tol=1e-12)
+    assert same_iterations(st12["iterations"], ref12, 1e-12)
+    assert _rel(u12, ref12["u"]) <= 1e-10
+    assert _rel(u12, solve_conforming(o)) <= 1e-9
+    s12.close()
+
+
+def test_graded_knots_parity():
+    """Explicit non-uniform knots with an interior double knot: FD apply,
+    stiffness, load and the solve agree with the oracle."""
+    torch = _torch()
+    from paper_2001_09626_amd import Solver
+    kv = np.array([0, 0, 0, 0, 0.15, 0.3, 0.3, 0.55, 0.8, 1, 1, 1, 1.0])
+    prob = W.make_c2(n_el=2, p=3, seed=7)
+    for pd in prob["patches"]:
+        pd["knots"] = [kv, kv, kv]
+    o = AFIETI(prob)
+    assert o.patches[0].n == [9, 9, 9]
+    s = Solver(prob, tol=1e-12)
+    r = W.random_vector(o.n_dof, 11)
+    rd = torch.from_numpy(r).cuda()
+    assert _rel(_host(s.apply_fd(rd)), o.apply_PA_inv(r)) <= 1e-12
+    assert _rel(_host(s.apply("stiffness", rd)), o.apply_A(r)) <= 1e-12
+    assert _rel(_host(s.apply("load")), o.load()) <= 1e-12
+    u, _, st = s.solve()
+    ref = o.solve(tol=1e-12)
+    assert same_iterations(st["iterations"], ref, 1e-12)
+    assert _rel(_host(u), ref["u"]) <= 1e-10
+    s.close()
+
+
+def test_adjoint_load_vectors():
+    """dJ/dc for the caller's load vectors: with the unit load modes as the
+    vectors it equals dJ/d(amplitude); for a random vector it is psi . F."""
+    torch = _torch()
+    from paper_2001_09626_amd import Solver
+    prob = W.make_c2(n_el=4, p=3, seed=3)
+    o = AFIETI(prob)
+    s = Solver(prob, tol=1e-12)
+    u, _, _ = s.solve()
+    dJdu = torch.from_numpy(W.random_vector(o.n_dof, 21)).cuda()
+    per_patch = [pa.mode_loads(o.load_modes) for pa in o.patches]
+    F = np.array([o.join([pp[j] for pp in per_patch]) for j in range(len(o.load_modes))])
+    F = np.concatenate([F, W.random_vector(o.n_dof, 22)[None]])
+    psi, dl, dm, da, its, dv = s.solve_adjoint(dJdu, u, load_vectors=torch.from_numpy(F).cuda())
+    n = len(o.load_modes)
+    assert _rel(dv[:n], da) <= 1e-12
+    ref = F[n] @ _host(psi)
+    assert abs(dv[n] - ref) <= 1e-12 * np.abs(F[n]).max() * np.abs(_host(psi)).sum()
+    s.close()
+
+
+def test_weak_scaling_workload_parity():
+    """The weak-scaling workload (2^3 unit-cube patches, manufactured
+    solution, Dirichlet data on four sides, tractions on two): GPU and
+    oracle take the same iterations and reach the same solution."""
+    _torch()
+    from paper_2001_09626_amd import Solver
+    prob = W.make_weak_scaling(k=2, n_el=4, p=3)
+    o = AFIETI(prob)
+    s = Solver(prob, tol=1e-8)
+    u, _, st = s.solve()
+    ref = o.solve(tol=1e-8)
+    print(f"  iterations gpu {st['iterations']} oracle {ref['iters']}", flush=True)
+    assert same_iterations(st["iterations"], ref, 1e-8)
+    assert _rel(_host(s.apply("load")), o.load()) <= 1e-12
+    assert _rel(_host(s.apply("dirichlet_lift")), o.u_dir) <= 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_weak_scaling_iterations_and_error(k):
+    """k^3 patches of 8^3 elements, p = 3: the solve converges, the error
+    against the exact solution at the Gauss points stays at the
+    discretisation level, and the iteration count is bounded as k grows
+    (the method's weak scalability)."""
+    _torch()
+    from paper_2001_09626_amd import Solver
+    prob = W.make_weak_scaling(k=k, n_el=8, p=3)
+    s = Solver(prob, tol=1e-8)
+    u, _, st = s.solve()
+    print(f"  k={k} patches={k ** 3} n_dof={s.n_dof} iterations {st['iterations']} ms {st['ms']:.1f}", flush=True)
+    assert st["converged"]
+    assert st["iterations"] <= 200
+    if k == 2:
+        o = AFIETI(prob, assembled=False)
+        uq, xq = _at_gauss_points(o, _host(u))
+        err = np.abs(uq - W.weak_scaling_solution(xq)).max()
+        print(f"  max error at Gauss points {err:.3e}", flush=True)
+        assert err <= 3e-3  # oracle direct solve: 2.06e-3
+    s.close()

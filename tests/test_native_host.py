@@ -117,3 +117,103 @@ def test_strerror_table():
     L = N.lib()
     for code in [0, 1, -1, -2, -3, -4, -5, -6, -7]:
         assert len(L.afieti_strerror(code)) > 0
+
+
+def _general_problem(mk, seed=0, knots=None):
+    """A problem with body force, tractions on half of its Neumann outer
+    faces and Dirichlet data, no load modes."""
+    prob = mk()
+    o = AFIETI(prob)
+    rng = np.random.default_rng(seed)
+    d = prob["dim"]
+    A, Bm = rng.standard_normal((d, d)), rng.standard_normal(d)
+    for pa, pd in zip(o.patches, prob["patches"]):
+        for f in range(2 * d):
+            fd, side = f // 2, f % 2
+            idx = [c for c in range(2 ** d) if ((c >> fd) & 1) == side]
+            if pd["bc"][f] == 0 and np.allclose(pa.corners[idx, fd], float(side)) and f % 2 == 1:
+                pd["bc"][f] = 2
+        if knots is not None:
+            pd["knots"] = knots
+    prob["load"] = []
+    prob["body_force"] = lambda x: np.sin(x @ A.T) + Bm
+    prob["traction"] = lambda x, n: np.cos(x @ A) * n[:, ::-1] + x
+    prob["dirichlet"] = lambda x: x @ A + Bm * np.prod(x, axis=1, keepdims=True)
+    return prob
+
+
+GENERAL = [lambda: W.make_c1(n_el=3, p=2, seed=4),
+           lambda: W.make_c2(n_el=2, p=3, seed=1),
+           lambda: W.make_c3(n_el=2, p=2, grid=(2, 1, 2), seed=3)]
+
+
+@pytest.mark.parametrize("mk", GENERAL)
+def test_host_load_and_dirichlet_data_match_oracle(mk):
+    """Body force and traction integrals assembled on the host and the
+    Dirichlet right-hand side c agree with the oracle's."""
+    from paper_2001_09626_amd import Solver
+    prob = _general_problem(mk)
+    assert any(2 in pd["bc"] for pd in prob["patches"])
+    s = Solver(prob, host_only=True)
+    o = AFIETI(prob)
+    F = s.export("fixed_load")
+    Fo = o.load()
+    assert np.abs(F - Fo).max() <= 1e-13 * np.abs(Fo).max()
+    c = s.export("dirichlet_c")
+    assert np.count_nonzero(o.c) > 0
+    assert np.abs(c - o.c).max() <= 1e-14 * np.abs(o.c).max()
+    s.close()
+
+
+def test_host_explicit_graded_knots_match_oracle():
+    """Explicit non-uniform open knot vectors (one interior double knot,
+    so C^(p-2) there): B, eigenvalues, G^T G and the load agree with the
+    oracle, and the uniform vector given explicitly equals the default."""
+    from paper_2001_09626_amd import Solver
+    kv = np.array([0, 0, 0, 0, 0.2, 0.45, 0.45, 1, 1, 1, 1.0])
+    prob = _general_problem(lambda: W.make_c2(n_el=2, p=3, seed=2), knots=[kv] * 3)
+    s = Solver(prob, host_only=True)
+    o = AFIETI(prob)
+    assert (s.n_dof, s.n_c) == (o.n_dof, o.n_c)
+    assert o.patches[0].n == [7, 7, 7]
+    D = s.export("eig")
+    Do = np.concatenate([o.fd[k][m]["D"] for k in range(len(o.patches)) for m in range(3)])
+    assert np.abs(D - Do).max() <= 1e-13 * np.abs(Do).max()
+    Fo = o.load()
+    assert np.abs(s.export("fixed_load") - Fo).max() <= 1e-13 * np.abs(Fo).max()
+    s.close()
+    prob = W.make_c2(n_el=3, p=2, seed=2)
+    a = Solver(prob, host_only=True)
+    for pd in prob["patches"]:
+        pd["knots"] = [np.array([0, 0, 0, 1 / 3, 2 / 3, 1, 1, 1.0])] * 3
+    b = Solver(prob, host_only=True)
+    for what in ("B", "eig", "H", "GtG"):
+        assert np.array_equal(a.export(what), b.export(what)), what
+
+
+def test_problem_statement_error_codes():
+    # traction face without a traction callback
+    prob = _general_problem(lambda: W.make_c1(n_el=2))
+    prob["traction"] = None
+    _expect_error(prob, -1)
+    # traction on an interface face
+    prob = W.make_c1(n_el=2)
+    pd = prob["patches"][0]
+    pd["bc"] = [2 if b == 0 else b for b in pd["bc"]]
+    prob["traction"] = lambda x, n: x
+    _expect_error(prob, -2)
+    # knot vector that is not open
+    prob = W.make_c1(n_el=2, p=2)
+    for pd in prob["patches"]:
+        pd["knots"] = [np.array([0, 0, 0.5, 1, 1, 1.0])] * 2
+    _expect_error(prob, -1)
+    # decreasing knots
+    prob = W.make_c1(n_el=2, p=2)
+    for pd in prob["patches"]:
+        pd["knots"] = [np.array([0, 0, 0, 0.6, 0.4, 1, 1, 1.0])] * 2
+    _expect_error(prob, -1)
+    # knots that differ across an interface
+    prob = W.make_c1(n_el=2, p=2)
+    prob["patches"][0]["knots"] = [np.array([0, 0, 0, 0.3, 1, 1, 1.0])] * 2
+    prob["patches"][1]["knots"] = [np.array([0, 0, 0, 0.5, 1, 1, 1.0])] * 2
+    _expect_error(prob, -2)

@@ -20,11 +20,16 @@ Problem dictionary layout
     ``n_el``     elements per parametric direction (uniform open knots).
     ``lam``, ``mu``  Lame parameters of the patch.
     ``bc``       2*dim face flags, order (dir1 min, dir1 max, dir2 min, ...):
-                 0 = natural (traction-free or interface), 1 = Dirichlet u=0.
+                 0 = natural (traction-free or interface), 1 = Dirichlet
+                 (u = 0, or the problem's ``dirichlet`` data), 2 = traction
+                 (the problem's ``traction``).
+    ``knots``    optional: explicit open knot vectors per direction.
 ``load``         list of separable trigonometric body-force modes
                  (component, amplitude, k[dim], phase[dim]) meaning
                  f_component(x) += amplitude * prod_d sin(pi*k_d*x_d + phase_d).
 ``tol``          MINRES tolerance on the preconditioned residual ratio.
+``body_force``, ``traction``, ``dirichlet``  optional callables on arrays of
+                 points (n, dim): f(x), g(x, normal), g_D(x), each -> (n, dim).
 
 Material constants: E = 1, nu = 0.3 gives lambda = 0.3/0.52, mu = 1/2.6
 (the paper's "steel" values, Section 6).
@@ -41,6 +46,7 @@ STEEL_MU = 1.0 / 2.6
 
 FACE_FREE = 0
 FACE_DIRICHLET = 1
+FACE_TRACTION = 2
 
 
 def _grid_vertices(grid, rng, delta):
@@ -193,6 +199,58 @@ def make_c5(seed=0, n_el=32, p=3, grid=(3, 3, 3), rel_delta=0.1, n_modes=64):
                                  [(2, 0)])
     return dict(name="c5", dim=3, patches=patches,
                 load=_random_modes(rng, n_modes, 3), tol=1e-8)
+
+
+def make_weak_scaling(k=2, n_el=8, p=3):
+    """Weak-scaling workload of the paper's third test (Section 6): the unit
+    cube split into k^3 equal cubes, p = 3 C^2, n_el^3 elements per patch,
+    E = 1, nu = 0.3, exact solution u* = (cos x, z sin y, (x y z)^2):
+    traction sigma(u*) n on x = 0 and x = 1, Dirichlet data u* on the other
+    four faces, body force f = -div sigma(u*).  Every entry is a closed-form
+    function of the point (problem data), evaluated on arrays of points."""
+    grid = (k, k, k)
+    verts = _grid_vertices(grid, np.random.default_rng(0), 0.0)
+    n_p = k ** 3
+    lam, mu = STEEL_LAM, STEEL_MU
+    patches = _patches_from_grid(grid, verts, p, p - 1, [n_el] * 3, np.full(n_p, lam), np.full(n_p, mu),
+                                 [(1, 0), (1, 1), (2, 0), (2, 1)])
+    for pd in patches:
+        for f in (0, 1):
+            if pd["bc"][f] == FACE_FREE and np.allclose(pd["corners"][[c for c in range(8) if (c & 1) == f], 0], f):
+                pd["bc"][f] = FACE_TRACTION
+    return dict(name=f"weak_{k}", dim=3, patches=patches, load=[], tol=1e-8,
+                body_force=lambda x: weak_scaling_force(x, lam, mu),
+                traction=lambda x, n: np.einsum("nij,nj->ni", weak_scaling_stress(x, lam, mu), n),
+                dirichlet=weak_scaling_solution, exact=weak_scaling_solution)
+
+
+def weak_scaling_solution(x):
+    """u*(x) = (cos x, z sin y, (x y z)^2) at points x (n, 3)."""
+    X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+    return np.stack([np.cos(X), Z * np.sin(Y), (X * Y * Z) ** 2], axis=1)
+
+
+def weak_scaling_stress(x, lam, mu):
+    """sigma(u*) = mu (grad u* + grad u*^T) + lam (div u*) I at points x."""
+    X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+    g = np.zeros((len(x), 3, 3))  # g[n, c, a] = d u*_c / d x_a
+    g[:, 0, 0] = -np.sin(X)
+    g[:, 1, 1] = Z * np.cos(Y)
+    g[:, 1, 2] = np.sin(Y)
+    g[:, 2, 0] = 2 * X * Y ** 2 * Z ** 2
+    g[:, 2, 1] = 2 * X ** 2 * Y * Z ** 2
+    g[:, 2, 2] = 2 * X ** 2 * Y ** 2 * Z
+    div = g[:, 0, 0] + g[:, 1, 1] + g[:, 2, 2]
+    return mu * (g + np.swapaxes(g, 1, 2)) + lam * div[:, None, None] * np.eye(3)
+
+
+def weak_scaling_force(x, lam, mu):
+    """f = -div sigma(u*) = -mu lap u* - (mu + lam) grad div u* at points x."""
+    X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+    lap = np.stack([-np.cos(X), -Z * np.sin(Y), 2 * (Y ** 2 * Z ** 2 + X ** 2 * Z ** 2 + X ** 2 * Y ** 2)], axis=1)
+    gdiv = np.stack([-np.cos(X) + 4 * X * Y ** 2 * Z, -Z * np.sin(Y) + 4 * X ** 2 * Y * Z,
+                     np.cos(Y) + 2 * X ** 2 * Y ** 2], axis=1)
+    return -mu * lap - (mu + lam) * gdiv
 
 
 def redraw_parameters(prob, seed):
