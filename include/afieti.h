@@ -168,6 +168,13 @@ typedef struct {
                             (0: 64, 1: 128 columns per block of the mode-3
                             pass).  All shapes give bitwise identical
                             results.                                       */
+    double ps_weight;    /* weight w of the multiplier block of the
+                            preconditioner, [P_u P_A^-1 P_u ; w P_chi P_S
+                            P_chi] (1).  Any w > 0 keeps it positive
+                            definite (w = 1 is the method as stated);
+                            w <= 0 makes it indefinite, and MINRES stops
+                            with AFIETI_EBREAKDOWN at the first iteration
+                            whose <z, v> is negative.                      */
 } afieti_options;
 
 typedef struct {
@@ -306,7 +313,9 @@ int afieti_apply(afieti_handle* h, int op, const double* x, double* y, void* str
  *  what = 4: the load terms assembled on the host, body force and
  *            tractions of every problem, DOF-ordered (double, n_dof)
  *  what = 5: c, the right-hand side of B u = c: Dirichlet data on the
- *            Dirichlet rows, zero elsewhere (double, n_c)                  */
+ *            Dirichlet rows, zero elsewhere (double, n_c)
+ *  what = 6: eigenvectors U of every patch and direction, in the order of
+ *            what = 1, each n x n row major (column j: eigenvalue j)      */
 int afieti_export(const afieti_handle* h, int what, void* buf, int64_t buf_bytes);
 int64_t afieti_export_size(const afieti_handle* h, int what);
 

@@ -109,7 +109,8 @@ class Solver:
     """One handle over one or more independent problems."""
 
     def __init__(self, problems, tol=1e-8, maxit=5000, fd_precision="fp64", ps_variant="nr",
-                 check_every=12, host_only=False, use_graph=True, stiffness="auto", fd_tune=-1):
+                 check_every=12, host_only=False, use_graph=True, stiffness="auto", fd_tune=-1,
+                 ps_weight=1.0):
         L = N.lib()
         self._L = L
         arr, keep = to_c_problems(problems)
@@ -124,6 +125,7 @@ class Solver:
         opt.use_graph = 1 if use_graph else 0
         opt.stiffness = N.STIFFNESS[stiffness]
         opt.fd_tune = int(fd_tune)
+        opt.ps_weight = float(ps_weight)
         self.host_only = host_only
         h = C.c_void_p()
         stream = C.c_void_p(0) if host_only else _stream()

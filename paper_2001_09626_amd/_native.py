@@ -10,6 +10,7 @@ LIB_PATH = os.environ.get("AFIETI_LIBRARY") or os.path.join(HERE, "libafieti.so"
 
 OK = 0
 NOT_CONVERGED = 1
+EBREAKDOWN = -4
 ERRORS = {-1: "EINVAL", -2: "EGEOM", -3: "ESINGULAR", -4: "EBREAKDOWN",
           -5: "ENOMEM", -6: "EHIP", -7: "EUNSUPPORTED"}
 
@@ -21,7 +22,7 @@ OPS = {"stiffness": 0, "B": 1, "Bt": 2, "P_u": 3, "P_chi": 4, "Shat": 5, "P_S": 
        "prec": 7, "saddle": 8, "fd_interior": 9, "Ahat": 10, "mass": 11, "load": 12,
        "dirichlet_lift": 13}
 
-EXPORT = {"B": 0, "eig": 1, "H": 2, "GtG": 3, "fixed_load": 4, "dirichlet_c": 5}
+EXPORT = {"B": 0, "eig": 1, "H": 2, "GtG": 3, "fixed_load": 4, "dirichlet_c": 5, "eigvec": 6}
 
 
 class Patch(C.Structure):
@@ -50,7 +51,8 @@ class Problem(C.Structure):
 class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("fd_precision", C.c_int),
                 ("ps_variant", C.c_int), ("check_every", C.c_int), ("host_only", C.c_int),
-                ("use_graph", C.c_int), ("stiffness", C.c_int), ("fd_tune", C.c_int)]
+                ("use_graph", C.c_int), ("stiffness", C.c_int), ("fd_tune", C.c_int),
+                ("ps_weight", C.c_double)]
 
 
 class Info(C.Structure):

@@ -959,13 +959,13 @@ void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hi
     op_fd_tmp(h, set, in, out, h->lane[ln].fdtmp, s);
 }
 
-// out = P_chi y  (in place allowed)
-void op_pchi(afieti_handle* h, const double* y, double* out, hipStream_t s, int ln = 0) {
+// out = w P_chi y  (in place allowed)
+void op_pchi(afieti_handle* h, const double* y, double* out, hipStream_t s, int ln = 0, double w = 1.0) {
     const Lane& L = h->lane[ln];
     launch_gamma_partial(h->d_gam_chunks, h->n_gam_chunks, h->d_mc_row, h->d_mc_val, h->n_mc, y, L.part, s);
     launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_gam_cptr, L.part,
                            h->d_cinv, L.zc, h->max_nc, s);
-    launch_G_apply(h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, h->n_c, L.zc, -1.0, 1.0, y, out, s);
+    launch_G_apply(h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, h->n_c, L.zc, -w, w, y, out, s);
 }
 
 // out = P_u x  (in place allowed)
@@ -1041,7 +1041,7 @@ void op_prec_branches(afieti_handle* h, const double* r, double* z, hipStream_t 
     // brick quadrature after it)
     if (h->capturing) HIP_OK(hipEventRecord(h->ev_ps, b.s));
     op_ps_stage(h, 4, h->c3, h->c4, b.s, b.ln);
-    op_pchi(h, h->c4, z + h->n_dof, b.s, b.ln);
+    op_pchi(h, h->c4, z + h->n_dof, b.s, b.ln, h->opt.ps_weight);
 }
 
 void op_prec(afieti_handle* h, const double* r, double* z, hipStream_t s) {
@@ -1140,10 +1140,11 @@ void minres_iteration(afieti_handle* h, hipStream_t s, MinresBufs& b, bool start
             // the second A-hat of P_S is still pending, it holds that kernel
             // back until the bricks drain, so it waits for it
             if (h->capturing) HIP_OK(hipStreamWaitEvent(s, h->ev_ps, 0));
-            // (it reads the stop flags while the Givens step below may set
-            // them: a problem that has just stopped is then either skipped
-            // or computed, and the gather, which runs after the join, skips
-            // it in both cases)
+            // (it reads the snapshot of the stop flags that k_minres_dv
+            // took before the fork, not the flags that the Givens step below
+            // writes: a problem that stops in this iteration is still
+            // computed by the bricks and by the gather of the next
+            // iteration, and skipped from the next k_minres_dv on)
             op_stiffness_bricks(h, b.z_new, s);
         }
         launch_dot_partial(h->d_vec_chunks, h->n_vec_chunks, b.z_new, b.v_new, h->d_part2, bp.s);
@@ -1328,6 +1329,7 @@ void afieti_default_options(afieti_options* opt) {
     opt->use_graph = 1;
     opt->stiffness = AFIETI_STIFFNESS_AUTO;
     opt->fd_tune = -1;
+    opt->ps_weight = 1.0;
 }
 
 const char* afieti_strerror(int code) {
@@ -1359,7 +1361,7 @@ int afieti_setup(const afieti_problem* probs, int n_problems, const afieti_optio
         if (!(h->opt.tol > 0) || h->opt.maxit < 1 ||
             (h->opt.fd_precision < AFIETI_FD_FP64 || h->opt.fd_precision > AFIETI_FD_FP64_VALU) ||
             (h->opt.ps_variant != AFIETI_PS_NR && h->opt.ps_variant != AFIETI_PS_PLAIN) ||
-            h->opt.fd_tune < -1 || h->opt.fd_tune >= 2 * kFdVariants)
+            h->opt.fd_tune < -1 || h->opt.fd_tune >= 2 * kFdVariants || !std::isfinite(h->opt.ps_weight))
             throw SetupError{AFIETI_EINVAL, "invalid options"};
         h->plan = build_plan(probs, n_problems);
         h->n_probs = (int)h->plan.probs.size();
@@ -1674,6 +1676,12 @@ int64_t afieti_export_size(const afieti_handle* h, int what) {
         }
         case 4: return pl.n_dof * (int64_t)sizeof(double);
         case 5: return pl.n_c * (int64_t)sizeof(double);
+        case 6: {
+            int64_t n = 0;
+            for (const auto& P : pl.patches)
+                for (int m = 0; m < P.dim; ++m) n += (int64_t)P.dir[m].n * P.dir[m].n;
+            return n * (int64_t)sizeof(double);
+        }
         default: return -1;
     }
 }
@@ -1703,6 +1711,10 @@ int afieti_export(const afieti_handle* h, int what, void* buf, int64_t buf_bytes
         std::fill(o, o + pl.n_dof, 0.0);
         for (const auto& pr : pl.probs)
             if (!pr.fixed_load.empty()) std::copy(pr.fixed_load.begin(), pr.fixed_load.end(), o + pr.dof_off);
+    } else if (what == 6) {
+        double* o = static_cast<double*>(buf);
+        for (const auto& P : pl.patches)
+            for (int m = 0; m < P.dim; ++m) o = std::copy(P.dir[m].U.begin(), P.dir[m].U.end(), o);
     } else {
         double* o = static_cast<double*>(buf);
         std::fill(o, o + pl.n_c, 0.0);

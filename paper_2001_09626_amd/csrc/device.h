@@ -90,6 +90,11 @@ struct MinresState {
     int its, maxit;
     int stop;                    // 1 converged, 2 breakdown, 3 maxit
     int upd;                     // 1 while the d/x update of this iteration is pending
+    int skip;                    // stop as it was before the preconditioner of this
+                                 // iteration forked (written by k_minres_dv on the
+                                 // main stream): the masked kernels read this copy,
+                                 // never stop, which the Givens step of the side
+                                 // branch may write meanwhile
 };
 
 }  // namespace afieti

@@ -262,7 +262,7 @@ __global__ void __launch_bounds__(kFdThreads) k_fdg_fwd(const FdGroup* __restric
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 it = slabs[blockIdx.x];
     const FdGroup& G = groups[it.x];
-    if (mask && mask[G.prob].stop) return;
+    if (mask && mask[G.prob].skip) return;
     const int i3 = it.y, n1 = G.n1, n2 = G.n2, nc = G.nc;
     const Pass12Layout L = pass12_layout<MODE, KM>(n1, n2, nc);
     T* XA = reinterpret_cast<T*>(smem);
@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(kFdThreads) k_fdg_mid(const FdGroup* __restric
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 it = cols[blockIdx.x];
     const FdGroup& G = groups[it.x];
-    if (mask && mask[G.prob].stop) return;
+    if (mask && mask[G.prob].skip) return;
     const int n1 = G.n1, n3 = G.n3;
     const int n12 = n1 * G.n2;
     const int64_t n123 = (int64_t)n12 * n3;
@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(kFdThreads) k_fdg_bwd(const FdGroup* __restric
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 it = slabs[blockIdx.x];
     const FdGroup& G = groups[it.x];
-    if (mask && mask[G.prob].stop) return;
+    if (mask && mask[G.prob].skip) return;
     const int i3 = it.y, n1 = G.n1, n2 = G.n2, nc = G.nc;
     const Pass12Layout L = pass12_layout<MODE, KM>(n1, n2, nc);
     T* ZA = reinterpret_cast<T*>(smem);

@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(kFdBlock) k_fd_fwd12(const FdTensor* __restric
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 it = slabs[blockIdx.x];
     const FdTensor t = tens[it.x];
-    if (mask && mask[t.prob].stop) return;
+    if (mask && mask[t.prob].skip) return;
     const int i3 = it.y, n1 = t.n1, n2 = t.n2, n12 = n1 * n2;
     T* X = reinterpret_cast<T*>(smem);
     T* Y = X + kMaxN * kMaxN;
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(kFdBlock) k_fd_mid3(const FdTensor* __restrict
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 it = cols[blockIdx.x];
     const FdTensor t = tens[it.x];
-    if (mask && mask[t.prob].stop) return;
+    if (mask && mask[t.prob].skip) return;
     const int n1 = t.n1, n3 = t.n3, n12 = t.n1 * t.n2;
     const int col0 = it.y * NC;
     T* Z = reinterpret_cast<T*>(smem);
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(kFdBlock) k_fd_bwd12(const FdTensor* __restric
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 it = slabs[blockIdx.x];
     const FdTensor t = tens[it.x];
-    if (mask && mask[t.prob].stop) return;
+    if (mask && mask[t.prob].skip) return;
     const int i3 = it.y, n1 = t.n1, n2 = t.n2, n12 = n1 * n2;
     T* Z = reinterpret_cast<T*>(smem);
     T* Y = Z + kMaxN * kMaxN;
@@ -601,7 +601,7 @@ __global__ void __launch_bounds__(kBlock) k_stiffness(const DevPatch* __restrict
     constexpr int P3 = DIM == 3 ? P : 0;
     const int4 b = rb[blockIdx.x];
     const DevPatch& pa = dps[b.x];
-    if (mask && mask[pa.prob].stop) return;
+    if (mask && mask[pa.prob].skip) return;
     const int64_t nodes = pa.nodes;
     const int64_t node = (int64_t)b.z + threadIdx.x;
     if (node >= nodes) return;
@@ -702,7 +702,7 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
     static_assert(2 * AK <= 9 * BK, "S must fit in the B / P buffer");
     const int4 br = bricks[blockIdx.x];
     const DevPatch& pa = dps[br.x];
-    if (mask && mask[pa.prob].stop) return;
+    if (mask && mask[pa.prob].skip) return;
     const int tid = threadIdx.x;
     const double* __restrict__ T1 = tab + pa.tab_off[0] + (int64_t)br.y * TS;
     const double* __restrict__ T2 = tab + pa.tab_off[1] + (int64_t)br.z * TS;
@@ -973,7 +973,7 @@ __global__ void __launch_bounds__(kBlock) k_mf_gather(const DevPatch* __restrict
     constexpr int NB3 = NB * NB * NB;
     const int4 b = rb[blockIdx.x];
     const DevPatch& pa = dps[b.x];
-    if (mask && mask[pa.prob].stop) return;
+    if (mask && mask[pa.prob].skip) return;
     const int64_t node = (int64_t)b.z + threadIdx.x;
     if (node >= pa.nodes) return;
     const int c = b.y;
@@ -1054,7 +1054,7 @@ __global__ void __launch_bounds__(kAhBlock) k_ahat(const DevPatch* __restrict__ 
     extern __shared__ __align__(16) unsigned char smem[];
     const int4 it = slabs[blockIdx.x];
     const DevPatch& pa = dps[it.x];
-    if (mask && mask[pa.prob].stop) return;
+    if (mask && mask[pa.prob].skip) return;
     const int l = it.y, i3 = it.z;
     const int n1 = pa.n[0], n2 = pa.n[1], n3 = pa.n[2], n12 = n1 * n2;
     const int p = P > 0 ? P : pa.p, W = 2 * p + 1;
@@ -1550,6 +1550,7 @@ __global__ void __launch_bounds__(kBlock) k_minres_init(MinresState* st, const i
         s.rel = s.gamma > 0 ? 1.0 : 0.0;
         s.stop = s.gamma > 0 ? 0 : 1;
     }
+    s.skip = s.stop;
     st[blockIdx.x] = s;
 }
 
@@ -1602,7 +1603,10 @@ __global__ void __launch_bounds__(kBlock) k_minres_dv(MinresState* __restrict__ 
     const int pr = c.seg;
     MinresState& s = st[pr];
     const bool first = (int)blockIdx.x == cptr[pr];
-    if (first && threadIdx.x == 0) s.upd = 0;
+    if (first && threadIdx.x == 0) {
+        s.upd = 0;
+        s.skip = s.stop;
+    }
     if (s.stop) return;
     {
         double acc[1] = {0.0};

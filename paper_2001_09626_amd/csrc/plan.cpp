@@ -496,6 +496,12 @@ void gauss_legendre(int n, double* x, double* w) {
 // M = L L^T (Cholesky), C = L^{-1} K L^{-T}, cyclic Jacobi rotations
 // C = V diag(d) V^T, U = L^{-T} V.  Then U^T M U = I and U^T K U = diag(d).
 // Eigenvalues ascending.  Returns nonzero if M is not positive definite.
+// A pair (p, q) is rotated while |c_pq| exceeds a few units of round-off of
+// sqrt(|c_pp c_qq|), not of the whole matrix, and the sweeps go on until
+// one rotates nothing: the eigenvectors of the small eigenvalues (which
+// dominate the fast-diagonalization inverse) are then limited by the
+// rounding of C itself, not by an off-diagonal remainder of the size of
+// round-off times the largest eigenvalue.
 int sym_gen_eig(int n, const double* K, const double* M, double* U, double* D) {
     std::vector<double> L(M, M + (size_t)n * n);
     if (!cholesky(n, L, 1e-300)) return 1;
@@ -520,20 +526,15 @@ int sym_gen_eig(int n, const double* K, const double* M, double* U, double* D) {
         }
     std::vector<double> V((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    constexpr double kRel = 1e-17;
     for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0, tot = 0;
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) {
-                double c2 = C[(size_t)i * n + j] * C[(size_t)i * n + j];
-                tot += c2;
-                if (i != j) off += c2;
-            }
-        if (off <= 1e-32 * tot || off == 0.0) break;
+        int rotated = 0;
         for (int p = 0; p < n - 1; ++p)
             for (int q = p + 1; q < n; ++q) {
                 double apq = C[(size_t)p * n + q];
-                if (apq == 0.0) continue;
                 double app = C[(size_t)p * n + p], aqq = C[(size_t)q * n + q];
+                if (std::fabs(apq) <= kRel * std::sqrt(std::fabs(app * aqq))) continue;
+                ++rotated;
                 double theta = (aqq - app) / (2.0 * apq);
                 double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
                 double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
@@ -547,12 +548,17 @@ int sym_gen_eig(int n, const double* K, const double* M, double* U, double* D) {
                     C[(size_t)p * n + k] = c * cpk - s * cqk;
                     C[(size_t)q * n + k] = s * cpk + c * cqk;
                 }
+                // the rotated pair, exactly: zero coupling, diagonal moved by t c_pq
+                C[(size_t)p * n + q] = C[(size_t)q * n + p] = 0.0;
+                C[(size_t)p * n + p] = app - t * apq;
+                C[(size_t)q * n + q] = aqq + t * apq;
                 for (int k = 0; k < n; ++k) {
                     double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
                     V[(size_t)k * n + p] = c * vkp - s * vkq;
                     V[(size_t)k * n + q] = s * vkp + c * vkq;
                 }
             }
+        if (!rotated) break;
     }
     std::vector<int> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
@@ -660,14 +666,25 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
                 }
             P.H = H;
             P.hscale = dim == 3 ? H : 1.0;
-            // det J > 0 at every Gauss point of the multilinear map
+            // det J > 0 at every Gauss point of the multilinear map.  The
+            // first column of J does not depend on eta_1 and the others are
+            // linear in it, so along a line of Gauss points det J is a
+            // quadratic in eta_1, fixed by its values at 0, 1/2 and 1.
             for (int64_t q3 = 0; q3 < (dim == 3 ? P.dir[2].nq : 1); ++q3)
-                for (int q2 = 0; q2 < P.dir[1].nq; ++q2)
+                for (int q2 = 0; q2 < P.dir[1].nq; ++q2) {
+                    double eta[3] = {0.0, P.dir[1].qx[q2], dim == 3 ? P.dir[2].qx[q3] : 0.0};
+                    const double d0 = multilinear_det(dim, P.corners, eta);
+                    eta[0] = 0.5;
+                    const double dh = multilinear_det(dim, P.corners, eta);
+                    eta[0] = 1.0;
+                    const double d1 = multilinear_det(dim, P.corners, eta);
+                    const double c1 = -3.0 * d0 + 4.0 * dh - d1, c2 = 2.0 * d0 - 4.0 * dh + 2.0 * d1;
                     for (int q1 = 0; q1 < P.dir[0].nq; ++q1) {
-                        double eta[3] = {P.dir[0].qx[q1], P.dir[1].qx[q2], dim == 3 ? P.dir[2].qx[q3] : 0.0};
-                        if (!(multilinear_det(dim, P.corners, eta) > 0))
+                        const double t = P.dir[0].qx[q1];
+                        if (!(d0 + t * (c1 + t * c2) > 0))
                             fail(AFIETI_EGEOM, "patch map is not orientation preserving");
                     }
+                }
             // control points at the Greville abscissae
             std::vector<double> g[3];
             for (int l = 0; l < 3; ++l) {

@@ -217,3 +217,30 @@ def test_problem_statement_error_codes():
     prob["patches"][0]["knots"] = [np.array([0, 0, 0, 0.3, 1, 1, 1.0])] * 2
     prob["patches"][1]["knots"] = [np.array([0, 0, 0, 0.5, 1, 1, 1.0])] * 2
     _expect_error(prob, -2)
+
+
+@pytest.mark.parametrize("mk", [lambda: W.make_c2(n_el=32, seed=0), lambda: W.make_c3(n_el=6, p=5, grid=(2, 1, 1))])
+def test_host_eigenvectors_diagonalise_the_pencils(mk):
+    """U^T M U = I and U^T K U = diag(D) for the oracle's univariate
+    matrices, and the one-dimensional fast-diagonalization inverse
+    U (1 + D)^{-1} U^T equals (M + K)^{-1} (Section 5.2.1, Algorithm 1)."""
+    from paper_2001_09626_amd import Solver
+    prob = mk()
+    s = Solver(prob, host_only=True)
+    o = AFIETI(prob, assembled=False)
+    D, U = s.export("eig"), s.export("eigvec")
+    off = offu = 0
+    for k in range(len(o.patches)):
+        for m in range(o.dim):
+            K, M = o.fd[k][m]["K"], o.fd[k][m]["M"]
+            n = len(K)
+            d, u = D[off:off + n], U[offu:offu + n * n].reshape(n, n)
+            off += n
+            offu += n * n
+            assert np.all(np.diff(d) > 0)
+            assert np.abs(u.T @ M @ u - np.eye(n)).max() <= 1e-13
+            assert np.abs(u.T @ K @ u - np.diag(d)).max() <= 1e-13 * d[-1]
+            F = (u / (1 + d)) @ u.T
+            Fx = np.linalg.inv(M + K)
+            assert np.abs(F - Fx).max() <= 1e-12 * np.abs(Fx).max()
+    s.close()
