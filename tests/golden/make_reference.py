@@ -2,7 +2,9 @@
 parity tests (tests/test_gpu_reference.py).
 
     python tests/golden/make_reference.py c2 1e-8       # C2 at one tolerance
-    python tests/golden/make_reference.py c4 0 3 5 ...  # problems of the C4 batch (tol 1e-8)
+    python tests/golden/make_reference.py c4 1e-8 0 3 5 ...  # problems of the C4 batch
+    python tests/golden/make_reference.py c3 p n_el     # C3's 4x4x4 patches, degree p,
+                                                        # n_el^3 elements (tol 1e-8, 1e-12)
 
 Only the oracle (``oracle/``) and the seeded workload generators are called.
 Each output file holds, per tolerance: the MINRES iteration count and the
@@ -42,27 +44,32 @@ def summarise(o, res, tol):
                 u_proj={str(s): float(W.random_vector(o.n_dof, s) @ u) for s in PROJ_SEEDS})
 
 
-def write(name, prob, tol):
-    """One oracle solve of ``prob`` at ``tol``, summarised into
+def write(name, prob, *tols):
+    """Oracle solves of ``prob`` at each tolerance, each summarised into
     ref_<name>_<tol>.json beside this script."""
-    t0 = time.time()
     o = AFIETI(prob)
-    res = o.solve(tol=tol, maxit=5000)
-    out = dict(workload=name, n_dof=int(o.n_dof), n_c=int(o.n_c), solves=[summarise(o, res, tol)])
-    path = os.path.join(HERE, f"ref_{name}_{tol:.0e}.json")
-    with open(path, "w") as f:
-        json.dump(out, f)
-    print(f"{name} tol {tol:.0e}: {res['iters']} iterations; wrote {path} ({time.time() - t0:.0f} s)", flush=True)
+    for tol in tols:
+        t0 = time.time()
+        res = o.solve(tol=tol, maxit=5000)
+        out = dict(workload=name, n_dof=int(o.n_dof), n_c=int(o.n_c), solves=[summarise(o, res, tol)])
+        path = os.path.join(HERE, f"ref_{name}_{tol:.0e}.json")
+        with open(path, "w") as f:
+            json.dump(out, f)
+        print(f"{name} tol {tol:.0e}: {res['iters']} iterations; wrote {path} ({time.time() - t0:.0f} s)",
+              flush=True)
 
 
 def main(argv):
     what = argv[1]
     if what == "c2":
         write("c2", W.make_c2(seed=0), float(argv[2]))
+    elif what == "c3":
+        p, n_el = int(argv[2]), int(argv[3])
+        write(f"c3_p{p}_e{n_el}", W.make_c3(seed=0, p=p, n_el=n_el), 1e-8, 1e-12)
     elif what == "c4":
         probs = W.make_c4(seed=0)
-        for j in argv[2:]:
-            write(f"c4_{int(j)}", probs[int(j)], 1e-8)
+        for j in argv[3:]:
+            write(f"c4_{int(j)}", probs[int(j)], float(argv[2]))
     else:
         raise SystemExit(f"unknown workload {what}")
 
