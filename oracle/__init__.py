@@ -13,6 +13,9 @@ Modules
   patch     patch geometry, physical stiffness / load / mass (Sections 2.2, 3, 4)
   afieti    tearing (B, R, G), projections, FD, Schur, preconditioner,
             MINRES and recovery (Sections 4, 5.2, 5.2.1, Remark 1)
+  geo       inexact local solvers with geometry inclusion: separable fit of
+            the pulled-back coefficients, weighted pencils, diagonal
+            scalings (Section 5.2.3, Remark 1)
   direct    the conforming Galerkin solve the method must reproduce (Section 3)
   adjoint   gradients of a scalar of the displacement w.r.t. load amplitudes
             and per-patch Lame parameters (not in the paper; follows from the

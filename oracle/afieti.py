@@ -59,7 +59,7 @@ class Breakdown(Exception):
 class AFIETI:
     """The AF-IETI system of one problem (``workloads`` dictionary)."""
 
-    def __init__(self, prob: dict, assembled: bool | None = None):
+    def __init__(self, prob: dict, assembled: bool | None = None, geometry: bool = False):
         self.dim = int(prob["dim"])
         self.patches = [Patch(pd, self.dim) for pd in prob["patches"]]
         self.load_modes = prob["load"]
@@ -79,6 +79,12 @@ class AFIETI:
         self._build_dirichlet_data()
         self._build_coarse()
         self._build_fd()
+        # geometry inclusion (Section 5.2.3): P~_A and P~_S replace the
+        # preconditioner's blocks
+        self.geo = None
+        if geometry:
+            from .geo import GeoPreconditioner
+            self.geo = GeoPreconditioner(self)
 
     # ------------------------------------------------------------ DOF helpers
     def split(self, x):
@@ -354,10 +360,15 @@ class AFIETI:
 
     def apply_prec(self, r, variant="nr"):
         """Block preconditioner of Section 4: [P_u P_A^{-1} P_u r_w;
-        P_chi P_S P_chi r_chi]."""
+        P_chi P_S P_chi r_chi], with P~_A and P~_S of Section 5.2.3 when
+        the system was built with ``geometry=True``."""
         rw, rc = r[:self.n_dof], r[self.n_dof:]
-        zw = self.P_u(self.apply_PA_inv(self.P_u(rw)))
-        zc = self.P_chi(self.apply_PS(self.P_chi(rc), variant))
+        if self.geo is not None:
+            zw = self.P_u(self.geo.apply_PA_inv(self.P_u(rw)))
+            zc = self.P_chi(self.geo.apply_PS(self.P_chi(rc), variant))
+        else:
+            zw = self.P_u(self.apply_PA_inv(self.P_u(rw)))
+            zc = self.P_chi(self.apply_PS(self.P_chi(rc), variant))
         return np.concatenate([zw, zc])
 
     # --------------------------------------------------------------- solve
