@@ -77,6 +77,18 @@ extern "C" {
 #define AFIETI_PS_NR 0
 #define AFIETI_PS_PLAIN 1
 
+/* the inexact local solvers: FD of the parametric operators (Section 5.2,
+ * eq. inexact_AP / inexact_SP with Algorithm 1, default), or with geometry
+ * inclusion (Section 5.2.3, eq. geo_A / geo_S / tildeshur): per patch and
+ * displacement component a separable fit of the diagonal of the
+ * pulled-back coefficient matrix (a least-squares fit in log space over the
+ * Gauss points, weighted by the product Gauss weights, of the diagonal
+ * entries together with |det J| as the product of the mass factors),
+ * weighted univariate pencils (d^2 per patch), and the diagonal scalings
+ * D_A, D_S.  With it P_A carries H^-2 on the mass and P_S no H factor. */
+#define AFIETI_PRECOND_FD 0
+#define AFIETI_PRECOND_GEO 1
+
 /* how the patch stiffness A^(k) is applied: AUTO = matrix-free where
  * possible (3D, C^{p-1}, p <= 6; sum-factorised Gauss quadrature of the
  * bilinear form of Section 3), assembled stencil elsewhere; ASSEMBLED =
@@ -175,6 +187,7 @@ typedef struct {
                             w <= 0 makes it indefinite, and MINRES stops
                             with AFIETI_EBREAKDOWN at the first iteration
                             whose <z, v> is negative.                      */
+    int precond;         /* AFIETI_PRECOND_* (FD)                          */
 } afieti_options;
 
 typedef struct {
@@ -221,7 +234,9 @@ int afieti_get_offsets(const afieti_handle* h, int64_t* dof_off, int64_t* c_off)
 /*
  * z = (P_A^inex)^{-1} r for all problems, patches and components
  * (Section 5.2, eq. inexact_AP; applied by Algorithm 1): per patch k and
- * component l, (H^(k))^{d-2} (A-hat_l + M-hat_l) z = r.  r, z: device DOF
+ * component l, (H^(k))^{d-2} (A-hat_l + M-hat_l) z = r.  With
+ * AFIETI_PRECOND_GEO it is P~_A (Section 5.2.3, eq. geo_A):
+ * D_A^{1/2} (A~_l + (H^(k))^-2 M~_l) D_A^{1/2} z = r.  r, z: device DOF
  * vectors (may not alias).  Precision of the mode products as configured.
  */
 int afieti_apply_fd(afieti_handle* h, const double* r, double* z, void* stream);
@@ -315,7 +330,11 @@ int afieti_apply(afieti_handle* h, int op, const double* x, double* y, void* str
  *  what = 5: c, the right-hand side of B u = c: Dirichlet data on the
  *            Dirichlet rows, zero elsewhere (double, n_c)
  *  what = 6: eigenvectors U of every patch and direction, in the order of
- *            what = 1, each n x n row major (column j: eigenvalue j)      */
+ *            what = 1, each n x n row major (column j: eigenvalue j)
+ *  what = 7: with AFIETI_PRECOND_GEO: D_A^{-1/2} per DOF (n_dof), then
+ *            D_S^{1/2} per DOF (n_dof), DOF-ordered
+ *  what = 8: with AFIETI_PRECOND_GEO: eigenvalues of the weighted pencils
+ *            per patch, component and direction, concatenated           */
 int afieti_export(const afieti_handle* h, int what, void* buf, int64_t buf_bytes);
 int64_t afieti_export_size(const afieti_handle* h, int what);
 

@@ -59,7 +59,8 @@ class Breakdown(Exception):
 class AFIETI:
     """The AF-IETI system of one problem (``workloads`` dictionary)."""
 
-    def __init__(self, prob: dict, assembled: bool | None = None, geometry: bool = False):
+    def __init__(self, prob: dict, assembled: bool | None = None, geometry: bool = False,
+                 eig_driver: str | None = None):
         self.dim = int(prob["dim"])
         self.patches = [Patch(pd, self.dim) for pd in prob["patches"]]
         self.load_modes = prob["load"]
@@ -67,6 +68,10 @@ class AFIETI:
         self.traction = prob.get("traction")
         self.dirichlet = prob.get("dirichlet")
         self.tol = float(prob.get("tol", 1e-8))
+        # LAPACK driver of the generalised eigensolves (scipy.linalg.eigh's
+        # default when None); another driver perturbs U and D at rounding
+        # level, which the tests use to measure the solve's own sensitivity
+        self.eig_driver = eig_driver
         sizes = [pa.n_dof for pa in self.patches]
         self.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
         self.n_dof = int(self.offsets[-1])
@@ -268,8 +273,8 @@ class AFIETI:
             per_dir = []
             for l in range(self.dim):
                 K, M = matrices_1d(pa.knots[l], pa.p)
-                D, U = sla.eigh(K, M)
-                Di, Ui = sla.eigh(K[1:-1, 1:-1], M[1:-1, 1:-1])
+                D, U = sla.eigh(K, M, driver=self.eig_driver)
+                Di, Ui = sla.eigh(K[1:-1, 1:-1], M[1:-1, 1:-1], driver=self.eig_driver)
                 per_dir.append(dict(K=K, M=M, D=D, U=U, Di=Di, Ui=Ui))
             self.fd.append(per_dir)
 

@@ -175,7 +175,7 @@ def mass_diagonal(pa):
 class GeoPatch:
     """Geometry-inclusion data of one patch (all components)."""
 
-    def __init__(self, pa):
+    def __init__(self, pa, eig_driver=None):
         self.pa = pa
         dim = pa.dim
         H = pa.diameter()
@@ -188,8 +188,8 @@ class GeoPatch:
             K, M = zip(*[weighted_1d(pa, m, nu[m], beta[m]) for m in range(dim)])
             fd = []
             for m in range(dim):
-                D, U = sla.eigh(K[m], M[m])
-                Di, Ui = sla.eigh(K[m][1:-1, 1:-1], M[m][1:-1, 1:-1])
+                D, U = sla.eigh(K[m], M[m], driver=eig_driver)
+                Di, Ui = sla.eigh(K[m][1:-1, 1:-1], M[m][1:-1, 1:-1], driver=eig_driver)
                 fd.append(dict(D=D, U=U, Di=Di, Ui=Ui))
             kd = [np.diag(K[m]) for m in range(dim)]
             md = [np.diag(M[m]) for m in range(dim)]
@@ -255,7 +255,7 @@ class GeoPreconditioner:
 
     def __init__(self, sysm):
         self.sysm = sysm
-        self.patches = [GeoPatch(pa) for pa in sysm.patches]
+        self.patches = [GeoPatch(pa, sysm.eig_driver) for pa in sysm.patches]
 
     def apply_PA_inv(self, r):
         s = self.sysm

@@ -110,7 +110,7 @@ class Solver:
 
     def __init__(self, problems, tol=1e-8, maxit=5000, fd_precision="fp64", ps_variant="nr",
                  check_every=12, host_only=False, use_graph=True, stiffness="auto", fd_tune=-1,
-                 ps_weight=1.0):
+                 ps_weight=1.0, precond="fd"):
         L = N.lib()
         self._L = L
         arr, keep = to_c_problems(problems)
@@ -126,6 +126,7 @@ class Solver:
         opt.stiffness = N.STIFFNESS[stiffness]
         opt.fd_tune = int(fd_tune)
         opt.ps_weight = float(ps_weight)
+        opt.precond = N.PRECOND[precond]
         self.host_only = host_only
         h = C.c_void_p()
         stream = C.c_void_p(0) if host_only else _stream()
@@ -257,6 +258,8 @@ class Solver:
         self._check(self._L.afieti_export(self._h, N.EXPORT[what], buf.ctypes.data_as(C.c_void_p), n))
         if what == "B":
             return buf.reshape(-1, 3)
+        if what == "geo_scale":
+            return buf.reshape(2, -1)
         if what == "GtG":
             m = int(round(np.sqrt(len(buf))))
             return buf.reshape(m, m)

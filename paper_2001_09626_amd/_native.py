@@ -16,13 +16,15 @@ ERRORS = {-1: "EINVAL", -2: "EGEOM", -3: "ESINGULAR", -4: "EBREAKDOWN",
 
 FD_PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "fp32_valu": 3, "fp64_valu": 4}
 PS_VARIANT = {"nr": 0, "plain": 1}
+PRECOND = {"fd": 0, "geo": 1}
 STIFFNESS = {"auto": 0, "assembled": 1, "matrix_free": 2}
 
 OPS = {"stiffness": 0, "B": 1, "Bt": 2, "P_u": 3, "P_chi": 4, "Shat": 5, "P_S": 6,
        "prec": 7, "saddle": 8, "fd_interior": 9, "Ahat": 10, "mass": 11, "load": 12,
        "dirichlet_lift": 13}
 
-EXPORT = {"B": 0, "eig": 1, "H": 2, "GtG": 3, "fixed_load": 4, "dirichlet_c": 5, "eigvec": 6}
+EXPORT = {"B": 0, "eig": 1, "H": 2, "GtG": 3, "fixed_load": 4, "dirichlet_c": 5, "eigvec": 6,
+          "geo_scale": 7, "geo_eig": 8}
 
 
 class Patch(C.Structure):
@@ -52,7 +54,7 @@ class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("fd_precision", C.c_int),
                 ("ps_variant", C.c_int), ("check_every", C.c_int), ("host_only", C.c_int),
                 ("use_graph", C.c_int), ("stiffness", C.c_int), ("fd_tune", C.c_int),
-                ("ps_weight", C.c_double)]
+                ("ps_weight", C.c_double), ("precond", C.c_int)]
 
 
 class Info(C.Structure):

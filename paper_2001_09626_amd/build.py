@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libafieti.so")
 
-SOURCES = ["plan.cpp", "afieti.cpp", "kernels.hip", "fd.hip"]
+SOURCES = ["plan.cpp", "geo.cpp", "afieti.cpp", "kernels.hip", "fd.hip"]
 HIP_FLAGS = [
     "-std=c++17", "-O3", "-fPIC", "-shared", "--offload-arch=gfx950",
     # every symbol resolved at link time (a missing definition fails the build)

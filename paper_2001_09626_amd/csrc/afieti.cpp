@@ -14,6 +14,7 @@
 #include <mutex>
 #include <tuple>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "afieti.h"
@@ -89,6 +90,12 @@ struct afieti_handle {
     double* d_geo = nullptr;
     double* d_load = nullptr;
     double* d_fixed = nullptr;   // loads of the body-force / traction callbacks (or NULL)
+    double* d_geo_da = nullptr;  // geometry inclusion: D_A^{-1/2} per DOF (or NULL)
+    double* d_geo_ds = nullptr;  // geometry inclusion: D_S^{1/2} per DOF (or NULL)
+    std::vector<int> hat_band;   // per patch and direction: band rows of the parametric K, M
+    int64_t geo_band_at = 0;     // first geometry-inclusion band entry in d_kband / d_mband
+    int64_t geo_fd_at = 0;       // first geometry-inclusion entry in the U table
+    int64_t geo_d_at = 0;        // first geometry-inclusion entry in the D table
     double* d_udir = nullptr;    // Dirichlet lift u_D = B^T (B B^T)^{-1} c (or NULL)
     double* d_part_u = nullptr;  // partials of the caller's load-vector products
     int64_t part_u_n = 0;
@@ -231,6 +238,7 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
     std::vector<FdGroup> groups[2];
     std::vector<int2> gslabs[2], gcols64[2], gcols128[2];
     int64_t tmp = 0;
+    const bool geo = h->opt.precond == AFIETI_PRECOND_GEO;
     for (size_t k = 0; k < h->plan.patches.size(); ++k) {
         const PatchPlan& P = h->plan.patches[k];
         const int dim = P.dim;
@@ -263,17 +271,21 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
             t.tmp_off = tmp;
             tmp += n123;
             for (int m = 0; m < 3; ++m) {
-                int idx = (int)k * 3 + m;
+                const int idx = ((int)k * 3 + l) * 3 + m;
                 t.u_off[m] = u_off[idx * 2 + (interior ? 1 : 0)];
                 t.d_off[m] = d_off[idx * 2 + (interior ? 1 : 0)];
-                t.kappa[m] = (m == l) ? 2 * P.mu + P.lam : P.mu;
-                g.u_off[m] = t.u_off[m];
-                g.d_off[m] = t.d_off[m];
+                // geometry inclusion: eigenvalues H^-2 + sum_m D_{l,m} (the
+                // Lame parameters are inside the weighted pencils)
+                t.kappa[m] = geo ? 1.0 : (m == l) ? 2 * P.mu + P.lam : P.mu;
+                if (l == 0) {  // layout 0 shares component 0's tables (FD mode only)
+                    g.u_off[m] = t.u_off[m];
+                    g.d_off[m] = t.d_off[m];
+                }
             }
             if (dim == 2) t.kappa[2] = 0.0;
             for (int m = 0; m < 3; ++m) g.kappa[l][m] = t.kappa[m];
-            t.scale = interior ? 1.0 : P.hscale;
-            t.mass = interior ? 0.0 : 1.0;
+            t.scale = interior || geo ? 1.0 : P.hscale;
+            t.mass = interior ? 0.0 : geo ? 1.0 / (P.H * P.H) : 1.0;
             t.alpha = interior ? -1.0 : 1.0;
             t.prob = P.prob;
             int ti = (int)ts.size();
@@ -282,8 +294,8 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
             int ncb = (t.n1 * t.n2 + 31) / 32;
             for (int cb = 0; cb < ncb; ++cb) cols.push_back(make_int2(ti, cb));
         }
-        g.scale = interior ? 1.0 : P.hscale;
-        g.mass = interior ? 0.0 : 1.0;
+        g.scale = interior || geo ? 1.0 : P.hscale;
+        g.mass = interior ? 0.0 : geo ? 1.0 / (P.H * P.H) : 1.0;
         g.alpha = interior ? -1.0 : 1.0;
         g.prob = P.prob;
         // layout 0: the patch's components together; layout 1: one each
@@ -297,6 +309,9 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
                     for (int m = 0; m < 3; ++m) {
                         q.kappa[0][m] = g.kappa[part][m];
                         q.kappa[1][m] = q.kappa[2][m] = 0.0;
+                        const int idx = ((int)k * 3 + part) * 3 + m;
+                        q.u_off[m] = u_off[idx * 2 + (interior ? 1 : 0)];
+                        q.d_off[m] = d_off[idx * 2 + (interior ? 1 : 0)];
                     }
                 }
                 const int gi = (int)groups[lay].size();
@@ -346,6 +361,101 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
     }
 }
 
+// band rows [i][t] (t = j - i + p) of a dense n x n matrix; a direction the
+// patch does not have is a 1 x 1 identity mass and zero stiffness
+void push_band(std::vector<double>& out, const std::vector<double>& A, int n, int p, bool active, bool mass) {
+    const int W = 2 * p + 1;
+    for (int i = 0; i < n; ++i)
+        for (int t = 0; t < W; ++t) {
+            const int j = i - p + t;
+            if (active) out.push_back(j >= 0 && j < n ? A[(size_t)i * n + j] : 0.0);
+            else out.push_back(mass && t == p ? 1.0 : 0.0);
+        }
+}
+
+// geometry inclusion: the band rows of the weighted pencils of every patch,
+// component and direction (appended to kb, mb in that order)
+void geo_bands(const afieti_handle* h, std::vector<double>& kb, std::vector<double>& mb) {
+    for (const PatchPlan& P : h->plan.patches)
+        for (int l = 0; l < 3; ++l)
+            for (int m = 0; m < 3; ++m) {
+                const bool active = m < P.dim && l < P.dim;
+                const GeoPencil& g = P.gp[active ? l : 0][active ? m : 0];
+                push_band(kb, g.K, P.n[m], P.p, active, false);
+                push_band(mb, g.M, P.n[m], P.p, active, true);
+            }
+}
+
+// geometry inclusion: U (full, interior) and D (full, interior) of every
+// patch, component and direction, in u64 / dt, which start at entries
+// ubase / dbase of the device tables; offsets into uoff / doff at
+// ((k * 3 + l) * 3 + m) * 2 + interior
+void geo_fd_tables(const afieti_handle* h, std::vector<double>& u64, std::vector<double>& dt, std::vector<int>& uoff,
+                   std::vector<int>& doff, int64_t ubase, int64_t dbase) {
+    for (size_t k = 0; k < h->plan.patches.size(); ++k) {
+        const PatchPlan& P = h->plan.patches[k];
+        for (int l = 0; l < 3; ++l)
+            for (int m = 0; m < 3; ++m) {
+                const int idx = (((int)k * 3 + l) * 3 + m) * 2;
+                if (l >= P.dim) {  // no such component: copy component 0's offsets
+                    uoff[idx] = uoff[idx - l * 6];
+                    uoff[idx + 1] = uoff[idx - l * 6 + 1];
+                    doff[idx] = doff[idx - l * 6];
+                    doff[idx + 1] = doff[idx - l * 6 + 1];
+                    continue;
+                }
+                const GeoPencil& g = P.gp[l][m];
+                uoff[idx] = (int)(ubase + (int64_t)u64.size());
+                u64.insert(u64.end(), g.U.begin(), g.U.end());
+                doff[idx] = (int)(dbase + (int64_t)dt.size());
+                dt.insert(dt.end(), g.D.begin(), g.D.end());
+                uoff[idx + 1] = (int)(ubase + (int64_t)u64.size());
+                u64.insert(u64.end(), g.Ui.begin(), g.Ui.end());
+                doff[idx + 1] = (int)(dbase + (int64_t)dt.size());
+                dt.insert(dt.end(), g.Di.begin(), g.Di.end());
+            }
+    }
+}
+
+// per-patch operator coefficients the kernels read: the band rows and
+// Kronecker coefficients of A-hat_l (or A~_l) per component and direction,
+// and the H factor of P_S
+void set_patch_coefficients(afieti_handle* h) {
+    const bool geo = h->opt.precond == AFIETI_PRECOND_GEO;
+    int64_t at = h->geo_band_at;
+    for (int k = 0; k < h->n_patches; ++k) {
+        const PatchPlan& P = h->plan.patches[k];
+        DevPatch& d = h->h_patches[k];
+        d.hscale = geo ? 1.0 : P.hscale;
+        for (int l = 0; l < 3; ++l)
+            for (int m = 0; m < 3; ++m) {
+                if (geo) {
+                    d.band_off[l][m] = (int)at;
+                    at += (int64_t)P.n[m] * (2 * P.p + 1);
+                    d.kap[l][m] = m < P.dim ? 1.0 : 0.0;
+                } else {
+                    d.band_off[l][m] = h->hat_band[k * 3 + m];
+                    d.kap[l][m] = m == l ? 2 * P.mu + P.lam : P.mu;
+                }
+            }
+    }
+}
+
+// geometry inclusion: D_A^{-1/2} and D_S^{1/2} per DOF
+void geo_scalings(const afieti_handle* h, std::vector<double>& da, std::vector<double>& ds) {
+    da.assign(h->n_dof, 1.0);
+    ds.assign(h->n_dof, 1.0);
+    for (const PatchPlan& P : h->plan.patches) {
+        std::copy(P.geo_da.begin(), P.geo_da.end(), da.begin() + P.dof_off);
+        std::copy(P.geo_ds.begin(), P.geo_ds.end(), ds.begin() + P.dof_off);
+    }
+}
+
+int geo_threads() {
+    const unsigned hc = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(16u, hc ? hc : 1u));
+}
+
 // stiffness stencils of every patch (Gauss-point geometry, then assembly)
 void assemble_all(afieti_handle* h, hipStream_t s) {
     for (int k = 0; k < h->n_patches; ++k) {
@@ -390,7 +500,8 @@ int64_t fd_choice_lds(const afieti_handle* h, const FdSet& set, int choice) {
 int tune_fd(afieti_handle* h, FdSet& set, const double* in, double* out, hipStream_t s) {
     static std::mutex mu;
     static std::map<std::string, int> cache;
-    std::string key = std::to_string(fd_prec(h)) + ":";
+    const bool geo = h->opt.precond == AFIETI_PRECOND_GEO;
+    std::string key = std::to_string(fd_prec(h)) + (geo ? "g:" : ":");
     for (const FdGroup& g : set.h_groups[0])
         key += std::to_string(g.n1) + "," + std::to_string(g.n2) + "," + std::to_string(g.n3) + "," +
                std::to_string(g.nc) + ";";
@@ -404,7 +515,7 @@ int tune_fd(afieti_handle* h, FdSet& set, const double* in, double* out, hipStre
     HIP_OK(hipEventCreate(&e1));
     int best = -1;
     float best_ms = 0;
-    for (int c = 0; c < 2 * kFdVariants; ++c) {
+    for (int c = geo ? kFdVariants : 0; c < 2 * kFdVariants; ++c) {
         if (fd_choice_lds(h, set, c) > kLdsBytes) continue;
         set.tune = c;
         op_fd_tmp(h, set, in, out, h->d_fdtmp, s);  // warm-up
@@ -444,6 +555,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     std::vector<int> qfirst, elf, ell;
     int64_t stencil = 0, geo_max = 0;
     h->h_patches.resize(np);
+    h->hat_band.assign((size_t)np * 3, 0);
     for (int k = 0; k < np; ++k) {
         const PatchPlan& P = pl.patches[k];
         DevPatch& d = h->h_patches[k];
@@ -494,7 +606,7 @@ void device_setup(afieti_handle* h, hipStream_t s) {
             d.nq[m] = m < P.dim ? D.nq : 1;
             d.q_off[m] = (int)qfirst.size();
             d.el_off[m] = (int)elf.size();
-            d.band_off[m] = (int)kband.size();
+            h->hat_band[k * 3 + m] = (int)kband.size();
             if (m < P.dim) {
                 for (int q = 0; q < D.nq; ++q) {
                     qfirst.push_back(D.qfirst[q]);
@@ -528,6 +640,9 @@ void device_setup(afieti_handle* h, hipStream_t s) {
         d.geo_off = 0;
         geo_max = std::max(geo_max, (int64_t)d.nq[0] * d.nq[1] * d.nq[2] * 13);
     }
+    h->geo_band_at = (int64_t)kband.size();
+    if (h->opt.precond == AFIETI_PRECOND_GEO) geo_bands(h, kband, mband);
+    set_patch_coefficients(h);
     h->d_patches = h->upload(h->h_patches, s);
     h->d_ctrl = h->upload(ctrl, s);
     h->d_qval = h->upload(qval, s);
@@ -690,23 +805,44 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     }
     combine_load(h, s);
     // ---- FD tables
+    // offsets per (patch, component, direction, full / interior): the
+    // parametric pencils are shared by the components; with geometry
+    // inclusion each component has its own weighted pencils
     std::vector<double> u64, dtab;
-    std::vector<int> u_off(np * 3 * 2), d_off(np * 3 * 2);
+    std::vector<int> u_off(np * 9 * 2), d_off(np * 9 * 2);
     int max_n = 1;
     for (int k = 0; k < np; ++k)
         for (int m = 0; m < 3; ++m) {
             const Dir1D& D = pl.patches[k].dir[m];
             max_n = std::max(max_n, D.n);
-            int idx = (k * 3 + m) * 2;
-            u_off[idx] = (int)u64.size();
+            const int uf = (int)u64.size();
             u64.insert(u64.end(), D.U.begin(), D.U.end());
-            d_off[idx] = (int)dtab.size();
+            const int df = (int)dtab.size();
             dtab.insert(dtab.end(), D.D.begin(), D.D.end());
-            u_off[idx + 1] = (int)u64.size();
+            const int ui = (int)u64.size();
             u64.insert(u64.end(), D.Ui.begin(), D.Ui.end());
-            d_off[idx + 1] = (int)dtab.size();
+            const int di = (int)dtab.size();
             dtab.insert(dtab.end(), D.Di.begin(), D.Di.end());
+            for (int l = 0; l < 3; ++l) {
+                const int idx = ((k * 3 + l) * 3 + m) * 2;
+                u_off[idx] = uf;
+                d_off[idx] = df;
+                u_off[idx + 1] = ui;
+                d_off[idx + 1] = di;
+            }
         }
+    h->geo_fd_at = (int64_t)u64.size();
+    h->geo_d_at = (int64_t)dtab.size();
+    if (h->opt.precond == AFIETI_PRECOND_GEO) {
+        std::vector<double> gu, gd;
+        geo_fd_tables(h, gu, gd, u_off, d_off, h->geo_fd_at, h->geo_d_at);
+        u64.insert(u64.end(), gu.begin(), gu.end());
+        dtab.insert(dtab.end(), gd.begin(), gd.end());
+        std::vector<double> da, ds;
+        geo_scalings(h, da, ds);
+        h->d_geo_da = h->upload(da, s);
+        h->d_geo_ds = h->upload(ds, s);
+    }
     if (max_n > kMaxN) throw SetupError{AFIETI_EUNSUPPORTED, "at most 48 basis functions per direction on the device"};
     std::vector<float> u32(u64.begin(), u64.end());
     h->d_u64 = h->upload(u64, s);
@@ -838,9 +974,13 @@ void device_setup(afieti_handle* h, hipStream_t s) {
         // matrix-core FD: launch shapes from the options or the autotuner
         for (FdSet* set : {&h->fd_pa, &h->fd_int}) {
             if (h->opt.fd_tune >= 0) {
-                if (h->opt.fd_tune >= 2 * kFdVariants || fd_choice_lds(h, *set, h->opt.fd_tune) > kLdsBytes)
+                // with geometry inclusion every component has its own
+                // eigenvectors: one component per workgroup (layout 1)
+                const int c = h->opt.precond == AFIETI_PRECOND_GEO ? kFdVariants + h->opt.fd_tune % kFdVariants
+                                                                    : h->opt.fd_tune;
+                if (c >= 2 * kFdVariants || fd_choice_lds(h, *set, c) > kLdsBytes)
                     throw SetupError{AFIETI_EUNSUPPORTED, "FD launch shape does not fit these tensors"};
-                set->tune = h->opt.fd_tune;
+                set->tune = c;
             } else {
                 launch_fill(h->s1, 1.0, h->n_dof, s);
                 set->tune = tune_fd(h, *set, h->s1, h->s2, s);
@@ -980,8 +1120,10 @@ void op_pu(afieti_handle* h, const double* x, double* out, hipStream_t s, int ln
 // stages so that a caller can interleave them with other work:
 //   1: v0 = B^T W y on Gamma, t = A-hat v0
 //   2: v_I = -((A-hat)_II)^{-1} t_I  (interior FD, in place in v)
-//   3: out = W B (H^{d-2} A-hat v)  (4: the same without the A-hat, when
-//      the caller has applied it)
+//   3: out = W B (H^{d-2} A-hat v)  (4: the same without the A-hat and the
+//      output scaling, when the caller has applied them)
+// With geometry inclusion A~_l replaces A-hat_l, there is no H factor, and
+// D_S^{1/2} scales the Gamma values after B^T and after the second A~.
 void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipStream_t s, int ln) {
     const bool nr = h->opt.ps_variant == AFIETI_PS_NR;
     if (stage == 1) {
@@ -991,11 +1133,15 @@ void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipS
             a = h->c1;
         }
         launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, a, h->tv, s);
+        if (h->d_geo_ds) launch_mul(h->d_geo_ds, h->tv, h->tv, h->n_dof, s);  // D_S^{1/2} (geometry inclusion)
         op_ahat(h, h->tv, h->tt, 0, s, true);
     } else if (stage == 2) {
         op_fd(h, h->fd_int, h->tt, h->tv, s, ln);
     } else {
-        if (stage == 3) op_ahat(h, h->tv, h->tt, 1, s, false, true);  // B reads only the Gamma part
+        if (stage == 3) {
+            op_ahat(h, h->tv, h->tt, 1, s, false, true);  // B reads only the Gamma part
+            if (h->d_geo_ds) launch_mul(h->d_geo_ds, h->tt, h->tt, h->n_dof, s);
+        }
         if (nr) {
             launch_BW(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->d_cplus, h->d_cminus, h->tt, out, s);
         } else {
@@ -1029,14 +1175,19 @@ void op_prec_branches(afieti_handle* h, const double* r, double* z, hipStream_t 
         launch_GW(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, L.zc,
                   r + h->n_dof, h->c1, b.s);
         launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, h->c1, h->tv, b.s);
+        if (h->d_geo_ds) launch_mul(h->d_geo_ds, h->tv, h->tv, h->n_dof, b.s);
         op_ahat(h, h->tv, h->tt, 0, b.s, true);
     } else {
         op_ps_stage(h, 1, h->c3, h->c4, b.s, b.ln);
     }
+    // geometry inclusion: P~_A^{-1} = D_A^{-1/2} (A~ + H^-2 M~)^{-1} D_A^{-1/2}
+    if (h->d_geo_da) launch_mul(h->d_geo_da, h->s1, h->s1, h->n_dof, s);
     op_fd(h, h->fd_pa, h->s1, h->s2, s);
+    if (h->d_geo_da) launch_mul(h->d_geo_da, h->s2, h->s2, h->n_dof, s);
     op_ps_stage(h, 2, h->c3, h->c4, b.s, b.ln);
     op_pu(h, h->s2, z, s);
     op_ahat(h, h->tv, h->tt, 1, b.s, false, true);
+    if (h->d_geo_ds) launch_mul(h->d_geo_ds, h->tt, h->tt, h->n_dof, b.s);
     // the last LDS-heavy kernel of P_S (a pipelined graph starts the next
     // brick quadrature after it)
     if (h->capturing) HIP_OK(hipEventRecord(h->ev_ps, b.s));
@@ -1079,13 +1230,16 @@ void op_mass(afieti_handle* h, const double* x, double* y, hipStream_t s) {
     }
 }
 
-// y = blockdiag_k H_k^{d-2} S-hat^(k) x on Gamma, interior of x ignored, of y zero
+// y = blockdiag_k H_k^{d-2} S-hat^(k) x on Gamma, interior of x ignored, of y
+// zero (geometry inclusion: blockdiag_k S~^(k) x, eq. tildeshur)
 void op_shat(afieti_handle* h, const double* x, double* y, hipStream_t s) {
     launch_copy(x, h->tv, h->n_dof, s);
     op_mask_interior(h, h->tv, s);
+    if (h->d_geo_ds) launch_mul(h->d_geo_ds, h->tv, h->tv, h->n_dof, s);
     op_ahat(h, h->tv, h->tt, 0, s, true);
     op_fd(h, h->fd_int, h->tt, h->tv, s);
     op_ahat(h, h->tv, y, 1, s, false, true);  // the interior of y is zeroed next
+    if (h->d_geo_ds) launch_mul(h->d_geo_ds, y, y, h->n_dof, s);
     op_mask_interior(h, y, s);
 }
 
@@ -1330,6 +1484,7 @@ void afieti_default_options(afieti_options* opt) {
     opt->stiffness = AFIETI_STIFFNESS_AUTO;
     opt->fd_tune = -1;
     opt->ps_weight = 1.0;
+    opt->precond = AFIETI_PRECOND_FD;
 }
 
 const char* afieti_strerror(int code) {
@@ -1361,9 +1516,11 @@ int afieti_setup(const afieti_problem* probs, int n_problems, const afieti_optio
         if (!(h->opt.tol > 0) || h->opt.maxit < 1 ||
             (h->opt.fd_precision < AFIETI_FD_FP64 || h->opt.fd_precision > AFIETI_FD_FP64_VALU) ||
             (h->opt.ps_variant != AFIETI_PS_NR && h->opt.ps_variant != AFIETI_PS_PLAIN) ||
-            h->opt.fd_tune < -1 || h->opt.fd_tune >= 2 * kFdVariants || !std::isfinite(h->opt.ps_weight))
+            h->opt.fd_tune < -1 || h->opt.fd_tune >= 2 * kFdVariants || !std::isfinite(h->opt.ps_weight) ||
+            (h->opt.precond != AFIETI_PRECOND_FD && h->opt.precond != AFIETI_PRECOND_GEO))
             throw SetupError{AFIETI_EINVAL, "invalid options"};
         h->plan = build_plan(probs, n_problems);
+        if (h->opt.precond == AFIETI_PRECOND_GEO) build_geometry_inclusion(h->plan, geo_threads());
         h->n_probs = (int)h->plan.probs.size();
         h->n_patches = (int)h->plan.patches.size();
         h->n_dof = h->plan.n_dof;
@@ -1427,7 +1584,14 @@ int afieti_apply_fd(afieti_handle* h, const double* r, double* z, void* stream) 
         return AFIETI_EINVAL;
     }
     try {
-        op_fd(h, h->fd_pa, r, z, (hipStream_t)stream);
+        hipStream_t s = (hipStream_t)stream;
+        if (h->d_geo_da) {  // D_A^{-1/2} (A~ + H^-2 M~)^{-1} D_A^{-1/2}
+            launch_mul(h->d_geo_da, r, h->s1, h->n_dof, s);
+            op_fd(h, h->fd_pa, h->s1, z, s);
+            launch_mul(h->d_geo_da, z, z, h->n_dof, s);
+        } else {
+            op_fd(h, h->fd_pa, r, z, s);
+        }
         HIP_OK(hipGetLastError());
         return AFIETI_OK;
     } catch (const SetupError& e) {
@@ -1460,7 +1624,13 @@ int afieti_apply_fd_noalloc(afieti_handle* h, const double* r, double* z, void* 
     }
     // the passes write every intermediate entry before reading it: nothing
     // of the previous call's contents is read
-    op_fd_tmp(h, h->fd_pa, r, z, tmp, (hipStream_t)stream);
+    if (h->d_geo_da) {  // the scaled input goes to a vector the handle owns
+        launch_mul(h->d_geo_da, r, h->s1, h->n_dof, (hipStream_t)stream);
+        op_fd_tmp(h, h->fd_pa, h->s1, z, tmp, (hipStream_t)stream);
+        launch_mul(h->d_geo_da, z, z, h->n_dof, (hipStream_t)stream);
+    } else {
+        op_fd_tmp(h, h->fd_pa, r, z, tmp, (hipStream_t)stream);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         h->err = std::string("kernel launch: ") + hipGetErrorString(e);
@@ -1621,6 +1791,26 @@ int afieti_set_parameters(afieti_handle* h, const double* lame, const double* am
                 h->plan.patches[k].lam = h->h_patches[k].lam = lame[2 * k];
                 h->plan.patches[k].mu = h->h_patches[k].mu = lame[2 * k + 1];
             }
+            if (h->opt.precond == AFIETI_PRECOND_GEO) {
+                // the weighted pencils and scalings depend on lambda, mu:
+                // rebuilt and written over their tables (same sizes)
+                build_geometry_inclusion(h->plan, geo_threads());
+                std::vector<double> kb, mb, gu, gd, da, ds;
+                geo_bands(h, kb, mb);
+                std::vector<int> uo = h->fd_uoff, dof = h->fd_doff;
+                geo_fd_tables(h, gu, gd, uo, dof, h->geo_fd_at, h->geo_d_at);
+                const std::vector<float> gu32(gu.begin(), gu.end());
+                geo_scalings(h, da, ds);
+                HIP_OK(hipMemcpyAsync(h->d_kband + h->geo_band_at, kb.data(), kb.size() * 8, hipMemcpyHostToDevice, s));
+                HIP_OK(hipMemcpyAsync(h->d_mband + h->geo_band_at, mb.data(), mb.size() * 8, hipMemcpyHostToDevice, s));
+                HIP_OK(hipMemcpyAsync(h->d_u64 + h->geo_fd_at, gu.data(), gu.size() * 8, hipMemcpyHostToDevice, s));
+                HIP_OK(hipMemcpyAsync(h->d_u32 + h->geo_fd_at, gu32.data(), gu32.size() * 4, hipMemcpyHostToDevice, s));
+                HIP_OK(hipMemcpyAsync(h->d_dtab + h->geo_d_at, gd.data(), gd.size() * 8, hipMemcpyHostToDevice, s));
+                HIP_OK(hipMemcpyAsync(h->d_geo_da, da.data(), da.size() * 8, hipMemcpyHostToDevice, s));
+                HIP_OK(hipMemcpyAsync(h->d_geo_ds, ds.data(), ds.size() * 8, hipMemcpyHostToDevice, s));
+                HIP_OK(hipStreamSynchronize(s));  // the host vectors end here
+            }
+            set_patch_coefficients(h);
             HIP_OK(hipMemcpyAsync(h->d_patches, h->h_patches.data(), h->h_patches.size() * sizeof(DevPatch),
                                   hipMemcpyHostToDevice, s));
             build_fd_set(h, h->fd_pa, false, h->fd_uoff, h->fd_doff, s);
@@ -1682,6 +1872,16 @@ int64_t afieti_export_size(const afieti_handle* h, int what) {
                 for (int m = 0; m < P.dim; ++m) n += (int64_t)P.dir[m].n * P.dir[m].n;
             return n * (int64_t)sizeof(double);
         }
+        case 7:
+            if (h->opt.precond != AFIETI_PRECOND_GEO) return -1;
+            return 2 * pl.n_dof * (int64_t)sizeof(double);
+        case 8: {
+            if (h->opt.precond != AFIETI_PRECOND_GEO) return -1;
+            int64_t n = 0;
+            for (const auto& P : pl.patches)
+                for (int m = 0; m < P.dim; ++m) n += (int64_t)P.dim * P.dir[m].n;
+            return n * (int64_t)sizeof(double);
+        }
         default: return -1;
     }
 }
@@ -1711,6 +1911,17 @@ int afieti_export(const afieti_handle* h, int what, void* buf, int64_t buf_bytes
         std::fill(o, o + pl.n_dof, 0.0);
         for (const auto& pr : pl.probs)
             if (!pr.fixed_load.empty()) std::copy(pr.fixed_load.begin(), pr.fixed_load.end(), o + pr.dof_off);
+    } else if (what == 7) {
+        double* o = static_cast<double*>(buf);
+        for (const auto& P : pl.patches) {
+            std::copy(P.geo_da.begin(), P.geo_da.end(), o + P.dof_off);
+            std::copy(P.geo_ds.begin(), P.geo_ds.end(), o + pl.n_dof + P.dof_off);
+        }
+    } else if (what == 8) {
+        double* o = static_cast<double*>(buf);
+        for (const auto& P : pl.patches)
+            for (int l = 0; l < P.dim; ++l)
+                for (int m = 0; m < P.dim; ++m) o = std::copy(P.gp[l][m].D.begin(), P.gp[l][m].D.end(), o);
     } else if (what == 6) {
         double* o = static_cast<double*>(buf);
         for (const auto& P : pl.patches)

@@ -22,7 +22,9 @@ struct DevPatch {
     int n[3];                    // basis counts (n[2] = 1 in 2D)
     int nq[3];                   // Gauss points per direction (nq[2] = 1 in 2D)
     int q_off[3];                // offsets into the univariate quadrature tables
-    int band_off[3];             // offsets into the banded univariate K, M tables
+    int band_off[3][3];          // [component][direction]: offsets into the banded univariate
+                                 // K, M tables of the operator A-hat_l (or A~_l)
+    double kap[3][3];            // [component][direction]: its Kronecker coefficients
     int el_off[3];               // offsets into the per-basis element ranges
     int dim, p, prob, nmodes;
     double lam, mu, hscale;

@@ -151,6 +151,8 @@ void launch_G_apply(const int* patch_plus, const int* patch_minus, const double*
 
 // ---- vector kernels
 void launch_copy(const double* x, double* y, int64_t n, hipStream_t s);
+// y = a .* x (elementwise; y may be x)
+void launch_mul(const double* a, const double* x, double* y, int64_t n, hipStream_t s);
 void launch_fill(double* y, double v, int64_t n, hipStream_t s);
 void launch_axpby(double a, const double* x, double b, const double* y, double* z, int64_t n, hipStream_t s);
 // per-chunk partial dot products <x, y>

@@ -1028,7 +1028,9 @@ void mf_gather_t(const DevPatch* dp, const int4* rb, int nrb, const double* ybuf
 }
 
 // A-hat_l x = kappa_1 (M3 x M2 x K1) x + kappa_2 (M3 x K2 x M1) x
-//           + kappa_3 (K3 x M2 x M1) x           (Kronecker form, Section 5.2)
+//           + kappa_3 (K3 x M2 x M1) x           (Kronecker form, Section 5.2;
+// with geometry inclusion A~_l, the same form with the weighted univariate
+// matrices of component l and kappa = 1, Section 5.2.3)
 //         = M2 (kappa_1 K1 u + kappa_3 M1 v) + kappa_2 K2 (M1 u),
 //           u = M3 x, v = K3 x,
 // by sum factorisation, one workgroup per slab i3 of a patch and component:
@@ -1063,10 +1065,10 @@ __global__ void __launch_bounds__(kAhBlock) k_ahat(const DevPatch* __restrict__ 
     const int nb1 = n1 * W, nb2 = n2 * W;
     // band rows of directions 1 and 2: staged in LDS for the specialised
     // degrees, read from global memory by the generic kernel
-    const double* K1 = kb + pa.band_off[0];
-    const double* Mb1 = mb + pa.band_off[0];
-    const double* K2 = kb + pa.band_off[1];
-    const double* Mb2 = mb + pa.band_off[1];
+    const double* K1 = kb + pa.band_off[l][0];
+    const double* Mb1 = mb + pa.band_off[l][0];
+    const double* K2 = kb + pa.band_off[l][1];
+    const double* Mb2 = mb + pa.band_off[l][1];
     if constexpr (P > 0) {
         double* T = V + max_n12;  // K1 | M1 (n1 x W), K2 | M2 (n2 x W)
         batched_copy<(4 * kMaxN * (2 * P + 1) + kAhBlock - 1) / kAhBlock, kAhBlock>(
@@ -1096,8 +1098,8 @@ __global__ void __launch_bounds__(kAhBlock) k_ahat(const DevPatch* __restrict__ 
     const bool ring_only = bnd_in && i3 > p && i3 < n3 - 1 - p;
     const bool thin = bnd_out && i3 > 0 && i3 < n3 - 1;
     // direction 3: the band row of i3 is uniform over the workgroup
-    const double* K3 = kb + pa.band_off[2] + i3 * W;
-    const double* M3 = mb + pa.band_off[2] + i3 * W;
+    const double* K3 = kb + pa.band_off[l][2] + i3 * W;
+    const double* M3 = mb + pa.band_off[l][2] + i3 * W;
     for (int e0 = threadIdx.x; e0 < n12; e0 += kAhBlock * kAhE) {
         bool need[kAhE], load[kAhE];
 #pragma unroll
@@ -1152,9 +1154,7 @@ __global__ void __launch_bounds__(kAhBlock) k_ahat(const DevPatch* __restrict__ 
     }
     __syncthreads();
     // direction 1 (results held in registers until every thread has read U, V)
-    const double k1 = l == 0 ? 2 * pa.mu + pa.lam : pa.mu;
-    const double k2 = l == 1 ? 2 * pa.mu + pa.lam : pa.mu;
-    const double k3 = l == 2 ? 2 * pa.mu + pa.lam : pa.mu;
+    const double k1 = pa.kap[l][0], k2 = pa.kap[l][1], k3 = pa.kap[l][2];
     constexpr int kR = (kMaxN * kMaxN + kAhBlock - 1) / kAhBlock;
     double ra[kR], rb[kR];
 #pragma unroll
@@ -1500,6 +1500,10 @@ __global__ void k_G_apply(const int* __restrict__ pp, const int* __restrict__ pm
 __global__ void k_copy(const double* __restrict__ x, double* __restrict__ y, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] = x[i];
+}
+__global__ void k_mul(const double* __restrict__ a, const double* x, double* y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a[i] * x[i];
 }
 __global__ void k_fill(double* __restrict__ y, double v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1940,6 +1944,9 @@ void launch_G_apply(const int* pp, const int* pm, const double* gp, const double
 
 void launch_copy(const double* x, double* y, int64_t n, hipStream_t s) {
     if (n) hipLaunchKernelGGL(k_copy, dim3(blocks_for(n)), dim3(kBlock), 0, s, x, y, n);
+}
+void launch_mul(const double* a, const double* x, double* y, int64_t n, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_mul, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, x, y, n);
 }
 void launch_fill(double* y, double v, int64_t n, hipStream_t s) {
     if (n) hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, y, v, n);

@@ -578,6 +578,10 @@ int sym_gen_eig(int n, const double* K, const double* M, double* U, double* D) {
 
 double rigid_mode(int dim, int m, int c, const double* X) { return rigid_mode_value(dim, m, c, X); }
 
+void multilinear_jacobian(int dim, const double* corners, const double* eta, double (&J)[3][3]) {
+    multilinear_jac(dim, corners, eta, J);
+}
+
 // -------------------------------------------------------------------- plan
 Plan build_plan(const afieti_problem* probs, int n_problems) {
     if (!probs || n_problems < 1) fail(AFIETI_EINVAL, "no problems");

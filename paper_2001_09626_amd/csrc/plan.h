@@ -36,6 +36,14 @@ struct Dir1D {
     std::vector<double> Ui, Di;   // interior pencil (n-2)
 };
 
+// Weighted univariate pencil of one (displacement component, direction) of a
+// patch for the geometry-inclusion local solvers (Section 5.2.3).
+struct GeoPencil {
+    std::vector<double> K, M;     // K~ = int nu b' b', M~ = int beta b b (n x n)
+    std::vector<double> U, D;     // U^T M~ U = I, U^T K~ U = diag(D)
+    std::vector<double> Ui, Di;   // interior pencil (n-2)
+};
+
 struct PatchPlan {
     int prob = 0;                 // problem index
     int dim = 3;
@@ -48,6 +56,10 @@ struct PatchPlan {
     double corners[24] = {0};
     int bc[6] = {0};
     std::vector<double> ctrl;     // [node][3] control points (z = 0 in 2D)
+    // geometry inclusion (filled by build_geometry_inclusion)
+    GeoPencil gp[3][3];           // [component][direction]
+    std::vector<double> geo_da;   // [component][node]: D_A^{-1/2}
+    std::vector<double> geo_ds;   // [component][node]: D_S^{1/2}
 };
 
 struct ProblemPlan {
@@ -89,6 +101,11 @@ struct Plan {
 // Build the host plan.  Throws SetupError.
 Plan build_plan(const afieti_problem* probs, int n_problems);
 
+// Geometry-inclusion data of every patch (separable fit, weighted pencils,
+// scalings; Section 5.2.3), on up to n_threads host threads.  Depends on
+// the patches' Lame parameters.  Throws SetupError.
+void build_geometry_inclusion(Plan& plan, int n_threads);
+
 // Helpers exposed for testing.
 std::vector<double> open_uniform_knots(int n_el, int p, int reg);
 // checks an explicit open knot vector of degree p on [0, 1]; returns the
@@ -98,6 +115,8 @@ void bspline_eval(const std::vector<double>& knots, int p, double x, int& first,
                   double* val, double* der);
 void gauss_legendre(int n, double* x, double* w);
 int sym_gen_eig(int n, const double* K, const double* M, double* U, double* D);
+// J[x][a] = dF_x / deta_a of the multilinear map of the 2^dim corners
+void multilinear_jacobian(int dim, const double* corners, const double* eta, double (&J)[3][3]);
 double rigid_mode(int dim, int m, int c, const double* X);
 
 }  // namespace afieti

@@ -244,3 +244,30 @@ def test_host_eigenvectors_diagonalise_the_pencils(mk):
             Fx = np.linalg.inv(M + K)
             assert np.abs(F - Fx).max() <= 1e-12 * np.abs(Fx).max()
     s.close()
+
+
+GEO_CASES = [lambda: W.make_c1(n_el=4, p=2, seed=3),
+             lambda: W.make_c2(n_el=3, p=3, seed=2, delta=0.1),
+             lambda: W.make_c3(n_el=2, p=2, grid=(2, 1, 2), seed=4)]
+
+
+@pytest.mark.parametrize("mk", GEO_CASES)
+def test_host_geometry_inclusion_matches_oracle(mk):
+    """Geometry inclusion (Section 5.2.3) on the host: the eigenvalues of the
+    weighted pencils of every patch, component and direction, and the
+    scalings D_A^{-1/2}, D_S^{1/2} per DOF, against the oracle's."""
+    from paper_2001_09626_amd import Solver
+    prob = mk()
+    s = Solver(prob, host_only=True, precond="geo")
+    o = AFIETI(prob, geometry=True)
+    D = s.export("geo_eig")
+    Do = np.concatenate([g.blocks[l]["fd"][m]["D"] for g in o.geo.patches
+                         for l in range(o.dim) for m in range(o.dim)])
+    assert D.shape == Do.shape
+    assert np.abs(D - Do).max() <= 1e-12 * np.abs(Do).max()
+    da, ds = s.export("geo_scale")
+    dao = o.join([np.array([g.blocks[l]["DA"] ** -0.5 for l in range(o.dim)]) for g in o.geo.patches])
+    dso = o.join([np.array([g.blocks[l]["DS"] ** 0.5 for l in range(o.dim)]) for g in o.geo.patches])
+    assert np.abs(da - dao).max() <= 1e-12 * np.abs(dao).max()
+    assert np.abs(ds - dso).max() <= 1e-12 * np.abs(dso).max()
+    s.close()
