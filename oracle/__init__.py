@@ -16,6 +16,8 @@ Modules
   geo       inexact local solvers with geometry inclusion: separable fit of
             the pulled-back coefficients, weighted pencils, diagonal
             scalings (Section 5.2.3, Remark 1)
+  exact     the exact local solvers: sparse factorisations of A + D_H M and
+            Dirichlet Schur complements (Section 5.1, Remark 1)
   direct    the conforming Galerkin solve the method must reproduce (Section 3)
   adjoint   gradients of a scalar of the displacement w.r.t. load amplitudes
             and per-patch Lame parameters (not in the paper; follows from the

@@ -60,7 +60,7 @@ class AFIETI:
     """The AF-IETI system of one problem (``workloads`` dictionary)."""
 
     def __init__(self, prob: dict, assembled: bool | None = None, geometry: bool = False,
-                 eig_driver: str | None = None):
+                 eig_driver: str | None = None, exact: bool = False):
         self.dim = int(prob["dim"])
         self.patches = [Patch(pd, self.dim) for pd in prob["patches"]]
         self.load_modes = prob["load"]
@@ -84,12 +84,17 @@ class AFIETI:
         self._build_dirichlet_data()
         self._build_coarse()
         self._build_fd()
-        # geometry inclusion (Section 5.2.3): P~_A and P~_S replace the
-        # preconditioner's blocks
+        # other local solvers replace the preconditioner's blocks: geometry
+        # inclusion (Section 5.2.3) or the exact ones (Section 5.1)
         self.geo = None
+        if geometry and exact:
+            raise ValueError("choose one of geometry inclusion and exact local solvers")
         if geometry:
             from .geo import GeoPreconditioner
             self.geo = GeoPreconditioner(self)
+        if exact:
+            from .exact import ExactPreconditioner
+            self.geo = ExactPreconditioner(self)
 
     # ------------------------------------------------------------ DOF helpers
     def split(self, x):
@@ -366,7 +371,8 @@ class AFIETI:
     def apply_prec(self, r, variant="nr"):
         """Block preconditioner of Section 4: [P_u P_A^{-1} P_u r_w;
         P_chi P_S P_chi r_chi], with P~_A and P~_S of Section 5.2.3 when
-        the system was built with ``geometry=True``."""
+        the system was built with ``geometry=True``, P_A^ex and P_S^{ex-nr}
+        of Section 5.1 with ``exact=True``."""
         rw, rc = r[:self.n_dof], r[self.n_dof:]
         if self.geo is not None:
             zw = self.P_u(self.geo.apply_PA_inv(self.P_u(rw)))
