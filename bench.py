@@ -57,6 +57,11 @@ def workload(name):
         p = int(name[2:]) if len(name) > 2 else 3
         prob = W.make_c3(seed=0, p=p)
         desc = f"3D unit cube, 4x4x4 patches, p={p} C^{p-1}, 24^3 elements/patch, lognormal Lame, 8 trig modes"
+    elif name.startswith("ws"):
+        k = int(name[2:]) if len(name) > 2 else 4
+        prob = W.make_weak_scaling(k=k, n_el=8, p=3)
+        desc = (f"weak-scaling cube: {k}^3 unit-cube patches, p=3 C^2, 8^3 elements/patch, steel, "
+                "manufactured solution, Dirichlet data on y=0,1 and z=0,1, tractions on x=0,1")
     else:
         raise SystemExit(f"unknown workload {name}")
     return prob, desc
@@ -189,6 +194,8 @@ def main():
     ap.add_argument("--mv-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-fp32", action="store_true")
+    ap.add_argument("--no-geometry", action="store_true",
+                    help="skip the geometry-inclusion variant of the local solvers")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -245,6 +252,31 @@ def main():
         rel = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
         out.update(fp64_fd_solve_s=ms64 / 1e3, iterations_fp64_fd=st64["iterations"],
                    solve_speedup_fp32_vs_fp64=ms64 / ms32, rel_diff_u_fp32_vs_fp64=rel)
+
+    # the geometry-inclusion local solvers (the variant of the paper's
+    # numerical results), FP32 FD: setup (fit, d^2 pencils per patch,
+    # scalings) and solve
+    if not args.no_geometry:
+        t = time.time()
+        log("setup geometry-inclusion FP32-FD handle")
+        sg = Solver(prob, fd_precision="fp32", tol=1e-8, precond="geo")
+        torch.cuda.synchronize()
+        setup_g = time.time() - t
+        ug = torch.empty(sg.n_dof, dtype=torch.float64, device="cuda")
+        lg = torch.empty(sg.n_c, dtype=torch.float64, device="cuda")
+        for i in range(args.warmup):
+            sg.solve(u=ug, lam=lg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            _, _, stg = sg.solve(u=ug, lam=lg)
+        torch.cuda.synchronize()
+        msg_ = (time.perf_counter() - t0) * 1e3 / args.steps
+        log(f"geometry-inclusion FP32-FD solve: {msg_:.1f} ms/step, {stg['iterations']} iterations "
+            f"(setup {setup_g:.1f}s)")
+        out["geometry_inclusion"] = dict(solve_s=msg_ / 1e3, iterations=stg["iterations"], setup_s=setup_g,
+                                         fd_precision="fp32")
+        sg.close()
 
     # FD-apply throughput (one apply over all patches and components)
     r = torch.from_numpy(W.random_vector(s32.n_dof, 3)).cuda()
