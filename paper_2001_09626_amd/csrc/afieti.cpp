@@ -482,7 +482,8 @@ void combine_load(afieti_handle* h, hipStream_t s) {
 }
 
 int fd_prec(const afieti_handle* h);
-void op_fd_tmp(afieti_handle* h, const FdSet& set, const double* in, double* out, void* tmp, hipStream_t s);
+void op_fd_tmp(afieti_handle* h, const FdSet& set, const double* in, double* out, void* tmp, hipStream_t s,
+               const double* scale = nullptr);
 
 constexpr int64_t kLdsBytes = 160 * 1024;  // LDS of one gfx950 compute unit
 
@@ -1083,20 +1084,24 @@ int64_t fd_tmp_bytes(const afieti_handle* h, const FdSet& set) {
 
 // FD launch: the vector-ALU kernels per tensor (FP64, FP32 VALU) or the
 // matrix-core kernels per group in the tuned layout and launch shape
-void op_fd_tmp(afieti_handle* h, const FdSet& set, const double* in, double* out, void* tmp, hipStream_t s) {
+// (scale: out = scale .* FD(scale .* in), folded into the first and last
+// pass; NULL for none)
+void op_fd_tmp(afieti_handle* h, const FdSet& set, const double* in, double* out, void* tmp, hipStream_t s,
+               const double* scale) {
     const int prec = fd_prec(h);
     const bool f64 = prec == 0 || prec == 4;
     const void* ut = f64 ? (const void*)h->d_u64 : (const void*)h->d_u32;
     if (prec >= 2)
         launch_fd_groups(prec - 2, set.tune % kFdVariants, set.gs[set.tune / kFdVariants], ut, h->d_dtab, in, out, tmp,
-                         h->mask, s);
+                         h->mask, scale, s);
     else
         launch_fd(prec, set.d_t, set.n_t, set.d_slabs, set.n_slabs, set.d_cols, set.n_cols, ut, h->d_dtab, in, out,
-                  tmp, h->mask, s);
+                  tmp, h->mask, scale, s);
 }
 
-void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s, int ln = 0) {
-    op_fd_tmp(h, set, in, out, h->lane[ln].fdtmp, s);
+void op_fd(afieti_handle* h, const FdSet& set, const double* in, double* out, hipStream_t s, int ln = 0,
+           const double* scale = nullptr) {
+    op_fd_tmp(h, set, in, out, h->lane[ln].fdtmp, s, scale);
 }
 
 // out = w P_chi y  (in place allowed)
@@ -1120,10 +1125,10 @@ void op_pu(afieti_handle* h, const double* x, double* out, hipStream_t s, int ln
 // stages so that a caller can interleave them with other work:
 //   1: v0 = B^T W y on Gamma, t = A-hat v0
 //   2: v_I = -((A-hat)_II)^{-1} t_I  (interior FD, in place in v)
-//   3: out = W B (H^{d-2} A-hat v)  (4: the same without the A-hat and the
-//      output scaling, when the caller has applied them)
+//   3: out = W B (H^{d-2} A-hat v)  (4: the same without the A-hat, when
+//      the caller has applied it)
 // With geometry inclusion A~_l replaces A-hat_l, there is no H factor, and
-// D_S^{1/2} scales the Gamma values after B^T and after the second A~.
+// D_S^{1/2} scales the Gamma values as B^T writes them and as B reads them.
 void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipStream_t s, int ln) {
     const bool nr = h->opt.ps_variant == AFIETI_PS_NR;
     if (stage == 1) {
@@ -1132,20 +1137,18 @@ void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipS
             launch_W(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, y, h->c1, s);
             a = h->c1;
         }
-        launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, a, h->tv, s);
-        if (h->d_geo_ds) launch_mul(h->d_geo_ds, h->tv, h->tv, h->n_dof, s);  // D_S^{1/2} (geometry inclusion)
+        // (D_S^{1/2} applied as B^T writes, with geometry inclusion)
+        launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, a, h->tv, s, h->d_geo_ds);
         op_ahat(h, h->tv, h->tt, 0, s, true);
     } else if (stage == 2) {
         op_fd(h, h->fd_int, h->tt, h->tv, s, ln);
     } else {
-        if (stage == 3) {
-            op_ahat(h, h->tv, h->tt, 1, s, false, true);  // B reads only the Gamma part
-            if (h->d_geo_ds) launch_mul(h->d_geo_ds, h->tt, h->tt, h->n_dof, s);
-        }
+        if (stage == 3) op_ahat(h, h->tv, h->tt, 1, s, false, true);  // B reads only the Gamma part
+        // (D_S^{1/2} applied as B reads, with geometry inclusion)
         if (nr) {
-            launch_BW(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->d_cplus, h->d_cminus, h->tt, out, s);
+            launch_BW(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->d_cplus, h->d_cminus, h->tt, out, s, h->d_geo_ds);
         } else {
-            launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, h->tt, out, s);
+            launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, h->tt, out, s, h->d_geo_ds);
         }
     }
 }
@@ -1174,20 +1177,17 @@ void op_prec_branches(afieti_handle* h, const double* r, double* z, hipStream_t 
         const Lane& L = h->lane[b.ln];
         launch_GW(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, L.zc,
                   r + h->n_dof, h->c1, b.s);
-        launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, h->c1, h->tv, b.s);
-        if (h->d_geo_ds) launch_mul(h->d_geo_ds, h->tv, h->tv, h->n_dof, b.s);
+        launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, h->c1, h->tv, b.s, h->d_geo_ds);
         op_ahat(h, h->tv, h->tt, 0, b.s, true);
     } else {
         op_ps_stage(h, 1, h->c3, h->c4, b.s, b.ln);
     }
-    // geometry inclusion: P~_A^{-1} = D_A^{-1/2} (A~ + H^-2 M~)^{-1} D_A^{-1/2}
-    if (h->d_geo_da) launch_mul(h->d_geo_da, h->s1, h->s1, h->n_dof, s);
-    op_fd(h, h->fd_pa, h->s1, h->s2, s);
-    if (h->d_geo_da) launch_mul(h->d_geo_da, h->s2, h->s2, h->n_dof, s);
+    // geometry inclusion: P~_A^{-1} = D_A^{-1/2} (A~ + H^-2 M~)^{-1} D_A^{-1/2},
+    // the scaling folded into the FD passes
+    op_fd(h, h->fd_pa, h->s1, h->s2, s, 0, h->d_geo_da);
     op_ps_stage(h, 2, h->c3, h->c4, b.s, b.ln);
     op_pu(h, h->s2, z, s);
     op_ahat(h, h->tv, h->tt, 1, b.s, false, true);
-    if (h->d_geo_ds) launch_mul(h->d_geo_ds, h->tt, h->tt, h->n_dof, b.s);
     // the last LDS-heavy kernel of P_S (a pipelined graph starts the next
     // brick quadrature after it)
     if (h->capturing) HIP_OK(hipEventRecord(h->ev_ps, b.s));
@@ -1584,14 +1584,8 @@ int afieti_apply_fd(afieti_handle* h, const double* r, double* z, void* stream) 
         return AFIETI_EINVAL;
     }
     try {
-        hipStream_t s = (hipStream_t)stream;
-        if (h->d_geo_da) {  // D_A^{-1/2} (A~ + H^-2 M~)^{-1} D_A^{-1/2}
-            launch_mul(h->d_geo_da, r, h->s1, h->n_dof, s);
-            op_fd(h, h->fd_pa, h->s1, z, s);
-            launch_mul(h->d_geo_da, z, z, h->n_dof, s);
-        } else {
-            op_fd(h, h->fd_pa, r, z, s);
-        }
+        // (geometry inclusion: D_A^{-1/2} (A~ + H^-2 M~)^{-1} D_A^{-1/2})
+        op_fd(h, h->fd_pa, r, z, (hipStream_t)stream, 0, h->d_geo_da);
         HIP_OK(hipGetLastError());
         return AFIETI_OK;
     } catch (const SetupError& e) {
@@ -1624,13 +1618,7 @@ int afieti_apply_fd_noalloc(afieti_handle* h, const double* r, double* z, void* 
     }
     // the passes write every intermediate entry before reading it: nothing
     // of the previous call's contents is read
-    if (h->d_geo_da) {  // the scaled input goes to a vector the handle owns
-        launch_mul(h->d_geo_da, r, h->s1, h->n_dof, (hipStream_t)stream);
-        op_fd_tmp(h, h->fd_pa, h->s1, z, tmp, (hipStream_t)stream);
-        launch_mul(h->d_geo_da, z, z, h->n_dof, (hipStream_t)stream);
-    } else {
-        op_fd_tmp(h, h->fd_pa, r, z, tmp, (hipStream_t)stream);
-    }
+    op_fd_tmp(h, h->fd_pa, r, z, tmp, (hipStream_t)stream, h->d_geo_da);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         h->err = std::string("kernel launch: ") + hipGetErrorString(e);

@@ -122,15 +122,14 @@ __device__ inline V bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     else return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
-// dst[i * ld + j] = element at byte offset roff(i) + coff(j) of the buffer
-// r (V typed; a kOob row or column gives zero) for i < rows, j < cols.
-// Wavefront w stages rows w, w + NW, ... (the row part of the address is
-// uniform over the wavefront); lane l takes columns l, l + 64, ... (cols <=
-// 64 CPL), the column part computed once per lane.  A thread issues the
-// loads of CH rows before it stores any of them.
-template <int NW, int CPL, typename V, typename T, typename RowOff, typename ColOff>
-__device__ inline void stage(T* dst, int ld, int rows, int cols, __amdgpu_buffer_rsrc_t r, RowOff roff,
-                             ColOff coff) {
+// dst[i * ld + j] = load(roff(i) + coff(j)), the element at that byte
+// offset of a buffer (V typed; a kOob row or column gives zero), for
+// i < rows, j < cols.  Wavefront w stages rows w, w + NW, ... (the row part
+// of the address is uniform over the wavefront); lane l takes columns l,
+// l + 64, ... (cols <= 64 CPL), the column part computed once per lane.  A
+// thread issues the loads of CH rows before it stores any of them.
+template <int NW, int CPL, typename V, typename T, typename RowOff, typename ColOff, typename Load>
+__device__ inline void stage_with(T* dst, int ld, int rows, int cols, RowOff roff, ColOff coff, Load load) {
     constexpr int CH = 8 / CPL;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     uint32_t co[CPL];
@@ -146,7 +145,7 @@ __device__ inline void stage(T* dst, int ld, int rows, int cols, __amdgpu_buffer
             const int i = i0 + u * NW;
             const uint32_t ro = i < rows ? roff(i) : kOob;
 #pragma unroll
-            for (int q = 0; q < CPL; ++q) v[u][q] = bload<V>(r, (ro == kOob || co[q] == kOob) ? kOob : ro + co[q]);
+            for (int q = 0; q < CPL; ++q) v[u][q] = load((ro == kOob || co[q] == kOob) ? kOob : ro + co[q]);
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
@@ -158,6 +157,13 @@ __device__ inline void stage(T* dst, int ld, int rows, int cols, __amdgpu_buffer
             }
         }
     }
+}
+
+// the elements of buffer r
+template <int NW, int CPL, typename V, typename T, typename RowOff, typename ColOff>
+__device__ inline void stage(T* dst, int ld, int rows, int cols, __amdgpu_buffer_rsrc_t r, RowOff roff,
+                             ColOff coff) {
+    stage_with<NW, CPL, V>(dst, ld, rows, cols, roff, coff, [&](uint32_t o) { return bload<V>(r, o); });
 }
 
 // operand of step s: A(m0 + r, k) (Tr: stored [k][m]) or B(k, n0 + r) (Tr:
@@ -255,7 +261,8 @@ __global__ void __launch_bounds__(kFdThreads) k_fdg_fwd(const FdGroup* __restric
                                                         const typename Mf<MODE>::U* __restrict__ ut,
                                                         const double* __restrict__ in,
                                                         typename Mf<MODE>::Tmp* __restrict__ tmp,
-                                                        const MinresState* __restrict__ mask) {
+                                                        const MinresState* __restrict__ mask,
+                                                        const double* __restrict__ scale) {
     using M = Mf<MODE>;
     using T = typename M::T;
     using D = Dep<MODE, KM>;
@@ -270,15 +277,24 @@ __global__ void __launch_bounds__(kFdThreads) k_fdg_fwd(const FdGroup* __restric
     T* YB = XA + L.oY;
     T* U2 = XA + L.oU2;
     const int R = nc * n2, C = nc * n1;
-    // the slab of every component: rows (c, i2), columns i1
+    // the slab of every component: rows (c, i2), columns i1 (times the
+    // per-DOF scale, at the same offsets of its vector, when given)
     const int64_t span = (int64_t)(nc - 1) * G.cstride + (int64_t)(n2 - 1) * G.s2 + n1;
-    stage<kFdWaves, (D::K + 63) / 64, double>(
-        XA, L.LDA, L.RP, D::K, rsrc(in + G.in_off + (int64_t)i3 * G.s3, span * 8),
-        [&](int r) {
-            const int c = r / n2, i2 = r - c * n2;
-            return r < R ? (uint32_t)((c * G.cstride + (int64_t)i2 * G.s2) * 8) : kOob;
-        },
-        [&](int k) { return k < n1 ? (uint32_t)(k * 8) : kOob; });
+    const int64_t first = G.in_off + (int64_t)i3 * G.s3;
+    const auto roff = [&](int r) {
+        const int c = r / n2, i2 = r - c * n2;
+        return r < R ? (uint32_t)((c * G.cstride + (int64_t)i2 * G.s2) * 8) : kOob;
+    };
+    const auto coff = [&](int k) { return k < n1 ? (uint32_t)(k * 8) : kOob; };
+    const __amdgpu_buffer_rsrc_t rx = rsrc(in + first, span * 8);
+    if (scale) {
+        const __amdgpu_buffer_rsrc_t rs = rsrc(scale + first, span * 8);
+        stage_with<kFdWaves, (D::K + 63) / 64, double>(XA, L.LDA, L.RP, D::K, roff, coff, [&](uint32_t o) {
+            return bload<double>(rx, o) * bload<double>(rs, o);
+        });
+    } else {
+        stage<kFdWaves, (D::K + 63) / 64, double>(XA, L.LDA, L.RP, D::K, rx, roff, coff);
+    }
     stage_u<MODE, KM>(U1, ut + G.u_off[0], n1);
     stage_u<MODE, KM>(U2, ut + G.u_off[1], n2);
     // depth rows of the second product past n2 and columns past C stay zero
@@ -405,14 +421,16 @@ __global__ void __launch_bounds__(kFdThreads) k_fdg_mid(const FdGroup* __restric
 
 // ---------------------------------------------------------------- pass 3
 // per (group, slab i3): Y[(c, a2)][i1] = sum_a1 W[(c, a2)][a1] U1[i1][a1];
-// X[i2][(c, i1)] = sum_a2 U2[i2][a2] Y[a2][(c, i1)];  out = alpha X
+// X[i2][(c, i1)] = sum_a2 U2[i2][a2] Y[a2][(c, i1)];  out = alpha X (times
+// the per-DOF scale, when given)
 template <int MODE, int KM>
 __global__ void __launch_bounds__(kFdThreads) k_fdg_bwd(const FdGroup* __restrict__ groups,
                                                         const int2* __restrict__ slabs,
                                                         const typename Mf<MODE>::U* __restrict__ ut,
                                                         const typename Mf<MODE>::Tmp* __restrict__ tmp,
                                                         double* __restrict__ out,
-                                                        const MinresState* __restrict__ mask) {
+                                                        const MinresState* __restrict__ mask,
+                                                        const double* __restrict__ scale) {
     using M = Mf<MODE>;
     using T = typename M::T;
     using D = Dep<MODE, KM>;
@@ -463,6 +481,7 @@ __global__ void __launch_bounds__(kFdThreads) k_fdg_bwd(const FdGroup* __restric
     // X = U2 Y: strips of one stacked column tile (c, i1) across the i2 tiles
     {
         double* dst = out + G.out_off + (int64_t)i3 * G.s3;
+        const double* sdst = scale ? scale + G.out_off + (int64_t)i3 * G.s3 : nullptr;
         for (int t = wave; t < CP / 16; t += kFdWaves) {
             typename M::Acc acc[D::NTU];
             strip_col<MODE, D::KS, D::NTU, false, false>(U2, L.LDU, YB, L.LDY, 16 * t, acc);
@@ -473,7 +492,11 @@ __global__ void __launch_bounds__(kFdThreads) k_fdg_bwd(const FdGroup* __restric
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int i2 = 16 * i + M::row(g, q);
-                    if (i2 < n2 && col < C) dst[c * G.cstride + (int64_t)i2 * G.s2 + i1] = G.alpha * (double)acc[i][q];
+                    if (i2 < n2 && col < C) {
+                        const int64_t o = c * G.cstride + (int64_t)i2 * G.s2 + i1;
+                        const double v = G.alpha * (double)acc[i][q];
+                        dst[o] = sdst ? v * sdst[o] : v;
+                    }
                 }
         }
     }
@@ -486,7 +509,7 @@ int64_t lds_elems(int pass, int n1, int n2, int nc, int ncb) {
 
 template <int MODE, int KM, int NCB>
 void fdg_run(const FdGroupSet& set, const void* ut, const double* dt, const double* in, double* out, void* tmp,
-             const MinresState* mask, hipStream_t s) {
+             const MinresState* mask, const double* scale, hipStream_t s) {
     using M = Mf<MODE>;
     const auto* u = static_cast<const typename M::U*>(ut);
     auto* tp = static_cast<typename M::Tmp*>(tmp);
@@ -503,27 +526,27 @@ void fdg_run(const FdGroupSet& set, const void* ut, const double* dt, const doub
         (void)hipFuncSetAttribute((const void*)k_fdg_mid<MODE, KM, NCB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)b3);
     hipLaunchKernelGGL((k_fdg_fwd<MODE, KM>), dim3(set.n_slabs), dim3(kFdThreads), b12, s, set.groups, set.slabs, u, in,
-                       tp, mask);
+                       tp, mask, scale);
     hipLaunchKernelGGL((k_fdg_mid<MODE, KM, NCB>), dim3(n_colblocks), dim3(kFdThreads), b3, s, set.groups, colblocks,
                        u, dt, tp, mask);
     hipLaunchKernelGGL((k_fdg_bwd<MODE, KM>), dim3(set.n_slabs), dim3(kFdThreads), b12, s, set.groups, set.slabs, u,
-                       tp, out, mask);
+                       tp, out, mask, scale);
 }
 
 template <int MODE, int KM>
 void fdg_ncb(int ncb, const FdGroupSet& set, const void* ut, const double* dt, const double* in, double* out,
-             void* tmp, const MinresState* mask, hipStream_t s) {
-    if (ncb == 64) fdg_run<MODE, KM, 64>(set, ut, dt, in, out, tmp, mask, s);
-    else fdg_run<MODE, KM, 128>(set, ut, dt, in, out, tmp, mask, s);
+             void* tmp, const MinresState* mask, const double* scale, hipStream_t s) {
+    if (ncb == 64) fdg_run<MODE, KM, 64>(set, ut, dt, in, out, tmp, mask, scale, s);
+    else fdg_run<MODE, KM, 128>(set, ut, dt, in, out, tmp, mask, scale, s);
 }
 
 template <int MODE>
 void fdg_dispatch(int ncb, const FdGroupSet& set, const void* ut, const double* dt, const double* in, double* out,
-                  void* tmp, const MinresState* mask, hipStream_t s) {
+                  void* tmp, const MinresState* mask, const double* scale, hipStream_t s) {
     switch (fd_depth_extent(set)) {
-        case 28: fdg_ncb<MODE, 28>(ncb, set, ut, dt, in, out, tmp, mask, s); break;
-        case 36: fdg_ncb<MODE, 36>(ncb, set, ut, dt, in, out, tmp, mask, s); break;
-        default: fdg_ncb<MODE, 48>(ncb, set, ut, dt, in, out, tmp, mask, s); break;
+        case 28: fdg_ncb<MODE, 28>(ncb, set, ut, dt, in, out, tmp, mask, scale, s); break;
+        case 36: fdg_ncb<MODE, 36>(ncb, set, ut, dt, in, out, tmp, mask, scale, s); break;
+        default: fdg_ncb<MODE, 48>(ncb, set, ut, dt, in, out, tmp, mask, scale, s); break;
     }
 }
 
@@ -563,12 +586,13 @@ int64_t fd_lds_bytes(int mode, int variant, const FdGroupSet& set) {
 }
 
 void launch_fd_groups(int mode, int variant, const FdGroupSet& set, const void* ut, const double* dt,
-                      const double* in, double* out, void* tmp, const MinresState* mask, hipStream_t s) {
+                      const double* in, double* out, void* tmp, const MinresState* mask, const double* scale,
+                      hipStream_t s) {
     if (set.n_slabs == 0) return;
     const int ncb = fd_variant_ncb(variant);
-    if (mode == 0) fdg_dispatch<0>(ncb, set, ut, dt, in, out, tmp, mask, s);
-    else if (mode == 1) fdg_dispatch<1>(ncb, set, ut, dt, in, out, tmp, mask, s);
-    else fdg_dispatch<2>(ncb, set, ut, dt, in, out, tmp, mask, s);
+    if (mode == 0) fdg_dispatch<0>(ncb, set, ut, dt, in, out, tmp, mask, scale, s);
+    else if (mode == 1) fdg_dispatch<1>(ncb, set, ut, dt, in, out, tmp, mask, scale, s);
+    else fdg_dispatch<2>(ncb, set, ut, dt, in, out, tmp, mask, scale, s);
 }
 
 }  // namespace afieti

@@ -9,12 +9,16 @@ namespace afieti {
 
 // ---- Fast Diagonalization (Algorithm 1) on the vector ALU: three passes
 // over the tensors.  Kernels of problems whose MINRES has stopped
-// (mask[prob].stop != 0) return at once; mask may be NULL.  prec 0: FP64;
-// 1: FP32.  d_cols: 32-column blocks of the mode-3 pass.
+// (mask[prob].skip != 0) return at once; mask may be NULL.  prec 0: FP64;
+// 1: FP32.  d_cols: 32-column blocks of the mode-3 pass.  scale (may be
+// NULL): a per-DOF factor applied to the input as it is read and to the
+// output as it is written, out = s .* FD(s .* in) (the diagonal scaling of
+// geometry inclusion).
 void launch_fd(int prec, const FdTensor* d_tensors, int n_tensors,
                const int2* d_slabs, int n_slabs, const int2* d_cols, int n_colblocks,
                const void* u_table, const double* d_table,
-               const double* in, double* out, void* tmp, const MinresState* mask, hipStream_t s);
+               const double* in, double* out, void* tmp, const MinresState* mask, const double* scale,
+               hipStream_t s);
 
 // ---- Fast Diagonalization on the matrix cores (fd.hip): the d component
 // tensors of a patch (a group) share U_m and are transformed together (or
@@ -38,8 +42,10 @@ int fd_depth_extent(const FdGroupSet& set);
 int64_t fd_lds_bytes(int mode, int variant, const FdGroupSet& set);
 // mode 0: FP32 operands, 1: BF16 operands (FP32 accumulation), 2: FP64.
 // tmp holds one FP32 (FP64 for mode 2) entry per tensor element.
+// scale as for launch_fd.
 void launch_fd_groups(int mode, int variant, const FdGroupSet& set, const void* ut, const double* dt,
-                      const double* in, double* out, void* tmp, const MinresState* mask, hipStream_t s);
+                      const double* in, double* out, void* tmp, const MinresState* mask, const double* scale,
+                      hipStream_t s);
 
 // ---- fixed scratch for callers that cannot allocate
 // Bytes of the file-scope device array that afieti_apply_fd_noalloc uses for
@@ -100,12 +106,14 @@ void launch_mf_gather(int p, const DevPatch* dp, const int4* rb, int nrb, const 
 int mf_brick_elems(int p);
 // doubles per (direction, brick) table of the matrix-free kernel for degree p
 int mf_table_doubles(int p);
-// y[r] = alpha (x[plus] - x[minus])
+// y[r] = alpha (x[plus] - x[minus]); with in_scale (may be NULL) x is read
+// as in_scale .* x
 void launch_B(const int64_t* plus, const int64_t* minus, int64_t n_c, double alpha,
-              const double* x, double* y, hipStream_t s);
-// y[i] = sum sign * x[row] for every DOF
+              const double* x, double* y, hipStream_t s, const double* in_scale = nullptr);
+// y[i] = sum sign * x[row] for every DOF; with out_scale (may be NULL)
+// y[i] = out_scale[i] * (that sum)
 void launch_Bt(const int64_t* bt_ptr, const int* bt_row, const double* bt_sign, int64_t n_dof,
-               const double* x, double* y, hipStream_t s);
+               const double* x, double* y, hipStream_t s, const double* out_scale = nullptr);
 // z = (B B^T)^{-1} y (node blocks)
 void launch_W(const int* blk_start, const int* blk_size, const int* blk_dir, int64_t n_c,
               const double* y, double* z, hipStream_t s);
@@ -122,7 +130,7 @@ void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, int 
 // z = (B B^T)^{-1} (B x), and z = (B B^T)^{-1} (y - G zc), with the B and the
 // G rows computed inside the block solve
 void launch_BW(const int* blk_start, const int* blk_size, const int* blk_dir, int64_t n_c, const int64_t* plus,
-               const int64_t* minus, const double* x, double* z, hipStream_t s);
+               const int64_t* minus, const double* x, double* z, hipStream_t s, const double* in_scale = nullptr);
 void launch_GW(const int* blk_start, const int* blk_size, const int* blk_dir, int64_t n_c, const int* patch_plus,
                const int* patch_minus, const double* g_plus, const double* g_minus, const double* zc,
                const double* y, double* z, hipStream_t s);

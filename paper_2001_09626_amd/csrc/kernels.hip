@@ -90,7 +90,8 @@ constexpr int kFdSlabIt = (kMaxN * kMaxN + kFdBlock - 1) / kFdBlock;  // loads p
 template <typename T>
 __global__ void __launch_bounds__(kFdBlock) k_fd_fwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
                                                      const T* __restrict__ ut, const double* __restrict__ in,
-                                                     T* __restrict__ tmp, const MinresState* __restrict__ mask) {
+                                                     T* __restrict__ tmp, const MinresState* __restrict__ mask,
+                                                     const double* __restrict__ scale) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 it = slabs[blockIdx.x];
     const FdTensor t = tens[it.x];
@@ -100,9 +101,11 @@ __global__ void __launch_bounds__(kFdBlock) k_fd_fwd12(const FdTensor* __restric
     T* Y = X + kMaxN * kMaxN;
     T* U = Y + kMaxN * kMaxN;
     const double* src = in + t.in_off + (int64_t)i3 * t.s3;
+    const double* ssrc = scale ? scale + t.in_off + (int64_t)i3 * t.s3 : nullptr;
     batched_copy<kFdSlabIt, kFdBlock>(X, n12, [&](int e) {
         const int i2 = e / n1, i1 = e - i2 * n1;
-        return (T)src[(int64_t)i2 * t.s2 + i1];
+        const int64_t o = (int64_t)i2 * t.s2 + i1;
+        return (T)(ssrc ? src[o] * ssrc[o] : src[o]);
     });
     batched_copy<kFdSlabIt, kFdBlock>(U, n1 * n1, [&](int e) { return ut[t.u_off[0] + e]; });
     __syncthreads();
@@ -170,7 +173,8 @@ __global__ void __launch_bounds__(kFdBlock) k_fd_mid3(const FdTensor* __restrict
 template <typename T>
 __global__ void __launch_bounds__(kFdBlock) k_fd_bwd12(const FdTensor* __restrict__ tens, const int2* __restrict__ slabs,
                                                      const T* __restrict__ ut, const T* __restrict__ tmp,
-                                                     double* __restrict__ out, const MinresState* __restrict__ mask) {
+                                                     double* __restrict__ out, const MinresState* __restrict__ mask,
+                                                     const double* __restrict__ scale) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int2 it = slabs[blockIdx.x];
     const FdTensor t = tens[it.x];
@@ -193,11 +197,14 @@ __global__ void __launch_bounds__(kFdBlock) k_fd_bwd12(const FdTensor* __restric
     batched_copy<kFdSlabIt, kFdBlock>(U, n2 * n2, [&](int e) { return ut[t.u_off[1] + e]; });
     __syncthreads();
     double* dst = out + t.out_off + (int64_t)i3 * t.s3;
+    const double* sdst = scale ? scale + t.out_off + (int64_t)i3 * t.s3 : nullptr;
     for (int e = threadIdx.x; e < n12; e += kFdBlock) {  // X[i2][i1] = sum_a2 U2[i2][a2] Y[a2][i1]
         int i2 = e / n1, i1 = e - i2 * n1;
         T acc = 0;
         for (int a2 = 0; a2 < n2; ++a2) acc += U[i2 * n2 + a2] * Y[a2 * n1 + i1];
-        dst[(int64_t)i2 * t.s2 + i1] = t.alpha * (double)acc;
+        const int64_t o = (int64_t)i2 * t.s2 + i1;
+        const double v = t.alpha * (double)acc;
+        dst[o] = sdst ? v * sdst[o] : v;
     }
 }
 
@@ -1226,21 +1233,26 @@ void ahat_t(const DevPatch* dp, const int4* slabs, int n_slabs, int max_n12, int
                        bnd_in, bnd_out, mask);
 }
 
+// x[i], or sc[i] x[i] with a per-DOF scale
+__device__ inline double scaled(const double* __restrict__ x, const double* __restrict__ sc, int64_t i) {
+    return sc ? x[i] * sc[i] : x[i];
+}
+
 __global__ void k_B(const int64_t* __restrict__ plus, const int64_t* __restrict__ minus, int64_t n_c, double alpha,
-                    const double* __restrict__ x, double* __restrict__ y) {
+                    const double* __restrict__ x, double* __restrict__ y, const double* __restrict__ sc) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_c) return;
     const int64_t m = minus[r];
-    y[r] = alpha * (x[plus[r]] - (m >= 0 ? x[m] : 0.0));
+    y[r] = alpha * (scaled(x, sc, plus[r]) - (m >= 0 ? scaled(x, sc, m) : 0.0));
 }
 
 __global__ void k_Bt(const int64_t* __restrict__ ptr, const int* __restrict__ row, const double* __restrict__ sgn,
-                     int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+                     int64_t n, const double* __restrict__ x, double* __restrict__ y, const double* __restrict__ sc) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double acc = 0.0;
     for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) acc += sgn[e] * x[row[e]];
-    y[i] = acc;
+    y[i] = sc ? sc[i] * acc : acc;
 }
 
 // (B B^T)^{-1} per node block.  Star block of size s: I + 1 1^T, whose
@@ -1279,10 +1291,10 @@ __device__ inline void w_rows(const int* __restrict__ bs, const int* __restrict_
 
 __global__ void k_BW(const int* __restrict__ bs, const int* __restrict__ bn, const int* __restrict__ bd, int64_t n_c,
                      const int64_t* __restrict__ plus, const int64_t* __restrict__ minus, const double* __restrict__ x,
-                     double* __restrict__ z) {
+                     double* __restrict__ z, const double* __restrict__ sc) {
     w_rows(bs, bn, bd, n_c, z, [&](int64_t q) {
         const int64_t m = minus[q];
-        return 1.0 * (x[plus[q]] - (m >= 0 ? x[m] : 0.0));
+        return 1.0 * (scaled(x, sc, plus[q]) - (m >= 0 ? scaled(x, sc, m) : 0.0));
     });
 }
 
@@ -1714,27 +1726,27 @@ void* noalloc_scratch_ptr(int device) {
 // ======================================================== launch wrappers
 void launch_fd(int prec, const FdTensor* tens, int n_tensors, const int2* slabs, int n_slabs, const int2* cols,
                int n_colblocks, const void* ut, const double* dt, const double* in, double* out, void* tmp,
-               const MinresState* mask, hipStream_t s) {
+               const MinresState* mask, const double* scale, hipStream_t s) {
     (void)n_tensors;
     if (n_slabs == 0) return;
     if (prec == 0) {
         const size_t sh12 = 3 * kMaxN * kMaxN * sizeof(double);
         const size_t sh3 = (2 * kMaxN * 32 + kMaxN * kMaxN) * sizeof(double);
         hipLaunchKernelGGL(k_fd_fwd12<double>, dim3(n_slabs), dim3(kFdBlock), sh12, s, tens, slabs,
-                           (const double*)ut, in, (double*)tmp, mask);
+                           (const double*)ut, in, (double*)tmp, mask, scale);
         hipLaunchKernelGGL(k_fd_mid3<double>, dim3(n_colblocks), dim3(kFdBlock), sh3, s, tens, cols,
                            (const double*)ut, dt, (double*)tmp, mask);
         hipLaunchKernelGGL(k_fd_bwd12<double>, dim3(n_slabs), dim3(kFdBlock), sh12, s, tens, slabs,
-                           (const double*)ut, (const double*)tmp, out, mask);
+                           (const double*)ut, (const double*)tmp, out, mask, scale);
     } else {
         const size_t sh12 = 3 * kMaxN * kMaxN * sizeof(float);
         const size_t sh3 = (2 * kMaxN * 32 + kMaxN * kMaxN) * sizeof(float);
         hipLaunchKernelGGL(k_fd_fwd12<float>, dim3(n_slabs), dim3(kFdBlock), sh12, s, tens, slabs,
-                           (const float*)ut, in, (float*)tmp, mask);
+                           (const float*)ut, in, (float*)tmp, mask, scale);
         hipLaunchKernelGGL(k_fd_mid3<float>, dim3(n_colblocks), dim3(kFdBlock), sh3, s, tens, cols,
                            (const float*)ut, dt, (float*)tmp, mask);
         hipLaunchKernelGGL(k_fd_bwd12<float>, dim3(n_slabs), dim3(kFdBlock), sh12, s, tens, slabs,
-                           (const float*)ut, (const float*)tmp, out, mask);
+                           (const float*)ut, (const float*)tmp, out, mask, scale);
     }
 }
 
@@ -1883,13 +1895,15 @@ int mf_table_doubles(int p) {
 }
 
 void launch_B(const int64_t* plus, const int64_t* minus, int64_t n_c, double alpha, const double* x, double* y,
-              hipStream_t s) {
-    if (n_c) hipLaunchKernelGGL(k_B, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, plus, minus, n_c, alpha, x, y);
+              hipStream_t s, const double* in_scale) {
+    if (n_c)
+        hipLaunchKernelGGL(k_B, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, plus, minus, n_c, alpha, x, y, in_scale);
 }
 
 void launch_Bt(const int64_t* bt_ptr, const int* bt_row, const double* bt_sign, int64_t n_dof, const double* x,
-               double* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_Bt, dim3(blocks_for(n_dof)), dim3(kBlock), 0, s, bt_ptr, bt_row, bt_sign, n_dof, x, y);
+               double* y, hipStream_t s, const double* out_scale) {
+    hipLaunchKernelGGL(k_Bt, dim3(blocks_for(n_dof)), dim3(kBlock), 0, s, bt_ptr, bt_row, bt_sign, n_dof, x, y,
+                       out_scale);
 }
 
 void launch_W(const int* bs, const int* bn, const int* bd, int64_t n_c, const double* y, double* z, hipStream_t s) {
@@ -1897,8 +1911,10 @@ void launch_W(const int* bs, const int* bn, const int* bd, int64_t n_c, const do
 }
 
 void launch_BW(const int* bs, const int* bn, const int* bd, int64_t n_c, const int64_t* plus, const int64_t* minus,
-               const double* x, double* z, hipStream_t s) {
-    if (n_c) hipLaunchKernelGGL(k_BW, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, bs, bn, bd, n_c, plus, minus, x, z);
+               const double* x, double* z, hipStream_t s, const double* in_scale) {
+    if (n_c)
+        hipLaunchKernelGGL(k_BW, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, bs, bn, bd, n_c, plus, minus, x, z,
+                           in_scale);
 }
 
 void launch_GW(const int* bs, const int* bn, const int* bd, int64_t n_c, const int* pp, const int* pm,

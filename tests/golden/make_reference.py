@@ -5,6 +5,9 @@ parity tests (tests/test_gpu_reference.py).
     python tests/golden/make_reference.py c4 1e-8 0 3 5 ...  # problems of the C4 batch
     python tests/golden/make_reference.py c3 p n_el     # C3's 4x4x4 patches, degree p,
                                                         # n_el^3 elements (tol 1e-8, 1e-12)
+    AFIETI_REF_DRIVER=gv python tests/golden/make_reference.py ...
+        # the same with LAPACK's 'gv' eigensolver driver: ref_<name>_<tol>_gv.json,
+        # the oracle's own rounding sensitivity for the parity rules
 
 Only the oracle (``oracle/``) and the seeded workload generators are called.
 Each output file holds, per tolerance: the MINRES iteration count and the
@@ -46,13 +49,14 @@ def summarise(o, res, tol):
 
 def write(name, prob, *tols):
     """Oracle solves of ``prob`` at each tolerance, each summarised into
-    ref_<name>_<tol>.json beside this script."""
-    o = AFIETI(prob)
+    ref_<name>_<tol>[_<driver>].json beside this script."""
+    driver = os.environ.get("AFIETI_REF_DRIVER") or None
+    o = AFIETI(prob, eig_driver=driver)
     for tol in tols:
         t0 = time.time()
         res = o.solve(tol=tol, maxit=5000)
         out = dict(workload=name, n_dof=int(o.n_dof), n_c=int(o.n_c), solves=[summarise(o, res, tol)])
-        path = os.path.join(HERE, f"ref_{name}_{tol:.0e}.json")
+        path = os.path.join(HERE, f"ref_{name}_{tol:.0e}" + (f"_{driver}" if driver else "") + ".json")
         with open(path, "w") as f:
             json.dump(out, f)
         print(f"{name} tol {tol:.0e}: {res['iters']} iterations; wrote {path} ({time.time() - t0:.0f} s)",
