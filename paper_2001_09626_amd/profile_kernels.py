@@ -20,14 +20,15 @@ def main():
     ap.add_argument("--op", default="stiffness")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--fd", default="fp64")
+    ap.add_argument("--precond", default="fd", help="local solvers: fd (parametric) or geo (geometry inclusion)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     args = ap.parse_args()
     import torch
     import workloads as W
     from paper_2001_09626_amd import Solver
-    make = {"c1": W.make_c1, "c2": W.make_c2, "c3": W.make_c3, "c5": W.make_c5}[args.workload]
+    make = {"c1": W.make_c1, "c2": W.make_c2, "c3": W.make_c3, "c4": W.make_c4, "c5": W.make_c5}[args.workload]
     prob = make(seed=0)
-    s = Solver(prob, fd_precision=args.fd)
+    s = Solver(prob, fd_precision=args.fd, precond=args.precond)
     n_in = s.n_dof + s.n_c if args.op in ("prec", "saddle") else (s.n_c if args.op in ("P_chi", "P_S", "Bt") else s.n_dof)
     x = torch.from_numpy(np.random.default_rng(0).standard_normal(n_in)).cuda()
     for i in range(args.reps):

@@ -115,6 +115,36 @@ def test_autograd_function():
     assert np.abs(amps.grad.numpy() - g["damp"]).max() <= 1e-8 * np.abs(g["damp"]).max()
 
 
+def test_autograd_with_geometry_inclusion():
+    """The gradients do not depend on the preconditioner: with the
+    geometry-inclusion local solvers (rebuilt by every parameter update)
+    the autograd function gives the oracle's gradients, also after the
+    parameters moved."""
+    torch = _torch()
+    from paper_2001_09626_amd import Solver, AfietiSolve, mass_norm_loss
+    prob = _small_c5(seed=6)
+    target = W.redraw_parameters(prob, seed=8)
+    u_t = AFIETI(target).solve(tol=1e-13)["u"]
+    s = Solver(prob, tol=1e-13, precond="geo")
+    for step, pr in enumerate((prob, W.redraw_parameters(prob, seed=12))):
+        lame = torch.tensor([[p["lam"], p["mu"]] for p in pr["patches"]], dtype=torch.float64, requires_grad=True)
+        amps = torch.tensor([m[1] for m in pr["load"]], dtype=torch.float64, requires_grad=True)
+        J = mass_norm_loss(AfietiSolve(lame, amps, s) - _dev(torch, u_t), s)
+        J.backward()
+        o = AFIETI(pr)
+        uo = o.solve(tol=1e-13)["u"]
+        Jo, dJdu = mass_loss(o, uo, u_t)
+        g = gradients(o, uo, dJdu, tol=1e-13)
+        gl = lame.grad.numpy()
+        e = max(np.abs(gl[:, 0] - g["dlam"]).max() / np.abs(g["dlam"]).max(),
+                np.abs(gl[:, 1] - g["dmu"]).max() / np.abs(g["dmu"]).max(),
+                np.abs(amps.grad.numpy() - g["damp"]).max() / np.abs(g["damp"]).max())
+        print(f"  step {step}: J {float(J):.6e} (oracle {Jo:.6e}), gradient rel err {e:.2e}")
+        assert float(J) == pytest.approx(Jo, rel=1e-9)
+        assert e <= 1e-8
+    s.close()
+
+
 def test_autograd_with_device_parameters():
     """Parameters living on the GPU get their gradients on the GPU, with
     the same values as for CPU parameters."""
