@@ -48,6 +48,9 @@ struct Lane {           // scratch of one concurrent branch
     void* fdtmp = nullptr;    // FD intermediate tensor
 };
 
+constexpr int kFdClasses = 3;
+inline int fd_class(int n) { return n <= 28 ? 0 : (n <= 36 ? 1 : 2); }
+
 struct FdSet {          // tensors of one FD operator (P_A or interior)
     FdTensor* d_t = nullptr;   // one per (patch, component): vector-ALU kernels
     int2* d_slabs = nullptr;
@@ -55,10 +58,13 @@ struct FdSet {          // tensors of one FD operator (P_A or interior)
     int n_t = 0, n_slabs = 0, n_cols = 0;
     int64_t tmp_elems = 0;
     // matrix-core kernels: groups of the d components of a patch (layout 0)
-    // or one component per group (layout 1)
-    FdGroupSet gs[2];
-    FdGroup* d_groups[2] = {nullptr, nullptr};
-    std::vector<FdGroup> h_groups[2];
+    // or one component per group (layout 1), per depth class (the largest
+    // extent of the group: <= 28, <= 36, <= 48), each class launched with
+    // its own compile-time depth so that the small tensors of a ragged
+    // batch are not padded to the largest
+    FdGroupSet gs[2][kFdClasses];
+    FdGroup* d_groups[2][kFdClasses] = {};
+    std::vector<FdGroup> h_groups[2][kFdClasses];
     int tune = 0;              // chosen layout * kFdVariants + variant
 };
 
@@ -235,8 +241,8 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
                   const std::vector<int>& d_off, hipStream_t s) {
     std::vector<FdTensor> ts;
     std::vector<int2> slabs, cols;
-    std::vector<FdGroup> groups[2];
-    std::vector<int2> gslabs[2], gcols64[2], gcols128[2];
+    std::vector<FdGroup> groups[2][kFdClasses];
+    std::vector<int2> gslabs[2][kFdClasses], gcols64[2][kFdClasses], gcols128[2][kFdClasses];
     int64_t tmp = 0;
     const bool geo = h->opt.precond == AFIETI_PRECOND_GEO;
     for (size_t k = 0; k < h->plan.patches.size(); ++k) {
@@ -314,22 +320,25 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
                         q.d_off[m] = d_off[idx * 2 + (interior ? 1 : 0)];
                     }
                 }
-                const int gi = (int)groups[lay].size();
-                groups[lay].push_back(q);
-                for (int i3 = 0; i3 < q.n3; ++i3) gslabs[lay].push_back(make_int2(gi, i3));
+                const int cl = fd_class(std::max(q.n1, std::max(q.n2, q.n3)));
+                const int gi = (int)groups[lay][cl].size();
+                groups[lay][cl].push_back(q);
+                for (int i3 = 0; i3 < q.n3; ++i3) gslabs[lay][cl].push_back(make_int2(gi, i3));
                 const int ncol = q.nc * q.n1 * q.n2;
-                for (int cb = 0; cb < (ncol + 63) / 64; ++cb) gcols64[lay].push_back(make_int2(gi, cb));
-                for (int cb = 0; cb < (ncol + 127) / 128; ++cb) gcols128[lay].push_back(make_int2(gi, cb));
+                for (int cb = 0; cb < (ncol + 63) / 64; ++cb) gcols64[lay][cl].push_back(make_int2(gi, cb));
+                for (int cb = 0; cb < (ncol + 127) / 128; ++cb) gcols128[lay][cl].push_back(make_int2(gi, cb));
             }
         }
     }
     if (set.d_t) {  // parameters changed: rewrite the descriptors in place
         HIP_OK(hipMemcpyAsync(set.d_t, ts.data(), ts.size() * sizeof(FdTensor), hipMemcpyHostToDevice, s));
-        for (int lay = 0; lay < 2; ++lay) {
-            set.h_groups[lay] = groups[lay];
-            HIP_OK(hipMemcpyAsync(set.d_groups[lay], set.h_groups[lay].data(), groups[lay].size() * sizeof(FdGroup),
-                                  hipMemcpyHostToDevice, s));
-        }
+        for (int lay = 0; lay < 2; ++lay)
+            for (int cl = 0; cl < kFdClasses; ++cl) {
+                set.h_groups[lay][cl] = groups[lay][cl];
+                if (groups[lay][cl].empty()) continue;
+                HIP_OK(hipMemcpyAsync(set.d_groups[lay][cl], set.h_groups[lay][cl].data(),
+                                      groups[lay][cl].size() * sizeof(FdGroup), hipMemcpyHostToDevice, s));
+            }
         HIP_OK(hipStreamSynchronize(s));
         return;
     }
@@ -340,25 +349,27 @@ void build_fd_set(afieti_handle* h, FdSet& set, bool interior, const std::vector
     set.d_t = h->upload(ts, s);
     set.d_slabs = h->upload(slabs, s);
     set.d_cols = h->upload(cols, s);
-    for (int lay = 0; lay < 2; ++lay) {
-        FdGroupSet& G = set.gs[lay];
-        set.h_groups[lay] = groups[lay];
-        set.d_groups[lay] = h->upload(set.h_groups[lay], s);
-        G.groups = set.d_groups[lay];
-        G.slabs = h->upload(gslabs[lay], s);
-        G.cols64 = h->upload(gcols64[lay], s);
-        G.cols128 = h->upload(gcols128[lay], s);
-        G.n_groups = (int)groups[lay].size();
-        G.n_slabs = (int)gslabs[lay].size();
-        G.n_cols64 = (int)gcols64[lay].size();
-        G.n_cols128 = (int)gcols128[lay].size();
-        for (const FdGroup& q : groups[lay]) {
-            G.max_n1 = std::max(G.max_n1, q.n1);
-            G.max_n2 = std::max(G.max_n2, q.n2);
-            G.max_n3 = std::max(G.max_n3, q.n3);
-            G.max_nc = std::max(G.max_nc, q.nc);
+    for (int lay = 0; lay < 2; ++lay)
+        for (int cl = 0; cl < kFdClasses; ++cl) {
+            FdGroupSet& G = set.gs[lay][cl];
+            set.h_groups[lay][cl] = groups[lay][cl];
+            if (groups[lay][cl].empty()) continue;
+            set.d_groups[lay][cl] = h->upload(set.h_groups[lay][cl], s);
+            G.groups = set.d_groups[lay][cl];
+            G.slabs = h->upload(gslabs[lay][cl], s);
+            G.cols64 = h->upload(gcols64[lay][cl], s);
+            G.cols128 = h->upload(gcols128[lay][cl], s);
+            G.n_groups = (int)groups[lay][cl].size();
+            G.n_slabs = (int)gslabs[lay][cl].size();
+            G.n_cols64 = (int)gcols64[lay][cl].size();
+            G.n_cols128 = (int)gcols128[lay][cl].size();
+            for (const FdGroup& q : groups[lay][cl]) {
+                G.max_n1 = std::max(G.max_n1, q.n1);
+                G.max_n2 = std::max(G.max_n2, q.n2);
+                G.max_n3 = std::max(G.max_n3, q.n3);
+                G.max_nc = std::max(G.max_nc, q.nc);
+            }
         }
-    }
 }
 
 // band rows [i][t] (t = j - i + p) of a dense n x n matrix; a direction the
@@ -489,7 +500,12 @@ constexpr int64_t kLdsBytes = 160 * 1024;  // LDS of one gfx950 compute unit
 
 // LDS bytes of a (layout, variant) choice of a set in the configured precision
 int64_t fd_choice_lds(const afieti_handle* h, const FdSet& set, int choice) {
-    return fd_lds_bytes(fd_prec(h) - 2, choice % kFdVariants, set.gs[choice / kFdVariants]);
+    int64_t b = 0;
+    for (int cl = 0; cl < kFdClasses; ++cl) {
+        const FdGroupSet& G = set.gs[choice / kFdVariants][cl];
+        if (G.n_groups) b = std::max(b, fd_lds_bytes(fd_prec(h) - 2, choice % kFdVariants, G));
+    }
+    return b;
 }
 
 // FD autotuner: the launch shape of the matrix-core FD kernels (layout of
@@ -503,9 +519,10 @@ int tune_fd(afieti_handle* h, FdSet& set, const double* in, double* out, hipStre
     static std::map<std::string, int> cache;
     const bool geo = h->opt.precond == AFIETI_PRECOND_GEO;
     std::string key = std::to_string(fd_prec(h)) + (geo ? "g:" : ":");
-    for (const FdGroup& g : set.h_groups[0])
-        key += std::to_string(g.n1) + "," + std::to_string(g.n2) + "," + std::to_string(g.n3) + "," +
-               std::to_string(g.nc) + ";";
+    for (int cl = 0; cl < kFdClasses; ++cl)
+        for (const FdGroup& g : set.h_groups[0][cl])
+            key += std::to_string(g.n1) + "," + std::to_string(g.n2) + "," + std::to_string(g.n3) + "," +
+                   std::to_string(g.nc) + ";";
     {
         std::lock_guard<std::mutex> lock(mu);
         auto it = cache.find(key);
@@ -1091,10 +1108,11 @@ void op_fd_tmp(afieti_handle* h, const FdSet& set, const double* in, double* out
     const int prec = fd_prec(h);
     const bool f64 = prec == 0 || prec == 4;
     const void* ut = f64 ? (const void*)h->d_u64 : (const void*)h->d_u32;
-    if (prec >= 2)
-        launch_fd_groups(prec - 2, set.tune % kFdVariants, set.gs[set.tune / kFdVariants], ut, h->d_dtab, in, out, tmp,
-                         h->mask, scale, s);
-    else
+    if (prec >= 2) {
+        for (int cl = 0; cl < kFdClasses; ++cl)
+            launch_fd_groups(prec - 2, set.tune % kFdVariants, set.gs[set.tune / kFdVariants][cl], ut, h->d_dtab, in,
+                             out, tmp, h->mask, scale, s);
+    } else
         launch_fd(prec, set.d_t, set.n_t, set.d_slabs, set.n_slabs, set.d_cols, set.n_cols, ut, h->d_dtab, in, out,
                   tmp, h->mask, scale, s);
 }
