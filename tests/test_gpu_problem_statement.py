@@ -236,7 +236,7 @@ def test_weak_scaling_workload_parity():
     s.close()
 
 
-@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("k", [2, 3, 4, 5])
 def test_weak_scaling_iterations_and_error(k):
     """k^3 patches of 8^3 elements, p = 3: the solve converges, the error
     against the exact solution at the Gauss points stays at the
