@@ -188,6 +188,16 @@ typedef struct {
                             with AFIETI_EBREAKDOWN at the first iteration
                             whose <z, v> is negative.                      */
     int precond;         /* AFIETI_PRECOND_* (FD)                          */
+    /* device memory of the handle (NULL: hipMalloc / hipFree): dev_alloc
+     * (bytes, ctx) returns memory on the device current at afieti_setup,
+     * or NULL on failure (the call then fails with AFIETI_ENOMEM); every
+     * block is returned through dev_free(ptr, bytes, ctx) by
+     * afieti_destroy, after the device has finished all work (e.g. a
+     * framework's caching allocator).  Blocks stay in use until then; a
+     * solve_adjoint with load vectors may allocate more.                   */
+    void* (*dev_alloc)(size_t bytes, void* ctx);
+    void (*dev_free)(void* ptr, size_t bytes, void* ctx);
+    void* alloc_ctx;
 } afieti_options;
 
 typedef struct {

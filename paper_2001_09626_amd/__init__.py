@@ -110,7 +110,10 @@ class Solver:
 
     def __init__(self, problems, tol=1e-8, maxit=5000, fd_precision="fp64", ps_variant="nr",
                  check_every=12, host_only=False, use_graph=True, stiffness="auto", fd_tune=-1,
-                 ps_weight=1.0, precond="fd"):
+                 ps_weight=1.0, precond="fd", allocator=None):
+        """``allocator="torch"``: the handle's device memory comes from
+        torch's caching allocator (on the current device and stream)
+        instead of hipMalloc, and goes back to it at ``close``."""
         L = N.lib()
         self._L = L
         arr, keep = to_c_problems(problems)
@@ -127,12 +130,40 @@ class Solver:
         opt.fd_tune = int(fd_tune)
         opt.ps_weight = float(ps_weight)
         opt.precond = N.PRECOND[precond]
+        self._alloc_cbs = None
+        self._alloc_error = None
+        if allocator == "torch":
+            import torch
+            dev = torch.cuda.current_device()
+            alloc_stream = int(torch.cuda.current_stream(dev).cuda_stream)
+
+            def _alloc(nbytes, ctx):
+                try:
+                    return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, alloc_stream))
+                except Exception as e:  # an exception cannot cross the C boundary: report NULL
+                    self._alloc_error = f"{type(e).__name__}: {e}"
+                    return 0
+
+            def _free(ptr, nbytes, ctx):
+                try:
+                    torch.cuda.caching_allocator_delete(ptr)
+                except Exception:
+                    pass
+
+            self._alloc_cbs = (N.DEV_ALLOC_FN(_alloc), N.DEV_FREE_FN(_free))
+            opt.dev_alloc = C.cast(self._alloc_cbs[0], C.c_void_p)
+            opt.dev_free = C.cast(self._alloc_cbs[1], C.c_void_p)
+        elif allocator is not None:
+            raise ValueError(f"unknown allocator {allocator!r}")
         self.host_only = host_only
         h = C.c_void_p()
         stream = C.c_void_p(0) if host_only else _stream()
         code = L.afieti_setup(arr, len(arr), C.byref(opt), stream, C.byref(h))
         if code != N.OK:
-            raise AfietiError(code, L.afieti_last_error(None).decode())
+            msg = L.afieti_last_error(None).decode()
+            if self._alloc_error:
+                msg += f" ({self._alloc_error})"
+            raise AfietiError(code, msg)
         self._h = h
         info = N.Info()
         L.afieti_get_info(h, C.byref(info))

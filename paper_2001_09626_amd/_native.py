@@ -54,7 +54,12 @@ class Options(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int), ("fd_precision", C.c_int),
                 ("ps_variant", C.c_int), ("check_every", C.c_int), ("host_only", C.c_int),
                 ("use_graph", C.c_int), ("stiffness", C.c_int), ("fd_tune", C.c_int),
-                ("ps_weight", C.c_double), ("precond", C.c_int)]
+                ("ps_weight", C.c_double), ("precond", C.c_int),
+                ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("alloc_ctx", C.c_void_p)]
+
+
+DEV_ALLOC_FN = C.CFUNCTYPE(C.c_uint64, C.c_size_t, C.c_void_p)  # returns the device address
+DEV_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
 
 
 class Info(C.Structure):

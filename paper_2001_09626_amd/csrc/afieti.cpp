@@ -76,7 +76,7 @@ struct afieti_handle {
     std::string err;
     bool host_only = false;
     int device = -1;                 // GPU the handle's memory lives on
-    std::vector<void*> allocs;
+    std::vector<std::pair<void*, size_t>> allocs;
     int64_t bytes = 0, stencil_bytes = 0;
     int n_probs = 0, n_patches = 0;
     int64_t n_dof = 0, n_c = 0, n_vec = 0;
@@ -176,11 +176,17 @@ struct afieti_handle {
     template <typename T>
     T* dalloc(int64_t n) {
         if (n <= 0) n = 1;
+        const size_t nb = (size_t)n * sizeof(T);
         void* p = nullptr;
-        hipError_t e = hipMalloc(&p, (size_t)n * sizeof(T));
-        if (e != hipSuccess) throw SetupError{AFIETI_ENOMEM, "hipMalloc failed"};
-        allocs.push_back(p);
-        bytes += n * (int64_t)sizeof(T);
+        if (opt.dev_alloc) {
+            p = opt.dev_alloc(nb, opt.alloc_ctx);
+            if (!p) throw SetupError{AFIETI_ENOMEM, "the caller's allocator returned NULL"};
+        } else {
+            hipError_t e = hipMalloc(&p, nb);
+            if (e != hipSuccess) throw SetupError{AFIETI_ENOMEM, "hipMalloc failed"};
+        }
+        allocs.push_back({p, nb});
+        bytes += (int64_t)nb;
         return static_cast<T*>(p);
     }
     template <typename T>
@@ -196,7 +202,14 @@ struct afieti_handle {
         if (ev_t1) (void)hipEventDestroy(ev_t1);
         if (gstream) (void)hipStreamSynchronize(gstream);
         if (side) (void)hipStreamSynchronize(side);
-        for (void* p : allocs) (void)hipFree(p);
+        if (opt.dev_free) {
+            // the caller's allocator may hand the blocks out at once: wait
+            // for the work on every stream, the caller's included
+            if (!allocs.empty()) (void)hipDeviceSynchronize();
+            for (auto& a : allocs) opt.dev_free(a.first, a.second, opt.alloc_ctx);
+        } else {
+            for (auto& a : allocs) (void)hipFree(a.first);
+        }
         if (h_state) (void)hipHostFree(h_state);
         if (ev_a) (void)hipEventDestroy(ev_a);
         if (ev_b) (void)hipEventDestroy(ev_b);
@@ -1503,6 +1516,9 @@ void afieti_default_options(afieti_options* opt) {
     opt->fd_tune = -1;
     opt->ps_weight = 1.0;
     opt->precond = AFIETI_PRECOND_FD;
+    opt->dev_alloc = nullptr;
+    opt->dev_free = nullptr;
+    opt->alloc_ctx = nullptr;
 }
 
 const char* afieti_strerror(int code) {
@@ -1535,7 +1551,8 @@ int afieti_setup(const afieti_problem* probs, int n_problems, const afieti_optio
             (h->opt.fd_precision < AFIETI_FD_FP64 || h->opt.fd_precision > AFIETI_FD_FP64_VALU) ||
             (h->opt.ps_variant != AFIETI_PS_NR && h->opt.ps_variant != AFIETI_PS_PLAIN) ||
             h->opt.fd_tune < -1 || h->opt.fd_tune >= 2 * kFdVariants || !std::isfinite(h->opt.ps_weight) ||
-            (h->opt.precond != AFIETI_PRECOND_FD && h->opt.precond != AFIETI_PRECOND_GEO))
+            (h->opt.precond != AFIETI_PRECOND_FD && h->opt.precond != AFIETI_PRECOND_GEO) ||
+            (!h->opt.dev_alloc != !h->opt.dev_free))
             throw SetupError{AFIETI_EINVAL, "invalid options"};
         h->plan = build_plan(probs, n_problems);
         if (h->opt.precond == AFIETI_PRECOND_GEO) build_geometry_inclusion(h->plan, geo_threads());

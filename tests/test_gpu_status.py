@@ -104,3 +104,28 @@ def test_unit_weight_is_the_default():
     assert sa["iterations"] == sb["iterations"] and torch.equal(ua, ub)
     a.close()
     b.close()
+
+
+def test_caller_allocator():
+    """With the caller's allocator (torch's caching allocator through the
+    dev_alloc / dev_free options) the handle's memory is torch's while the
+    handle lives and goes back at close; results equal the default
+    allocator's bitwise."""
+    torch = _torch()
+    from paper_2001_09626_amd import Solver
+    prob = W.make_c2(n_el=3, p=2, seed=1)
+    ref = Solver(prob)
+    u0, _, st0 = ref.solve()
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    s = Solver(prob, allocator="torch")
+    held = torch.cuda.memory_allocated() - base
+    print(f"\n  handle memory {s.device_bytes} B, torch allocator holds {held} B more", flush=True)
+    assert held >= s.device_bytes
+    u1, _, st1 = s.solve()
+    assert st1["iterations"] == st0["iterations"] and torch.equal(u0, u1)
+    del u1
+    s.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() - base <= 0
+    ref.close()
