@@ -116,6 +116,15 @@ typedef struct {
     int face_bc[6];    /* AFIETI_FACE_*                                    */
     const double* knots[3];  /* explicit open knot vectors, or NULL         */
     int n_knots[3];
+    const double* ctrl;      /* explicit control net (host, read during
+                                afieti_setup), or NULL for the multilinear
+                                map of the corners: ctrl[3*node + x],
+                                node = i1 + n1 (i2 + n2 i3) colexicographic
+                                over the n1 x n2 (x n3) B-splines (z read
+                                as 0 in 2D); the geometry is then the spline
+                                map sum_i ctrl_i B_i (Section 2.2), corners
+                                is ignored (the corner control points take
+                                its place), and the stiffness is assembled  */
 } afieti_patch;
 
 /* body force f_comp(x) += amp * prod_d sin(pi k[d] x_d + phase[d]) */

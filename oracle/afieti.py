@@ -14,7 +14,8 @@ Readings of points the paper leaves open:
   * Rigid modes in 2D: two translations and (x2, -x1).
   * lambda_0: any solution of G^T lambda_0 = R^T f is allowed; reading: the
     minimal-norm one, G (G^T G)^{-1} R^T f.
-  * H^(k): largest distance between two patch corners.
+  * H^(k): largest distance between two patch corners (for an explicit
+    control net: between two control points).
   * P_S^{inex-nr}: Remark 1 with S replaced by S-hat and the per-patch factor
     (H^(k))^{d-2} of the inexact P_S kept; B_Gamma B_Gamma^T = B B^T because
     B only touches interface unknowns.

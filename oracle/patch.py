@@ -68,7 +68,6 @@ class Patch:
         self.lam = float(pd["lam"])
         self.mu = float(pd["mu"])
         self.bc = list(pd["bc"])
-        self.corners = np.asarray(pd["corners"], dtype=float)
         if pd.get("knots") is not None:
             # explicit open knot vectors (Section 2.1); elements = non-empty spans
             self.knots = [np.asarray(pd["knots"][l], dtype=float) for l in range(dim)]
@@ -80,10 +79,21 @@ class Patch:
         self.shape = tuple(reversed(self.n))  # (n_d, ..., n_1)
         self.n_nodes = int(np.prod(self.n))
         self.n_dof = dim * self.n_nodes
-        # control points: images of the Greville points under the corner map
-        g = [bspline.greville(k, self.p) for k in self.knots]
-        grid = np.stack(np.meshgrid(*reversed(g), indexing="ij"), axis=-1)[..., ::-1]
-        self.ctrl = multilinear(self.corners, grid)  # (n_d..n_1, dim)
+        if pd.get("ctrl") is not None:
+            # explicit control net: the spline map sum_i X_i B_i (Section 2.2);
+            # the corners are its corner control points
+            self.ctrl = np.asarray(pd["ctrl"], dtype=float).reshape(self.shape + (dim,))
+            idx = [tuple((n - 1) * ((c >> (dim - 1 - a)) & 1) for a, n in enumerate(self.shape))
+                   for c in range(2 ** dim)]
+            self.corners = np.array([self.ctrl[i] for i in idx])
+            self.general = True
+        else:
+            # control points: images of the Greville points under the corner map
+            self.corners = np.asarray(pd["corners"], dtype=float)
+            g = [bspline.greville(k, self.p) for k in self.knots]
+            grid = np.stack(np.meshgrid(*reversed(g), indexing="ij"), axis=-1)[..., ::-1]
+            self.ctrl = multilinear(self.corners, grid)  # (n_d..n_1, dim)
+            self.general = False
         # quadrature tables per direction
         self.qx, self.qw, self.V, self.D = [], [], [], []
         for l in range(dim):
@@ -98,10 +108,13 @@ class Patch:
     # ---------------------------------------------------------------- geometry
     def diameter(self) -> float:
         """H^(k): reading of "diameter" as the largest distance between two
-        corners (exact for multilinear patches, the hull of their corners)."""
-        c = self.corners
-        return float(max(np.linalg.norm(c[i] - c[j])
-                         for i in range(len(c)) for j in range(len(c))))
+        corners (exact for multilinear patches, the hull of their corners);
+        for an explicit control net the largest distance between two control
+        points (the patch lies in their hull; equal to the corner reading for
+        a multilinear net)."""
+        c = self.ctrl.reshape(-1, self.dim) if self.general else self.corners
+        from scipy.spatial.distance import pdist
+        return float(pdist(c).max())
 
     def geometry(self):
         """Physical points, weight w|det J| and J^{-1} at the tensor Gauss

@@ -45,7 +45,8 @@ def _traction_cb(fn, dim):
 def to_c_problems(problems):
     """Convert ``workloads`` problem dictionaries into the C structs; returns
     (array, keepalive).  Optional entries: a patch's ``knots`` (explicit
-    open knot vectors per direction), a problem's ``body_force(x)``,
+    open knot vectors per direction) and ``ctrl`` (explicit control net,
+    shape (n_d, .., n_1, dim), in place of ``corners``), a problem's ``body_force(x)``,
     ``traction(x, normal)`` and ``dirichlet(x)`` callables (arrays of
     points in, arrays of values out)."""
     if isinstance(problems, dict):
@@ -61,10 +62,19 @@ def to_c_problems(problems):
             P.reg = int(pd["reg"])
             for l in range(3):
                 P.n_el[l] = int(pd["n_el"][l]) if l < dim else 1
-            cs = np.asarray(pd["corners"], dtype=float)
-            for c in range(2 ** dim):
-                for x in range(dim):
-                    P.corners[3 * c + x] = float(cs[c, x])
+            if pd.get("ctrl") is not None:
+                # explicit control net (n_d, .., n_1, dim) -> [node][3]
+                X = np.asarray(pd["ctrl"], dtype=np.float64).reshape(-1, dim)
+                X3 = np.zeros((len(X), 3))
+                X3[:, :dim] = X
+                X3 = np.ascontiguousarray(X3)
+                keep.append(X3)
+                P.ctrl = X3.ctypes.data_as(C.POINTER(C.c_double))
+            else:
+                cs = np.asarray(pd["corners"], dtype=float)
+                for c in range(2 ** dim):
+                    for x in range(dim):
+                        P.corners[3 * c + x] = float(cs[c, x])
             P.lam = float(pd["lam"])
             P.mu = float(pd["mu"])
             for f in range(2 * dim):

@@ -30,7 +30,8 @@ EXPORT = {"B": 0, "eig": 1, "H": 2, "GtG": 3, "fixed_load": 4, "dirichlet_c": 5,
 class Patch(C.Structure):
     _fields_ = [("p", C.c_int), ("reg", C.c_int), ("n_el", C.c_int * 3),
                 ("corners", C.c_double * 24), ("lam", C.c_double), ("mu", C.c_double),
-                ("face_bc", C.c_int * 6), ("knots", C.POINTER(C.c_double) * 3), ("n_knots", C.c_int * 3)]
+                ("face_bc", C.c_int * 6), ("knots", C.POINTER(C.c_double) * 3), ("n_knots", C.c_int * 3),
+                ("ctrl", C.POINTER(C.c_double))]
 
 
 class LoadMode(C.Structure):

@@ -622,10 +622,11 @@ void device_setup(afieti_handle* h, hipStream_t s) {
             }
         }
         // matrix-free stiffness: 3D, maximal continuity, p <= 6
-        const bool mf_ok = P.dim == 3 && P.reg == P.p - 1 && P.p <= 6;
+        const bool mf_ok = P.dim == 3 && P.reg == P.p - 1 && P.p <= 6 && !P.general;
         d.mf = (h->opt.stiffness == AFIETI_STIFFNESS_MATRIX_FREE || h->opt.stiffness == AFIETI_STIFFNESS_AUTO) && mf_ok;
         if (h->opt.stiffness == AFIETI_STIFFNESS_MATRIX_FREE && !mf_ok)
-            throw SetupError{AFIETI_EUNSUPPORTED, "matrix-free stiffness needs 3D C^{p-1} patches with p <= 6"};
+            throw SetupError{AFIETI_EUNSUPPORTED,
+                             "matrix-free stiffness needs 3D C^{p-1} patches with p <= 6 and the corners' multilinear map"};
         for (int m = 0; m < 3; ++m) {
             const int be = mf_brick_elems(P.p);
             d.nb[m] = m < P.dim ? (P.dir[m].n_el + be - 1) / be : 1;

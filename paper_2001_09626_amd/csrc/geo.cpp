@@ -185,7 +185,7 @@ void build_patch(PatchPlan& P) {
             for (int q1 = 0; q1 < nq[0]; ++q1) {
                 const double eta[3] = {L[0].x[q1], L[1].x[q2], dim == 3 ? L[2].x[q3] : 0.0};
                 double J[3][3], Ji[3][3], det;
-                multilinear_jacobian(dim, P.corners, eta, J);
+                patch_map(P, eta, nullptr, J);
                 invert3(J, dim, Ji, det);
                 adet[q1] = std::fabs(det);
                 for (int l = 0; l < dim; ++l) {

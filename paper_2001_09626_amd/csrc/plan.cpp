@@ -98,14 +98,18 @@ void multilinear_jac(int dim, const double* corners, const double* eta, double (
     }
 }
 
-// det of the Jacobian of the multilinear corner map at eta
-double multilinear_det(int dim, const double* corners, const double* eta) {
-    double J[3][3];
-    multilinear_jac(dim, corners, eta, J);
+double det_of(int dim, const double (&J)[3][3]) {
     if (dim == 2) return J[0][0] * J[1][1] - J[0][1] * J[1][0];
     return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
            J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
            J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+// det of the Jacobian of the multilinear corner map at eta
+double multilinear_det(int dim, const double* corners, const double* eta) {
+    double J[3][3];
+    multilinear_jac(dim, corners, eta, J);
+    return det_of(dim, J);
 }
 
 struct UnionFind {
@@ -242,8 +246,10 @@ void add_body_force(const PatchPlan& P, afieti_field_fn fn, void* ctx, double* F
             for (int q1 = 0; q1 < Q0.nq; ++q1) {
                 const int64_t q = q1 + (int64_t)Q0.nq * (q2 + (int64_t)Q1.nq * q3);
                 const double eta[3] = {Q0.qx[q1], Q1.qx[q2], Q2.qx[q3]};
-                for (int c = 0; c < dim; ++c) x[q * dim + c] = multilinear_coord(dim, P.corners, eta, c);
-                W[q] = Q0.qw[q1] * Q1.qw[q2] * Q2.qw[q3] * std::fabs(multilinear_det(dim, P.corners, eta));
+                double X[3], J[3][3];
+                patch_map(P, eta, X, J);
+                for (int c = 0; c < dim; ++c) x[q * dim + c] = X[c];
+                W[q] = Q0.qw[q1] * Q1.qw[q2] * Q2.qw[q3] * std::fabs(det_of(dim, J));
             }
     fn(nq, x.data(), f.data(), ctx);
     for (double v : f)
@@ -303,8 +309,8 @@ void add_traction(const PatchPlan& P, int face, afieti_traction_fn fn, void* ctx
             eta[fd] = side ? 1.0 : 0.0;
             eta[tan[0]] = Qa.qx[qa];
             if (dim == 3) eta[tan[1]] = Qb.qx[qb];
-            double J[3][3];
-            multilinear_jac(dim, P.corners, eta, J);
+            double J[3][3], X[3];
+            patch_map(P, eta, X, J);
             double n[3] = {0, 0, 0};
             if (dim == 3) {
                 const int a = tan[0], b = tan[1];
@@ -332,12 +338,12 @@ void add_traction(const PatchPlan& P, int face, afieti_traction_fn fn, void* ctx
                 grad[0] = (fd == 0 ? 1.0 : -1.0) * J[1][a];
                 grad[1] = (fd == 0 ? -1.0 : 1.0) * J[0][a];
             }
-            const double det = multilinear_det(dim, P.corners, eta);
+            const double det = det_of(dim, J);
             double dot = 0;
             for (int c = 0; c < dim; ++c) dot += grad[c] * n[c];
             const double sgn = ((dot * det) >= 0 ? 1.0 : -1.0) * (side ? 1.0 : -1.0);
             for (int c = 0; c < dim; ++c) {
-                x[q * dim + c] = multilinear_coord(dim, P.corners, eta, c);
+                x[q * dim + c] = X[c];
                 nrm[q * dim + c] = sgn * n[c] / area;
             }
             wa[q] = Qa.qw[qa] * Qb.qw[qb] * area;
@@ -582,6 +588,45 @@ void multilinear_jacobian(int dim, const double* corners, const double* eta, dou
     multilinear_jac(dim, corners, eta, J);
 }
 
+void patch_map(const PatchPlan& P, const double* eta, double* x, double (&J)[3][3]) {
+    const int dim = P.dim;
+    if (!P.general) {
+        multilinear_jac(dim, P.corners, eta, J);
+        if (x)
+            for (int c = 0; c < 3; ++c) x[c] = c < dim ? multilinear_coord(dim, P.corners, eta, c) : 0.0;
+        return;
+    }
+    // spline map: x = sum_i X_i B_i(eta), dx/deta_a with the derivative in a
+    double val[3][9] = {}, der[3][9] = {};
+    int first[3] = {0, 0, 0}, cnt[3] = {1, 1, 1};
+    for (int l = 0; l < 3; ++l) {
+        if (l < dim) {
+            bspline_eval(P.dir[l].knots, P.p, eta[l], first[l], val[l], der[l]);
+            cnt[l] = P.p + 1;
+        } else {
+            val[l][0] = 1.0;
+        }
+    }
+    for (auto& r : J)
+        for (double& v : r) v = 0.0;
+    double xx[3] = {0, 0, 0};
+    for (int t3 = 0; t3 < cnt[2]; ++t3)
+        for (int t2 = 0; t2 < cnt[1]; ++t2)
+            for (int t1 = 0; t1 < cnt[0]; ++t1) {
+                const int64_t nd = node_index(P.n, first[0] + t1, first[1] + t2, first[2] + t3);
+                const double* X = &P.ctrl[nd * 3];
+                const double b = val[0][t1] * val[1][t2] * val[2][t3];
+                const double g[3] = {der[0][t1] * val[1][t2] * val[2][t3], val[0][t1] * der[1][t2] * val[2][t3],
+                                     val[0][t1] * val[1][t2] * der[2][t3]};
+                for (int c = 0; c < dim; ++c) {
+                    xx[c] += b * X[c];
+                    for (int a = 0; a < dim; ++a) J[c][a] += g[a] * X[c];
+                }
+            }
+    if (x)
+        for (int c = 0; c < 3; ++c) x[c] = xx[c];
+}
+
 // -------------------------------------------------------------------- plan
 Plan build_plan(const afieti_problem* probs, int n_problems) {
     if (!probs || n_problems < 1) fail(AFIETI_EINVAL, "no problems");
@@ -620,7 +665,8 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
                 fail(AFIETI_EINVAL, "Lame parameters must be positive");
             P.lam = in.lambda;
             P.mu = in.mu;
-            for (int c = 0; c < 24; ++c) {
+            P.general = in.ctrl != nullptr;
+            for (int c = 0; c < 24 && !P.general; ++c) {
                 if (!std::isfinite(in.corners[c])) fail(AFIETI_EINVAL, "non-finite corner");
                 P.corners[c] = in.corners[c];
             }
@@ -657,57 +703,98 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
             P.nodes = (int64_t)P.n[0] * P.n[1] * P.n[2];
             P.dof_off = dof;
             dof += dim * P.nodes;
-            // diameter: largest corner distance
-            double H = 0;
-            for (int a = 0; a < (1 << dim); ++a)
-                for (int b = 0; b < (1 << dim); ++b) {
-                    double s = 0;
+            if (P.general) {
+                // explicit control net: the spline map sum_i X_i B_i; the
+                // corners are the corner control points; the diameter is the
+                // largest distance between two control points (the patch
+                // lies in their convex hull; for a multilinear net this is
+                // the largest corner distance)
+                P.ctrl.assign((size_t)P.nodes * 3, 0.0);
+                for (int64_t nd = 0; nd < P.nodes; ++nd)
                     for (int x = 0; x < dim; ++x) {
-                        double dd = P.corners[3 * a + x] - P.corners[3 * b + x];
-                        s += dd * dd;
+                        const double v = in.ctrl[nd * 3 + x];
+                        if (!std::isfinite(v)) fail(AFIETI_EINVAL, "non-finite control point");
+                        P.ctrl[nd * 3 + x] = v;
                     }
-                    H = std::max(H, std::sqrt(s));
+                for (int c = 0; c < (1 << dim); ++c) {
+                    const int64_t nd = node_index(P.n, (c & 1) ? P.n[0] - 1 : 0, (c & 2) ? P.n[1] - 1 : 0,
+                                                  (c & 4) ? P.n[2] - 1 : 0);
+                    for (int x = 0; x < 3; ++x) P.corners[3 * c + x] = P.ctrl[nd * 3 + x];
                 }
-            P.H = H;
-            P.hscale = dim == 3 ? H : 1.0;
-            // det J > 0 at every Gauss point of the multilinear map.  The
-            // first column of J does not depend on eta_1 and the others are
-            // linear in it, so along a line of Gauss points det J is a
-            // quadratic in eta_1, fixed by its values at 0, 1/2 and 1.
-            for (int64_t q3 = 0; q3 < (dim == 3 ? P.dir[2].nq : 1); ++q3)
-                for (int q2 = 0; q2 < P.dir[1].nq; ++q2) {
-                    double eta[3] = {0.0, P.dir[1].qx[q2], dim == 3 ? P.dir[2].qx[q3] : 0.0};
-                    const double d0 = multilinear_det(dim, P.corners, eta);
-                    eta[0] = 0.5;
-                    const double dh = multilinear_det(dim, P.corners, eta);
-                    eta[0] = 1.0;
-                    const double d1 = multilinear_det(dim, P.corners, eta);
-                    const double c1 = -3.0 * d0 + 4.0 * dh - d1, c2 = 2.0 * d0 - 4.0 * dh + 2.0 * d1;
-                    for (int q1 = 0; q1 < P.dir[0].nq; ++q1) {
-                        const double t = P.dir[0].qx[q1];
-                        if (!(d0 + t * (c1 + t * c2) > 0))
-                            fail(AFIETI_EGEOM, "patch map is not orientation preserving");
+                double H2 = 0;
+                for (int64_t a = 0; a < P.nodes; ++a)
+                    for (int64_t b = a + 1; b < P.nodes; ++b) {
+                        double s2 = 0;
+                        for (int x = 0; x < dim; ++x) {
+                            const double dd = P.ctrl[a * 3 + x] - P.ctrl[b * 3 + x];
+                            s2 += dd * dd;
+                        }
+                        H2 = std::max(H2, s2);
                     }
-                }
-            // control points at the Greville abscissae
-            std::vector<double> g[3];
-            for (int l = 0; l < 3; ++l) {
-                g[l].assign(P.n[l], 0.0);
-                if (l < dim)
-                    for (int i = 0; i < P.n[l]; ++i) {
+                P.H = std::sqrt(H2);
+                P.hscale = dim == 3 ? P.H : 1.0;
+                // det J > 0 at every Gauss point of the spline map
+                for (int64_t q3 = 0; q3 < (dim == 3 ? P.dir[2].nq : 1); ++q3)
+                    for (int q2 = 0; q2 < P.dir[1].nq; ++q2)
+                        for (int q1 = 0; q1 < P.dir[0].nq; ++q1) {
+                            const double eta[3] = {P.dir[0].qx[q1], P.dir[1].qx[q2], dim == 3 ? P.dir[2].qx[q3] : 0.0};
+                            double J[3][3];
+                            patch_map(P, eta, nullptr, J);
+                            if (!(det_of(dim, J) > 0)) fail(AFIETI_EGEOM, "patch map is not orientation preserving");
+                        }
+            } else {
+                // diameter: largest corner distance
+                double H = 0;
+                for (int a = 0; a < (1 << dim); ++a)
+                    for (int b = 0; b < (1 << dim); ++b) {
                         double s = 0;
-                        for (int r = 1; r <= P.p; ++r) s += P.dir[l].knots[i + r];
-                        g[l][i] = s / P.p;
+                        for (int x = 0; x < dim; ++x) {
+                            double dd = P.corners[3 * a + x] - P.corners[3 * b + x];
+                            s += dd * dd;
+                        }
+                        H = std::max(H, std::sqrt(s));
                     }
+                P.H = H;
+                P.hscale = dim == 3 ? H : 1.0;
+                // det J > 0 at every Gauss point of the multilinear map.  The
+                // first column of J does not depend on eta_1 and the others are
+                // linear in it, so along a line of Gauss points det J is a
+                // quadratic in eta_1, fixed by its values at 0, 1/2 and 1.
+                for (int64_t q3 = 0; q3 < (dim == 3 ? P.dir[2].nq : 1); ++q3)
+                    for (int q2 = 0; q2 < P.dir[1].nq; ++q2) {
+                        double eta[3] = {0.0, P.dir[1].qx[q2], dim == 3 ? P.dir[2].qx[q3] : 0.0};
+                        const double d0 = multilinear_det(dim, P.corners, eta);
+                        eta[0] = 0.5;
+                        const double dh = multilinear_det(dim, P.corners, eta);
+                        eta[0] = 1.0;
+                        const double d1 = multilinear_det(dim, P.corners, eta);
+                        const double c1 = -3.0 * d0 + 4.0 * dh - d1, c2 = 2.0 * d0 - 4.0 * dh + 2.0 * d1;
+                        for (int q1 = 0; q1 < P.dir[0].nq; ++q1) {
+                            const double t = P.dir[0].qx[q1];
+                            if (!(d0 + t * (c1 + t * c2) > 0))
+                                fail(AFIETI_EGEOM, "patch map is not orientation preserving");
+                        }
+                    }
+                // control points at the Greville abscissae
+                std::vector<double> g[3];
+                for (int l = 0; l < 3; ++l) {
+                    g[l].assign(P.n[l], 0.0);
+                    if (l < dim)
+                        for (int i = 0; i < P.n[l]; ++i) {
+                            double s = 0;
+                            for (int r = 1; r <= P.p; ++r) s += P.dir[l].knots[i + r];
+                            g[l][i] = s / P.p;
+                        }
+                }
+                P.ctrl.assign((size_t)P.nodes * 3, 0.0);
+                for (int i3 = 0; i3 < P.n[2]; ++i3)
+                    for (int i2 = 0; i2 < P.n[1]; ++i2)
+                        for (int i1 = 0; i1 < P.n[0]; ++i1) {
+                            double eta[3] = {g[0][i1], g[1][i2], g[2][i3]};
+                            int64_t nd = node_index(P.n, i1, i2, i3);
+                            for (int x = 0; x < dim; ++x) P.ctrl[nd * 3 + x] = multilinear_coord(dim, P.corners, eta, x);
+                        }
             }
-            P.ctrl.assign((size_t)P.nodes * 3, 0.0);
-            for (int i3 = 0; i3 < P.n[2]; ++i3)
-                for (int i2 = 0; i2 < P.n[1]; ++i2)
-                    for (int i1 = 0; i1 < P.n[0]; ++i1) {
-                        double eta[3] = {g[0][i1], g[1][i2], g[2][i3]};
-                        int64_t nd = node_index(P.n, i1, i2, i3);
-                        for (int x = 0; x < dim; ++x) P.ctrl[nd * 3 + x] = multilinear_coord(dim, P.corners, eta, x);
-                    }
             plan.patches.push_back(std::move(P));
         }
         pp.n_dof = dof - pp.dof_off;
@@ -802,8 +889,17 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
                                 ib[fb / 2] = (fb % 2) ? B.n[fb / 2] - 1 : 0;
                                 ib[to[0]] = flip[0] ? B.n[to[0]] - 1 - s1 : s1;
                                 if (dim == 3) ib[to[1]] = flip[1] ? B.n[to[1]] - 1 - s2 : s2;
-                                uf.unite(node_off[ka] + node_index(A.n, ia[0], ia[1], ia[2]),
-                                         node_off[kb] + node_index(B.n, ib[0], ib[1], ib[2]));
+                                const int64_t na_ = node_index(A.n, ia[0], ia[1], ia[2]);
+                                const int64_t nb_ = node_index(B.n, ib[0], ib[1], ib[2]);
+                                if (A.general || B.general) {  // the two faces' nets must coincide
+                                    double d2 = 0;
+                                    for (int x = 0; x < 3; ++x) {
+                                        const double dd = A.ctrl[na_ * 3 + x] - B.ctrl[nb_ * 3 + x];
+                                        d2 += dd * dd;
+                                    }
+                                    if (std::sqrt(d2) > tol) fail(AFIETI_EGEOM, "interface control points differ");
+                                }
+                                uf.unite(node_off[ka] + na_, node_off[kb] + nb_);
                             }
                     }
             }

@@ -56,6 +56,7 @@ struct PatchPlan {
     double corners[24] = {0};
     int bc[6] = {0};
     std::vector<double> ctrl;     // [node][3] control points (z = 0 in 2D)
+    bool general = false;         // explicit control net (else the corners' multilinear map)
     // geometry inclusion (filled by build_geometry_inclusion)
     GeoPencil gp[3][3];           // [component][direction]
     std::vector<double> geo_da;   // [component][node]: D_A^{-1/2}
@@ -117,6 +118,10 @@ void gauss_legendre(int n, double* x, double* w);
 int sym_gen_eig(int n, const double* K, const double* M, double* U, double* D);
 // J[x][a] = dF_x / deta_a of the multilinear map of the 2^dim corners
 void multilinear_jacobian(int dim, const double* corners, const double* eta, double (&J)[3][3]);
+// point x (may be NULL) and Jacobian J[x][a] = dF_x / deta_a of a patch's
+// geometry map at eta: the corners' multilinear map, or the spline map of
+// an explicit control net
+void patch_map(const PatchPlan& P, const double* eta, double* x, double (&J)[3][3]);
 double rigid_mode(int dim, int m, int c, const double* X);
 
 }  // namespace afieti

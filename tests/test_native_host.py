@@ -271,3 +271,58 @@ def test_host_geometry_inclusion_matches_oracle(mk):
     assert np.abs(da - dao).max() <= 1e-12 * np.abs(dao).max()
     assert np.abs(ds - dso).max() <= 1e-12 * np.abs(dso).max()
     s.close()
+
+
+def _explicit(prob):
+    import copy
+    prob = copy.deepcopy(prob)
+    o = AFIETI(prob)
+    for pa, pd in zip(o.patches, prob["patches"]):
+        pd["ctrl"] = pa.ctrl.copy()
+        del pd["corners"]
+    return prob
+
+
+def test_host_explicit_control_nets():
+    """Explicit control nets: the net of the corners' multilinear map gives
+    the corners' plan (B and eigenvalues exactly, the rest to rounding: the
+    spline map evaluates the same points in another order); a curved net
+    matches the oracle (B, H,
+    eigenvalues, loads of the callbacks); an inverted net and interface
+    nets that differ are rejected."""
+    from paper_2001_09626_amd import Solver
+    prob = _general_problem(lambda: W.make_c2(n_el=2, p=3, seed=1))
+    a, b = Solver(prob, host_only=True), Solver(_explicit(prob), host_only=True)
+    for what in ("B", "eig"):
+        assert np.array_equal(a.export(what), b.export(what)), what
+    for what in ("GtG", "fixed_load", "dirichlet_c"):
+        x, y = a.export(what), b.export(what)
+        assert np.abs(x - y).max() <= 1e-13 * np.abs(x).max(), what
+    assert np.allclose(a.export("H"), b.export("H"), rtol=1e-15)
+    curved = W.make_curved(n_el=3, p=2)
+    s = Solver(curved, host_only=True)
+    o = AFIETI(curved)
+    assert (s.n_dof, s.n_c) == (o.n_dof, o.n_c)
+    Bo = o.B.tolil()
+    for r, (rr, pl, mi) in enumerate(s.export("B")):
+        exp = {int(pl): 1.0}
+        if mi >= 0:
+            exp[int(mi)] = -1.0
+        assert dict(zip(Bo.rows[r], Bo.data[r])) == exp, r
+    assert np.allclose(s.export("H"), [pa.diameter() for pa in o.patches], rtol=1e-14)
+    # loads of callbacks on the curved patches
+    import copy
+    cb = copy.deepcopy(curved)
+    cb["load"] = []
+    cb["body_force"] = lambda x: np.sin(x) + 0.5
+    sc, oc = Solver(cb, host_only=True), AFIETI(cb)
+    Fo = oc.load()
+    assert np.abs(sc.export("fixed_load") - Fo).max() <= 1e-13 * np.abs(Fo).max()
+    # an inverted net (mirror one patch's first parametric direction)
+    bad = copy.deepcopy(curved)
+    bad["patches"][0]["ctrl"] = bad["patches"][0]["ctrl"][:, :, ::-1].copy()
+    _expect_error(bad, -2)
+    # a bulge on an interface face of one patch only
+    bad = copy.deepcopy(curved)
+    bad["patches"][0]["ctrl"][1, 1, -1, 0] += 0.05
+    _expect_error(bad, -2)

@@ -215,3 +215,51 @@ def test_weak_scaling_solution_converges_to_exact():
         uq, xq = _at_gauss_points(s, s.solve(tol=1e-12)["u"])
         errs.append(np.abs(uq - W.weak_scaling_solution(xq)).max())
     assert errs[1] < errs[0] / 2 and errs[1] < 1e-2
+
+
+def _as_explicit_net(prob):
+    """The same problem with every patch given by its control net (the
+    multilinear net of its corners) instead of its corners."""
+    prob = copy.deepcopy(prob)
+    s = AFIETI(prob)
+    for pa, pd in zip(s.patches, prob["patches"]):
+        pd["ctrl"] = pa.ctrl.copy()
+        del pd["corners"]
+    return prob
+
+
+def test_explicit_net_of_the_multilinear_map_changes_nothing():
+    """A patch given by the control net of its corners' multilinear map is
+    the same patch: identical stiffness, load, diameter and solution."""
+    prob = W.make_c2(n_el=2, p=2, seed=3)
+    a, b = AFIETI(prob), AFIETI(_as_explicit_net(prob))
+    assert all(pb.general and not pa.general for pa, pb in zip(a.patches, b.patches))
+    x = W.random_vector(a.n_dof, 2)
+    assert np.array_equal(a.apply_A(x), b.apply_A(x))
+    assert np.array_equal(a.load(), b.load())
+    assert [pa.diameter() for pa in a.patches] == pytest.approx([pb.diameter() for pb in b.patches], rel=1e-15)
+    assert np.abs(a.solve(tol=1e-10)["u"] - b.solve(tol=1e-10)["u"]).max() <= 1e-14 * np.abs(a.solve(tol=1e-10)["u"]).max()
+
+
+def test_curved_patches():
+    """Explicit control nets of a curved domain (quarter of a thick
+    cylinder): rigid modes are in the kernel of every patch stiffness
+    (their strain vanishes pointwise, whatever the geometry), the
+    volume is within 2 % of the cylinder sector's (the nets approximate
+    the curved faces: measured 1.0 % below), the AF-IETI
+    solution equals the direct conforming solve, and geometry inclusion
+    needs far fewer iterations than the parametric FD (the preconditioner
+    the paper proposes for curved patches)."""
+    prob = W.make_curved(n_el=3, p=2)
+    s = AFIETI(prob)
+    for k, pa in enumerate(s.patches):
+        A = s.A[k]
+        assert np.abs(A @ pa.rigid_modes().T).max() <= 1e-13 * np.abs(A).max()
+    vol = sum(pa.geometry()[1].sum() for pa in s.patches)
+    assert vol == pytest.approx(0.25 * np.pi * (2.0 ** 2 - 1.0), rel=2e-2)
+    res = s.solve(tol=1e-12)
+    ud = solve_conforming(s)
+    assert np.abs(res["u"] - ud).max() <= 1e-9 * np.abs(ud).max()
+    its_fd = s.solve(tol=1e-8)["iters"]
+    its_geo = AFIETI(prob, geometry=True).solve(tol=1e-8)["iters"]
+    assert its_geo < its_fd / 2

@@ -201,6 +201,33 @@ def make_c5(seed=0, n_el=32, p=3, grid=(3, 3, 3), rel_delta=0.1, n_modes=64):
                 load=_random_modes(rng, n_modes, 3), tol=1e-8)
 
 
+def make_curved(seed=0, n_el=4, p=3, grid=(2, 2, 2), n_modes=8, r_in=1.0, r_out=2.0, height=1.0):
+    """3D curved domain with explicit control nets: a quarter of a thick
+    cylinder, r in [r_in, r_out], theta in [0, pi/2], z in [0, height], in
+    grid[0] x grid[1] x grid[2] patches of (r, theta, z); p C^{p-1}, n_el^3
+    elements per patch.  The control points of a patch are the cylinder map
+    of an equispaced grid of its (r, theta, z) box (n_el + p points per
+    direction, shared by neighbouring patches on their common faces), so the
+    patches are B-spline approximations of the curved sectors.  Steel,
+    ``n_modes`` seeded trig load modes, u = 0 on z = 0."""
+    rng = np.random.default_rng(seed)
+    n = n_el + p
+    edges = [np.linspace(r_in, r_out, grid[0] + 1), np.linspace(0.0, 0.5 * math.pi, grid[1] + 1),
+             np.linspace(0.0, height, grid[2] + 1)]
+    patches = []
+    for pidx in np.ndindex(*tuple(reversed(grid))):
+        pidx = tuple(reversed(pidx))
+        ax = [np.linspace(edges[d][pidx[d]], edges[d][pidx[d] + 1], n) for d in range(3)]
+        Z, T, R = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")     # (n3, n2, n1)
+        ctrl = np.stack([R * np.cos(T), R * np.sin(T), Z], axis=-1)
+        bc = [FACE_FREE] * 6
+        if pidx[2] == 0:
+            bc[4] = FACE_DIRICHLET
+        patches.append(dict(ctrl=ctrl, p=int(p), reg=int(p - 1), n_el=[int(n_el)] * 3,
+                            lam=STEEL_LAM, mu=STEEL_MU, bc=bc))
+    return dict(name="curved", dim=3, patches=patches, load=_random_modes(rng, n_modes, 3), tol=1e-8)
+
+
 def make_weak_scaling(k=2, n_el=8, p=3):
     """Weak-scaling workload of the paper's third test (Section 6): the unit
     cube split into k^3 equal cubes, p = 3 C^2, n_el^3 elements per patch,
