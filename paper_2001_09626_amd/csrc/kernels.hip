@@ -719,29 +719,48 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
     // this q1 (each A value is formed by exactly one thread, from the NB x NB
     // coefficients of the row's (c, t3) plane, read through the cache), then
     // B00 = V2 A0, B10 = D2 A0, B01 = V2 A1 along direction 2
+    // (a brick whose basis functions all lie in the patch reads its
+    // coefficients without bounds checks: every brick, when the element
+    // counts are multiples of the brick size)
+    const bool full = i1 + NB <= pa.n[0] && i2 + NB <= pa.n[1] && i3 + NB <= pa.n[2];
+    auto fphase = [&](auto checked) {
+    constexpr bool CHK = decltype(checked)::value;
     for (int row = tid; row < 3 * NB * QB; row += NT) {
         const int c = row / (NB * QB), t3 = (row / QB) % NB, q1 = row % QB;
-        const bool pin = i3 + t3 < pa.n[2];
-        const double* xp = x + pa.dof_off + (int64_t)c * pa.nodes + (int64_t)pa.n[0] * pa.n[1] * (i3 + t3) + i1;
-        double v1[NB], d1[NB];
+        // basis functions e1..e1+P are the ones supported at Gauss point q1
+        const int e1 = S::tlo(q1);
+        const bool pin = !CHK || i3 + t3 < pa.n[2];
+        const double* xp = x + pa.dof_off + (int64_t)c * pa.nodes + (int64_t)pa.n[0] * pa.n[1] * (i3 + t3) +
+                           (int64_t)pa.n[0] * i2 + i1 + e1;
+        double v1[P + 1], d1[P + 1];
 #pragma unroll
-        for (int t = 0; t < NB; ++t) {
-            v1[t] = T1[q1 * NB + t];
-            d1[t] = T1[OD + q1 * NB + t];
+        for (int u = 0; u <= P; ++u) {
+            v1[u] = T1[q1 * NB + e1 + u];
+            d1[u] = T1[OD + q1 * NB + e1 + u];
         }
         double a0[NB], a1[NB];
 #pragma unroll
         for (int t2 = 0; t2 < NB; ++t2) {
-            const bool rin = pin && i2 + t2 < pa.n[1];
-            const double* xr = xp + (int64_t)pa.n[0] * (i2 + t2);
-            double xl[NB];
+            const bool rin = pin && (!CHK || i2 + t2 < pa.n[1]);
+            const double* xr = xp + pa.n[0] * t2;
+            double xl[P + 1];
 #pragma unroll
-            for (int t = 0; t < NB; ++t) xl[t] = (rin && i1 + t < pa.n[0]) ? xr[t] : 0.0;
+            for (int u = 0; u <= P; ++u) {
+                if constexpr (CHK) {
+                    // coefficients outside the patch are zero: load from a
+                    // valid address and select, without a branch
+                    const bool ok = rin && i1 + e1 + u < pa.n[0];
+                    const double v = *(ok ? xr + u : x);
+                    xl[u] = ok ? v : 0.0;
+                } else {
+                    xl[u] = xr[u];
+                }
+            }
             double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-            for (int t = 0; t < NB; ++t) {
-                s0 += v1[t] * xl[t];
-                s1 += d1[t] * xl[t];
+            for (int u = 0; u <= P; ++u) {
+                s0 += v1[u] * xl[u];
+                s1 += d1[u] * xl[u];
             }
             a0[t2] = s0;
             a1[t2] = s1;
@@ -761,6 +780,9 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
             b[2 * BK + q * QB] = b01;
         }
     }
+    };
+    if (full) fphase(std::false_type{});
+    else fphase(std::true_type{});
     __syncthreads();
     // ---- Q: Gauss columns, wavefront w owns q3 in [w QPG, w QPG + QPG)
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -825,42 +847,46 @@ __global__ void __launch_bounds__(MfShape<P>::NT) k_mf_brick(const DevPatch* __r
                         J[xx][a] = (c4[0] + c4[1] * eb) + (c4[2] + c4[3] * eb) * ec;
                     }
                 }
-                const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-                const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-                const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-                const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-                // 1/det: hardware reciprocal refined by two Newton-Raphson
-                // steps (e <- e + e (1 - det e)), within an ulp or so of the
+                // adjugate: Ad[a][x] = det(J) d eta_a / d x_x
+                double Ad[3][3];
+                Ad[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+                Ad[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+                Ad[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+                Ad[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+                Ad[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+                Ad[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+                Ad[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+                Ad[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+                Ad[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+                const double ad = fabs(J[0][0] * Ad[0][0] + J[0][1] * Ad[1][0] + J[0][2] * Ad[2][0]);
+                // 1/|det|: hardware reciprocal refined by two Newton-Raphson
+                // steps (e <- e + e (1 - |det| e)), within an ulp or so of the
                 // correctly rounded quotient at half its instruction count
-                double id = __builtin_amdgcn_rcp(det);
-                id = fma(fma(-det, id, 1.0), id, id);
-                id = fma(fma(-det, id, 1.0), id, id);
-                double Ji[3][3];  // Ji[a][x] = d eta_a / d x_x
-                Ji[0][0] = c00 * id;
-                Ji[1][0] = c01 * id;
-                Ji[2][0] = c02 * id;
-                Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
-                Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
-                Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
-                Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
-                Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
-                Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
-                const double W = w12 * T3[OW + q3a + j] * fabs(det);
-                double gr[3][3];  // physical gradient [c][x]
+                double id = __builtin_amdgcn_rcp(ad);
+                id = fma(fma(-ad, id, 1.0), id, id);
+                id = fma(fma(-ad, id, 1.0), id, id);
+                // with Ji = Ad / det and the weight w |det|, the flux
+                // w |det| sigma(G Ji) Ji^T equals (w / |det|) sigma(G Ad) Ad^T
+                const double sw = w12 * T3[OW + q3a + j] * id;
+                const double ms = mu * sw, ls = lam * sw, ms2 = ms + ms;
+                double g[3][3];  // G Ad: det(J) times the physical gradient [c][x]
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
                     for (int xx = 0; xx < 3; ++xx)
-                        gr[c][xx] = F[c][0][j] * Ji[0][xx] + F[c][1][j] * Ji[1][xx] + F[c][2][j] * Ji[2][xx];
-                const double dv = gr[0][0] + gr[1][1] + gr[2][2];
+                        g[c][xx] = F[c][0][j] * Ad[0][xx] + F[c][1][j] * Ad[1][xx] + F[c][2][j] * Ad[2][xx];
+                const double ldv = ls * (g[0][0] + g[1][1] + g[2][2]);
+                double sg[3][3];  // scaled stress, symmetric
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    double sg[3];
+                    sg[c][c] = fma(ms2, g[c][c], ldv);
 #pragma unroll
-                    for (int xx = 0; xx < 3; ++xx) sg[xx] = mu * (gr[c][xx] + gr[xx][c]) + (c == xx ? lam * dv : 0.0);
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) F[c][a][j] = W * (sg[0] * Ji[a][0] + sg[1] * Ji[a][1] + sg[2] * Ji[a][2]);
+                    for (int xx = c + 1; xx < 3; ++xx) sg[c][xx] = sg[xx][c] = ms * (g[c][xx] + g[xx][c]);
                 }
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) F[c][a][j] = sg[c][0] * Ad[a][0] + sg[c][1] * Ad[a][1] + sg[c][2] * Ad[a][2];
             }
         }
         // P = sum over wavefronts (in order) of the partial contractions
