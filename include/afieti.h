@@ -11,8 +11,9 @@
  * patch, a body force f (trigonometric modes and/or a callback), a traction
  * g on faces marked AFIETI_FACE_TRACTION (Gamma_N), Dirichlet data u = g_D
  * on faces marked AFIETI_FACE_DIRICHLET (homogeneous, or from a callback),
- * natural conditions elsewhere.  Interfaces are found by matching patch
- * faces; they must be conforming (equal knot vectors).
+ * natural conditions elsewhere.  Interfaces (Section 2.2) are the pairs of
+ * patch faces whose corners coincide, or the pairs listed explicitly;
+ * they must be conforming (equal knot vectors).
  *
  * Vector layouts (all double precision, device memory, caller owned):
  *   DOF vector   patch-stacked (Section 4): for each problem, for each
@@ -162,6 +163,23 @@ typedef struct {
     afieti_traction_fn traction;      /* may be NULL                     */
     afieti_field_fn dirichlet;        /* may be NULL (homogeneous)       */
     void* ctx;                        /* passed to the callbacks         */
+    /* Interfaces: n_interfaces = 0 glues every pair of faces whose corners
+     * coincide.  Otherwise only the listed pairs are glued (coinciding
+     * faces not listed stay apart: a crack), interfaces[5 i .. 5 i + 4] =
+     * (patch_a, face_a, patch_b, face_b, orient), host memory read during
+     * afieti_setup; faces numbered as face_bc.  orient = -1 takes the
+     * orientation from the corners; otherwise it must equal
+     * swap + 2 flip_0 + 4 flip_1, where t_0 < t_1 are the parametric
+     * directions along face_a and u_0 < u_1 those along face_b: swap = 1
+     * when t_0 runs along u_1, flip_j = 1 when t_j runs against the
+     * direction it lies along (in 2D orient is 0 or 2).  Errors:
+     * AFIETI_EINVAL for indices out of range, a patch paired with itself
+     * or a face listed twice; AFIETI_EGEOM for listed faces whose corners
+     * (or, with explicit control nets, face nets) do not coincide, knot
+     * vectors that differ along the face, an orient that the corners
+     * contradict, or a traction face. */
+    int n_interfaces;
+    const int* interfaces;
 } afieti_problem;
 
 typedef struct {

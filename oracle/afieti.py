@@ -68,6 +68,10 @@ class AFIETI:
         self.body_force = prob.get("body_force")
         self.traction = prob.get("traction")
         self.dirichlet = prob.get("dirichlet")
+        # explicit interface list (patch_a, face_a, patch_b, face_b, orient),
+        # or None: every coinciding pair of boundary control points is glued
+        itf = prob.get("interfaces")
+        self.interfaces = None if itf is None or len(itf) == 0 else [tuple(int(v) for v in e) for e in itf]
         self.tol = float(prob.get("tol", 1e-8))
         # LAPACK driver of the generalised eigensolves (scipy.linalg.eigh's
         # default when None); another driver perturbs U and D at rounding
@@ -114,8 +118,11 @@ class AFIETI:
     # ------------------------------------------------------------- numbering
     def _build_numbering(self):
         """Geometric nodes: copies of a control point shared by patches that
-        meet conformingly.  Two boundary copies are the same node when their
-        control points coincide (equal knots and a common face map)."""
+        meet conformingly (Section 2.2).  Two boundary copies are the same
+        node when their control points coincide (equal knots and a common
+        face map); with an explicit interface list, only copies on the two
+        faces of a listed pair are identified (directly, or through other
+        listed pairs)."""
         recs = []  # (patch, local node, coords)
         for k, pa in enumerate(self.patches):
             gm = pa.gamma_mask().reshape(-1)
@@ -124,7 +131,6 @@ class AFIETI:
             for i, x in zip(nodes, X):
                 recs.append((k, int(i), x))
         pts = np.array([r[2] for r in recs])
-        tree = cKDTree(pts)
         parent = list(range(len(recs)))
 
         def find(a):
@@ -133,10 +139,29 @@ class AFIETI:
                 a = parent[a]
             return a
 
-        for a, b in tree.query_pairs(r=1e-9):
+        def unite(a, b):
             ra, rb = find(a), find(b)
             if ra != rb:
                 parent[max(ra, rb)] = min(ra, rb)
+
+        if self.interfaces is None:
+            # every pair of coinciding boundary control points
+            for a, b in cKDTree(pts).query_pairs(r=1e-9):
+                unite(a, b)
+        else:
+            # only across the listed face pairs: each control point of one
+            # face coincides with one of the other face (conforming faces)
+            rec_of = {(k, i): j for j, (k, i, _) in enumerate(recs)}
+            for ka, fa, kb, fb, _orient in self.interfaces:
+                ia = self.patches[ka].face_nodes(fa)
+                ib = self.patches[kb].face_nodes(fb)
+                ja = [rec_of[(ka, int(i))] for i in ia]
+                jb = [rec_of[(kb, int(i))] for i in ib]
+                dist, near = cKDTree(pts[jb]).query(pts[ja])
+                if len(ia) != len(ib) or np.max(dist) > 1e-9 or len(set(near.tolist())) != len(ib):
+                    raise ValueError("listed interface faces do not coincide")
+                for x, y in zip(ja, near):
+                    unite(x, jb[y])
         groups = {}
         for idx in range(len(recs)):
             groups.setdefault(find(idx), []).append(idx)

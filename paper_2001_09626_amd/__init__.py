@@ -48,7 +48,9 @@ def to_c_problems(problems):
     open knot vectors per direction) and ``ctrl`` (explicit control net,
     shape (n_d, .., n_1, dim), in place of ``corners``), a problem's ``body_force(x)``,
     ``traction(x, normal)`` and ``dirichlet(x)`` callables (arrays of
-    points in, arrays of values out)."""
+    points in, arrays of values out), and ``interfaces``: rows (patch_a,
+    face_a, patch_b, face_b, orient) gluing only the listed faces (orient
+    -1: from the corners)."""
     if isinstance(problems, dict):
         problems = [problems]
     arr = (N.Problem * len(problems))()
@@ -98,6 +100,13 @@ def to_c_problems(problems):
         arr[j].patches = pats
         arr[j].n_load_modes = len(pr["load"])
         arr[j].load_modes = modes
+        if pr.get("interfaces") is not None:
+            # explicit interface list: rows (patch_a, face_a, patch_b, face_b, orient)
+            itf = np.ascontiguousarray(np.asarray(pr["interfaces"], dtype=np.int32).reshape(-1, 5))
+            keep.append(itf)
+            arr[j].n_interfaces = len(itf)
+            if len(itf):
+                arr[j].interfaces = itf.ctypes.data_as(C.POINTER(C.c_int))
         for key, make in (("body_force", _field_cb), ("traction", _traction_cb), ("dirichlet", _field_cb)):
             if pr.get(key) is not None:
                 cb = make(pr[key], dim)

@@ -48,7 +48,7 @@ class Problem(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_patches", C.c_int), ("patches", C.POINTER(Patch)),
                 ("n_load_modes", C.c_int), ("load_modes", C.POINTER(LoadMode)),
                 ("body_force", FIELD_FN), ("traction", TRACTION_FN), ("dirichlet", FIELD_FN),
-                ("ctx", C.c_void_p)]
+                ("ctx", C.c_void_p), ("n_interfaces", C.c_int), ("interfaces", C.POINTER(C.c_int))]
 
 
 class Options(C.Structure):

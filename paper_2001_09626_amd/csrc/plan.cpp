@@ -638,6 +638,8 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
             fail(AFIETI_EINVAL, "problem needs dim 2 or 3 and at least one patch");
         if (pr.n_load_modes < 0 || (pr.n_load_modes > 0 && !pr.load_modes))
             fail(AFIETI_EINVAL, "bad load modes");
+        if (pr.n_interfaces < 0 || (pr.n_interfaces > 0 && !pr.interfaces))
+            fail(AFIETI_EINVAL, "bad interface list");
         const int dim = pr.dim;
         ProblemPlan pp;
         pp.dim = dim;
@@ -832,77 +834,101 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
             }
             for (int x = 0; x < 3; ++x) X[x] = P.corners[3 * bits + x];
         };
-        for (int ka = 0; ka < pr.n_patches; ++ka)
-            for (int kb = ka + 1; kb < pr.n_patches; ++kb) {
-                const PatchPlan& A = plan.patches[pp.patch0 + ka];
-                const PatchPlan& B = plan.patches[pp.patch0 + kb];
-                for (int fa = 0; fa < 2 * dim; ++fa)
-                    for (int fb = 0; fb < 2 * dim; ++fb) {
-                        int map[4];
-                        bool ok = true;
-                        for (int s = 0; s < nfc && ok; ++s) {
-                            double Xa[3], Xb[3];
-                            face_corner(A, fa, s, Xa);
-                            map[s] = -1;
-                            for (int t = 0; t < nfc; ++t) {
-                                face_corner(B, fb, t, Xb);
-                                double d2 = 0;
-                                for (int x = 0; x < 3; ++x) d2 += (Xa[x] - Xb[x]) * (Xa[x] - Xb[x]);
-                                if (std::sqrt(d2) <= tol) map[s] = t;
-                            }
-                            if (map[s] < 0) ok = false;
-                        }
-                        if (!ok) continue;
-                        // tangential directions of each face, ascending
-                        int ta[2], tb[2], na = 0, nb = 0;
-                        for (int l = 0; l < dim; ++l) {
-                            if (l != fa / 2) ta[na++] = l;
-                            if (l != fb / 2) tb[nb++] = l;
-                        }
-                        // where does tangential direction j of A go in B, flipped?
-                        int to[2], flip[2];
-                        for (int j = 0; j < dim - 1; ++j) {
-                            int u0 = map[0], u1 = map[1 << j];
-                            int diff = u0 ^ u1;
-                            if (diff != 1 && diff != 2) fail(AFIETI_EGEOM, "degenerate face correspondence");
-                            int jb = diff == 1 ? 0 : 1;
-                            to[j] = tb[jb];
-                            flip[j] = (u0 >> jb) & 1;
-                            // equal knot vectors along the face (reversed where flipped)
-                            const std::vector<double>& ka = A.dir[ta[j]].knots;
-                            const std::vector<double>& kb = B.dir[to[j]].knots;
-                            bool same = A.p == B.p && ka.size() == kb.size();
-                            for (size_t i = 0; same && i < ka.size(); ++i)
-                                same = std::fabs(ka[i] - (flip[j] ? 1.0 - kb[kb.size() - 1 - i] : kb[i])) <= 1e-12;
-                            if (!same) fail(AFIETI_EGEOM, "non-conforming interface");
-                        }
-                        if (A.bc[fa] == AFIETI_FACE_TRACTION || B.bc[fb] == AFIETI_FACE_TRACTION)
-                            fail(AFIETI_EGEOM, "a traction face is an interface");
-                        // unite the face nodes
-                        int na1 = A.n[ta[0]], na2 = dim == 3 ? A.n[ta[1]] : 1;
-                        for (int s2 = 0; s2 < na2; ++s2)
-                            for (int s1 = 0; s1 < na1; ++s1) {
-                                int ia[3] = {0, 0, 0}, ib[3] = {0, 0, 0};
-                                ia[fa / 2] = (fa % 2) ? A.n[fa / 2] - 1 : 0;
-                                ia[ta[0]] = s1;
-                                if (dim == 3) ia[ta[1]] = s2;
-                                ib[fb / 2] = (fb % 2) ? B.n[fb / 2] - 1 : 0;
-                                ib[to[0]] = flip[0] ? B.n[to[0]] - 1 - s1 : s1;
-                                if (dim == 3) ib[to[1]] = flip[1] ? B.n[to[1]] - 1 - s2 : s2;
-                                const int64_t na_ = node_index(A.n, ia[0], ia[1], ia[2]);
-                                const int64_t nb_ = node_index(B.n, ib[0], ib[1], ib[2]);
-                                if (A.general || B.general) {  // the two faces' nets must coincide
-                                    double d2 = 0;
-                                    for (int x = 0; x < 3; ++x) {
-                                        const double dd = A.ctrl[na_ * 3 + x] - B.ctrl[nb_ * 3 + x];
-                                        d2 += dd * dd;
-                                    }
-                                    if (std::sqrt(d2) > tol) fail(AFIETI_EGEOM, "interface control points differ");
-                                }
-                                uf.unite(node_off[ka] + na_, node_off[kb] + nb_);
-                            }
-                    }
+        // glue face fa of patch ka to face fb of patch kb if their corners
+        // coincide (returns false otherwise); `orient` >= 0 must equal the
+        // orientation the corners give (swap + 2 flip_0 + 4 flip_1)
+        auto glue = [&](int ka, int fa, int kb, int fb, int orient) -> bool {
+            const PatchPlan& A = plan.patches[pp.patch0 + ka];
+            const PatchPlan& B = plan.patches[pp.patch0 + kb];
+            int map[4];
+            for (int s = 0; s < nfc; ++s) {
+                double Xa[3], Xb[3];
+                face_corner(A, fa, s, Xa);
+                map[s] = -1;
+                for (int t = 0; t < nfc; ++t) {
+                    face_corner(B, fb, t, Xb);
+                    double d2 = 0;
+                    for (int x = 0; x < 3; ++x) d2 += (Xa[x] - Xb[x]) * (Xa[x] - Xb[x]);
+                    if (std::sqrt(d2) <= tol) map[s] = t;
+                }
+                if (map[s] < 0) return false;
             }
+            // tangential directions of each face, ascending
+            int ta[2], tb[2], na = 0, nb = 0;
+            for (int l = 0; l < dim; ++l) {
+                if (l != fa / 2) ta[na++] = l;
+                if (l != fb / 2) tb[nb++] = l;
+            }
+            // where does tangential direction j of A go in B, flipped?
+            int to[2], flip[2] = {0, 0}, swap = 0;
+            for (int j = 0; j < dim - 1; ++j) {
+                int u0 = map[0], u1 = map[1 << j];
+                int diff = u0 ^ u1;
+                if (diff != 1 && diff != 2) fail(AFIETI_EGEOM, "degenerate face correspondence");
+                int jb = diff == 1 ? 0 : 1;
+                to[j] = tb[jb];
+                flip[j] = (u0 >> jb) & 1;
+                if (j == 0) swap = jb;
+                // equal knot vectors along the face (reversed where flipped)
+                const std::vector<double>& ka_ = A.dir[ta[j]].knots;
+                const std::vector<double>& kb_ = B.dir[to[j]].knots;
+                bool same = A.p == B.p && ka_.size() == kb_.size();
+                for (size_t i = 0; same && i < ka_.size(); ++i)
+                    same = std::fabs(ka_[i] - (flip[j] ? 1.0 - kb_[kb_.size() - 1 - i] : kb_[i])) <= 1e-12;
+                if (!same) fail(AFIETI_EGEOM, "non-conforming interface");
+            }
+            if (orient >= 0 && orient != swap + 2 * flip[0] + 4 * flip[1])
+                fail(AFIETI_EGEOM, "interface orientation does not match the corners");
+            if (A.bc[fa] == AFIETI_FACE_TRACTION || B.bc[fb] == AFIETI_FACE_TRACTION)
+                fail(AFIETI_EGEOM, "a traction face is an interface");
+            // unite the face nodes
+            int na1 = A.n[ta[0]], na2 = dim == 3 ? A.n[ta[1]] : 1;
+            for (int s2 = 0; s2 < na2; ++s2)
+                for (int s1 = 0; s1 < na1; ++s1) {
+                    int ia[3] = {0, 0, 0}, ib[3] = {0, 0, 0};
+                    ia[fa / 2] = (fa % 2) ? A.n[fa / 2] - 1 : 0;
+                    ia[ta[0]] = s1;
+                    if (dim == 3) ia[ta[1]] = s2;
+                    ib[fb / 2] = (fb % 2) ? B.n[fb / 2] - 1 : 0;
+                    ib[to[0]] = flip[0] ? B.n[to[0]] - 1 - s1 : s1;
+                    if (dim == 3) ib[to[1]] = flip[1] ? B.n[to[1]] - 1 - s2 : s2;
+                    const int64_t na_ = node_index(A.n, ia[0], ia[1], ia[2]);
+                    const int64_t nb_ = node_index(B.n, ib[0], ib[1], ib[2]);
+                    if (A.general || B.general) {  // the two faces' nets must coincide
+                        double d2 = 0;
+                        for (int x = 0; x < 3; ++x) {
+                            const double dd = A.ctrl[na_ * 3 + x] - B.ctrl[nb_ * 3 + x];
+                            d2 += dd * dd;
+                        }
+                        if (std::sqrt(d2) > tol) fail(AFIETI_EGEOM, "interface control points differ");
+                    }
+                    uf.unite(node_off[ka] + na_, node_off[kb] + nb_);
+                }
+            return true;
+        };
+        if (pr.n_interfaces == 0) {
+            // every pair of faces whose corners coincide
+            for (int ka = 0; ka < pr.n_patches; ++ka)
+                for (int kb = ka + 1; kb < pr.n_patches; ++kb)
+                    for (int fa = 0; fa < 2 * dim; ++fa)
+                        for (int fb = 0; fb < 2 * dim; ++fb) glue(ka, fa, kb, fb, -1);
+        } else {
+            // only the listed pairs (coinciding faces not listed stay apart)
+            std::vector<char> used((size_t)pr.n_patches * 2 * dim, 0);
+            for (int i = 0; i < pr.n_interfaces; ++i) {
+                const int* e = pr.interfaces + 5 * i;
+                const int ka = e[0], fa = e[1], kb = e[2], fb = e[3], orient = e[4];
+                if (ka < 0 || ka >= pr.n_patches || kb < 0 || kb >= pr.n_patches || ka == kb || fa < 0 ||
+                    fa >= 2 * dim || fb < 0 || fb >= 2 * dim || orient < -1 || orient > (dim == 3 ? 7 : 2) ||
+                    (dim == 2 && orient >= 0 && (orient & 5)))
+                    fail(AFIETI_EINVAL, "bad interface entry");
+                char& ua = used[(size_t)ka * 2 * dim + fa];
+                char& ub = used[(size_t)kb * 2 * dim + fb];
+                if (ua || ub) fail(AFIETI_EINVAL, "a face is listed in two interfaces");
+                ua = ub = 1;
+                if (!glue(ka, fa, kb, fb, orient)) fail(AFIETI_EGEOM, "listed interface faces do not coincide");
+            }
+        }
         // ---- classes in (lowest patch, local index) order
         struct Copy { int k; int64_t node; };
         std::vector<std::vector<Copy>> classes;

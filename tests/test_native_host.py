@@ -326,3 +326,66 @@ def test_host_explicit_control_nets():
     bad = copy.deepcopy(curved)
     bad["patches"][0]["ctrl"][1, 1, -1, 0] += 0.05
     _expect_error(bad, -2)
+
+
+# ------------------------------------------------------------ interface lists
+def _B_equal(s, o):
+    Bo = o.B.tolil()
+    Bx = s.export("B")
+    assert len(Bx) == o.n_c
+    for r, (rr, pl, mi) in enumerate(Bx):
+        exp = {int(pl): 1.0}
+        if mi >= 0:
+            exp[int(mi)] = -1.0
+        assert dict(zip(Bo.rows[r], Bo.data[r])) == exp, r
+
+
+@pytest.mark.parametrize("mk", [lambda: W.make_cracked(2, n_el=3), lambda: W.make_cracked(3, n_el=2),
+                                lambda: dict(W.make_c2(n_el=2, p=2), interfaces=W.grid_interfaces((2, 2, 2)))])
+def test_host_interface_list_matches_oracle(mk):
+    from paper_2001_09626_amd import Solver
+    prob = mk()
+    s = Solver(prob, host_only=True)
+    o = AFIETI(prob)
+    assert (s.n_dof, s.n_c) == (o.n_dof, o.n_c)
+    _B_equal(s, o)
+    # the full list of a grid is the automatic matching
+    auto = dict(prob)
+    auto.pop("interfaces")
+    if len(prob["interfaces"]) == len(W.grid_interfaces((2,) * prob["dim"])):
+        assert s.n_c == Solver(auto, host_only=True).n_c
+    else:
+        assert s.n_c < Solver(auto, host_only=True).n_c
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_host_interface_orientation(dim):
+    from paper_2001_09626_amd import Solver
+    prob, pair, orient = W.make_rotated_pair(dim)
+    o = AFIETI(prob)  # automatic matching by coinciding control points
+    for value in (-1, orient):
+        s = Solver(dict(prob, interfaces=[pair + (value,)]), host_only=True)
+        _B_equal(s, o)
+    for value in range(8 if dim == 3 else 3):
+        if value == orient or (dim == 2 and value & 5):
+            continue
+        _expect_error(dict(prob, interfaces=[pair + (value,)]), -2)
+
+
+def test_interface_list_error_codes():
+    prob = W.make_c1(n_el=2)
+    good = W.grid_interfaces((2, 2))
+    for bad in [(0, 1, 4, 0, 0), (0, 1, 0, 0, 0), (0, 4, 1, 0, 0), (0, 1, 1, 0, 1), (0, 1, 1, 0, 8),
+                (-1, 1, 1, 0, 0)]:
+        _expect_error(dict(prob, interfaces=good[1:] + [bad]), -1)
+    # a face in two interfaces
+    _expect_error(dict(prob, interfaces=good + [(0, 1, 1, 0, -1)]), -1)
+    # faces that do not coincide
+    _expect_error(dict(prob, interfaces=[(0, 0, 1, 0, 0)]), -2)
+    # an orientation the corners contradict
+    _expect_error(dict(prob, interfaces=[(0, 1, 1, 0, 2)]), -2)
+    # a traction face listed as an interface
+    tr = W.make_c1(n_el=2)
+    tr["patches"][0]["bc"][1] = 2
+    tr["traction"] = lambda x, n: np.zeros_like(x)
+    _expect_error(dict(tr, interfaces=good), -2)

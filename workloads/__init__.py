@@ -30,6 +30,9 @@ Problem dictionary layout
 ``tol``          MINRES tolerance on the preconditioned residual ratio.
 ``body_force``, ``traction``, ``dirichlet``  optional callables on arrays of
                  points (n, dim): f(x), g(x, normal), g_D(x), each -> (n, dim).
+``interfaces``   optional list of (patch_a, face_a, patch_b, face_b, orient):
+                 only these face pairs are glued (orient -1: from the
+                 corners); absent, every pair of coinciding faces is.
 
 Material constants: E = 1, nu = 0.3 gives lambda = 0.3/0.52, mu = 1/2.6
 (the paper's "steel" values, Section 6).
@@ -226,6 +229,71 @@ def make_curved(seed=0, n_el=4, p=3, grid=(2, 2, 2), n_modes=8, r_in=1.0, r_out=
         patches.append(dict(ctrl=ctrl, p=int(p), reg=int(p - 1), n_el=[int(n_el)] * 3,
                             lam=STEEL_LAM, mu=STEEL_MU, bc=bc))
     return dict(name="curved", dim=3, patches=patches, load=_random_modes(rng, n_modes, 3), tol=1e-8)
+
+
+def grid_interfaces(grid):
+    """Explicit interface list of a patch grid (colexicographic patches, all
+    parametrised alike): for every pair of neighbours along direction d the
+    row (patch_a, face 2d + 1, patch_b, face 2d, orient 0)."""
+    dim = len(grid)
+    out = []
+    for pidx in np.ndindex(*tuple(reversed(grid))):
+        pidx = tuple(reversed(pidx))
+        ka = sum(pidx[d] * int(np.prod(grid[:d])) for d in range(dim))
+        for d in range(dim):
+            if pidx[d] + 1 < grid[d]:
+                out.append((ka, 2 * d + 1, ka + int(np.prod(grid[:d])), 2 * d, 0))
+    return out
+
+
+def make_cracked(dim=2, seed=0, n_el=8, p=2, n_modes=4):
+    """A patch grid with a crack: 2D, the unit square in 2x2 patches with the
+    interface between patches 0 and 1 left open (a slit from (1/2, 0) to the
+    centre); 3D, the unit cube in 2x2x2 patches with the interfaces of patch
+    0 to patches 1 and 2 left open (two crack faces meeting along the edge
+    x = y = 1/2, z < 1/2).  Interior vertex moved by U(-0.05, 0.05)^dim, p
+    C^{p-1}, n_el elements per direction, steel, seeded trig loads, u = 0 on
+    the far side (y = 1 in 2D, z = 1 in 3D); the crack faces are free."""
+    rng = np.random.default_rng(seed)
+    grid = (2,) * dim
+    verts = _grid_vertices(grid, rng, 0.05)
+    n_p = 2 ** dim
+    patches = _patches_from_grid(grid, verts, p, p - 1, [n_el] * dim,
+                                 np.full(n_p, STEEL_LAM), np.full(n_p, STEEL_MU), [(dim - 1, 1)])
+    itf = grid_interfaces(grid)
+    cut = {(0, 1)} if dim == 2 else {(0, 1), (0, 2)}
+    itf = [e for e in itf if (e[0], e[2]) not in cut]
+    return dict(name=f"cracked{dim}d", dim=dim, patches=patches, interfaces=itf,
+                load=_random_modes(rng, n_modes, dim), tol=1e-8)
+
+
+def make_rotated_pair(dim):
+    """Two unit patches sharing the plane x = 1, the second parametrised in a
+    rotated way: 2D (eta1, eta2) -> (2 - eta1, 1 - eta2), shared faces 1 and
+    1, the common edge running against the first patch's direction (orient
+    2); 3D (eta1, eta2, eta3) -> (1 + eta1, 1 - eta3, eta2), shared faces 1
+    and 0, the first patch's y running along the second's eta3 reversed and
+    its z along eta2 (orient swap 1 + 2 flip_0 = 3).  p = 2 C^1, 2 elements
+    per direction, lambda = mu = 1, u = 0 on x = 0, trig loads.  Returns
+    (problem, (patch_a, face_a, patch_b, face_b), orient)."""
+    pats = []
+    for k in range(2):
+        cs = np.zeros((2 ** dim, dim))
+        for c in range(2 ** dim):
+            a = [(c >> d) & 1 for d in range(dim)]
+            if k == 0:
+                cs[c] = a
+            elif dim == 2:
+                cs[c] = [2 - a[0], 1 - a[1]]
+            else:
+                cs[c] = [1 + a[0], 1 - a[2], a[1]]
+        bc = [FACE_FREE] * (2 * dim)
+        if k == 0:
+            bc[0] = FACE_DIRICHLET
+        pats.append(dict(corners=cs, p=2, reg=1, n_el=[2] * dim, lam=1.0, mu=1.0, bc=bc))
+    load = [(c, 1.0, [1] * dim, [0.1 * c] * dim) for c in range(dim)]
+    face_b = 1 if dim == 2 else 0
+    return dict(dim=dim, patches=pats, load=load, tol=1e-8), (0, 1, 1, face_b), (2 if dim == 2 else 3)
 
 
 def make_weak_scaling(k=2, n_el=8, p=3):
