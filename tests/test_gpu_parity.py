@@ -162,13 +162,15 @@ def test_solve_tight_matches_oracle_1e10(pair):
     st_ = Solver(prob, tol=1e-12)
     ref = o.solve(tol=1e-12)
     alt = AFIETI(prob, eig_driver="gv").solve(tol=1e-12)
+    ext = o.solve(tol=1e-14, maxit=len(ref["history"]) + 20)
+    alt_ext = AFIETI(prob, eig_driver="gv").solve(tol=1e-14, maxit=len(ref["history"]) + 20)
     u, lam, st = st_.solve()
     u, lam = _host(u), _host(lam)
     diff = np.linalg.norm(u - ref["u"]) / np.linalg.norm(ref["u"])
     dl = np.linalg.norm(lam - ref["lam"]) / np.linalg.norm(ref["lam"])
     print(f"  tol 1e-12: iterations gpu {st['iterations']} oracle {ref['iters']}; rel diff u {diff:.2e} "
           f"lam {dl:.2e}", flush=True)
-    assert same_iterations(st["iterations"], ref, 1e-12, alt=alt)
+    assert same_iterations(st["iterations"], ref, 1e-12, alt=alt, ext=ext, alt_ext=alt_ext)
     assert diff <= 1e-10 and dl <= 1e-9
     st_.close()
 
