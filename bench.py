@@ -26,7 +26,7 @@ METRIC = "AF-IETI solve s to 1e-8 rel.res (FP32-FD vs FP64-FD); FD-apply DOF/s"
 # read from the FETCH_SIZE / WRITE_SIZE counters (scaled by a 1 GiB device
 # copy's readings): profiles/k_mf_stiffness_c2_traffic.md.  Valid for the
 # kernels that were measured; None for workloads without such a run.
-MEASURED_TRAFFIC = {"c2": 231.1e6}
+MEASURED_TRAFFIC = {"c2": 230.8e6}
 # HBM bytes of one FP32 P_A^{-1} application (k_fdg_fwd + k_fdg_mid +
 # k_fdg_bwd), from the same counters: profiles/fd_c2_fp32_counters.md
 MEASURED_FD_TRAFFIC = {"c2": 36.98e6}
@@ -122,8 +122,9 @@ def mf_flops(prob):
     multiply-add per Gauss point and supported basis function (p + 1 of
     them): 2 products along direction 1 on 3 NB^2 lines, 3 along direction 2
     on 3 NB QB lines, 3 along direction 3 on 3 QB^2 lines, forward and
-    transposed -- plus 238 flops per Gauss point for the Jacobian of the
-    trilinear map, its inverse, the stress and the flux."""
+    transposed -- plus 196 flops per Gauss point for the Jacobian of the
+    trilinear map, its adjugate and determinant, the reciprocal of |det J|,
+    the scaled stress and the flux."""
     if isinstance(prob, list):
         return sum(mf_flops(q) for q in prob)
     total = 0
@@ -135,7 +136,7 @@ def mf_flops(prob):
         for e in pd["n_el"]:
             nb *= -(-e // BE)
         fma = 3 * QB * (p + 1) * (2 * NB * NB + 3 * NB * QB + 3 * QB * QB)
-        total += nb * (2 * 2 * fma + 238 * QB ** 3)
+        total += nb * (2 * 2 * fma + 196 * QB ** 3)
     return total
 
 
