@@ -13,7 +13,8 @@
  * on faces marked AFIETI_FACE_DIRICHLET (homogeneous, or from a callback),
  * natural conditions elsewhere.  Interfaces (Section 2.2) are the pairs of
  * patch faces whose corners coincide, or the pairs listed explicitly;
- * they must be conforming (equal knot vectors).
+ * they must be conforming (equal knot vectors; nested knot vectors, the
+ * non-conforming interfaces of Section 2.2, give AFIETI_EUNSUPPORTED).
  *
  * Vector layouts (all double precision, device memory, caller owned):
  *   DOF vector   patch-stacked (Section 4): for each problem, for each
@@ -55,7 +56,9 @@ extern "C" {
 #define AFIETI_EBREAKDOWN (-4)   /* MINRES gamma^2 < 0: preconditioner not SPD */
 #define AFIETI_ENOMEM (-5)
 #define AFIETI_EHIP (-6)         /* a HIP runtime call failed                */
-#define AFIETI_EUNSUPPORTED (-7)
+#define AFIETI_EUNSUPPORTED (-7)   /* valid input the library does not build:
+                                    non-conforming (nested) interfaces, FD
+                                    tiles beyond the device limit, ...       */
 
 #define AFIETI_FACE_FREE 0       /* natural condition or interface (auto)    */
 #define AFIETI_FACE_DIRICHLET 1  /* Dirichlet u = g_D (g_D = 0 without the

@@ -18,6 +18,9 @@ Modules
             scalings (Section 5.2.3, Remark 1)
   exact     the exact local solvers: sparse factorisations of A + D_H M and
             Dirichlet Schur complements (Section 5.1, Remark 1)
+  nonconforming  knot insertion and the gluing rows of non-conforming
+            nested interfaces (Section 2.2, the non-conforming test of
+            Section 6)
   direct    the conforming Galerkin solve the method must reproduce (Section 3)
   adjoint   gradients of a scalar of the displacement w.r.t. load amplitudes
             and per-patch Lame parameters (not in the paper; follows from the

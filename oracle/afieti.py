@@ -123,14 +123,35 @@ class AFIETI:
         face map); with an explicit interface list, only copies on the two
         faces of a listed pair are identified (directly, or through other
         listed pairs)."""
+        # non-conforming (nested) interfaces: the finer side's face
+        # coefficients are glued to the coarse trace by rows of their own
+        # (_build_B), not identified with other copies; on the Dirichlet
+        # boundary too, so that the trace is continuous there as well
+        from .nonconforming import find_interfaces
+        self.nonconforming = find_interfaces(self, self.interfaces)
+        glued = set()
+        for nc in self.nonconforming:
+            for i in nc["snodes"]:
+                glued.add((nc["slave"], int(i)))
         recs = []  # (patch, local node, coords)
         for k, pa in enumerate(self.patches):
             gm = pa.gamma_mask().reshape(-1)
             nodes = np.nonzero(gm)[0]
             X = pa.ctrl.reshape(-1, self.dim)[nodes]
             for i, x in zip(nodes, X):
-                recs.append((k, int(i), x))
+                if (k, int(i)) not in glued:
+                    recs.append((k, int(i), x))
         pts = np.array([r[2] for r in recs])
+        if glued:
+            tree = cKDTree(pts)
+            masters = {nc["slave"]: set() for nc in self.nonconforming}
+            for nc in self.nonconforming:
+                masters[nc["slave"]].add(nc["master"])
+            for (k, i) in glued:
+                x = self.patches[k].ctrl.reshape(-1, self.dim)[i]
+                for j in tree.query_ball_point(x, 1e-9):
+                    if recs[j][0] != k and recs[j][0] not in masters[k]:
+                        raise NotImplementedError("a non-conforming face coefficient is shared with a third patch")
         parent = list(range(len(recs)))
 
         def find(a):
@@ -152,7 +173,10 @@ class AFIETI:
             # only across the listed face pairs: each control point of one
             # face coincides with one of the other face (conforming faces)
             rec_of = {(k, i): j for j, (k, i, _) in enumerate(recs)}
+            ncpairs = {(nc["slave"], nc["sface"]) for nc in self.nonconforming}
             for ka, fa, kb, fb, _orient in self.interfaces:
+                if (ka, fa) in ncpairs or (kb, fb) in ncpairs:
+                    continue
                 ia = self.patches[ka].face_nodes(fa)
                 ib = self.patches[kb].face_nodes(fb)
                 ja = [rec_of[(ka, int(i))] for i in ia]
@@ -213,6 +237,19 @@ class AFIETI:
                         cols += [self.dof(k1, c, i1), self.dof(k, c, i)]
                         vals += [1.0, -1.0]
                         r += 1
+            # non-conforming interfaces: u_f(i) - sum_j T_ij u_c(j) = 0 for
+            # every coefficient of the finer face
+            for nc in self.nonconforming:
+                ks, km = nc["slave"], nc["master"]
+                for a, i in enumerate(nc["snodes"]):
+                    rows.append(r)
+                    cols.append(self.dof(ks, c, int(i)))
+                    vals.append(1.0)
+                    for b in np.nonzero(np.abs(nc["T"][a]) > 0)[0]:
+                        rows.append(r)
+                        cols.append(self.dof(km, c, int(nc["mnodes"][b])))
+                        vals.append(-float(nc["T"][a, b]))
+                    r += 1
         self.n_c = r
         self._dir_rows = dir_rows
         self.B = sp.csr_matrix((vals, (rows, cols)), shape=(r, self.n_dof))

@@ -8,7 +8,10 @@ Z maps the conforming unknowns (one per geometric node and component, nodes
 on the Dirichlet boundary removed) to their patch copies; A_c = Z^T A Z,
 f_c = Z^T f, u = Z A_c^{-1} f_c.
 
-Pinned by: the patch test and polynomial reproduction (tests/test_oracle_solve.py).
+Pinned by: the patch test and polynomial reproduction (tests/test_oracle_solve.py);
+``solve_kkt`` (any gluing matrix, e.g. non-conforming interfaces) by the
+same patch test and by agreement with ``solve_conforming`` on conforming
+problems (tests/test_oracle_nonconforming.py).
 """
 from __future__ import annotations
 
@@ -59,3 +62,19 @@ def solve_conforming(sysm, f=None):
     Ac = (Z.T @ A @ Z).tocsc()
     uc = spla.spsolve(Ac, Z.T @ (f - A @ sysm.u_dir))
     return Z @ uc + sysm.u_dir
+
+
+def solve_kkt(sysm, f=None):
+    """The constrained Galerkin problem in saddle form, [A B^T; B 0]
+    [u; lam] = [f; c], solved directly with the assembled patch matrices:
+    the definition of the discrete solution for any gluing B (conforming
+    classes and non-conforming interface rows alike; ker A and ker B meet
+    only in zero, Section 4)."""
+    if not sysm.assembled:
+        raise ValueError("direct solve needs assembled patch matrices")
+    f = sysm.load() if f is None else f
+    A = sp.block_diag(sysm.A, format="csr")
+    K = sp.bmat([[A, sysm.B.T], [sysm.B, None]], format="csc")
+    rhs = np.concatenate([f, sysm.c])
+    sol = spla.spsolve(K, rhs)
+    return sol[:sysm.n_dof]

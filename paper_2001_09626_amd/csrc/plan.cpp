@@ -875,7 +875,25 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
                 bool same = A.p == B.p && ka_.size() == kb_.size();
                 for (size_t i = 0; same && i < ka_.size(); ++i)
                     same = std::fabs(ka_[i] - (flip[j] ? 1.0 - kb_[kb_.size() - 1 - i] : kb_[i])) <= 1e-12;
-                if (!same) fail(AFIETI_EGEOM, "non-conforming interface");
+                if (!same) {
+                    // nested knot vectors (one side refines the other) make a
+                    // valid non-conforming interface (Section 2.2) that this
+                    // library does not glue
+                    std::vector<double> kbo(kb_.size());
+                    for (size_t i = 0; i < kb_.size(); ++i) kbo[i] = flip[j] ? 1.0 - kb_[kb_.size() - 1 - i] : kb_[i];
+                    auto nested = [](const std::vector<double>& c, const std::vector<double>& f) {
+                        size_t i = 0;
+                        for (double t : c) {
+                            while (i < f.size() && f[i] < t - 1e-12) ++i;
+                            if (i == f.size() || std::fabs(f[i] - t) > 1e-12) return false;
+                            ++i;
+                        }
+                        return true;
+                    };
+                    if (A.p == B.p && (nested(ka_, kbo) || nested(kbo, ka_)))
+                        fail(AFIETI_EUNSUPPORTED, "non-conforming (nested) interface: only conforming interfaces are glued");
+                    fail(AFIETI_EGEOM, "non-conforming interface");
+                }
             }
             if (orient >= 0 && orient != swap + 2 * flip[0] + 4 * flip[1])
                 fail(AFIETI_EGEOM, "interface orientation does not match the corners");

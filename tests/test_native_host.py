@@ -107,6 +107,10 @@ def test_error_codes():
     prob = W.make_c1(n_el=3)
     prob["patches"][1]["n_el"] = [4, 3]
     _expect_error(prob, -2)
+    # nested knot vectors on a shared face (a non-conforming interface of the
+    # paper's kind): valid, not glued by the library
+    _expect_error(W.make_nonconforming(p=2, n_els=(1, 2, 4), dim=2), -7)
+    _expect_error(W.make_nonconforming(p=2, n_els=(1, 2, 4), dim=3), -7)
     # too many basis functions for the device FD tiles
     prob = W.make_c1(n_el=60, p=2)
     _expect_error(prob, -7)

@@ -296,6 +296,41 @@ def make_rotated_pair(dim):
     return dict(dim=dim, patches=pats, load=load, tol=1e-8), (0, 1, 1, face_b), (2 if dim == 2 else 3)
 
 
+def make_nonconforming(p=3, n_els=(4, 8, 16), dim=3):
+    """The paper's non-conforming test (Section 6, Table 1): the box
+    (0,1) x (0,3) x (0,1) in three unit cubes stacked along y with n_els[k]
+    elements per direction in cube k (4, 8, 16: each interface nested, the
+    finer side refining the coarser by two), p C^{p-1}, E = 1, nu = 0.3, the
+    exact solution u* = (cos x, z sin y, (x y z)^2): Dirichlet data u* on the
+    whole outer boundary, body force -div sigma(u*).  ``dim`` = 2: the
+    rectangle (0,1) x (0,3) in three unit squares, u* = (cos x, sin y)."""
+    lam, mu = STEEL_LAM, STEEL_MU
+    patches = []
+    for k, ne in enumerate(n_els):
+        cs = np.zeros((2 ** dim, dim))
+        for c in range(2 ** dim):
+            a = [(c >> d) & 1 for d in range(dim)]
+            cs[c] = a
+            cs[c, 1] += k
+        bc = [FACE_DIRICHLET] * (2 * dim)
+        if k > 0:
+            bc[2] = FACE_FREE
+        if k < len(n_els) - 1:
+            bc[3] = FACE_FREE
+        patches.append(dict(corners=cs, p=int(p), reg=int(p - 1), n_el=[int(ne)] * dim,
+                            lam=lam, mu=mu, bc=bc))
+    if dim == 3:
+        sol = weak_scaling_solution
+        force = lambda x: weak_scaling_force(x, lam, mu)  # noqa: E731
+    else:
+        sol = lambda x: np.stack([np.cos(x[:, 0]), np.sin(x[:, 1])], axis=1)  # noqa: E731
+        # -div sigma for u = (cos x, sin y): sigma = diag(mu 2 u1' + lam div, mu 2 u2' + lam div)
+        force = lambda x: np.stack([(2 * mu + lam) * np.cos(x[:, 0]),  # noqa: E731
+                                    (2 * mu + lam) * np.sin(x[:, 1])], axis=1)
+    return dict(name=f"nonconforming_p{p}", dim=dim, patches=patches, load=[], tol=1e-8,
+                body_force=force, dirichlet=sol, exact=sol)
+
+
 def make_weak_scaling(k=2, n_el=8, p=3):
     """Weak-scaling workload of the paper's third test (Section 6): the unit
     cube split into k^3 equal cubes, p = 3 C^2, n_el^3 elements per patch,
