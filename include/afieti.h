@@ -361,7 +361,10 @@ int afieti_set_parameters(afieti_handle* h, const double* lame, const double* am
 int afieti_apply(afieti_handle* h, int op, const double* x, double* y, void* stream);
 
 /* Host copies of setup data, for checking (valid also with host_only):
- *  what = 0: B as triples, buf = [row, dof_plus, dof_minus(-1 if none)] x n_c int64
+ *  what = 0: B as triples, buf = [row, dof_plus, dof_minus] x n_c int64:
+ *            dof_minus -1 for a Dirichlet row (entry +1 on dof_plus), -2 - g
+ *            for the gluing row g of a non-conforming interface (entries
+ *            listed by what = 9)
  *  what = 1: eigenvalues D of every patch and direction, concatenated (double)
  *  what = 2: diameters H^(k) (double, one per patch)
  *  what = 3: G^T G of problem 0, row major (double)
@@ -374,7 +377,11 @@ int afieti_apply(afieti_handle* h, int op, const double* x, double* y, void* str
  *  what = 7: with AFIETI_PRECOND_GEO: D_A^{-1/2} per DOF (n_dof), then
  *            D_S^{1/2} per DOF (n_dof), DOF-ordered
  *  what = 8: with AFIETI_PRECOND_GEO: eigenvalues of the weighted pencils
- *            per patch, component and direction, concatenated           */
+ *            per patch, component and direction, concatenated
+ *  what = 9: the weighted entries of the gluing rows of non-conforming
+ *            interfaces (Section 2.2): [row, dof, value] per entry (double),
+ *            in row order; the row has +1 on its dof_plus and these
+ *            values (minus the coarse trace's knot-insertion weights)     */
 int afieti_export(const afieti_handle* h, int what, void* buf, int64_t buf_bytes);
 int64_t afieti_export_size(const afieti_handle* h, int what);
 

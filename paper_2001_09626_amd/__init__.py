@@ -310,6 +310,8 @@ class Solver:
             return buf.reshape(-1, 3)
         if what == "geo_scale":
             return buf.reshape(2, -1)
+        if what == "glue":
+            return buf.reshape(-1, 3)
         if what == "GtG":
             m = int(round(np.sqrt(len(buf))))
             return buf.reshape(m, m)

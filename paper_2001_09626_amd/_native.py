@@ -24,7 +24,7 @@ OPS = {"stiffness": 0, "B": 1, "Bt": 2, "P_u": 3, "P_chi": 4, "Shat": 5, "P_S": 
        "dirichlet_lift": 13}
 
 EXPORT = {"B": 0, "eig": 1, "H": 2, "GtG": 3, "fixed_load": 4, "dirichlet_c": 5, "eigvec": 6,
-          "geo_scale": 7, "geo_eig": 8}
+          "geo_scale": 7, "geo_eig": 8, "glue": 9}
 
 
 class Patch(C.Structure):

@@ -128,6 +128,8 @@ struct afieti_handle {
     // constraints
     int64_t *d_cplus = nullptr, *d_cminus = nullptr;
     int *d_bstart = nullptr, *d_bsize = nullptr, *d_bdir = nullptr;
+    GlueRows glue;      // weighted rows of non-conforming interfaces
+    DenseBlocks dense;  // their dense blocks of B B^T
     int *d_ppl = nullptr, *d_pmi = nullptr;
     double *d_gpl = nullptr, *d_gmi = nullptr;
     int64_t* d_btptr = nullptr;
@@ -691,9 +693,11 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     h->d_geo = h->dalloc<double>(geo_max);
     h->d_load = h->dalloc<double>(pl.n_dof);
     {
-        // loads of the callbacks, and the Dirichlet lift: B B^T is the
-        // identity on a Dirichlet row's block, so u_D = B^T c puts each
-        // row's value c_r on its DOF
+        // loads of the callbacks, and the Dirichlet lift u_D = B^T (B B^T)^{-1} c:
+        // B B^T is the identity on a Dirichlet row's own block, so each such
+        // row puts its value c_r on its DOF; a Dirichlet row inside a dense
+        // block (coupled to a non-conforming interface) goes through the
+        // block's inverse and B^T
         bool fixed = false;
         for (const auto& pr : pl.probs) fixed |= !pr.fixed_load.empty();
         if (fixed) {
@@ -705,7 +709,23 @@ void device_setup(afieti_handle* h, hipStream_t s) {
         if (!pl.c_rhs.empty()) {
             std::vector<double> ud(pl.n_dof, 0.0);
             for (int64_t r = 0; r < pl.n_c; ++r)
-                if (pl.c_minus[r] < 0) ud[pl.c_plus[r]] = pl.c_rhs[r];
+                if (pl.c_minus[r] == -1 && pl.c_blk_dir[r] == 1) ud[pl.c_plus[r]] = pl.c_rhs[r];
+            for (size_t b = 0; b + 1 < pl.dblk_ptr.size(); ++b) {
+                const int64_t b0 = pl.dblk_ptr[b];
+                const int n = (int)(pl.dblk_ptr[b + 1] - b0);
+                const double* M = &pl.dblk_mat[pl.dblk_moff[b]];
+                for (int a = 0; a < n; ++a) {
+                    double y = 0.0;
+                    for (int c = 0; c < n; ++c) y += M[(int64_t)a * n + c] * pl.c_rhs[pl.dblk_rows[b0 + c]];
+                    const int64_t r = pl.dblk_rows[b0 + a];
+                    ud[pl.c_plus[r]] += y;
+                    if (pl.c_minus[r] <= -2) {
+                        const int64_t g = -2 - pl.c_minus[r];
+                        for (int64_t e = pl.glue_ptr[g]; e < pl.glue_ptr[g + 1]; ++e)
+                            ud[pl.glue_col[e]] -= pl.glue_val[e] * y;
+                    }
+                }
+            }
             h->d_udir = h->upload(ud, s);
         }
     }
@@ -892,6 +912,22 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     h->d_bstart = h->upload(pl.c_blk_start, s);
     h->d_bsize = h->upload(pl.c_blk_size, s);
     h->d_bdir = h->upload(pl.c_blk_dir, s);
+    if (!pl.glue_col.empty()) {
+        h->glue.ptr = h->upload(pl.glue_ptr, s);
+        h->glue.col = h->upload(pl.glue_col, s);
+        h->glue.val = h->upload(pl.glue_val, s);
+    }
+    if (pl.dblk_ptr.size() > 1) {
+        h->dense.n = (int)pl.dblk_ptr.size() - 1;
+        for (int b = 0; b < h->dense.n; ++b)
+            h->dense.max_size = std::max(h->dense.max_size, (int)(pl.dblk_ptr[b + 1] - pl.dblk_ptr[b]));
+        if (h->dense.max_size > 8192)
+            throw SetupError{AFIETI_EUNSUPPORTED, "a non-conforming interface with more than 8192 gluing rows"};
+        h->dense.ptr = h->upload(pl.dblk_ptr, s);
+        h->dense.rows = h->upload(pl.dblk_rows, s);
+        h->dense.moff = h->upload(pl.dblk_moff, s);
+        h->dense.mat = h->upload(pl.dblk_mat, s);
+    }
     h->d_ppl = h->upload(pl.c_patch_plus, s);
     h->d_pmi = h->upload(pl.c_patch_minus, s);
     h->d_gpl = h->upload(pl.g_plus, s);
@@ -1166,7 +1202,7 @@ void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipS
     if (stage == 1) {
         const double* a = y;
         if (nr) {
-            launch_W(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, y, h->c1, s);
+            launch_W(h->d_bstart, h->d_bsize, h->d_bdir, h->dense, h->n_c, y, h->c1, s);
             a = h->c1;
         }
         // (D_S^{1/2} applied as B^T writes, with geometry inclusion)
@@ -1178,9 +1214,9 @@ void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipS
         if (stage == 3) op_ahat(h, h->tv, h->tt, 1, s, false, true);  // B reads only the Gamma part
         // (D_S^{1/2} applied as B reads, with geometry inclusion)
         if (nr) {
-            launch_BW(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->d_cplus, h->d_cminus, h->tt, out, s, h->d_geo_ds);
+            launch_BW(h->d_bstart, h->d_bsize, h->d_bdir, h->dense, h->n_c, h->d_cplus, h->d_cminus, h->glue, h->tt, out, s, h->d_geo_ds);
         } else {
-            launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, h->tt, out, s, h->d_geo_ds);
+            launch_B(h->d_cplus, h->d_cminus, h->glue, h->n_c, 1.0, h->tt, out, s, h->d_geo_ds);
         }
     }
 }
@@ -1207,7 +1243,7 @@ void op_prec_branches(afieti_handle* h, const double* r, double* z, hipStream_t 
     op_pu(h, r, h->s1, s);
     if (nr) {
         const Lane& L = h->lane[b.ln];
-        launch_GW(h->d_bstart, h->d_bsize, h->d_bdir, h->n_c, h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, L.zc,
+        launch_GW(h->d_bstart, h->d_bsize, h->d_bdir, h->dense, h->n_c, h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, L.zc,
                   r + h->n_dof, h->c1, b.s);
         launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, h->c1, h->tv, b.s, h->d_geo_ds);
         op_ahat(h, h->tv, h->tt, 0, b.s, true);
@@ -1236,7 +1272,7 @@ void op_prec(afieti_handle* h, const double* r, double* z, hipStream_t s) {
 // the multiplier part of the saddle operator: c5 = P_chi chi, y_chi = P_chi B w
 void op_saddle_side(afieti_handle* h, const double* x, double* y, hipStream_t s, int ln) {
     op_pchi(h, x + h->n_dof, h->c5, s, ln);
-    launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, x, h->c6, s);
+    launch_B(h->d_cplus, h->d_cminus, h->glue, h->n_c, 1.0, x, h->c6, s);
     op_pchi(h, h->c6, y + h->n_dof, s, ln);
 }
 
@@ -1481,7 +1517,7 @@ int solve_impl(afieti_handle* h, const double* f, double* u, double* lambda, afi
     int code = run_minres(h, s, st);
     // recovery: u = w - R (G^T G)^{-1} G^T B w,  lambda = lambda_0 + chi
     const double* w = h->vec[8];
-    launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, w, h->c1, s);
+    launch_B(h->d_cplus, h->d_cminus, h->glue, h->n_c, 1.0, w, h->c1, s);
     launch_gamma_partial(h->d_gam_chunks, h->n_gam_chunks, h->d_mc_row, h->d_mc_val, h->n_mc, h->c1, h->d_part, s);
     launch_coarse_finalize(h->d_pr_p0, h->d_pr_np, h->d_pr_nm, h->d_pr_coff, h->n_probs, h->d_gam_cptr, h->d_part,
                            h->d_cinv, h->d_zc, h->max_nc, s);
@@ -1674,7 +1710,7 @@ int afieti_apply(afieti_handle* h, int op, const double* x, double* y, void* str
     try {
         switch (op) {
             case AFIETI_OP_STIFFNESS: op_stiffness(h, x, y, nullptr, s); break;
-            case AFIETI_OP_B: launch_B(h->d_cplus, h->d_cminus, h->n_c, 1.0, x, y, s); break;
+            case AFIETI_OP_B: launch_B(h->d_cplus, h->d_cminus, h->glue, h->n_c, 1.0, x, y, s); break;
             case AFIETI_OP_BT: launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, x, y, s); break;
             case AFIETI_OP_P_U: op_pu(h, x, y, s); break;
             case AFIETI_OP_P_CHI: op_pchi(h, x, y, s); break;
@@ -1899,6 +1935,7 @@ int64_t afieti_export_size(const afieti_handle* h, int what) {
         case 7:
             if (h->opt.precond != AFIETI_PRECOND_GEO) return -1;
             return 2 * pl.n_dof * (int64_t)sizeof(double);
+        case 9: return 3 * (int64_t)pl.glue_col.size() * (int64_t)sizeof(double);
         case 8: {
             if (h->opt.precond != AFIETI_PRECOND_GEO) return -1;
             int64_t n = 0;
@@ -1940,6 +1977,17 @@ int afieti_export(const afieti_handle* h, int what, void* buf, int64_t buf_bytes
         for (const auto& P : pl.patches) {
             std::copy(P.geo_da.begin(), P.geo_da.end(), o + P.dof_off);
             std::copy(P.geo_ds.begin(), P.geo_ds.end(), o + pl.n_dof + P.dof_off);
+        }
+    } else if (what == 9) {
+        double* o = static_cast<double*>(buf);
+        for (int64_t r = 0; r < pl.n_c; ++r) {
+            if (pl.c_minus[r] > -2) continue;
+            const int64_t g = -2 - pl.c_minus[r];
+            for (int64_t e = pl.glue_ptr[g]; e < pl.glue_ptr[g + 1]; ++e) {
+                *o++ = (double)r;
+                *o++ = (double)pl.glue_col[e];
+                *o++ = -pl.glue_val[e];
+            }
         }
     } else if (what == 8) {
         double* o = static_cast<double*>(buf);

@@ -106,16 +106,35 @@ void launch_mf_gather(int p, const DevPatch* dp, const int4* rb, int nrb, const 
 int mf_brick_elems(int p);
 // doubles per (direction, brick) table of the matrix-free kernel for degree p
 int mf_table_doubles(int p);
-// y[r] = alpha (x[plus] - x[minus]); with in_scale (may be NULL) x is read
-// as in_scale .* x
-void launch_B(const int64_t* plus, const int64_t* minus, int64_t n_c, double alpha,
+// Rows of B that glue a non-conforming interface: a row r with
+// minus[r] <= -2 reads x[plus] - sum_e val[e] x[col[e]] over e in
+// [ptr[g], ptr[g + 1]), g = -2 - minus[r] (empty when there are none).
+struct GlueRows {
+    const int64_t* ptr = nullptr;
+    const int64_t* col = nullptr;
+    const double* val = nullptr;
+};
+// Dense blocks of B B^T (rows whose block kind is 2): block b holds the rows
+// rows[ptr[b] .. ptr[b + 1]) and its inverse, row major, at mat + moff[b];
+// max_size is the largest block.
+struct DenseBlocks {
+    int n = 0, max_size = 0;
+    const int64_t* ptr = nullptr;
+    const int* rows = nullptr;
+    const int64_t* moff = nullptr;
+    const double* mat = nullptr;
+};
+// y[r] = alpha (x[plus] - x[minus]) (Dirichlet rows: alpha x[plus]; gluing
+// rows as GlueRows); with in_scale (may be NULL) x is read as in_scale .* x
+void launch_B(const int64_t* plus, const int64_t* minus, const GlueRows& glue, int64_t n_c, double alpha,
               const double* x, double* y, hipStream_t s, const double* in_scale = nullptr);
 // y[i] = sum sign * x[row] for every DOF; with out_scale (may be NULL)
 // y[i] = out_scale[i] * (that sum)
 void launch_Bt(const int64_t* bt_ptr, const int* bt_row, const double* bt_sign, int64_t n_dof,
                const double* x, double* y, hipStream_t s, const double* out_scale = nullptr);
-// z = (B B^T)^{-1} y (node blocks)
-void launch_W(const int* blk_start, const int* blk_size, const int* blk_dir, int64_t n_c,
+// z = (B B^T)^{-1} y (node blocks, and the dense blocks of the
+// non-conforming interfaces)
+void launch_W(const int* blk_start, const int* blk_size, const int* blk_dir, const DenseBlocks& dense, int64_t n_c,
               const double* y, double* z, hipStream_t s);
 // y = scale_k * A-hat x per patch and component for the patches of degree p
 // (banded Kronecker form, sum-factorised, one workgroup per slab).  slabs:
@@ -129,11 +148,12 @@ void launch_ahat(int p, const DevPatch* dp, const int4* slabs, int n_slabs, int 
                  const MinresState* mask, hipStream_t s);
 // z = (B B^T)^{-1} (B x), and z = (B B^T)^{-1} (y - G zc), with the B and the
 // G rows computed inside the block solve
-void launch_BW(const int* blk_start, const int* blk_size, const int* blk_dir, int64_t n_c, const int64_t* plus,
-               const int64_t* minus, const double* x, double* z, hipStream_t s, const double* in_scale = nullptr);
-void launch_GW(const int* blk_start, const int* blk_size, const int* blk_dir, int64_t n_c, const int* patch_plus,
-               const int* patch_minus, const double* g_plus, const double* g_minus, const double* zc,
-               const double* y, double* z, hipStream_t s);
+void launch_BW(const int* blk_start, const int* blk_size, const int* blk_dir, const DenseBlocks& dense, int64_t n_c,
+               const int64_t* plus, const int64_t* minus, const GlueRows& glue, const double* x, double* z,
+               hipStream_t s, const double* in_scale = nullptr);
+void launch_GW(const int* blk_start, const int* blk_size, const int* blk_dir, const DenseBlocks& dense, int64_t n_c,
+               const int* patch_plus, const int* patch_minus, const double* g_plus, const double* g_minus,
+               const double* zc, const double* y, double* z, hipStream_t s);
 // partial sums of R^T x over patch DOF chunks (nm values per chunk)
 void launch_rigid_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks,
                           const double* ctrl, const double* x, double* partials, hipStream_t s);

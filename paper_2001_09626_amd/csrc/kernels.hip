@@ -1264,12 +1264,23 @@ __device__ inline double scaled(const double* __restrict__ x, const double* __re
     return sc ? x[i] * sc[i] : x[i];
 }
 
-__global__ void k_B(const int64_t* __restrict__ plus, const int64_t* __restrict__ minus, int64_t n_c, double alpha,
-                    const double* __restrict__ x, double* __restrict__ y, const double* __restrict__ sc) {
+// value of row r of B applied to x (read as sc .* x with a scale)
+__device__ inline double b_row(const int64_t* __restrict__ plus, const int64_t* __restrict__ minus,
+                               const GlueRows& gl, const double* __restrict__ x, const double* __restrict__ sc,
+                               int64_t r) {
+    const int64_t m = minus[r];
+    if (m >= -1) return scaled(x, sc, plus[r]) - (m >= 0 ? scaled(x, sc, m) : 0.0);
+    const int64_t g = -2 - m;
+    double v = scaled(x, sc, plus[r]);
+    for (int64_t e = gl.ptr[g]; e < gl.ptr[g + 1]; ++e) v -= gl.val[e] * scaled(x, sc, gl.col[e]);
+    return v;
+}
+
+__global__ void k_B(const int64_t* __restrict__ plus, const int64_t* __restrict__ minus, GlueRows gl, int64_t n_c,
+                    double alpha, const double* __restrict__ x, double* __restrict__ y, const double* __restrict__ sc) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_c) return;
-    const int64_t m = minus[r];
-    y[r] = alpha * (scaled(x, sc, plus[r]) - (m >= 0 ? scaled(x, sc, m) : 0.0));
+    y[r] = alpha * b_row(plus, minus, gl, x, sc, r);
 }
 
 __global__ void k_Bt(const int64_t* __restrict__ ptr, const int* __restrict__ row, const double* __restrict__ sgn,
@@ -1281,61 +1292,90 @@ __global__ void k_Bt(const int64_t* __restrict__ ptr, const int* __restrict__ ro
     y[i] = sc ? sc[i] * acc : acc;
 }
 
-// (B B^T)^{-1} per node block.  Star block of size s: I + 1 1^T, whose
-// inverse is I - 1 1^T / (s + 1).  Dirichlet block: identity.
-__global__ void k_W(const int* __restrict__ bs, const int* __restrict__ bn, const int* __restrict__ bd, int64_t n_c,
-                    const double* __restrict__ y, double* __restrict__ z) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_c) return;
-    if (bd[r]) {
-        z[r] = y[r];
-        return;
-    }
-    const int s0 = bs[r], sz = bn[r];
-    double sum = 0.0;
-    for (int j = 0; j < sz; ++j) sum += y[s0 + j];
-    z[r] = y[r] - sum / (sz + 1);
-}
-
-// The same block solve applied to values computed row by row on the fly:
-// z = (B B^T)^{-1} (B x) (k_BW) and z = (B B^T)^{-1} (y - G zc) (k_GW); the
-// arithmetic of every row value equals k_B / k_G_apply.
+// (B B^T)^{-1} row by row, for values computed per row on the fly: star
+// block of size s: I + 1 1^T, whose inverse is I - 1 1^T / (s + 1);
+// Dirichlet block: identity; rows of dense blocks are left to k_w_dense.
+// z = (B B^T)^{-1} y (k_W), (B B^T)^{-1} (B x) (k_BW), (B B^T)^{-1} (y - G zc)
+// (k_GW); the arithmetic of every row value equals k_B / k_G_apply.
 template <typename RowValue>
-__device__ inline void w_rows(const int* __restrict__ bs, const int* __restrict__ bn, const int* __restrict__ bd,
-                              int64_t n_c, double* __restrict__ z, RowValue val) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_c) return;
-    if (bd[r]) {
+__device__ inline void w_row(const int* __restrict__ bs, const int* __restrict__ bn, const int* __restrict__ bd,
+                             int64_t r, double* __restrict__ z, const RowValue& val) {
+    const int kind = bd[r];
+    if (kind == 1) {
         z[r] = val(r);
         return;
     }
+    if (kind == 2) return;
     const int s0 = bs[r], sz = bn[r];
     double sum = 0.0;
     for (int j = 0; j < sz; ++j) sum += val(s0 + j);
     z[r] = val(r) - sum / (sz + 1);
 }
 
-__global__ void k_BW(const int* __restrict__ bs, const int* __restrict__ bn, const int* __restrict__ bd, int64_t n_c,
-                     const int64_t* __restrict__ plus, const int64_t* __restrict__ minus, const double* __restrict__ x,
-                     double* __restrict__ z, const double* __restrict__ sc) {
-    w_rows(bs, bn, bd, n_c, z, [&](int64_t q) {
-        const int64_t m = minus[q];
-        return 1.0 * (scaled(x, sc, plus[q]) - (m >= 0 ? scaled(x, sc, m) : 0.0));
-    });
-}
+struct PlainVal {
+    const double* y;
+    __device__ double operator()(int64_t q) const { return y[q]; }
+};
 
-__global__ void k_GW(const int* __restrict__ bs, const int* __restrict__ bn, const int* __restrict__ bd, int64_t n_c,
-                     const int* __restrict__ pp, const int* __restrict__ pm, const double* __restrict__ gp,
-                     const double* __restrict__ gm, const double* __restrict__ zc, const double* __restrict__ y,
-                     double* __restrict__ z) {
-    w_rows(bs, bn, bd, n_c, z, [&](int64_t q) {
+struct BVal {
+    const int64_t* plus;
+    const int64_t* minus;
+    GlueRows gl;
+    const double* x;
+    const double* sc;
+    __device__ double operator()(int64_t q) const { return 1.0 * b_row(plus, minus, gl, x, sc, q); }
+};
+
+struct GVal {
+    const int* pp;
+    const int* pm;
+    const double* gp;
+    const double* gm;
+    const double* zc;
+    const double* y;
+    __device__ double operator()(int64_t q) const {
         const int a = pp[q], b = pm[q];
         double s = 0.0;
         for (int m = 0; m < 6; ++m) s += gp[q * 6 + m] * zc[a * 6 + m];
         if (b >= 0)
             for (int m = 0; m < 6; ++m) s -= gm[q * 6 + m] * zc[b * 6 + m];
         return 1.0 * y[q] + -1.0 * s;
-    });
+    }
+};
+
+__global__ void k_W(const int* __restrict__ bs, const int* __restrict__ bn, const int* __restrict__ bd, int64_t n_c,
+                    double* __restrict__ z, PlainVal val) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n_c) w_row(bs, bn, bd, r, z, val);
+}
+
+__global__ void k_BW(const int* __restrict__ bs, const int* __restrict__ bn, const int* __restrict__ bd, int64_t n_c,
+                     double* __restrict__ z, BVal val) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n_c) w_row(bs, bn, bd, r, z, val);
+}
+
+__global__ void k_GW(const int* __restrict__ bs, const int* __restrict__ bn, const int* __restrict__ bd, int64_t n_c,
+                     double* __restrict__ z, GVal val) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n_c) w_row(bs, bn, bd, r, z, val);
+}
+
+// dense blocks: one workgroup per block, the block's row values in LDS,
+// then z_a = sum_b Minv[a][b] v_b in a fixed order
+template <typename RowValue>
+__global__ void __launch_bounds__(kBlock) k_w_dense(DenseBlocks db, double* __restrict__ z, RowValue val) {
+    extern __shared__ double sv[];
+    const int64_t b0 = db.ptr[blockIdx.x];
+    const int n = (int)(db.ptr[blockIdx.x + 1] - b0);
+    for (int a = threadIdx.x; a < n; a += kBlock) sv[a] = val(db.rows[b0 + a]);
+    __syncthreads();
+    const double* M = db.mat + db.moff[blockIdx.x];
+    for (int a = threadIdx.x; a < n; a += kBlock) {
+        double acc = 0.0;
+        for (int c = 0; c < n; ++c) acc += M[(int64_t)a * n + c] * sv[c];
+        z[db.rows[b0 + a]] = acc;
+    }
 }
 
 // f(integral_constant<int, dim>) for the dimension of a patch (uniform per
@@ -1920,10 +1960,11 @@ int mf_table_doubles(int p) {
     return 2 * qb * nb + 2 * qb;
 }
 
-void launch_B(const int64_t* plus, const int64_t* minus, int64_t n_c, double alpha, const double* x, double* y,
-              hipStream_t s, const double* in_scale) {
+void launch_B(const int64_t* plus, const int64_t* minus, const GlueRows& glue, int64_t n_c, double alpha,
+              const double* x, double* y, hipStream_t s, const double* in_scale) {
     if (n_c)
-        hipLaunchKernelGGL(k_B, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, plus, minus, n_c, alpha, x, y, in_scale);
+        hipLaunchKernelGGL(k_B, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, plus, minus, glue, n_c, alpha, x, y,
+                           in_scale);
 }
 
 void launch_Bt(const int64_t* bt_ptr, const int* bt_row, const double* bt_sign, int64_t n_dof, const double* x,
@@ -1932,21 +1973,32 @@ void launch_Bt(const int64_t* bt_ptr, const int* bt_row, const double* bt_sign, 
                        out_scale);
 }
 
-void launch_W(const int* bs, const int* bn, const int* bd, int64_t n_c, const double* y, double* z, hipStream_t s) {
-    if (n_c) hipLaunchKernelGGL(k_W, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, bs, bn, bd, n_c, y, z);
+template <typename RowValue>
+void w_launch(void (*rows)(const int*, const int*, const int*, int64_t, double*, RowValue), const int* bs,
+              const int* bn, const int* bd, const DenseBlocks& db, int64_t n_c, double* z, const RowValue& val,
+              hipStream_t s) {
+    if (!n_c) return;
+    hipLaunchKernelGGL(rows, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, bs, bn, bd, n_c, z, val);
+    if (db.n)
+        hipLaunchKernelGGL(k_w_dense<RowValue>, dim3(db.n), dim3(kBlock), db.max_size * sizeof(double), s, db, z,
+                           val);
 }
 
-void launch_BW(const int* bs, const int* bn, const int* bd, int64_t n_c, const int64_t* plus, const int64_t* minus,
-               const double* x, double* z, hipStream_t s, const double* in_scale) {
-    if (n_c)
-        hipLaunchKernelGGL(k_BW, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, bs, bn, bd, n_c, plus, minus, x, z,
-                           in_scale);
+void launch_W(const int* bs, const int* bn, const int* bd, const DenseBlocks& db, int64_t n_c, const double* y,
+              double* z, hipStream_t s) {
+    w_launch(k_W, bs, bn, bd, db, n_c, z, PlainVal{y}, s);
 }
 
-void launch_GW(const int* bs, const int* bn, const int* bd, int64_t n_c, const int* pp, const int* pm,
-               const double* gp, const double* gm, const double* zc, const double* y, double* z, hipStream_t s) {
-    if (n_c)
-        hipLaunchKernelGGL(k_GW, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, bs, bn, bd, n_c, pp, pm, gp, gm, zc, y, z);
+void launch_BW(const int* bs, const int* bn, const int* bd, const DenseBlocks& db, int64_t n_c, const int64_t* plus,
+               const int64_t* minus, const GlueRows& glue, const double* x, double* z, hipStream_t s,
+               const double* in_scale) {
+    w_launch(k_BW, bs, bn, bd, db, n_c, z, BVal{plus, minus, glue, x, in_scale}, s);
+}
+
+void launch_GW(const int* bs, const int* bn, const int* bd, const DenseBlocks& db, int64_t n_c, const int* pp,
+               const int* pm, const double* gp, const double* gm, const double* zc, const double* y, double* z,
+               hipStream_t s) {
+    w_launch(k_GW, bs, bn, bd, db, n_c, z, GVal{pp, pm, gp, gm, zc, y}, s);
 }
 
 void launch_rigid_partial(const DevPatch* dp, const Chunk* chunks, int n_chunks, const double* ctrl, const double* x,

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <numeric>
 
 #include "rigid.h"
@@ -111,6 +112,26 @@ double multilinear_det(int dim, const double* corners, const double* eta) {
     multilinear_jac(dim, corners, eta, J);
     return det_of(dim, J);
 }
+
+// A non-conforming interface: face `sface` of patch `slave` refines face
+// `mface` of patch `master` (parametric directions aligned); T[j] (ns[j] x
+// nm[j], row major) takes the coarse B-splines along tangential direction
+// tang[j] to the fine ones.
+struct NcIface {
+    int slave = 0, sface = 0, master = 0, mface = 0;
+    int tang[2] = {0, -1};
+    int ns[2] = {1, 1}, nm[2] = {1, 1};
+    std::vector<double> T[2];
+    // node of the slave (fine) or master face at face position (i1, i2)
+    int64_t face_node(const PatchPlan& P, int i1, int i2, bool is_slave = false) const {
+        const int f = is_slave ? sface : mface;
+        int idx[3] = {0, 0, 0};
+        idx[f / 2] = (f % 2) ? P.n[f / 2] - 1 : 0;
+        idx[tang[0]] = i1;
+        if (tang[1] >= 0) idx[tang[1]] = i2;
+        return idx[0] + (int64_t)P.n[0] * (idx[1] + (int64_t)P.n[1] * idx[2]);
+    }
+};
 
 struct UnionFind {
     std::vector<int64_t> parent;
@@ -385,6 +406,46 @@ bool is_gamma(const PatchPlan& pp, int64_t node) {
 }  // namespace
 
 // ------------------------------------------------------------------ spline
+// Knot insertion (Boehm): the coefficients of the coarse B-splines in the
+// basis of a refined knot vector, T[i * n_c + j] with b^c_j = sum_i T_ij
+// b^f_i; the knots of `fine` missing from `coarse` are inserted one at a
+// time, each insertion mixing p consecutive coefficients with the weights
+// (t - u_i) / (u_{i+p} - u_i).  Empty if `fine` does not contain `coarse`.
+std::vector<double> knot_insertion_matrix(const std::vector<double>& coarse, const std::vector<double>& fine, int p) {
+    std::vector<double> ins;
+    size_t a = 0;
+    for (double t : fine) {
+        if (a < coarse.size() && std::fabs(coarse[a] - t) <= 1e-12) ++a;
+        else ins.push_back(t);
+    }
+    if (a != coarse.size()) return {};
+    std::vector<double> U = coarse;
+    const int nc = (int)coarse.size() - p - 1;
+    int n = nc;
+    std::vector<double> P((size_t)n * nc, 0.0);  // rows: current basis, columns: coarse functions
+    for (int j = 0; j < nc; ++j) P[(size_t)j * nc + j] = 1.0;
+    for (double t : ins) {
+        int k = p;
+        while (k + 1 < (int)U.size() - p - 1 && U[k + 1] <= t) ++k;
+        std::vector<double> Q((size_t)(n + 1) * nc, 0.0);
+        for (int i = 0; i <= n; ++i) {
+            double* q = &Q[(size_t)i * nc];
+            if (i <= k - p) {
+                for (int j = 0; j < nc; ++j) q[j] = P[(size_t)i * nc + j];
+            } else if (i <= k) {
+                const double al = (t - U[i]) / (U[i + p] - U[i]);
+                for (int j = 0; j < nc; ++j) q[j] = al * P[(size_t)i * nc + j] + (1.0 - al) * P[(size_t)(i - 1) * nc + j];
+            } else {
+                for (int j = 0; j < nc; ++j) q[j] = P[(size_t)(i - 1) * nc + j];
+            }
+        }
+        U.insert(U.begin() + k + 1, t);
+        P.swap(Q);
+        ++n;
+    }
+    return P;
+}
+
 int check_open_knots(const std::vector<double>& t, int p) {
     const int m = (int)t.size();
     if (m < 2 * (p + 1)) fail(AFIETI_EINVAL, "knot vector too short for its degree");
@@ -627,6 +688,87 @@ void patch_map(const PatchPlan& P, const double* eta, double* x, double (&J)[3][
         for (int c = 0; c < 3; ++c) x[c] = xx[c];
 }
 
+// Rows of B for the non-conforming interfaces of a problem and component
+// (Section 2.2): for every node i of the finer face, e_{f,i} - sum_j T_ij
+// e_{c,j} (the coarse trace in the fine basis), and the dense blocks of
+// B B^T they form with the Dirichlet rows of the coarse nodes they touch
+// (inverted here).  Rows of this component start at comp_start.
+void add_gluing_rows(Plan& plan, const ProblemPlan& pp, const std::vector<NcIface>& ncs, int comp, int64_t comp_start) {
+    std::map<int64_t, int64_t> dir_row;  // DOF -> its Dirichlet row (this component)
+    std::vector<char> star_dof;
+    for (int64_t r = comp_start; r < (int64_t)plan.c_plus.size(); ++r) {
+        if (plan.c_minus[r] == -1) dir_row[plan.c_plus[r]] = r;
+    }
+    std::map<int64_t, char> in_star;
+    for (int64_t r = comp_start; r < (int64_t)plan.c_plus.size(); ++r)
+        if (plan.c_minus[r] >= 0) in_star[plan.c_plus[r]] = in_star[plan.c_minus[r]] = 1;
+    for (const NcIface& nc : ncs) {
+        const PatchPlan& Ps = plan.patches[pp.patch0 + nc.slave];
+        const PatchPlan& Pm = plan.patches[pp.patch0 + nc.master];
+        std::vector<int64_t> rows;
+        std::map<int64_t, int64_t> touched;  // Dirichlet rows coupled to the gluing rows
+        for (int s2 = 0; s2 < nc.ns[1]; ++s2)
+            for (int s1 = 0; s1 < nc.ns[0]; ++s1) {
+                const int64_t r = (int64_t)plan.c_plus.size();
+                rows.push_back(r);
+                plan.c_plus.push_back(Ps.dof_off + comp * Ps.nodes + nc.face_node(Ps, s1, s2, true));
+                plan.c_minus.push_back(-2 - (int64_t)(plan.glue_ptr.size() - 1));
+                for (int t2 = 0; t2 < nc.nm[1]; ++t2)
+                    for (int t1 = 0; t1 < nc.nm[0]; ++t1) {
+                        const double w = nc.T[0][(size_t)s1 * nc.nm[0] + t1] * nc.T[1][(size_t)s2 * nc.nm[1] + t2];
+                        if (w == 0.0) continue;
+                        const int64_t d = Pm.dof_off + comp * Pm.nodes + nc.face_node(Pm, t1, t2);
+                        if (in_star.count(d))
+                            throw SetupError{AFIETI_EUNSUPPORTED,
+                                             "a coarse node of a non-conforming interface shared with a third patch"};
+                        auto it = dir_row.find(d);
+                        if (it != dir_row.end()) touched[it->second] = 1;
+                        plan.glue_col.push_back(d);
+                        plan.glue_val.push_back(w);
+                    }
+                plan.glue_ptr.push_back((int64_t)plan.glue_col.size());
+                plan.c_patch_plus.push_back(pp.patch0 + nc.slave);
+                plan.c_patch_minus.push_back(pp.patch0 + nc.master);
+                plan.c_blk_start.push_back(0);
+                plan.c_blk_size.push_back(0);
+                plan.c_blk_dir.push_back(2);
+            }
+        for (const auto& kv : touched) {
+            if (plan.c_blk_dir[kv.first] == 2)
+                throw SetupError{AFIETI_EUNSUPPORTED, "a Dirichlet node coupled to two non-conforming interfaces"};
+            rows.push_back(kv.first);
+        }
+        // B B^T on the block: rows as sparse vectors over DOFs
+        const int n = (int)rows.size();
+        std::map<int64_t, std::vector<std::pair<int, double>>> by_dof;
+        for (int a = 0; a < n; ++a) {
+            const int64_t r = rows[a];
+            by_dof[plan.c_plus[r]].push_back({a, 1.0});
+            if (plan.c_minus[r] <= -2) {
+                const int64_t g = -2 - plan.c_minus[r];
+                for (int64_t e = plan.glue_ptr[g]; e < plan.glue_ptr[g + 1]; ++e)
+                    by_dof[plan.glue_col[e]].push_back({a, -plan.glue_val[e]});
+            }
+        }
+        std::vector<double> M((size_t)n * n, 0.0);
+        for (const auto& kv : by_dof)
+            for (const auto& x : kv.second)
+                for (const auto& y : kv.second) M[(size_t)x.first * n + y.first] += x.second * y.second;
+        if (!cholesky(n, M, 1e-14)) throw SetupError{AFIETI_ESINGULAR, "B B^T of a non-conforming interface is singular"};
+        const std::vector<double> inv = chol_inverse(n, M);
+        const int blk = (int)plan.dblk_ptr.size() - 1;
+        for (int a = 0; a < n; ++a) {
+            plan.c_blk_dir[rows[a]] = 2;
+            plan.c_blk_start[rows[a]] = blk;
+            plan.c_blk_size[rows[a]] = a;
+            plan.dblk_rows.push_back((int)rows[a]);
+        }
+        plan.dblk_ptr.push_back((int64_t)plan.dblk_rows.size());
+        plan.dblk_mat.insert(plan.dblk_mat.end(), inv.begin(), inv.end());
+        plan.dblk_moff.push_back((int64_t)plan.dblk_mat.size());
+    }
+}
+
 // -------------------------------------------------------------------- plan
 Plan build_plan(const afieti_problem* probs, int n_problems) {
     if (!probs || n_problems < 1) fail(AFIETI_EINVAL, "no problems");
@@ -837,6 +979,7 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
         // glue face fa of patch ka to face fb of patch kb if their corners
         // coincide (returns false otherwise); `orient` >= 0 must equal the
         // orientation the corners give (swap + 2 flip_0 + 4 flip_1)
+        std::vector<NcIface> ncs;  // non-conforming interfaces of the problem
         auto glue = [&](int ka, int fa, int kb, int fb, int orient) -> bool {
             const PatchPlan& A = plan.patches[pp.patch0 + ka];
             const PatchPlan& B = plan.patches[pp.patch0 + kb];
@@ -861,6 +1004,7 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
             }
             // where does tangential direction j of A go in B, flipped?
             int to[2], flip[2] = {0, 0}, swap = 0;
+            bool a_finer = false, b_finer = false;  // knot vectors along the face nested
             for (int j = 0; j < dim - 1; ++j) {
                 int u0 = map[0], u1 = map[1 << j];
                 int diff = u0 ^ u1;
@@ -869,36 +1013,66 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
                 to[j] = tb[jb];
                 flip[j] = (u0 >> jb) & 1;
                 if (j == 0) swap = jb;
-                // equal knot vectors along the face (reversed where flipped)
+                // equal knot vectors along the face (reversed where flipped),
+                // or nested ones (a non-conforming interface, Section 2.2)
                 const std::vector<double>& ka_ = A.dir[ta[j]].knots;
                 const std::vector<double>& kb_ = B.dir[to[j]].knots;
                 bool same = A.p == B.p && ka_.size() == kb_.size();
                 for (size_t i = 0; same && i < ka_.size(); ++i)
                     same = std::fabs(ka_[i] - (flip[j] ? 1.0 - kb_[kb_.size() - 1 - i] : kb_[i])) <= 1e-12;
                 if (!same) {
-                    // nested knot vectors (one side refines the other) make a
-                    // valid non-conforming interface (Section 2.2) that this
-                    // library does not glue
                     std::vector<double> kbo(kb_.size());
                     for (size_t i = 0; i < kb_.size(); ++i) kbo[i] = flip[j] ? 1.0 - kb_[kb_.size() - 1 - i] : kb_[i];
-                    auto nested = [](const std::vector<double>& c, const std::vector<double>& f) {
-                        size_t i = 0;
-                        for (double t : c) {
-                            while (i < f.size() && f[i] < t - 1e-12) ++i;
-                            if (i == f.size() || std::fabs(f[i] - t) > 1e-12) return false;
-                            ++i;
-                        }
-                        return true;
-                    };
-                    if (A.p == B.p && (nested(ka_, kbo) || nested(kbo, ka_)))
-                        fail(AFIETI_EUNSUPPORTED, "non-conforming (nested) interface: only conforming interfaces are glued");
-                    fail(AFIETI_EGEOM, "non-conforming interface");
+                    if (A.p == B.p && !knot_insertion_matrix(ka_, kbo, A.p).empty()) b_finer = true;
+                    else if (A.p == B.p && !knot_insertion_matrix(kbo, ka_, A.p).empty()) a_finer = true;
+                    else fail(AFIETI_EGEOM, "non-conforming interface");
                 }
             }
             if (orient >= 0 && orient != swap + 2 * flip[0] + 4 * flip[1])
                 fail(AFIETI_EGEOM, "interface orientation does not match the corners");
             if (A.bc[fa] == AFIETI_FACE_TRACTION || B.bc[fb] == AFIETI_FACE_TRACTION)
                 fail(AFIETI_EGEOM, "a traction face is an interface");
+            if (a_finer || b_finer) {
+                // non-conforming: the finer face is glued to the coarse trace
+                // (rows of their own below); parametric directions aligned
+                if (a_finer && b_finer) fail(AFIETI_EGEOM, "non-conforming interface refined on both sides");
+                if (fa / 2 != fb / 2 || swap || flip[0] || flip[1])
+                    fail(AFIETI_EUNSUPPORTED, "non-conforming interface with differently oriented parametrisations");
+                NcIface nc;
+                nc.slave = a_finer ? ka : kb;
+                nc.sface = a_finer ? fa : fb;
+                nc.master = a_finer ? kb : ka;
+                nc.mface = a_finer ? fb : fa;
+                const PatchPlan& Ps = a_finer ? A : B;
+                const PatchPlan& Pm = a_finer ? B : A;
+                for (int j = 0; j < dim - 1; ++j) {
+                    nc.ns[j] = Ps.n[ta[j]];
+                    nc.nm[j] = Pm.n[ta[j]];
+                    nc.T[j] = knot_insertion_matrix(Pm.dir[ta[j]].knots, Ps.dir[ta[j]].knots, Ps.p);
+                }
+                if (dim == 2) nc.ns[1] = nc.nm[1] = 1, nc.T[1] = {1.0};
+                nc.tang[0] = ta[0];
+                nc.tang[1] = dim == 3 ? ta[1] : -1;
+                if (Ps.general || Pm.general) {  // the finer face net is the coarse one refined
+                    for (int s2 = 0; s2 < nc.ns[1]; ++s2)
+                        for (int s1 = 0; s1 < nc.ns[0]; ++s1) {
+                            double X[3] = {0, 0, 0};
+                            for (int t2 = 0; t2 < nc.nm[1]; ++t2)
+                                for (int t1 = 0; t1 < nc.nm[0]; ++t1) {
+                                    const double w = nc.T[0][(size_t)s1 * nc.nm[0] + t1] * nc.T[1][(size_t)s2 * nc.nm[1] + t2];
+                                    if (w == 0.0) continue;
+                                    const int64_t nd = nc.face_node(Pm, t1, t2);
+                                    for (int x = 0; x < 3; ++x) X[x] += w * Pm.ctrl[nd * 3 + x];
+                                }
+                            const int64_t nd = nc.face_node(Ps, s1, s2, true);
+                            double d2 = 0;
+                            for (int x = 0; x < 3; ++x) d2 += (X[x] - Ps.ctrl[nd * 3 + x]) * (X[x] - Ps.ctrl[nd * 3 + x]);
+                            if (std::sqrt(d2) > tol) fail(AFIETI_EGEOM, "interface control points differ");
+                        }
+                }
+                ncs.push_back(std::move(nc));
+                return true;
+            }
             // unite the face nodes
             int na1 = A.n[ta[0]], na2 = dim == 3 ? A.n[ta[1]] : 1;
             for (int s2 = 0; s2 < na2; ++s2)
@@ -947,6 +1121,26 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
                 if (!glue(ka, fa, kb, fb, orient)) fail(AFIETI_EGEOM, "listed interface faces do not coincide");
             }
         }
+        // ---- the finer faces of non-conforming interfaces: their nodes are
+        // glued to the coarse trace by rows of their own, not identified with
+        // other copies (a node shared with a third patch is not supported)
+        std::vector<char> glued(node_off.back(), 0);
+        for (const NcIface& nc : ncs) {
+            const PatchPlan& Ps = plan.patches[pp.patch0 + nc.slave];
+            for (int s2 = 0; s2 < nc.ns[1]; ++s2)
+                for (int s1 = 0; s1 < nc.ns[0]; ++s1) {
+                    const int64_t g = node_off[nc.slave] + nc.face_node(Ps, s1, s2, true);
+                    if (glued[g]) fail(AFIETI_EUNSUPPORTED, "a face node in two non-conforming interfaces");
+                    glued[g] = 1;
+                }
+        }
+        {
+            std::vector<int64_t> size(node_off.back(), 0);
+            for (int64_t g = 0; g < node_off.back(); ++g) size[uf.find(g)]++;
+            for (int64_t g = 0; g < node_off.back(); ++g)
+                if (glued[g] && size[uf.find(g)] > 1)
+                    fail(AFIETI_EUNSUPPORTED, "a non-conforming face node shared with a third patch");
+        }
         // ---- classes in (lowest patch, local index) order
         struct Copy { int k; int64_t node; };
         std::vector<std::vector<Copy>> classes;
@@ -954,7 +1148,7 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
         for (int k = 0; k < pr.n_patches; ++k) {
             const PatchPlan& P = plan.patches[pp.patch0 + k];
             for (int64_t nd = 0; nd < P.nodes; ++nd) {
-                if (!is_gamma(P, nd)) continue;
+                if (!is_gamma(P, nd) || glued[node_off[k] + nd]) continue;
                 int64_t root = uf.find(node_off[k] + nd);
                 if (class_of[root] < 0) {
                     class_of[root] = (int64_t)classes.size();
@@ -981,7 +1175,8 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
             const PatchPlan& P = plan.patches[pp.patch0 + c.k];
             return P.dof_off + comp * P.nodes + c.node;
         };
-        for (int comp = 0; comp < dim; ++comp)
+        for (int comp = 0; comp < dim; ++comp) {
+            const int64_t comp_start = (int64_t)plan.c_plus.size();
             for (size_t ci = 0; ci < classes.size(); ++ci) {
                 const auto& cp = classes[ci];
                 int r = (int)cp.size();
@@ -1009,6 +1204,8 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
                     }
                 }
             }
+            if (!ncs.empty()) add_gluing_rows(plan, pp, ncs, comp, comp_start);
+        }
         crow = (int64_t)plan.c_plus.size();
         pp.n_c = crow - pp.c_off;
         if (pp.n_c == 0) fail(AFIETI_ESINGULAR, "no constraints: the problem has no Dirichlet boundary");
@@ -1019,7 +1216,7 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
             std::vector<int64_t> rows;
             std::vector<double> pts;
             for (int64_t r = pp.c_off; r < crow; ++r) {
-                if (plan.c_minus[r] >= 0) continue;
+                if (plan.c_minus[r] != -1) continue;
                 const PatchPlan& P = plan.patches[plan.c_patch_plus[r]];
                 const int64_t loc = plan.c_plus[r] - P.dof_off;
                 const int64_t nd = loc % P.nodes;
@@ -1054,6 +1251,10 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
     for (int64_t r = 0; r < plan.n_c; ++r) {
         cnt[plan.c_plus[r] + 1]++;
         if (plan.c_minus[r] >= 0) cnt[plan.c_minus[r] + 1]++;
+        if (plan.c_minus[r] <= -2) {
+            const int64_t g = -2 - plan.c_minus[r];
+            for (int64_t e = plan.glue_ptr[g]; e < plan.glue_ptr[g + 1]; ++e) cnt[plan.glue_col[e] + 1]++;
+        }
     }
     for (int64_t i = 0; i < plan.n_dof; ++i) cnt[i + 1] += cnt[i];
     plan.bt_ptr = cnt;
@@ -1068,6 +1269,14 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
             int64_t b = fill[plan.c_minus[r]]++;
             plan.bt_row[b] = (int)r;
             plan.bt_sign[b] = -1.0;
+        }
+        if (plan.c_minus[r] <= -2) {
+            const int64_t g = -2 - plan.c_minus[r];
+            for (int64_t e = plan.glue_ptr[g]; e < plan.glue_ptr[g + 1]; ++e) {
+                int64_t b = fill[plan.glue_col[e]]++;
+                plan.bt_row[b] = (int)r;
+                plan.bt_sign[b] = -plan.glue_val[e];
+            }
         }
     }
     // ---- rigid modes: G rows, R^T R per patch, G^T G per problem
@@ -1086,6 +1295,13 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
         for (int m = 0; m < nm; ++m) {
             plan.g_plus[r * 6 + m] = dof_mode(plan.c_plus[r], kp, m);
             if (plan.c_minus[r] >= 0) plan.g_minus[r * 6 + m] = dof_mode(plan.c_minus[r], plan.c_patch_minus[r], m);
+            if (plan.c_minus[r] <= -2) {  // the coarse trace's modes: sum_j T_ij R(j)
+                const int64_t g = -2 - plan.c_minus[r];
+                double v = 0.0;
+                for (int64_t e = plan.glue_ptr[g]; e < plan.glue_ptr[g + 1]; ++e)
+                    v += plan.glue_val[e] * dof_mode(plan.glue_col[e], plan.c_patch_minus[r], m);
+                plan.g_minus[r * 6 + m] = v;
+            }
         }
     }
     plan.RtR_inv.assign(plan.patches.size() * 36, 0.0);
@@ -1111,7 +1327,7 @@ Plan build_plan(const afieti_problem* probs, int n_problems) {
         std::vector<double> C((size_t)nc * nc, 0.0);
         for (int64_t r = pp.c_off; r < pp.c_off + pp.n_c; ++r) {
             int ia = (plan.c_patch_plus[r] - pp.patch0) * nm;
-            int ib = plan.c_minus[r] >= 0 ? (plan.c_patch_minus[r] - pp.patch0) * nm : -1;
+            int ib = plan.c_patch_minus[r] >= 0 ? (plan.c_patch_minus[r] - pp.patch0) * nm : -1;
             const double* gp = &plan.g_plus[r * 6];
             const double* gm = &plan.g_minus[r * 6];
             for (int a = 0; a < nm; ++a)

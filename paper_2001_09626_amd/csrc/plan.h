@@ -82,9 +82,23 @@ struct Plan {
     std::vector<ProblemPlan> probs;
     int64_t n_dof = 0, n_c = 0;
     // constraints (global rows): B row r = e_{plus[r]} - e_{minus[r]}
-    // (minus = -1 for a Dirichlet row, whose entry is +1 on plus)
+    // (minus = -1 for a Dirichlet row, whose entry is +1 on plus; minus =
+    // -2 - g for the gluing row g of a non-conforming interface, B row
+    // e_{plus} - sum_e glue_val[e] e_{glue_col[e]} over e in
+    // [glue_ptr[g], glue_ptr[g + 1]))
     std::vector<int64_t> c_plus, c_minus;
-    std::vector<int> c_blk_start, c_blk_size, c_blk_dir;  // node block of B B^T
+    std::vector<int64_t> glue_ptr{0}, glue_col;
+    std::vector<double> glue_val;
+    // block of B B^T holding each row: dir 0 star block (start, size), 1
+    // identity (a Dirichlet row alone), 2 dense block (start = block index,
+    // size = the row's position in it)
+    std::vector<int> c_blk_start, c_blk_size, c_blk_dir;
+    // dense blocks of B B^T (non-conforming interfaces with the Dirichlet
+    // rows they couple to): rows dblk_rows[dblk_ptr[b] ..], inverse
+    // dblk_mat[dblk_moff[b] ..] row major
+    std::vector<int64_t> dblk_ptr{0}, dblk_moff{0};
+    std::vector<int> dblk_rows;
+    std::vector<double> dblk_mat;
     // B^T by DOF: CSR over all DOFs, entries (row, sign)
     std::vector<int64_t> bt_ptr;
     std::vector<int> bt_row;
@@ -112,6 +126,9 @@ std::vector<double> open_uniform_knots(int n_el, int p, int reg);
 // checks an explicit open knot vector of degree p on [0, 1]; returns the
 // smallest continuity p - (largest interior multiplicity)
 int check_open_knots(const std::vector<double>& t, int p);
+// coarse B-splines in the basis of a refined knot vector (knot insertion):
+// T[i * n_c + j], b^c_j = sum_i T_ij b^f_i; empty unless fine contains coarse
+std::vector<double> knot_insertion_matrix(const std::vector<double>& coarse, const std::vector<double>& fine, int p);
 void bspline_eval(const std::vector<double>& knots, int p, double x, int& first,
                   double* val, double* der);
 void gauss_legendre(int n, double* x, double* w);

@@ -5,6 +5,8 @@ parity tests (tests/test_gpu_reference.py).
     python tests/golden/make_reference.py c4 1e-8 0 3 5 ...  # problems of the C4 batch
     python tests/golden/make_reference.py c3 p n_el     # C3's 4x4x4 patches, degree p,
                                                         # n_el^3 elements (tol 1e-8, 1e-12)
+    python tests/golden/make_reference.py nc 1 2 3 4    # the non-conforming three-cube box,
+                                                        # degrees p (tol 1e-8, 1e-12)
     AFIETI_REF_DRIVER=gv python tests/golden/make_reference.py ...
         # the same with LAPACK's 'gv' eigensolver driver: ref_<name>_<tol>_gv.json,
         # the oracle's own rounding sensitivity for the parity rules
@@ -70,6 +72,10 @@ def main(argv):
     elif what == "c3":
         p, n_el = int(argv[2]), int(argv[3])
         write(f"c3_p{p}_e{n_el}", W.make_c3(seed=0, p=p, n_el=n_el), 1e-8, 1e-12)
+    elif what == "nc":
+        # the non-conforming three-cube box (4, 8, 16 elements per direction)
+        for p in argv[2:]:
+            write(f"nc_p{int(p)}", W.make_nonconforming(p=int(p)), 1e-8, 1e-12)
     elif what == "c4":
         probs = W.make_c4(seed=0)
         for j in argv[3:]:

@@ -199,3 +199,31 @@ def test_c4_batch_against_oracle(prec):
         assert (d1 - d0, c1 - c0) == (ref8["n_dof"], ref8["n_c"])
         _check(f"c4[{j}] {prec}", u[d0:d1], lam[c0:c1], int(its[j]), ref8, ref12, prec, 1e-8, alt8)
     s.close()
+
+
+# ---------------------------------------------- non-conforming three-cube box
+NC_REFS = sorted({os.path.basename(p)[4:].rsplit("_", 1)[0]
+                  for p in glob.glob(os.path.join(GOLDEN, "ref_nc_p*.json")) if not p.endswith("_gv.json")})
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp64", 1e-12), ("fp32", 1e-8)])
+@pytest.mark.parametrize("name", NC_REFS or ["nc_missing"])
+def test_nonconforming_box_against_oracle(name, prec, tol):
+    """The paper's non-conforming test (Section 6): the box (0,1)x(0,3)x(0,1)
+    in three cubes of 4, 8 and 16 elements per direction, nested knot
+    vectors on both interfaces, Dirichlet data of the exact solution on the
+    whole boundary."""
+    ref8, ref12 = _ref(name, 1e-8), _ref(name, 1e-12)
+    alt8, alt12 = _ref(name, 1e-8, "gv"), _ref(name, 1e-12, "gv")
+    if ref8 is None or (tol == 1e-12 and ref12 is None):
+        pytest.skip("oracle reference not generated")
+    _torch()
+    from paper_2001_09626_amd import Solver
+    p = int(name.split("_p")[1])
+    print(f"\n[{name} {prec} tol {tol:.0e}]", flush=True)
+    s = Solver(W.make_nonconforming(p=p), tol=tol, fd_precision=prec, maxit=5000)
+    assert (s.n_dof, s.n_c) == (ref8["n_dof"], ref8["n_c"])
+    u, lam, st = s.solve()
+    assert st["converged"]
+    _check(f"{name} {prec}", _host(u), _host(lam), st["iterations"], ref8, ref12, prec, tol, alt8, alt12)
+    s.close()

@@ -107,10 +107,11 @@ def test_error_codes():
     prob = W.make_c1(n_el=3)
     prob["patches"][1]["n_el"] = [4, 3]
     _expect_error(prob, -2)
-    # nested knot vectors on a shared face (a non-conforming interface of the
-    # paper's kind): valid, not glued by the library
-    _expect_error(W.make_nonconforming(p=2, n_els=(1, 2, 4), dim=2), -7)
-    _expect_error(W.make_nonconforming(p=2, n_els=(1, 2, 4), dim=3), -7)
+    # nested knot vectors on a face whose parametrisation is rotated against
+    # its neighbour's: a non-conforming interface the library does not glue
+    prob, _pair, _orient = W.make_rotated_pair(2)
+    prob["patches"][1]["n_el"] = [4, 4]
+    _expect_error(prob, -7)
     # too many basis functions for the device FD tiles
     prob = W.make_c1(n_el=60, p=2)
     _expect_error(prob, -7)
@@ -393,3 +394,36 @@ def test_interface_list_error_codes():
     tr["patches"][0]["bc"][1] = 2
     tr["traction"] = lambda x, n: np.zeros_like(x)
     _expect_error(dict(tr, interfaces=good), -2)
+
+
+# ------------------------------------------------- non-conforming interfaces
+def _B_sparse(s):
+    import scipy.sparse as sp
+    bx = s.export("B")
+    gl = s.export("glue")
+    rows, cols, vals = [], [], []
+    for r, pl, mi in bx:
+        rows.append(r); cols.append(pl); vals.append(1.0)
+        if mi >= 0:
+            rows.append(r); cols.append(mi); vals.append(-1.0)
+    for r, c, v in gl:
+        rows.append(int(r)); cols.append(int(c)); vals.append(v)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(len(bx), s.n_dof))
+
+
+@pytest.mark.parametrize("dim,n_els,p", [(2, (2, 4, 8), 2), (3, (1, 2, 4), 2), (3, (2, 4, 8), 3)])
+def test_host_nonconforming_matches_oracle(dim, n_els, p):
+    from paper_2001_09626_amd import Solver
+    prob = W.make_nonconforming(p=p, n_els=n_els, dim=dim)
+    o = AFIETI(prob)
+    s = Solver(prob, host_only=True)
+    assert (s.n_dof, s.n_c) == (o.n_dof, o.n_c)
+    B = _B_sparse(s)
+    d = abs(B - o.B)
+    assert d.max() <= 1e-14, d.max()
+    # same entries (the oracle's knot insertion, a linear solve, leaves
+    # rounding-level values where Boehm's insertion gives exact zeros)
+    assert np.array_equal((abs(B) > 1e-13).toarray(), (abs(o.B) > 1e-13).toarray())
+    G = o.G.T @ o.G
+    assert np.abs(s.export("GtG") - G).max() <= 1e-12 * np.abs(G).max()
+    assert np.abs(s.export("dirichlet_c") - o.c).max() <= 1e-13 * max(1.0, np.abs(o.c).max())
