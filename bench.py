@@ -57,6 +57,11 @@ def workload(name):
         p = int(name[2:]) if len(name) > 2 else 3
         prob = W.make_c3(seed=0, p=p)
         desc = f"3D unit cube, 4x4x4 patches, p={p} C^{p-1}, 24^3 elements/patch, lognormal Lame, 8 trig modes"
+    elif name.startswith("nc"):
+        p = int(name[2:]) if len(name) > 2 else 3
+        prob = W.make_nonconforming(p=p)
+        desc = (f"non-conforming box (0,1)x(0,3)x(0,1): three cubes of 4, 8, 16 elements per direction "
+                f"(nested interfaces), p={p} C^{p-1}, steel, Dirichlet data of a manufactured solution")
     elif name.startswith("ws"):
         k = int(name[2:]) if len(name) > 2 else 4
         prob = W.make_weak_scaling(k=k, n_el=8, p=3)
