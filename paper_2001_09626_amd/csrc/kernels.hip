@@ -1019,28 +1019,34 @@ __global__ void __launch_bounds__(kBlock) k_mf_gather(const DevPatch* __restrict
         hi[d] = min(pa.nb[d] - 1, i[d] / BE);
     }
     const int64_t nbr = (int64_t)pa.nb[0] * pa.nb[1] * pa.nb[2];
-    // at most NR bricks per direction contain a node: all loads are issued
-    // before the sum, which runs in the fixed (b3, b2, b1) order
+    // at most NR bricks per direction contain a node; the sum runs in the
+    // fixed (b3, b2, b1) order.  All loads are issued before the sum when
+    // they fit in registers (NR <= 3); for larger NR, one (b2, b1) plane of
+    // loads at a time (the same order)
     constexpr int NR = (NB + BE - 1) / BE;
-    double v[NR * NR * NR];
-#pragma unroll
-    for (int a3 = 0; a3 < NR; ++a3)
-#pragma unroll
-        for (int a2 = 0; a2 < NR; ++a2)
-#pragma unroll
-            for (int a1 = 0; a1 < NR; ++a1) {
-                const int b3 = lo[2] + a3, b2 = lo[1] + a2, b1 = lo[0] + a1;
-                double r = 0.0;
-                if (b3 <= hi[2] && b2 <= hi[1] && b1 <= hi[0]) {
-                    const int64_t g = (int64_t)(b3 * pa.nb[1] + b2) * pa.nb[0] + b1;
-                    const int t1 = i[0] - b1 * BE, t2 = i[1] - b2 * BE, t3 = i[2] - b3 * BE;
-                    r = ybuf[pa.ybuf_off + ((int64_t)((c * NB + t3) * NB + t2) * NB + t1) * nbr + g];
-                }
-                v[(a3 * NR + a2) * NR + a1] = r;
-            }
+    constexpr int NA = NR <= 3 ? NR : 1;  // b3 planes of loads in flight
     double acc = 0.0;
+#pragma unroll 1
+    for (int a30 = 0; a30 < NR; a30 += NA) {
+        double v[NA * NR * NR];
 #pragma unroll
-    for (int a = 0; a < NR * NR * NR; ++a) acc += v[a];
+        for (int a3 = 0; a3 < NA; ++a3)
+#pragma unroll
+            for (int a2 = 0; a2 < NR; ++a2)
+#pragma unroll
+                for (int a1 = 0; a1 < NR; ++a1) {
+                    const int b3 = lo[2] + a30 + a3, b2 = lo[1] + a2, b1 = lo[0] + a1;
+                    double r = 0.0;
+                    if (b3 <= hi[2] && b2 <= hi[1] && b1 <= hi[0]) {
+                        const int64_t g = (int64_t)(b3 * pa.nb[1] + b2) * pa.nb[0] + b1;
+                        const int t1 = i[0] - b1 * BE, t2 = i[1] - b2 * BE, t3 = i[2] - b3 * BE;
+                        r = ybuf[pa.ybuf_off + ((int64_t)((c * NB + t3) * NB + t2) * NB + t1) * nbr + g];
+                    }
+                    v[(a3 * NR + a2) * NR + a1] = r;
+                }
+#pragma unroll
+        for (int a = 0; a < NA * NR * NR; ++a) acc += v[a];
+    }
     const int64_t row = pa.dof_off + (int64_t)c * pa.nodes + node;
     if (t) {
         for (int64_t e = bt_ptr[row]; e < bt_ptr[row + 1]; ++e) acc += bt_sign[e] * t[bt_row[e]];
