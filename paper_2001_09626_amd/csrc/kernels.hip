@@ -675,10 +675,7 @@ struct MfShape {
     static constexpr int TS = 2 * QB * NB + 2 * QB;         // table doubles per (direction, brick)
     static constexpr int QA = QB | 1;                       // row stride of A / S in LDS (odd: no bank conflicts)
     static constexpr int NCB = (NCOL + 15) / 16 * 16 + 8;   // t3 stride of B / P in LDS
-#ifndef AFIETI_MF_WAVES
-#define AFIETI_MF_WAVES 2
-#endif
-    static constexpr int NW = AFIETI_MF_WAVES;              // wavefronts per brick
+    static constexpr int NW = 2;                            // wavefronts per brick
     static constexpr int QPG = (QB + NW - 1) / NW;          // q3 values per wavefront
     static constexpr int NT = 64 * NW;                      // threads per brick
     // support: at brick Gauss point q (element q / (P + 1)) only basis
