@@ -427,3 +427,19 @@ def test_host_nonconforming_matches_oracle(dim, n_els, p):
     G = o.G.T @ o.G
     assert np.abs(s.export("GtG") - G).max() <= 1e-12 * np.abs(G).max()
     assert np.abs(s.export("dirichlet_c") - o.c).max() <= 1e-13 * max(1.0, np.abs(o.c).max())
+
+
+def test_host_nonconforming_listed_equals_matched():
+    from paper_2001_09626_amd import Solver
+    prob = W.make_nonconforming(p=2, n_els=(1, 2, 4), dim=3)
+    a = Solver(prob, host_only=True)
+    listed = dict(prob, interfaces=[(0, 3, 1, 2, 0), (1, 3, 2, 2, -1)])
+    b = Solver(listed, host_only=True)
+    assert np.array_equal(a.export("B"), b.export("B"))
+    assert np.array_equal(a.export("glue"), b.export("glue"))
+    # a non-conforming pair listed with an orientation the corners contradict
+    _expect_error(dict(prob, interfaces=[(0, 3, 1, 2, 2), (1, 3, 2, 2, 0)]), -2)
+    # leaving the second interface out decouples the finest cube, which has
+    # Dirichlet faces of its own
+    c = Solver(dict(prob, interfaces=[(0, 3, 1, 2, 0)]), host_only=True)
+    assert c.n_c < a.n_c
