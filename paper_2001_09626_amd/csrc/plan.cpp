@@ -695,7 +695,6 @@ void patch_map(const PatchPlan& P, const double* eta, double* x, double (&J)[3][
 // (inverted here).  Rows of this component start at comp_start.
 void add_gluing_rows(Plan& plan, const ProblemPlan& pp, const std::vector<NcIface>& ncs, int comp, int64_t comp_start) {
     std::map<int64_t, int64_t> dir_row;  // DOF -> its Dirichlet row (this component)
-    std::vector<char> star_dof;
     for (int64_t r = comp_start; r < (int64_t)plan.c_plus.size(); ++r) {
         if (plan.c_minus[r] == -1) dir_row[plan.c_plus[r]] = r;
     }
