@@ -46,6 +46,7 @@ struct Lane {           // scratch of one concurrent branch
     double* coef = nullptr;   // rigid-mode coefficients (P_u)
     double* zc = nullptr;     // coarse coefficients (P_chi)
     void* fdtmp = nullptr;    // FD intermediate tensor
+    double* wtmp = nullptr;   // row values of the dense B B^T blocks
 };
 
 constexpr int kFdClasses = 3;
@@ -919,12 +920,13 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     }
     if (pl.dblk_ptr.size() > 1) {
         h->dense.n = (int)pl.dblk_ptr.size() - 1;
+        h->dense.total = (int)pl.dblk_rows.size();
+        std::vector<int> blk(h->dense.total);
         for (int b = 0; b < h->dense.n; ++b)
-            h->dense.max_size = std::max(h->dense.max_size, (int)(pl.dblk_ptr[b + 1] - pl.dblk_ptr[b]));
-        if (h->dense.max_size > 8192)
-            throw SetupError{AFIETI_EUNSUPPORTED, "a non-conforming interface with more than 8192 gluing rows"};
+            for (int64_t j = pl.dblk_ptr[b]; j < pl.dblk_ptr[b + 1]; ++j) blk[j] = b;
         h->dense.ptr = h->upload(pl.dblk_ptr, s);
         h->dense.rows = h->upload(pl.dblk_rows, s);
+        h->dense.blk = h->upload(blk, s);
         h->dense.moff = h->upload(pl.dblk_moff, s);
         h->dense.mat = h->upload(pl.dblk_mat, s);
     }
@@ -1031,6 +1033,10 @@ void device_setup(afieti_handle* h, hipStream_t s) {
     h->lane[1].part = h->dalloc<double>(maxch * 6);
     h->lane[1].coef = h->dalloc<double>(np * 6);
     h->lane[1].zc = h->dalloc<double>(np * 6);
+    if (h->dense.n) {
+        h->lane[0].wtmp = h->dalloc<double>(h->dense.total);
+        h->lane[1].wtmp = h->dalloc<double>(h->dense.total);
+    }
     HIP_OK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
     HIP_OK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     HIP_OK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
@@ -1197,12 +1203,19 @@ void op_pu(afieti_handle* h, const double* x, double* out, hipStream_t s, int ln
 //      the caller has applied it)
 // With geometry inclusion A~_l replaces A-hat_l, there is no H factor, and
 // D_S^{1/2} scales the Gamma values as B^T writes them and as B reads them.
+// the dense B B^T blocks with the row-value scratch of branch ln
+DenseBlocks dense_for(const afieti_handle* h, int ln) {
+    DenseBlocks d = h->dense;
+    d.tmp = h->lane[ln].wtmp;
+    return d;
+}
+
 void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipStream_t s, int ln) {
     const bool nr = h->opt.ps_variant == AFIETI_PS_NR;
     if (stage == 1) {
         const double* a = y;
         if (nr) {
-            launch_W(h->d_bstart, h->d_bsize, h->d_bdir, h->dense, h->n_c, y, h->c1, s);
+            launch_W(h->d_bstart, h->d_bsize, h->d_bdir, dense_for(h, ln), h->n_c, y, h->c1, s);
             a = h->c1;
         }
         // (D_S^{1/2} applied as B^T writes, with geometry inclusion)
@@ -1214,7 +1227,7 @@ void op_ps_stage(afieti_handle* h, int stage, const double* y, double* out, hipS
         if (stage == 3) op_ahat(h, h->tv, h->tt, 1, s, false, true);  // B reads only the Gamma part
         // (D_S^{1/2} applied as B reads, with geometry inclusion)
         if (nr) {
-            launch_BW(h->d_bstart, h->d_bsize, h->d_bdir, h->dense, h->n_c, h->d_cplus, h->d_cminus, h->glue, h->tt, out, s, h->d_geo_ds);
+            launch_BW(h->d_bstart, h->d_bsize, h->d_bdir, dense_for(h, ln), h->n_c, h->d_cplus, h->d_cminus, h->glue, h->tt, out, s, h->d_geo_ds);
         } else {
             launch_B(h->d_cplus, h->d_cminus, h->glue, h->n_c, 1.0, h->tt, out, s, h->d_geo_ds);
         }
@@ -1243,7 +1256,7 @@ void op_prec_branches(afieti_handle* h, const double* r, double* z, hipStream_t 
     op_pu(h, r, h->s1, s);
     if (nr) {
         const Lane& L = h->lane[b.ln];
-        launch_GW(h->d_bstart, h->d_bsize, h->d_bdir, h->dense, h->n_c, h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, L.zc,
+        launch_GW(h->d_bstart, h->d_bsize, h->d_bdir, dense_for(h, b.ln), h->n_c, h->d_ppl, h->d_pmi, h->d_gpl, h->d_gmi, L.zc,
                   r + h->n_dof, h->c1, b.s);
         launch_Bt(h->d_btptr, h->d_btrow, h->d_btsgn, h->n_dof, h->c1, h->tv, b.s, h->d_geo_ds);
         op_ahat(h, h->tv, h->tt, 0, b.s, true);

@@ -115,14 +115,18 @@ struct GlueRows {
     const double* val = nullptr;
 };
 // Dense blocks of B B^T (rows whose block kind is 2): block b holds the rows
-// rows[ptr[b] .. ptr[b + 1]) and its inverse, row major, at mat + moff[b];
-// max_size is the largest block.
+// rows[ptr[b] .. ptr[b + 1]) and its inverse at mat + moff[b], row major;
+// blk[j] is the block of the j-th listed
+// row, total the number of listed rows and tmp (total doubles) the row
+// values between the two kernels of an application.
 struct DenseBlocks {
-    int n = 0, max_size = 0;
+    int n = 0, total = 0;
     const int64_t* ptr = nullptr;
     const int* rows = nullptr;
+    const int* blk = nullptr;
     const int64_t* moff = nullptr;
     const double* mat = nullptr;
+    double* tmp = nullptr;
 };
 // y[r] = alpha (x[plus] - x[minus]) (Dirichlet rows: alpha x[plus]; gluing
 // rows as GlueRows); with in_scale (may be NULL) x is read as in_scale .* x

@@ -1297,7 +1297,7 @@ __global__ void k_Bt(const int64_t* __restrict__ ptr, const int* __restrict__ ro
 
 // (B B^T)^{-1} row by row, for values computed per row on the fly: star
 // block of size s: I + 1 1^T, whose inverse is I - 1 1^T / (s + 1);
-// Dirichlet block: identity; rows of dense blocks are left to k_w_dense.
+// Dirichlet block: identity; rows of dense blocks are left to k_w_dense_*.
 // z = (B B^T)^{-1} y (k_W), (B B^T)^{-1} (B x) (k_BW), (B B^T)^{-1} (y - G zc)
 // (k_GW); the arithmetic of every row value equals k_B / k_G_apply.
 template <typename RowValue>
@@ -1364,21 +1364,29 @@ __global__ void k_GW(const int* __restrict__ bs, const int* __restrict__ bn, con
     if (r < n_c) w_row(bs, bn, bd, r, z, val);
 }
 
-// dense blocks: one workgroup per block, the block's row values in LDS,
-// then z_a = sum_b Minv[a][b] v_b in a fixed order
+// dense blocks: the row values of every listed row (k_w_dense_val), then
+// z_a = sum_c Minv[a][c] v_c per row, summed in a fixed order (k_w_dense_mv)
 template <typename RowValue>
-__global__ void __launch_bounds__(kBlock) k_w_dense(DenseBlocks db, double* __restrict__ z, RowValue val) {
-    extern __shared__ double sv[];
-    const int64_t b0 = db.ptr[blockIdx.x];
-    const int n = (int)(db.ptr[blockIdx.x + 1] - b0);
-    for (int a = threadIdx.x; a < n; a += kBlock) sv[a] = val(db.rows[b0 + a]);
-    __syncthreads();
-    const double* M = db.mat + db.moff[blockIdx.x];
-    for (int a = threadIdx.x; a < n; a += kBlock) {
-        double acc = 0.0;
-        for (int c = 0; c < n; ++c) acc += M[(int64_t)a * n + c] * sv[c];
-        z[db.rows[b0 + a]] = acc;
-    }
+__global__ void __launch_bounds__(kBlock) k_w_dense_val(DenseBlocks db, RowValue val) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j < db.total) db.tmp[j] = val(db.rows[j]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_w_dense_mv(DenseBlocks db, double* __restrict__ z) {
+    // one wavefront per row: lane l sums the columns c = l (mod 64), then a
+    // fixed butterfly adds the lanes' sums
+    const int j = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (j >= db.total) return;
+    const int b = db.blk[j];
+    const int64_t b0 = db.ptr[b];
+    const int n = (int)(db.ptr[b + 1] - b0), a = (int)(j - b0);
+    const double* M = db.mat + db.moff[b] + (int64_t)a * n;
+    const double* v = db.tmp + b0;
+    double acc = 0.0;
+    for (int c = lane; c < n; c += 64) acc += M[c] * v[c];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) z[db.rows[j]] = acc;
 }
 
 // f(integral_constant<int, dim>) for the dimension of a patch (uniform per
@@ -1982,9 +1990,10 @@ void w_launch(void (*rows)(const int*, const int*, const int*, int64_t, double*,
               hipStream_t s) {
     if (!n_c) return;
     hipLaunchKernelGGL(rows, dim3(blocks_for(n_c)), dim3(kBlock), 0, s, bs, bn, bd, n_c, z, val);
-    if (db.n)
-        hipLaunchKernelGGL(k_w_dense<RowValue>, dim3(db.n), dim3(kBlock), db.max_size * sizeof(double), s, db, z,
-                           val);
+    if (db.n) {
+        hipLaunchKernelGGL(k_w_dense_val<RowValue>, dim3(blocks_for(db.total)), dim3(kBlock), 0, s, db, val);
+        hipLaunchKernelGGL(k_w_dense_mv, dim3(blocks_for(db.total, kBlock / 64)), dim3(kBlock), 0, s, db, z);
+    }
 }
 
 void launch_W(const int* bs, const int* bn, const int* bd, const DenseBlocks& db, int64_t n_c, const double* y,
