@@ -12,9 +12,16 @@
  * g on faces marked AFIETI_FACE_TRACTION (Gamma_N), Dirichlet data u = g_D
  * on faces marked AFIETI_FACE_DIRICHLET (homogeneous, or from a callback),
  * natural conditions elsewhere.  Interfaces (Section 2.2) are the pairs of
- * patch faces whose corners coincide, or the pairs listed explicitly;
- * they must be conforming (equal knot vectors; nested knot vectors, the
- * non-conforming interfaces of Section 2.2, give AFIETI_EUNSUPPORTED).
+ * patch faces whose corners coincide, or the pairs listed explicitly.  With
+ * equal knot vectors along the face an interface is conforming (its nodes
+ * are matched one to one); with nested knot vectors (one side refines the
+ * other) it is non-conforming, and every node of the finer face is glued to
+ * the coarse trace written in the fine basis by knot insertion.  A
+ * non-conforming interface needs aligned parametrisations of its two faces
+ * and finer-face nodes that no third patch shares (AFIETI_EUNSUPPORTED
+ * otherwise); unequal degrees, knot vectors along a face that are neither
+ * equal nor nested, or a face refined on each side in another direction
+ * give AFIETI_EGEOM.
  *
  * Vector layouts (all double precision, device memory, caller owned):
  *   DOF vector   patch-stacked (Section 4): for each problem, for each
@@ -27,7 +34,11 @@
  * Rows of B ("star" pattern to the lowest patch index): for each problem,
  * component c, geometric node (ordered by lowest patch, then its local
  * index) with copies k_1 < ... < k_r: a node on the Dirichlet boundary has
- * the r rows e_{k_j}; any other node the r-1 rows e_{k_1} - e_{k_j}.
+ * the r rows e_{k_j}; any other node the r-1 rows e_{k_1} - e_{k_j}.  Then,
+ * per component, for each non-conforming interface and each node i of its
+ * finer face, the row e_{f,i} - sum_j T_ij e_{c,j} (T the face's
+ * knot-insertion matrix, j over the coarse face's nodes); the finer face's
+ * nodes take no other row.
  *
  * Streams: every `stream` argument is a hipStream_t (NULL = default
  * stream).  Work is enqueued on it; calls that report a scalar result to
@@ -57,7 +68,7 @@ extern "C" {
 #define AFIETI_ENOMEM (-5)
 #define AFIETI_EHIP (-6)         /* a HIP runtime call failed                */
 #define AFIETI_EUNSUPPORTED (-7)   /* valid input the library does not build:
-                                    non-conforming (nested) interfaces, FD
+                                    rotated non-conforming interfaces, FD
                                     tiles beyond the device limit, ...       */
 
 #define AFIETI_FACE_FREE 0       /* natural condition or interface (auto)    */
