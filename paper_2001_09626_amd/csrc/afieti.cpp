@@ -1576,7 +1576,7 @@ const char* afieti_strerror(int code) {
         case AFIETI_OK: return "ok";
         case AFIETI_NOT_CONVERGED: return "MINRES reached maxit before the tolerance";
         case AFIETI_EINVAL: return "invalid argument";
-        case AFIETI_EGEOM: return "invalid geometry or non-conforming interface";
+        case AFIETI_EGEOM: return "invalid geometry, or interface faces that do not match";
         case AFIETI_ESINGULAR: return "singular coarse problem (not enough constraints)";
         case AFIETI_EBREAKDOWN: return "MINRES breakdown: preconditioner not positive definite";
         case AFIETI_ENOMEM: return "out of device memory";
