@@ -62,7 +62,7 @@ extern "C" {
 #define AFIETI_OK 0
 #define AFIETI_NOT_CONVERGED 1
 #define AFIETI_EINVAL (-1)       /* bad sizes, degree, NULL pointer, NaN     */
-#define AFIETI_EGEOM (-2)        /* det J <= 0 or faces that do not conform  */
+#define AFIETI_EGEOM (-2)        /* det J <= 0 or faces that do not match    */
 #define AFIETI_ESINGULAR (-3)    /* G^T G or B B^T not positive definite     */
 #define AFIETI_EBREAKDOWN (-4)   /* MINRES gamma^2 < 0: preconditioner not SPD */
 #define AFIETI_ENOMEM (-5)
