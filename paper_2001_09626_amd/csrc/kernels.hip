@@ -1487,12 +1487,17 @@ __global__ void __launch_bounds__(kBlock) k_rigid_finalize(const int* __restrict
         }
 }
 
-// one block per problem: g = sum of the partials per patch and mode (one
-// wave per entry, lanes strided over the chunks, fixed shuffle tree),
-// zc = (G^T G)^{-1} g, scattered to zc[patch * 6 + mode]; the slots of the
-// modes a 2D patch does not have are set to zero (G_apply reads all six)
+// g = sum of the partials per patch and mode (one wave per entry, lanes
+// strided over the chunks, fixed shuffle tree), zc = (G^T G)^{-1} g,
+// scattered to zc[patch * 6 + mode]; the slots of the modes a 2D patch does
+// not have are set to zero (G_apply reads all six).  Grid (problem, row
+// block): every block forms all of g (cheap) and kFinBlock / kFinSub rows
+// of the product, so that a large coarse matrix (64 patches: 384 x 384) is
+// read by many CUs at once.  Loads are issued in batches before their sums;
+// every sum keeps its order, so the result does not depend on the grid.
 constexpr int kFinBlock = 1024;  // threads of the coarse finalisation (16 wavefronts)
 constexpr int kFinSub = 16;      // lanes per row of the (G^T G)^{-1} product
+constexpr int kFinRows = kFinBlock / kFinSub;  // product rows per block
 
 __global__ void __launch_bounds__(kFinBlock) k_coarse_finalize(const int* __restrict__ p0, const int* __restrict__ np,
                                                                const int* __restrict__ nmod,
@@ -1503,12 +1508,15 @@ __global__ void __launch_bounds__(kFinBlock) k_coarse_finalize(const int* __rest
                                                                double* __restrict__ zc) {
     extern __shared__ __align__(16) unsigned char smem[];
     double* g = reinterpret_cast<double*>(smem);
-    constexpr int NWV = kFinBlock / 64, U = 4;
+    constexpr int NWV = kFinBlock / 64, U = 8, KU = 8;
     const int pr = blockIdx.x;
     const int nm = nmod[pr], npch = np[pr], patch0 = p0[pr];
     const int nc = nm * npch;
+    const int rbase = blockIdx.y * kFinRows;
+    if (rbase >= nc) return;  // (uniform over the block)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // U entries per wavefront at a time, so that their loads overlap
+    // U entries per wavefront at a time; each lane's first chunk of every
+    // entry is loaded before any sum
     for (int e0 = wave; e0 < nc; e0 += U * NWV) {
         double s[U];
 #pragma unroll
@@ -1517,7 +1525,16 @@ __global__ void __launch_bounds__(kFinBlock) k_coarse_finalize(const int* __rest
             s[u] = 0.0;
             if (e < nc) {
                 const int k = patch0 + e / nm, m = e % nm;
-                for (int c = cptr[k] + lane; c < cptr[k + 1]; c += 64) s[u] += part[(int64_t)c * 6 + m];
+                const int c = cptr[k] + lane;
+                if (c < cptr[k + 1]) s[u] = 0.0 + part[(int64_t)c * 6 + m];  // (as a sum from zero)
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * NWV;
+            if (e < nc) {  // more than 64 chunks in a patch: the rest, in order
+                const int k = patch0 + e / nm, m = e % nm;
+                for (int c = cptr[k] + lane + 64; c < cptr[k + 1]; c += 64) s[u] += part[(int64_t)c * 6 + m];
             }
         }
 #pragma unroll
@@ -1527,21 +1544,28 @@ __global__ void __launch_bounds__(kFinBlock) k_coarse_finalize(const int* __rest
         }
     }
     __syncthreads();
-    // zc = C g: kFinSub lanes per row, partial sums over j = sub (mod kFinSub),
-    // then a fixed butterfly over the kFinSub lanes
-    const double* C = cinv + coff[pr];
+    // zc = C g: kFinSub lanes per row, partial sums over j = sub (mod kFinSub)
+    // in ascending j, then a fixed butterfly over the kFinSub lanes
     const int sub = threadIdx.x % kFinSub;
-    for (int base = 0; base < nc; base += kFinBlock / kFinSub) {
-        const int e = base + threadIdx.x / kFinSub;
-        double s = 0.0;
-        if (e < nc)
-            for (int j = sub; j < nc; j += kFinSub) s += C[(int64_t)e * nc + j] * g[j];
+    const int e = rbase + threadIdx.x / kFinSub;
+    double acc = 0.0;
+    if (e < nc) {
+        const double* Ce = cinv + coff[pr] + (int64_t)e * nc;
+        for (int j = sub; j < nc; j += KU * kFinSub) {
+            double cv[KU];
 #pragma unroll
-        for (int o = kFinSub / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-        if (sub == 0 && e < nc) zc[(patch0 + e / nm) * 6 + e % nm] = s;
+            for (int u = 0; u < KU; ++u) cv[u] = j + u * kFinSub < nc ? Ce[j + u * kFinSub] : 0.0;
+#pragma unroll
+            for (int u = 0; u < KU; ++u)
+                if (j + u * kFinSub < nc) acc += cv[u] * g[j + u * kFinSub];
+        }
     }
-    for (int e = threadIdx.x; e < npch * (6 - nm); e += kFinBlock)
-        zc[(patch0 + e / (6 - nm)) * 6 + nm + e % (6 - nm)] = 0.0;
+#pragma unroll
+    for (int o = kFinSub / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (sub == 0 && e < nc) zc[(patch0 + e / nm) * 6 + e % nm] = acc;
+    if (blockIdx.y == 0)
+        for (int t = threadIdx.x; t < npch * (6 - nm); t += kFinBlock)
+            zc[(patch0 + t / (6 - nm)) * 6 + nm + t % (6 - nm)] = 0.0;
 }
 
 // y = x - R coef over chunks of patch DOFs
@@ -2028,8 +2052,8 @@ void launch_gamma_partial(const Chunk* chunks, int n_chunks, const int* mc_row, 
 void launch_coarse_finalize(const int* p0, const int* np, const int* nm, const int64_t* coff, int n_probs,
                             const int* cptr, const double* partials, const double* Cinv, double* zc, int max_nc,
                             hipStream_t s) {
-    hipLaunchKernelGGL(k_coarse_finalize, dim3(n_probs), dim3(kFinBlock), max_nc * sizeof(double), s, p0, np, nm,
-                       coff, cptr, partials, Cinv, zc);
+    hipLaunchKernelGGL(k_coarse_finalize, dim3(n_probs, (max_nc + kFinRows - 1) / kFinRows), dim3(kFinBlock),
+                       max_nc * sizeof(double), s, p0, np, nm, coff, cptr, partials, Cinv, zc);
 }
 
 void launch_rigid_finalize(const int* cptr, int n_patches, const double* partials, const double* RtR_inv,
