@@ -140,7 +140,7 @@ def test_autograd_with_geometry_inclusion():
                 np.abs(gl[:, 1] - g["dmu"]).max() / np.abs(g["dmu"]).max(),
                 np.abs(amps.grad.numpy() - g["damp"]).max() / np.abs(g["damp"]).max())
         print(f"  step {step}: J {float(J.detach()):.6e} (oracle {Jo:.6e}), gradient rel err {e:.2e}")
-        assert float(J) == pytest.approx(Jo, rel=1e-9)
+        assert float(J.detach()) == pytest.approx(Jo, rel=1e-9)
         assert e <= 1e-8
     s.close()
 
