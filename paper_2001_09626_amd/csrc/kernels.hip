@@ -1487,17 +1487,13 @@ __global__ void __launch_bounds__(kBlock) k_rigid_finalize(const int* __restrict
         }
 }
 
-// g = sum of the partials per patch and mode (one wave per entry, lanes
-// strided over the chunks, fixed shuffle tree), zc = (G^T G)^{-1} g,
-// scattered to zc[patch * 6 + mode]; the slots of the modes a 2D patch does
-// not have are set to zero (G_apply reads all six).  Grid (problem, row
-// block): every block forms all of g (cheap) and kFinBlock / kFinSub rows
-// of the product, so that a large coarse matrix (64 patches: 384 x 384) is
-// read by many CUs at once.  Loads are issued in batches before their sums;
-// every sum keeps its order, so the result does not depend on the grid.
+// one block per problem: g = sum of the partials per patch and mode (one
+// wave per entry, lanes strided over the chunks, fixed shuffle tree),
+// zc = (G^T G)^{-1} g, scattered to zc[patch * 6 + mode]; the slots of the
+// modes a 2D patch does not have are set to zero (G_apply reads all six)
 constexpr int kFinBlock = 1024;  // threads of the coarse finalisation (16 wavefronts)
 constexpr int kFinSub = 16;      // lanes per row of the (G^T G)^{-1} product
-constexpr int kFinRows = kFinBlock / kFinSub;  // product rows per block
+constexpr int kFinRows = kFinBlock / kFinSub;  // product rows per pass
 
 __global__ void __launch_bounds__(kFinBlock) k_coarse_finalize(const int* __restrict__ p0, const int* __restrict__ np,
                                                                const int* __restrict__ nmod,
@@ -1506,6 +1502,61 @@ __global__ void __launch_bounds__(kFinBlock) k_coarse_finalize(const int* __rest
                                                                const double* __restrict__ part,
                                                                const double* __restrict__ cinv,
                                                                double* __restrict__ zc) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* g = reinterpret_cast<double*>(smem);
+    constexpr int NWV = kFinBlock / 64, U = 4;
+    const int pr = blockIdx.x;
+    const int nm = nmod[pr], npch = np[pr], patch0 = p0[pr];
+    const int nc = nm * npch;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // U entries per wavefront at a time, so that their loads overlap
+    for (int e0 = wave; e0 < nc; e0 += U * NWV) {
+        double s[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * NWV;
+            s[u] = 0.0;
+            if (e < nc) {
+                const int k = patch0 + e / nm, m = e % nm;
+                for (int c = cptr[k] + lane; c < cptr[k + 1]; c += 64) s[u] += part[(int64_t)c * 6 + m];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double t = wave_sum(s[u]);
+            if (lane == 0 && e0 + u * NWV < nc) g[e0 + u * NWV] = t;
+        }
+    }
+    __syncthreads();
+    // zc = C g: kFinSub lanes per row, partial sums over j = sub (mod kFinSub),
+    // then a fixed butterfly over the kFinSub lanes
+    const double* C = cinv + coff[pr];
+    const int sub = threadIdx.x % kFinSub;
+    for (int base = 0; base < nc; base += kFinRows) {
+        const int e = base + threadIdx.x / kFinSub;
+        double s = 0.0;
+        if (e < nc)
+            for (int j = sub; j < nc; j += kFinSub) s += C[(int64_t)e * nc + j] * g[j];
+#pragma unroll
+        for (int o = kFinSub / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (sub == 0 && e < nc) zc[(patch0 + e / nm) * 6 + e % nm] = s;
+    }
+    for (int e = threadIdx.x; e < npch * (6 - nm); e += kFinBlock)
+        zc[(patch0 + e / (6 - nm)) * 6 + nm + e % (6 - nm)] = 0.0;
+}
+
+// The same on a grid (problem, row block), for coarse matrices of more than
+// kFinRows rows: every block forms all of g (cheap) and kFinRows rows of the
+// product, so that a large coarse matrix (64 patches: 384 x 384) is read by
+// many CUs at once.  Loads are issued in batches before their sums; every
+// sum keeps its order, so the result equals the one-block kernel's.
+__global__ void __launch_bounds__(kFinBlock) k_coarse_finalize_rows(const int* __restrict__ p0, const int* __restrict__ np,
+                                                                    const int* __restrict__ nmod,
+                                                                    const int64_t* __restrict__ coff,
+                                                                    const int* __restrict__ cptr,
+                                                                    const double* __restrict__ part,
+                                                                    const double* __restrict__ cinv,
+                                                                    double* __restrict__ zc) {
     extern __shared__ __align__(16) unsigned char smem[];
     double* g = reinterpret_cast<double*>(smem);
     constexpr int NWV = kFinBlock / 64, U = 8, KU = 8;
@@ -2052,8 +2103,13 @@ void launch_gamma_partial(const Chunk* chunks, int n_chunks, const int* mc_row, 
 void launch_coarse_finalize(const int* p0, const int* np, const int* nm, const int64_t* coff, int n_probs,
                             const int* cptr, const double* partials, const double* Cinv, double* zc, int max_nc,
                             hipStream_t s) {
-    hipLaunchKernelGGL(k_coarse_finalize, dim3(n_probs, (max_nc + kFinRows - 1) / kFinRows), dim3(kFinBlock),
-                       max_nc * sizeof(double), s, p0, np, nm, coff, cptr, partials, Cinv, zc);
+    // (one block per problem while the coarse matrices fit one pass of rows)
+    if (max_nc <= kFinRows)
+        hipLaunchKernelGGL(k_coarse_finalize, dim3(n_probs), dim3(kFinBlock), max_nc * sizeof(double), s, p0, np,
+                           nm, coff, cptr, partials, Cinv, zc);
+    else
+        hipLaunchKernelGGL(k_coarse_finalize_rows, dim3(n_probs, (max_nc + kFinRows - 1) / kFinRows),
+                           dim3(kFinBlock), max_nc * sizeof(double), s, p0, np, nm, coff, cptr, partials, Cinv, zc);
 }
 
 void launch_rigid_finalize(const int* cptr, int n_patches, const double* partials, const double* RtR_inv,
